@@ -1,0 +1,186 @@
+"""CPU FP64 oracle for hybrid dealiased convolution -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
+``cpu_baseline`` leg may import this package.  The GPU library never calls it
+and shares no code with it.
+
+The convolution oracle is ``oracle.c`` (plain C, FP64, OpenMP), built into
+``liboracle.so`` next to this file by :func:`build`.  It computes the linear
+convolution of eq. (4) (section 2.3) two independent ways:
+
+* :func:`direct_1d`, :func:`direct_1d_sampled`, :func:`direct_nd_sampled` --
+  the defining sum;
+* :func:`padded_1d`, :func:`padded_nd` -- explicit dealiasing (section 3.1):
+  zero padding to the smallest 2^a 3^b 5^c 7^d size >= 2L-1, DFT with
+  zeta = e^{+2 pi i/n}, product, inverse DFT with 1/n, crop to M.
+
+:func:`padded_dft` is the zero-extended forward DFT whose entries the residues
+of eq. (1) (section 2.2) enumerate.  ``mlp.py`` holds the FP64 reference of
+the parameter predictor's network.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_I64 = ctypes.c_int64
+_P = ctypes.c_void_p
+
+
+def build(force: bool = True) -> str:
+    """Compile ``oracle.c`` into ``liboracle.so`` (gcc, -O2, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-D_GNU_SOURCE",
+                               _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        lib.oracle_direct_1d.argtypes = [_I64, _I64, _I64, _P, _P, _P]
+        lib.oracle_direct_1d_sampled.argtypes = [_I64, _I64, _P, _P, _P, _I64, _P]
+        lib.oracle_direct_nd_sampled.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P, _I64, _P]
+        lib.oracle_padded_1d.argtypes = [_I64, _I64, _I64, _P, _P, _P]
+        lib.oracle_padded_nd.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P]
+        lib.oracle_dft.argtypes = [_I64, _P, ctypes.c_int]
+        lib.oracle_padded_dft.argtypes = [_I64, _I64, _P, _P]
+        lib.oracle_friendly_size.argtypes = [_I64]
+        lib.oracle_friendly_size.restype = _I64
+        lib.oracle_num_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _c128(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a), dtype=np.complex128)
+
+
+def _as_2d(x):
+    x = _c128(x)
+    if x.ndim == 1:
+        return x.reshape(-1, 1), True
+    if x.ndim != 2:
+        raise ValueError("1D oracle takes (L,) or (L, C) arrays")
+    return x, False
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+def friendly_size(n: int) -> int:
+    """Smallest 2^a 3^b 5^c 7^d >= n."""
+    return int(_load().oracle_friendly_size(int(n)))
+
+
+def _check(rc, name):
+    if rc != 0:
+        raise ValueError(f"{name}: invalid arguments")
+
+
+def direct_1d(f, g, M: int) -> np.ndarray:
+    """h_k = sum_j f_j g_{k-j} for k < M (eq. (4)); f, g of shape (L,) or (L, C)."""
+    f2, flat = _as_2d(f)
+    g2, _ = _as_2d(g)
+    if f2.shape != g2.shape:
+        raise ValueError("f and g must have the same shape")
+    L, C = f2.shape
+    h = np.empty((int(M), C), np.complex128)
+    _check(_load().oracle_direct_1d(L, int(M), C, f2.ctypes.data, g2.ctypes.data, h.ctypes.data), "direct_1d")
+    return h.reshape(-1) if flat else h
+
+
+def direct_1d_sampled(f, g, ks) -> np.ndarray:
+    """eq. (4) evaluated only at the output indices ``ks``."""
+    f2, flat = _as_2d(f)
+    g2, _ = _as_2d(g)
+    L, C = f2.shape
+    ks = np.ascontiguousarray(ks, dtype=np.int64)
+    out = np.empty((ks.size, C), np.complex128)
+    _load().oracle_direct_1d_sampled(L, C, f2.ctypes.data, g2.ctypes.data, ks.ctypes.data, ks.size,
+                                     out.ctypes.data)
+    return out.reshape(-1) if flat else out
+
+
+def direct_nd_sampled(f, g, M, ks) -> np.ndarray:
+    """N-D eq. (4) at the row-major linear indices ``ks`` of the output box M."""
+    f = _c128(f)
+    g = _c128(g)
+    nd = f.ndim
+    Ls = np.ascontiguousarray(f.shape, dtype=np.int64)
+    Ms = np.ascontiguousarray(M, dtype=np.int64)
+    ks = np.ascontiguousarray(ks, dtype=np.int64)
+    out = np.empty(ks.size, np.complex128)
+    _check(_load().oracle_direct_nd_sampled(nd, Ls.ctypes.data, Ms.ctypes.data, f.ctypes.data, g.ctypes.data,
+                                            ks.ctypes.data, ks.size, out.ctypes.data), "direct_nd_sampled")
+    return out
+
+
+def direct_nd(f, g, M) -> np.ndarray:
+    """N-D eq. (4) over the whole output box (small problems only)."""
+    M = tuple(int(x) for x in M)
+    ks = np.arange(int(np.prod(M)), dtype=np.int64)
+    return direct_nd_sampled(f, g, M, ks).reshape(M)
+
+
+def padded_1d(f, g, M: int) -> np.ndarray:
+    """Explicitly zero-padded FFT convolution (section 3.1), output length M."""
+    f2, flat = _as_2d(f)
+    g2, _ = _as_2d(g)
+    if f2.shape != g2.shape:
+        raise ValueError("f and g must have the same shape")
+    L, C = f2.shape
+    h = np.empty((int(M), C), np.complex128)
+    _check(_load().oracle_padded_1d(L, int(M), C, f2.ctypes.data, g2.ctypes.data, h.ctypes.data), "padded_1d")
+    return h.reshape(-1) if flat else h
+
+
+def padded_nd(f, g, M) -> np.ndarray:
+    """Explicitly zero-padded FFT convolution in 1..3 dimensions."""
+    f = _c128(f)
+    g = _c128(g)
+    Ls = np.ascontiguousarray(f.shape, dtype=np.int64)
+    Ms = np.ascontiguousarray(M, dtype=np.int64)
+    h = np.empty(tuple(int(x) for x in M), np.complex128)
+    _check(_load().oracle_padded_nd(f.ndim, Ls.ctypes.data, Ms.ctypes.data, f.ctypes.data, g.ctypes.data,
+                                    h.ctypes.data), "padded_nd")
+    return h
+
+
+def dft(x, sign: int) -> np.ndarray:
+    """X_k = sum_j exp(sign 2 pi i k j / n) x_j (unscaled)."""
+    y = _c128(x).copy()
+    _check(_load().oracle_dft(y.size, y.ctypes.data, int(sign)), "dft")
+    return y
+
+
+def padded_dft(x, N: int) -> np.ndarray:
+    """X_k = sum_{j<L} zeta_N^{+kj} x_j, k < N (the zero-extended forward transform)."""
+    x = _c128(x)
+    X = np.empty(int(N), np.complex128)
+    _check(_load().oracle_padded_dft(x.size, int(N), x.ctypes.data, X.ctypes.data), "padded_dft")
+    return X
+
+
+def rel_l2(a, b) -> float:
+    """||a - b||_2 / ||b||_2 over all entries (b is the reference)."""
+    a = np.asarray(a, np.complex128).ravel()
+    b = np.asarray(b, np.complex128).ravel()
+    nb = np.linalg.norm(b)
+    if nb == 0.0:
+        return float(np.linalg.norm(a))
+    return float(np.linalg.norm(a - b) / nb)

@@ -1,0 +1,250 @@
+"""Pins of the CPU FP64 oracle against facts that do not come from the oracle.
+
+Each test names what fixes the expected value: a library routine
+(numpy.convolve, numpy.fft, scipy.signal), exact integer arithmetic, a closed
+form of eq. (4) (section 2.3), the orthogonality relation of section 2.1, or
+the structure of explicit dealiasing (section 3.1).
+"""
+import numpy as np
+import pytest
+import scipy.signal
+
+import oracle
+import synth
+
+
+def _gauss_int(L, C=None, seed=0, bound=8):
+    shape = (L,) if C is None else (L, C)
+    return (synth.gaussian_integers(shape, bound, 90, seed, 0),
+            synth.gaussian_integers(shape, bound, 90, seed, 1))
+
+
+def _exact_int_conv(f, g, M):
+    """Brute-force eq. (4) in Python integers (exact)."""
+    fr = [(int(z.real), int(z.imag)) for z in f]
+    gr = [(int(z.real), int(z.imag)) for z in g]
+    L = len(fr)
+    out = []
+    for k in range(M):
+        re = im = 0
+        for j in range(max(0, k - L + 1), min(k, L - 1) + 1):
+            a, b = fr[j]
+            c, d = gr[k - j]
+            re += a * c - b * d
+            im += a * d + b * c
+        out.append(complex(re, im))
+    return np.array(out, np.complex128)
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 5, 6, 17, 64, 100, 257, 1024])
+def test_direct_matches_numpy_convolve(L):
+    f, g = synth.pair(L, 91, L)
+    M = 2 * L - 1
+    ref = np.convolve(f, g)  # library routine, full mode: length 2L-1
+    assert oracle.rel_l2(oracle.direct_1d(f, g, M), ref) < 1e-14
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 6, 31, 100, 243, 1000, 2187])
+def test_padded_matches_numpy_convolve(L):
+    f, g = synth.pair(L, 92, L)
+    ref = np.convolve(f, g)
+    assert oracle.rel_l2(oracle.padded_1d(f, g, 2 * L - 1), ref) < 1e-14
+
+
+@pytest.mark.parametrize("L,M", [(6, 11), (6, 12), (6, 20), (100, 250), (1, 5)])
+def test_output_tail_beyond_2L_minus_1_is_exactly_zero(L, M):
+    f, g = synth.pair(L, 93, L)
+    for h in (oracle.direct_1d(f, g, M), oracle.padded_1d(f, g, M)):
+        assert np.all(h[2 * L - 1:] == 0)
+        assert oracle.rel_l2(h[:2 * L - 1], np.convolve(f, g)) < 1e-14
+
+
+@pytest.mark.parametrize("L", [6, 37, 300])
+def test_gaussian_integers_exact(L):
+    """Integer inputs: eq. (4) by Python integer arithmetic is exact."""
+    f, g = _gauss_int(L, seed=L)
+    M = 2 * L - 1
+    exact = _exact_int_conv(f, g, M)
+    assert np.array_equal(oracle.direct_1d(f, g, M), exact)  # FP64 sums of small integers are exact
+    assert np.array_equal(np.round(oracle.padded_1d(f, g, M)), exact)
+
+
+def test_gaussian_integers_exact_large():
+    L = 4096
+    f, g = _gauss_int(L, seed=1)
+    d = oracle.direct_1d(f, g, 2 * L - 1)
+    assert np.array_equal(d, np.round(d))  # integer-valued, no rounding in the direct sum
+    assert np.array_equal(np.round(oracle.padded_1d(f, g, 2 * L - 1)), d)
+
+
+def test_delta_pairs_hit_every_index():
+    """delta_a * delta_b = delta_{a+b} for all a, b < L."""
+    L = 12
+    M = 2 * L - 1
+    for a in range(L):
+        for b in range(L):
+            f = np.zeros(L, complex)
+            g = np.zeros(L, complex)
+            f[a] = 1.0
+            g[b] = 1.0
+            want = np.zeros(M, complex)
+            want[a + b] = 1.0
+            assert np.array_equal(oracle.direct_1d(f, g, M), want)
+            assert np.max(np.abs(oracle.padded_1d(f, g, M) - want)) < 1e-15
+
+
+def test_ones_give_triangle():
+    L = 50
+    f = np.ones(L, complex)
+    k = np.arange(2 * L - 1)
+    tri = np.minimum(k + 1, 2 * L - 1 - k).astype(complex)
+    assert np.array_equal(oracle.direct_1d(f, f, 2 * L - 1), tri)
+    assert np.max(np.abs(oracle.padded_1d(f, f, 2 * L - 1) - tri)) < 1e-12
+
+
+def test_geometric_closed_form():
+    """f_j = z^j, g_j = w^j: h_k = w^k sum_{j=lo}^{hi} (z/w)^j, a finite geometric series."""
+    L = 40
+    z, w = 0.97 * np.exp(0.3j), 1.01 * np.exp(-0.7j)
+    j = np.arange(L)
+    f, g = z ** j, w ** j
+    M = 2 * L - 1
+    k = np.arange(M)
+    lo = np.maximum(0, k - L + 1)
+    hi = np.minimum(k, L - 1)
+    ratio = z / w
+    want = w ** k * (ratio ** lo - ratio ** (hi + 1)) / (1 - ratio)
+    assert oracle.rel_l2(oracle.direct_1d(f, g, M), want) < 1e-13
+    assert oracle.rel_l2(oracle.padded_1d(f, g, M), want) < 1e-13
+
+
+def test_copies_are_independent_columns():
+    L, C = 33, 5
+    f, g = synth.pair((L, C), 94, 0)
+    h = oracle.direct_1d(f, g, 2 * L - 1)
+    hp = oracle.padded_1d(f, g, 2 * L - 1)
+    for c in range(C):
+        ref = np.convolve(f[:, c], g[:, c])
+        assert oracle.rel_l2(h[:, c], ref) < 1e-14
+        assert oracle.rel_l2(hp[:, c], ref) < 1e-14
+
+
+def test_sampled_equals_full():
+    L = 500
+    f, g = synth.pair(L, 95, 0)
+    ks = np.array([0, 1, 7, 250, 499, 500, 998, 999, 1200])
+    full = oracle.direct_1d(f, g, 1300)
+    assert np.array_equal(oracle.direct_1d_sampled(f, g, ks), full[ks])
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7, 8, 12, 30, 49, 64, 97, 210, 1000, 2048])
+def test_dft_matches_numpy_fft(n):
+    x = synth.uniform_complex(n, 96, n, 0)
+    assert oracle.rel_l2(oracle.dft(x, -1), np.fft.fft(x)) < 1e-14
+    assert oracle.rel_l2(oracle.dft(x, +1), n * np.fft.ifft(x)) < 1e-14
+
+
+def test_dft_orthogonality():
+    """sum_j zeta_n^{l j} = n if n | l else 0 (section 2.1): the DFT of ones is n*delta."""
+    for n in (6, 16, 35):
+        X = oracle.dft(np.ones(n, complex), +1)
+        want = np.zeros(n, complex)
+        want[0] = n
+        assert np.max(np.abs(X - want)) < 1e-12
+        for a in range(n):  # DFT of delta_a is zeta^{k a}
+            d = np.zeros(n, complex)
+            d[a] = 1.0
+            want = np.exp(2j * np.pi * ((np.arange(n) * a) % n) / n)
+            assert np.max(np.abs(oracle.dft(d, +1) - want)) < 1e-14
+
+
+@pytest.mark.parametrize("L,N", [(6, 12), (100, 360), (37, 80), (1024, 2048)])
+def test_padded_dft_is_N_ifft_of_zero_padding(L, N):
+    x = synth.uniform_complex(L, 97, L, 0)
+    pad = np.concatenate([x, np.zeros(N - L, complex)])
+    assert oracle.rel_l2(oracle.padded_dft(x, N), N * np.fft.ifft(pad)) < 1e-14
+
+
+def test_friendly_sizes():
+    want = {1: 1, 2: 2, 11: 12, 13: 14, 97: 98, 121: 125, 2047: 2048, 4095: 4096, 2 * 3 ** 13 - 1: 2 * 3 ** 13}
+    for n, v in want.items():
+        assert oracle.friendly_size(n) == v
+    for n in range(1, 400):
+        s = oracle.friendly_size(n)
+        r = s
+        for p in (2, 3, 5, 7):
+            while r % p == 0:
+                r //= p
+        assert s >= n and r == 1
+        assert all(_not_friendly(c) for c in range(n, s))
+
+
+def _not_friendly(c):
+    for p in (2, 3, 5, 7):
+        while c % p == 0:
+            c //= p
+    return c != 1
+
+
+@pytest.mark.parametrize("shape", [(1, 7), (5, 1), (6, 9), (16, 16), (13, 40)])
+def test_nd2_matches_scipy(shape):
+    f, g = synth.pair(shape, 98, shape[0])
+    M = tuple(2 * s - 1 for s in shape)
+    ref = scipy.signal.convolve(f, g, method="direct")
+    assert oracle.rel_l2(oracle.direct_nd(f, g, M), ref) < 1e-14
+    assert oracle.rel_l2(oracle.padded_nd(f, g, M), ref) < 1e-14
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 5), (8, 8, 8), (1, 6, 2)])
+def test_nd3_matches_scipy(shape):
+    f, g = synth.pair(shape, 99, shape[0])
+    M = tuple(2 * s - 1 for s in shape)
+    ref = scipy.signal.convolve(f, g, method="direct")
+    assert oracle.rel_l2(oracle.direct_nd(f, g, M), ref) < 1e-14
+    assert oracle.rel_l2(oracle.padded_nd(f, g, M), ref) < 1e-14
+
+
+def test_nd_separable_closed_form():
+    """f = a (x) b, g = c (x) d  =>  h = (a*c) (x) (b*d)."""
+    a = synth.uniform_complex(9, 100, 0, 0)
+    b = synth.uniform_complex(14, 100, 1, 0)
+    c = synth.uniform_complex(9, 100, 2, 0)
+    d = synth.uniform_complex(14, 100, 3, 0)
+    f, g = np.outer(a, b), np.outer(c, d)
+    M = (17, 27)
+    want = np.outer(np.convolve(a, c), np.convolve(b, d))
+    assert oracle.rel_l2(oracle.padded_nd(f, g, M), want) < 1e-13
+    assert oracle.rel_l2(oracle.direct_nd(f, g, M), want) < 1e-13
+
+
+def test_nd_with_unit_axis_reduces_to_1d():
+    f, g = synth.pair((1, 50), 101, 0)
+    h = oracle.padded_nd(f, g, (1, 99))
+    assert oracle.rel_l2(h[0], np.convolve(f[0], g[0])) < 1e-14
+
+
+def test_nd_tail_is_zero():
+    f, g = synth.pair((4, 5), 102, 0)
+    h = oracle.padded_nd(f, g, (9, 12))
+    assert np.all(h[7:, :] == 0) and np.all(h[:, 9:] == 0)
+
+
+def test_fft_route_error_bound():
+    """Round-off of the padded-FFT route stays within O(eps log2 N) of the exact result."""
+    L = 1 << 14
+    f, g = _gauss_int(L, seed=5, bound=8)
+    exact = oracle.direct_1d(f, g, 2 * L - 1)  # exact integers (see test above)
+    h = oracle.padded_1d(f, g, 2 * L - 1)
+    eps = np.finfo(np.float64).eps
+    assert oracle.rel_l2(h, exact) < 4 * eps * np.log2(2 * L)
+
+
+@pytest.mark.parametrize("name", ["fig2_L6_M11.txt", "int_L37_M80.txt"])
+def test_golden_fixtures_exact(name):
+    """Stored exact-integer outputs (written by tests/golden/make_golden.py)."""
+    from golden_io import load
+    L, M, f, g, h = load(name)
+    assert f.size == L and h.size == M
+    assert np.array_equal(h, _exact_int_conv(f, g, M))
+    assert np.array_equal(oracle.direct_1d(f, g, M), h)
+    assert np.array_equal(np.round(oracle.padded_1d(f, g, M)), h)
