@@ -1,0 +1,179 @@
+/*
+ * hdc -- hybrid dealiased convolution for AMD MI355X (gfx950).
+ *
+ * The operation (section 2.2 eq. (1), section 2.3 eq. (4), section 3.3):
+ *   given f, g of length L, compute the linear convolution
+ *       h_k = sum_j f_j g_{k-j},  k = 0 .. M-1,  M >= 2L-1,
+ *   by hybrid dealiasing: choose an FFT size m, explicitly extend the inputs
+ *   to p*m >= L (p = ceil(L/m), zeros never stored), implicitly pad to
+ *   N = q*m >= M (q = ceil(M/m)), and compute the length-N transform as q
+ *   "residues" r = 0..q-1, each an m-point DFT of the block sum
+ *       w^(r)_s = zeta_N^{r s} sum_{t<p} zeta_q^{r t} f_{t m + s}
+ *   (forward of eq. (1), zeta_n = exp(+2 pi i / n), unscaled).  The product
+ *   H = F.G is taken residue by residue and the backward of eq. (1)
+ *       h_{t m + s} = (1/N) sum_r zeta_q^{-t r} zeta_N^{-s r} sum_l zeta_m^{-s l} H_{q l + r}
+ *   is accumulated over output blocks t < ceil(M/m).  Residues are taken D
+ *   at a time (section 2.5); C copies are transformed together.
+ *
+ * Conventions for every entry point:
+ *   - all sizes are int64_t; complex data are interleaved (re, im) pairs of
+ *     float (HDC_C64) or double (HDC_C128), i.e. torch.complex64/complex128;
+ *   - data pointers (f, g, h, residue buffers, workspaces) are DEVICE
+ *     pointers owned by the caller; the plan owns only its twiddle tables;
+ *   - a 1D problem with C copies stores element j of copy c at j*C + c;
+ *     N-D arrays are row-major with the last axis contiguous;
+ *   - h must not alias f or g; f == g (autoconvolution) is allowed;
+ *   - calls enqueue work on `stream` and never synchronise; errors in
+ *     arguments are reported before any launch, asynchronous device faults
+ *     surface at the caller's next synchronisation;
+ *   - on failure a status other than HDC_OK is returned and
+ *     hdc_last_error() describes it (thread-local string).
+ *   - a plan is immutable after creation and may be used concurrently on
+ *     different streams with different workspaces.
+ */
+#ifndef HDC_H
+#define HDC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { HDC_C64 = 0, HDC_C128 = 1 } hdc_dtype;
+
+typedef enum {
+    HDC_OK = 0,
+    HDC_ERR_INVALID_ARG = 1, /* inadmissible parameters or null pointers */
+    HDC_ERR_UNSUPPORTED = 2, /* admissible but outside what the kernels implement */
+    HDC_ERR_WORKSPACE = 3,   /* workspace missing or too small */
+    HDC_ERR_HIP = 4          /* a HIP runtime call failed */
+} hdc_status;
+
+typedef struct hdc_plan_s* hdc_plan_t;
+typedef struct hdc_batch_s* hdc_batch_t;
+
+/* Derived description of one axis of a plan (filled by hdc_derive / hdc_plan_axis). */
+typedef struct {
+    int64_t L, M;     /* input length, output length                         */
+    int64_t m, p, q;  /* FFT size, explicit blocks ceil(L/m), residues ceil(M/m) */
+    int64_t N;        /* transform length q*m                                 */
+    int64_t D;        /* residues per pass (clamped to 1..q)                  */
+    int64_t C;        /* copies                                               */
+    int64_t q_out;    /* output blocks ceil(M/m)                              */
+    int64_t m1, m2;   /* m = m1*m2: column-stage and row-stage FFT lengths    */
+    int32_t variant;  /* 0 = fused single kernel, 1 = column/row/column passes */
+    int32_t reserved;
+} hdc_axis_desc;
+
+/*
+ * Admissibility and derivation, host only (no device is touched).
+ * Section 2.5 defines p = ceil(L/m), q = ceil(M/m) as the smallest values with
+ * p m >= L and q m >= M; section 2.2 requires q >= p.  Admissible means
+ * m >= 1, L >= 1, p m >= L, q m >= M, q >= p, M >= 2L-1 (else the output
+ * would alias), C >= 1, 1 <= D.  p or q = 0 derives the ceiling; D = 0
+ * means D = q; D > q is clamped to q.  Returns HDC_ERR_INVALID_ARG for
+ * inadmissible input and HDC_ERR_UNSUPPORTED when m is not a power of two,
+ * m > 2^22, or the transform does not fit the kernels' index range.
+ */
+hdc_status hdc_derive(int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, int64_t C, int64_t D,
+                      hdc_dtype dtype, hdc_axis_desc* out);
+
+/* 1D plan (eq. (1)).  Allocates the device twiddle tables on the current device
+ * (the only allocation a plan makes).  Errors as hdc_derive, plus HDC_ERR_HIP. */
+hdc_status hdc_plan(hdc_plan_t* out, int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, int64_t C,
+                    int64_t D, hdc_dtype dtype);
+
+/* N-D plan, ndim = 1..3 (section 3.6): per-axis L, M, m, p, q, D (p, q, D may
+ * be 0 to derive).  The outer axes are transformed as strided column passes
+ * whose copies are the inner extents (section 2.5's C copies); the innermost
+ * axis is a 1D hybrid convolution per outer-residue row. */
+hdc_status hdc_plan_nd(hdc_plan_t* out, int ndim, const int64_t* L, const int64_t* M, const int64_t* m,
+                       const int64_t* p, const int64_t* q, const int64_t* D, hdc_dtype dtype);
+
+hdc_status hdc_plan_destroy(hdc_plan_t plan);
+
+/* Number of axes and the description of axis `axis`. */
+hdc_status hdc_plan_axis(hdc_plan_t plan, int axis, int* ndim, hdc_axis_desc* out);
+
+/* Bytes of device workspace that hdc_convolve (and hdc_forward/backward) need;
+ * the caller allocates it (256-byte alignment).  May be 0. */
+hdc_status hdc_workspace_size(hdc_plan_t plan, size_t* bytes);
+
+/* Bytes of one residue buffer (D residues x m x C complex values), 1D plans. */
+hdc_status hdc_residue_buffer_size(hdc_plan_t plan, size_t* bytes);
+
+/*
+ * Full convolution: h[0 .. M) (x C copies, or the N-D output box) from f, g
+ * (L values each).  All residue groups, the products and the backward
+ * accumulation run on `stream`.  f == g allowed; h must not alias f or g.
+ */
+hdc_status hdc_convolve(hdc_plan_t plan, const void* f, const void* g, void* h, void* ws, hipStream_t stream);
+
+/*
+ * Forward residues [r0, r0 + D') of a 1D plan, D' = min(D, q - r0): the m-point
+ * DFTs of eq. (1).  F holds D' x m x C values; within a residue the order is
+ * implementation-defined (hdc_residues_natural gives the natural order).
+ * r0 must be a multiple of D.  ws: hdc_workspace_size bytes.
+ */
+hdc_status hdc_forward(hdc_plan_t plan, const void* f, void* F, int64_t r0, void* ws, hipStream_t stream);
+
+/* Pointwise product of two residue buffers of the same group: F <- F . G. */
+hdc_status hdc_multiply(hdc_plan_t plan, void* F, const void* G, int64_t r0, hipStream_t stream);
+
+/*
+ * Backward of eq. (1) for residues [r0, r0 + D'): inverse m-point DFTs,
+ * twiddle, and accumulation into the output blocks t < ceil(M/m) of h.
+ * r0 == 0 overwrites h; r0 > 0 adds to it, so calling r0 = 0, D, 2D, ... in
+ * order on one stream yields the convolution.  F is overwritten.
+ */
+hdc_status hdc_backward(hdc_plan_t plan, void* F, void* h, int64_t r0, void* ws, hipStream_t stream);
+
+/* Debug view: copy residues [r0, r0 + D') of F into `out` in the natural order,
+ * out[(d*m + l)*C + c] = F_{q l + r0 + d} of copy c (= the length-N zero-extended
+ * DFT of f at index k = q l + r). */
+hdc_status hdc_residues_natural(hdc_plan_t plan, const void* F, int64_t r0, void* out, hipStream_t stream);
+
+/*
+ * Batched uneven 1D convolutions (n independent problems of lengths L[i], output
+ * lengths M[i], M == NULL means 2 L[i] - 1).  Operands are packed back to back:
+ * f and g at offsets sum_{j<i} L[j], h at sum_{j<i} M[j].  Problems are grouped
+ * into buckets that share (m, p, q, D); `bucket_m` (length n, may be NULL) gives
+ * the FFT size chosen for each problem, 0 meaning the built-in default.
+ * The first hdc_batch_convolve on a stream captures the launches in a HIP graph;
+ * later calls with the same stream and buffers replay it.
+ */
+hdc_status hdc_batch_plan(hdc_batch_t* out, int64_t n, const int64_t* L, const int64_t* M, const int64_t* bucket_m,
+                          hdc_dtype dtype);
+hdc_status hdc_batch_workspace_size(hdc_batch_t batch, size_t* bytes);
+hdc_status hdc_batch_convolve(hdc_batch_t batch, const void* f, const void* g, void* h, void* ws,
+                              hipStream_t stream);
+/* Same work as hdc_batch_convolve, launched directly without a graph. */
+hdc_status hdc_batch_convolve_eager(hdc_batch_t batch, const void* f, const void* g, void* h, void* ws,
+                                   hipStream_t stream);
+hdc_status hdc_batch_info(hdc_batch_t batch, int64_t* n_buckets, int64_t* total_L, int64_t* total_M);
+hdc_status hdc_batch_destroy(hdc_batch_t batch);
+
+/*
+ * Timing core for the autotuner (section 4.2's score R): runs hdc_convolve
+ * `warmup` times, then `reps` times each bracketed by HIP events on `stream`,
+ * and writes the per-repetition milliseconds to ms_out[reps].  Synchronises
+ * the stream.
+ */
+hdc_status hdc_time_convolve(hdc_plan_t plan, const void* f, const void* g, void* h, void* ws, hipStream_t stream,
+                             int warmup, int reps, float* ms_out);
+
+/* Thread-local description of the last error (never NULL). */
+const char* hdc_last_error(void);
+
+/* Library version string. */
+const char* hdc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HDC_H */

@@ -1,0 +1,267 @@
+"""Python binding of libhdc (hybrid dealiased convolution on MI355X / gfx950).
+
+Argument marshalling only: every step of the convolution runs in the HIP
+kernels of ``libhdc.so``; PyTorch supplies device memory and streams.  There
+is no CPU fallback: if the shared library is missing, importing the binding
+raises.
+
+Names follow ``include/hdc.h``:
+
+* :class:`Plan` wraps ``hdc_plan`` / ``hdc_plan_nd`` and exposes
+  ``convolve`` (``hdc_convolve``), ``forward``, ``multiply``, ``backward`` and
+  ``residues_natural``;
+* :class:`Batch` wraps ``hdc_batch_*`` (uneven-length batches, replayed
+  from a captured HIP graph);
+* :func:`derive` is the host-only admissibility check (``hdc_derive``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+from . import _lib
+from ._lib import AxisDesc, HdcError, lib, check  # noqa: F401
+
+C64, C128 = 0, 1
+_DT = {"c64": C64, "complex64": C64, "c128": C128, "complex128": C128, C64: C64, C128: C128}
+
+
+def dtype_code(dtype) -> int:
+    if hasattr(dtype, "is_complex"):  # torch dtype
+        import torch
+        return C128 if dtype == torch.complex128 else C64
+    return _DT[dtype]
+
+
+def torch_dtype(code: int):
+    import torch
+    return torch.complex128 if code == C128 else torch.complex64
+
+
+def derive(L: int, M: int, m: int, p: int = 0, q: int = 0, C: int = 1, D: int = 0, dtype="c128") -> dict:
+    """Admissibility and derived parameters (no device is touched)."""
+    d = AxisDesc()
+    check(lib().hdc_derive(L, M, m, p, q, C, D, dtype_code(dtype), ctypes.byref(d)))
+    return d.as_dict()
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_tensor(t, dtype_code_, numel: int, name: str):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch_dtype(dtype_code_):
+        raise TypeError(f"{name} has dtype {t.dtype}, plan expects {torch_dtype(dtype_code_)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {numel}")
+
+
+class Plan:
+    """A 1D (``Plan(L, M, m, ...)``) or N-D (``Plan.nd(...)``) hybrid-dealiasing plan."""
+
+    def __init__(self, L: int, M: int, m: int, p: int = 0, q: int = 0, C: int = 1, D: int = 0, dtype="c128",
+                 _handle=None):
+        self._lib = lib()
+        if _handle is None:
+            h = ctypes.c_void_p()
+            check(self._lib.hdc_plan(ctypes.byref(h), int(L), int(M), int(m), int(p), int(q), int(C), int(D),
+                                     dtype_code(dtype)))
+            _handle = h
+        self._h = _handle
+        self.dtype = dtype_code(dtype)
+        nd = ctypes.c_int()
+        self.axes = []
+        check(self._lib.hdc_plan_axis(self._h, 0, ctypes.byref(nd), None))
+        self.ndim = nd.value
+        for a in range(self.ndim):
+            d = AxisDesc()
+            check(self._lib.hdc_plan_axis(self._h, a, None, ctypes.byref(d)))
+            self.axes.append(d.as_dict())
+        sz = ctypes.c_size_t()
+        check(self._lib.hdc_workspace_size(self._h, ctypes.byref(sz)))
+        self.workspace_bytes = sz.value
+        self._ws = None
+
+    @classmethod
+    def nd(cls, L: Sequence[int], M: Sequence[int], m: Sequence[int], p=None, q=None, D=None, dtype="c64"):
+        n = len(L)
+        arr = ctypes.c_int64 * n
+
+        def a(v):
+            return arr(*[int(x) for x in v]) if v is not None else None
+        h = ctypes.c_void_p()
+        check(lib().hdc_plan_nd(ctypes.byref(h), n, a(L), a(M), a(m), a(p), a(q), a(D), dtype_code(dtype)))
+        return cls(0, 0, 0, dtype=dtype, _handle=h)
+
+    # -- properties
+    @property
+    def L(self):
+        return tuple(ax["L"] for ax in self.axes) if self.ndim > 1 else self.axes[0]["L"]
+
+    @property
+    def M(self):
+        return tuple(ax["M"] for ax in self.axes) if self.ndim > 1 else self.axes[0]["M"]
+
+    @property
+    def C(self) -> int:
+        return self.axes[0]["C"]
+
+    def in_numel(self) -> int:
+        n = 1
+        for ax in self.axes:
+            n *= ax["L"]
+        return n * (self.C if self.ndim == 1 else 1)
+
+    def out_numel(self) -> int:
+        n = 1
+        for ax in self.axes:
+            n *= ax["M"]
+        return n * (self.C if self.ndim == 1 else 1)
+
+    def out_shape(self):
+        if self.ndim == 1:
+            return (self.axes[0]["M"],) if self.C == 1 else (self.axes[0]["M"], self.C)
+        return tuple(ax["M"] for ax in self.axes)
+
+    def workspace(self, device=None):
+        """A cached device workspace of ``workspace_bytes`` (allocated by torch)."""
+        import torch
+        if self.workspace_bytes == 0:
+            return None
+        if self._ws is None or self._ws.numel() < self.workspace_bytes:
+            self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device or "cuda")
+        return self._ws
+
+    def residue_buffer(self, device=None):
+        import torch
+        sz = ctypes.c_size_t()
+        check(self._lib.hdc_residue_buffer_size(self._h, ctypes.byref(sz)))
+        esz = 16 if self.dtype == C128 else 8
+        return torch.empty(sz.value // esz, dtype=torch_dtype(self.dtype), device=device or "cuda")
+
+    # -- execution
+    def convolve(self, f, g, out=None, ws=None, stream=None):
+        """h = f * g (hdc_convolve); returns ``out`` (allocated if None)."""
+        import torch
+        _check_tensor(f, self.dtype, self.in_numel(), "f")
+        _check_tensor(g, self.dtype, self.in_numel(), "g")
+        if out is None:
+            out = torch.empty(self.out_shape(), dtype=torch_dtype(self.dtype), device=f.device)
+        _check_tensor(out, self.dtype, self.out_numel(), "out")
+        if ws is None:
+            ws = self.workspace(f.device)
+        check(self._lib.hdc_convolve(self._h, _ptr(f), _ptr(g), _ptr(out),
+                                     _ptr(ws) if ws is not None else None, _stream(stream)))
+        return out
+
+    def forward(self, f, F, r0: int, stream=None):
+        _check_tensor(f, self.dtype, self.in_numel(), "f")
+        check(self._lib.hdc_forward(self._h, _ptr(f), _ptr(F), int(r0), None, _stream(stream)))
+        return F
+
+    def multiply(self, F, G, r0: int, stream=None):
+        check(self._lib.hdc_multiply(self._h, _ptr(F), _ptr(G), int(r0), _stream(stream)))
+        return F
+
+    def backward(self, F, h, r0: int, stream=None):
+        _check_tensor(h, self.dtype, self.out_numel(), "h")
+        check(self._lib.hdc_backward(self._h, _ptr(F), _ptr(h), int(r0), None, _stream(stream)))
+        return h
+
+    def residues_natural(self, F, r0: int, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(F)
+        check(self._lib.hdc_residues_natural(self._h, _ptr(F), int(r0), _ptr(out), _stream(stream)))
+        return out
+
+    def time_convolve(self, f, g, out, ws=None, warmup: int = 2, reps: int = 5, stream=None):
+        """Per-repetition milliseconds from hdc_time_convolve (HIP events)."""
+        ms = (ctypes.c_float * reps)()
+        if ws is None:
+            ws = self.workspace(f.device)
+        check(self._lib.hdc_time_convolve(self._h, _ptr(f), _ptr(g), _ptr(out),
+                                          _ptr(ws) if ws is not None else None, _stream(stream),
+                                          int(warmup), int(reps), ms))
+        return list(ms)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hdc_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Uneven-length batch of 1D convolutions packed back to back (hdc_batch_plan)."""
+
+    def __init__(self, L: Sequence[int], M: Optional[Sequence[int]] = None, bucket_m: Optional[Sequence[int]] = None,
+                 dtype="c64"):
+        self._lib = lib()
+        n = len(L)
+        arr = ctypes.c_int64 * n
+        self.L = [int(x) for x in L]
+        self.M = [int(x) for x in M] if M is not None else [2 * x - 1 for x in self.L]
+        h = ctypes.c_void_p()
+        check(self._lib.hdc_batch_plan(ctypes.byref(h), n, arr(*self.L), arr(*self.M),
+                                       arr(*[int(x) for x in bucket_m]) if bucket_m is not None else None,
+                                       dtype_code(dtype)))
+        self._h = h
+        self.dtype = dtype_code(dtype)
+        sz = ctypes.c_size_t()
+        check(self._lib.hdc_batch_workspace_size(self._h, ctypes.byref(sz)))
+        self.workspace_bytes = sz.value
+        nb, tl, tm = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        check(self._lib.hdc_batch_info(self._h, ctypes.byref(nb), ctypes.byref(tl), ctypes.byref(tm)))
+        self.n_buckets, self.total_L, self.total_M = nb.value, tl.value, tm.value
+        self._ws = None
+
+    def workspace(self, device=None):
+        import torch
+        if self.workspace_bytes == 0:
+            return None
+        if self._ws is None:
+            self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device or "cuda")
+        return self._ws
+
+    def convolve(self, f, g, out=None, ws=None, stream=None, graph: bool = True):
+        import torch
+        _check_tensor(f, self.dtype, self.total_L, "f")
+        _check_tensor(g, self.dtype, self.total_L, "g")
+        if out is None:
+            out = torch.empty(self.total_M, dtype=torch_dtype(self.dtype), device=f.device)
+        _check_tensor(out, self.dtype, self.total_M, "out")
+        if ws is None:
+            ws = self.workspace(f.device)
+        fn = self._lib.hdc_batch_convolve if graph else self._lib.hdc_batch_convolve_eager
+        check(fn(self._h, _ptr(f), _ptr(g), _ptr(out), _ptr(ws) if ws is not None else None, _stream(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hdc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

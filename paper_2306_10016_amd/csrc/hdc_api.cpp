@@ -1,0 +1,976 @@
+// Host side of the hdc library: parameter derivation (section 2.5), FP64
+// twiddle tables, kernel-variant choice, the N-D recursion over axes
+// (section 3.6) and the C-ABI entry points declared in include/hdc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/hdc.h"
+#include "hdc_internal.h"
+
+using namespace hdc;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+hdc_status fail(hdc_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+hdc_status hip_fail(hipError_t e, const char* what) {
+    return fail(HDC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        hipError_t _e = (expr);                         \
+        if (_e != hipSuccess) return hip_fail(_e, #expr); \
+    } while (0)
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+int ilog2i(int64_t x) {
+    int l = 0;
+    while ((int64_t(1) << l) < x) ++l;
+    return l;
+}
+
+size_t elem_bytes(hdc_dtype t) { return t == HDC_C128 ? 16 : 8; }
+
+// exp(+2 pi i e / n) from an exactly reduced exponent, evaluated in long double.
+void root(int64_t e, int64_t n, double* re, double* im) {
+    e %= n;
+    if (e < 0) e += n;
+    const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)e / (long double)n;
+    *re = (double)cosl(a);
+    *im = (double)sinl(a);
+}
+
+size_t device_lds_max() {
+    static size_t cached = 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0, v = 0;
+        cached = 65536;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+            cached = (size_t)v;
+    });
+    return cached;
+}
+
+// LDS budget the fused kernel may use for one row (N values + q twiddles).
+constexpr size_t kFusedRowLds = 65536;
+
+}  // namespace
+
+// ------------------------------------------------------------------ plans --
+
+struct AxisPlan {
+    hdc_axis_desc d{};
+    bool dbl = false;
+    bool hiprec = false;
+    // fused geometry
+    int Dc = 1, f_rpw = 1, f_threads = 1;
+    size_t f_lds = 0;
+    // column/row geometry
+    int cf_tile = 1, cf_threads = 1, cb_tile = 1, cb_threads = 1, r_rpw = 1, r_threads = 1;
+    size_t cf_lds = 0, cb_lds = 0, r_lds = 0;
+    // device tables
+    TwN tw{};
+    const void* tw_m = nullptr;
+    const void* tw_m1 = nullptr;
+    const void* tw_m2 = nullptr;
+    // table layout offsets (bytes) inside the plan's table block
+    size_t off_lo = 0, off_hi = 0, off_m = 0, off_m1 = 0, off_m2 = 0;
+    int64_t nlo = 0, nhi = 0;
+};
+
+struct hdc_plan_s {
+    int ndim = 1;
+    hdc_dtype dtype = HDC_C128;
+    AxisPlan ax[3];
+    void* tables = nullptr;
+    size_t ws_bytes = 0;
+};
+
+namespace {
+
+// Derivation and admissibility (section 2.5, section 2.2's q >= p).
+hdc_status derive_axis(int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, int64_t C, int64_t D, hdc_dtype dtype,
+                       hdc_axis_desc* o) {
+    if (dtype != HDC_C64 && dtype != HDC_C128) return fail(HDC_ERR_INVALID_ARG, "dtype must be HDC_C64 or HDC_C128");
+    if (L < 1) return fail(HDC_ERR_INVALID_ARG, "L = %lld must be >= 1", (long long)L);
+    if (M < 2 * L - 1)
+        return fail(HDC_ERR_INVALID_ARG, "M = %lld < 2L-1 = %lld: the output would alias", (long long)M,
+                    (long long)(2 * L - 1));
+    if (m < 1) return fail(HDC_ERR_INVALID_ARG, "m = %lld must be >= 1", (long long)m);
+    if (C < 1) return fail(HDC_ERR_INVALID_ARG, "C = %lld must be >= 1", (long long)C);
+    if (p < 0 || q < 0 || D < 0) return fail(HDC_ERR_INVALID_ARG, "p, q, D must be >= 0 (0 derives)");
+    if (p == 0) p = ceil_div(L, m);
+    if (q == 0) q = ceil_div(M, m);
+    if (p * m < L) return fail(HDC_ERR_INVALID_ARG, "p m = %lld < L = %lld", (long long)(p * m), (long long)L);
+    if (q * m < M) return fail(HDC_ERR_INVALID_ARG, "q m = %lld < M = %lld", (long long)(q * m), (long long)M);
+    if (q < p) return fail(HDC_ERR_INVALID_ARG, "q = %lld < p = %lld", (long long)q, (long long)p);
+    if (D == 0 || D > q) D = q;
+    if (!is_pow2(m)) return fail(HDC_ERR_UNSUPPORTED, "m = %lld: only powers of two are implemented", (long long)m);
+    const int64_t N = q * m;
+    if (N >= (int64_t(1) << 31) || M * C >= (int64_t(1) << 40))
+        return fail(HDC_ERR_UNSUPPORTED, "N = %lld exceeds the 32-bit twiddle index range", (long long)N);
+    o->L = L;
+    o->M = M;
+    o->m = m;
+    o->p = p;
+    o->q = q;
+    o->N = N;
+    o->D = D;
+    o->C = C;
+    o->q_out = ceil_div(M, m);
+    // four-step split of the m-point DFT for the column/row passes
+    const int64_t rowmax = kMaxRow;
+    int64_t m2 = std::min<int64_t>(m, rowmax);
+    int64_t m1 = m / m2;
+    if (m1 > kMaxM1)
+        return fail(HDC_ERR_UNSUPPORTED, "m = %lld exceeds %lld (column stage %d x row stage %d)", (long long)m,
+                    (long long)(kMaxM1 * rowmax), kMaxM1, (int)rowmax);
+    o->m1 = m1;
+    o->m2 = m2;
+    const size_t b = elem_bytes(dtype);
+    const size_t fused_lds = (size_t)N * b + (size_t)q * 16 + 16;
+    o->variant = (m <= kMaxFused && fused_lds <= kFusedRowLds) ? 0 : 1;
+    o->reserved = 0;
+    return HDC_OK;
+}
+
+int tile_for(int tpf, int tmin, int maxthreads) {
+    int t = std::max(tmin, 256 / std::max(tpf, 1));
+    while (t > 1 && t * tpf > maxthreads) t /= 2;
+    return std::max(t, 1);
+}
+
+// Geometry of every kernel for one axis; `outer` = transformed as a column
+// stage of an N-D problem (m1 = m, m2 = 1).
+hdc_status geometry(AxisPlan& A, bool outer) {
+    hdc_axis_desc& d = A.d;
+    const size_t b = A.dbl ? 16 : 8;
+    if (outer) {
+        if (d.m > kMaxM1)
+            return fail(HDC_ERR_UNSUPPORTED, "outer-axis m = %lld exceeds %d", (long long)d.m, kMaxM1);
+        d.m1 = d.m;
+        d.m2 = 1;
+        d.variant = 1;
+    }
+    const int tmin = A.dbl ? 8 : 16;
+    // fused
+    {
+        const int ppt = ppt_for((int)d.m);
+        const int tpf = (int)d.m / ppt;
+        int Dc = (int)std::min<int64_t>(d.D, d.q);
+        Dc = std::max(1, std::min(Dc, 512 / tpf));
+        const int rowthreads = tpf * Dc;
+        const size_t rowlds = (size_t)d.N * b;
+        int rpw = std::max(1, 256 / rowthreads);
+        while (rpw > 1 && (size_t)rpw * rowlds > kFusedRowLds) rpw /= 2;
+        A.Dc = Dc;
+        A.f_rpw = rpw;
+        A.f_threads = rowthreads * rpw;
+        A.f_lds = ((size_t)rpw * rowlds + 15) / 16 * 16 + (size_t)d.q * 16;
+    }
+    // columns
+    {
+        const int ppt = ppt_for((int)d.m1);
+        const int tpf = (int)d.m1 / ppt;
+        A.cf_tile = tile_for(tpf, tmin, 1024);
+        A.cf_threads = A.cf_tile * tpf;
+        A.cf_lds = (size_t)d.m1 * A.cf_tile * b;
+        A.cb_tile = tile_for(tpf, tmin, 512);
+        A.cb_threads = A.cb_tile * tpf;
+        A.cb_lds = (size_t)d.m1 * A.cb_tile * b;
+        if (A.cf_lds > device_lds_max() || A.cb_lds > device_lds_max())
+            return fail(HDC_ERR_UNSUPPORTED, "column stage m1 = %lld needs %zu bytes of LDS", (long long)d.m1,
+                        A.cf_lds);
+    }
+    // rows
+    {
+        const int ppt = ppt_for((int)d.m2);
+        const int tpf = (int)d.m2 / ppt;
+        int rpw = std::max(1, 256 / tpf);
+        A.r_rpw = rpw;
+        A.r_threads = rpw * tpf;
+        A.r_lds = (size_t)rpw * d.m2 * b;
+        if (A.r_lds > device_lds_max())
+            return fail(HDC_ERR_UNSUPPORTED, "row stage m2 = %lld needs %zu bytes of LDS", (long long)d.m2, A.r_lds);
+    }
+    if (d.variant == 0 && A.f_lds > device_lds_max()) d.variant = 1;
+    A.hiprec = !A.dbl && d.N > (int64_t(1) << 20);
+    return HDC_OK;
+}
+
+// Append tables for one axis to the host staging blob.
+void stage_tables(AxisPlan& A, std::vector<unsigned char>& blob) {
+    auto align = [&](size_t a) {
+        while (blob.size() % a) blob.push_back(0);
+    };
+    const int64_t N = A.d.N;
+    const int lgN = ilog2i(N);
+    const int lgB = (lgN + 1) / 2;
+    const int64_t B = int64_t(1) << lgB;
+    A.nlo = B;
+    A.nhi = ceil_div(N, B);
+    align(256);
+    A.off_lo = blob.size();
+    for (int64_t e = 0; e < B; ++e) {
+        double v[2];
+        root(e, N, &v[0], &v[1]);
+        blob.insert(blob.end(), (unsigned char*)v, (unsigned char*)v + 16);
+    }
+    A.off_hi = blob.size();
+    for (int64_t e = 0; e < A.nhi; ++e) {
+        double v[2];
+        root(e * B, N, &v[0], &v[1]);
+        blob.insert(blob.end(), (unsigned char*)v, (unsigned char*)v + 16);
+    }
+    auto small_table = [&](int64_t n) {
+        align(256);
+        size_t off = blob.size();
+        for (int64_t e = 0; e < n; ++e) {
+            double re, im;
+            root(e, n, &re, &im);
+            if (A.dbl) {
+                double v[2] = {re, im};
+                blob.insert(blob.end(), (unsigned char*)v, (unsigned char*)v + 16);
+            } else {
+                float v[2] = {(float)re, (float)im};
+                blob.insert(blob.end(), (unsigned char*)v, (unsigned char*)v + 8);
+            }
+        }
+        return off;
+    };
+    A.off_m = small_table(A.d.m <= kMaxFused ? A.d.m : 1);
+    A.off_m1 = small_table(A.d.m1);
+    A.off_m2 = small_table(A.d.m2);
+    A.tw.lgB = lgB;
+    A.tw.mask = (int32_t)(B - 1);
+}
+
+void bind_tables(AxisPlan& A, unsigned char* base) {
+    A.tw.lo = reinterpret_cast<const double2*>(base + A.off_lo);
+    A.tw.hi = reinterpret_cast<const double2*>(base + A.off_hi);
+    A.tw_m = base + A.off_m;
+    A.tw_m1 = base + A.off_m1;
+    A.tw_m2 = base + A.off_m2;
+}
+
+// ---------------------------------------------------------------- launches --
+
+hdc_status run_fused(const AxisPlan& A, const void* f, const void* g, void* h, int64_t nrows, RowAddr in, RowAddr out,
+                     const int64_t* desc, hipStream_t s) {
+    if (nrows <= 0) return HDC_OK;
+    FusedArgs a{};
+    a.f = f;
+    a.g = g;
+    a.h = h;
+    a.nrows = nrows;
+    a.in = in;
+    a.out = out;
+    a.desc = desc;
+    a.L = (int32_t)A.d.L;
+    a.M = (int32_t)A.d.M;
+    a.p = (int32_t)A.d.p;
+    a.q = (int32_t)A.d.q;
+    a.qout = (int32_t)A.d.q_out;
+    a.N = (int32_t)A.d.N;
+    a.Dc = A.Dc;
+    a.rpw = A.f_rpw;
+    a.same = (f == g) ? 1 : 0;
+    a.hiprec = A.hiprec ? 1 : 0;
+    a.tw = A.tw;
+    a.twm = A.tw_m;
+    a.invN = 1.0 / (double)A.d.N;
+    const int64_t blocks = ceil_div(nrows, A.f_rpw);
+    if (blocks > 0x7fffffff) return fail(HDC_ERR_UNSUPPORTED, "too many rows");
+    hipError_t e = launch_fused(A.dbl, (int)A.d.m, a, A.f_threads, blocks, A.f_lds, s);
+    if (e != hipSuccess) return hip_fail(e, "fused convolution launch");
+    return HDC_OK;
+}
+
+hdc_status run_col_fwd(const AxisPlan& A, const void* x, void* X, int64_t B, int64_t in_bs, int64_t out_bs,
+                       int64_t C1, int64_t r0, int64_t Dg, hipStream_t s, const int64_t* desc = nullptr) {
+    ColFwdArgs a{};
+    a.desc = desc;
+    a.x = x;
+    a.X = X;
+    a.B = B;
+    a.in_bs = in_bs;
+    a.out_bs = out_bs;
+    a.L = (int32_t)A.d.L;
+    a.Ccols = (int32_t)(A.d.m2 * C1);
+    a.C1 = (int32_t)C1;
+    a.m2 = (int32_t)A.d.m2;
+    a.m = (int32_t)A.d.m;
+    a.q = (int32_t)A.d.q;
+    a.p = (int32_t)A.d.p;
+    a.N = (int32_t)A.d.N;
+    a.r0 = (int32_t)r0;
+    a.Dg = (int32_t)Dg;
+    a.tile = A.cf_tile;
+    a.ntiles = (int32_t)ceil_div(a.Ccols, A.cf_tile);
+    a.hiprec = A.hiprec ? 1 : 0;
+    a.tw = A.tw;
+    a.tw1 = A.tw_m1;
+    const int64_t gx = (int64_t)a.ntiles * Dg;
+    if (gx > 0x7fffffff || B > 65535) return fail(HDC_ERR_UNSUPPORTED, "column grid too large (B = %lld)", (long long)B);
+    hipError_t e = launch_col_fwd(A.dbl, (int)A.d.m1, a, A.cf_threads, gx, B, A.cf_lds, s);
+    if (e != hipSuccess) return hip_fail(e, "column forward launch");
+    return HDC_OK;
+}
+
+hdc_status run_col_bwd(const AxisPlan& A, const void* Y, void* h, int64_t B, int64_t in_bs, int64_t out_bs,
+                       int64_t C1, int64_t r0, int64_t Dg, bool accumulate, hipStream_t s,
+                       const int64_t* desc = nullptr) {
+    ColBwdArgs a{};
+    a.desc = desc;
+    a.Y = Y;
+    a.h = h;
+    a.B = B;
+    a.in_bs = in_bs;
+    a.out_bs = out_bs;
+    a.M = (int32_t)A.d.M;
+    a.Ccols = (int32_t)(A.d.m2 * C1);
+    a.C1 = (int32_t)C1;
+    a.m2 = (int32_t)A.d.m2;
+    a.m = (int32_t)A.d.m;
+    a.q = (int32_t)A.d.q;
+    a.N = (int32_t)A.d.N;
+    a.qout = (int32_t)A.d.q_out;
+    a.r0 = (int32_t)r0;
+    a.Dg = (int32_t)Dg;
+    a.accumulate = accumulate ? 1 : 0;
+    a.tile = A.cb_tile;
+    a.ntiles = (int32_t)ceil_div(a.Ccols, A.cb_tile);
+    a.hiprec = A.hiprec ? 1 : 0;
+    a.tw = A.tw;
+    a.tw1 = A.tw_m1;
+    a.invN = 1.0 / (double)A.d.N;
+    if (B > 65535) return fail(HDC_ERR_UNSUPPORTED, "column grid too large");
+    hipError_t e = launch_col_bwd(A.dbl, (int)A.d.m1, a, A.cb_threads, a.ntiles, B, A.cb_lds, s);
+    if (e != hipSuccess) return hip_fail(e, "column backward launch");
+    return HDC_OK;
+}
+
+// Rows of the residue buffer [B][Dg][m1][m2*C1]: row = ((b Dg + d) m1 + l1) C1 + c1.
+hdc_status run_rows(const AxisPlan& A, const void* a_, const void* b_, void* out, int64_t nrows, int64_t C1, int mode,
+                    hipStream_t s) {
+    if (nrows <= 0) return HDC_OK;
+    RowArgs a{};
+    a.a = a_;
+    a.b = b_;
+    a.out = out;
+    a.nrows = nrows;
+    a.addr.inner_cnt = C1;
+    a.addr.outer_stride = A.d.m2 * C1;
+    a.addr.inner_stride = 1;
+    a.addr.es = C1;
+    a.mode = mode;
+    a.same = (a_ == b_) ? 1 : 0;
+    a.rpw = A.r_rpw;
+    a.tw = A.tw_m2;
+    const int64_t blocks = ceil_div(nrows, A.r_rpw);
+    if (blocks > 0x7fffffff) return fail(HDC_ERR_UNSUPPORTED, "too many rows");
+    hipError_t e = launch_row(A.dbl, (int)A.d.m2, a, A.r_threads, blocks, A.r_lds, s);
+    if (e != hipSuccess) return hip_fail(e, "row launch");
+    return HDC_OK;
+}
+
+size_t elem(const hdc_plan_s* P) { return elem_bytes(P->dtype); }
+
+// Workspace (elements) of a 1D convolution of B rows x C1 copies on axis A.
+int64_t ws1d(const AxisPlan& A, int64_t B, int64_t C1) {
+    if (A.d.variant == 0) return 0;
+    const int64_t Dg = std::min(A.d.D, A.d.q);
+    return 2 * B * Dg * A.d.m * C1;
+}
+
+// 1D convolution along axis A: B batches (strides in_bs / out_bs) of C1 interleaved copies.
+hdc_status conv1d(const AxisPlan& A, const void* xf, const void* xg, void* out, int64_t B, int64_t in_bs, int64_t out_bs,
+                  int64_t C1, char* ws, size_t eb, hipStream_t s) {
+    if (A.d.variant == 0) {
+        RowAddr in{C1, in_bs, 1, C1};
+        RowAddr ou{C1, out_bs, 1, C1};
+        return run_fused(A, xf, xg, out, B * C1, in, ou, nullptr, s);
+    }
+    const bool same = xf == xg;
+    const int64_t D = std::min(A.d.D, A.d.q);
+    char* Xf = ws;
+    char* Xg = same ? ws : ws + (size_t)(B * D * A.d.m * C1) * eb;
+    for (int64_t r0 = 0; r0 < A.d.q; r0 += D) {
+        const int64_t Dg = std::min(D, A.d.q - r0);
+        const int64_t xbs = Dg * A.d.m * C1;
+        hdc_status st = run_col_fwd(A, xf, Xf, B, in_bs, xbs, C1, r0, Dg, s);
+        if (st != HDC_OK) return st;
+        if (!same) {
+            st = run_col_fwd(A, xg, Xg, B, in_bs, xbs, C1, r0, Dg, s);
+            if (st != HDC_OK) return st;
+        }
+        st = run_rows(A, Xf, Xg, Xf, B * Dg * A.d.m1 * C1, C1, MODE_CONV, s);
+        if (st != HDC_OK) return st;
+        st = run_col_bwd(A, Xf, out, B, xbs, out_bs, C1, r0, Dg, r0 > 0, s);
+        if (st != HDC_OK) return st;
+    }
+    return HDC_OK;
+}
+
+int64_t prod_L(const hdc_plan_s* P, int from) {
+    int64_t v = 1;
+    for (int a = from; a < P->ndim; ++a) v *= P->ax[a].d.L;
+    return v;
+}
+int64_t prod_M(const hdc_plan_s* P, int from) {
+    int64_t v = 1;
+    for (int a = from; a < P->ndim; ++a) v *= P->ax[a].d.M;
+    return v;
+}
+
+// Workspace (elements) of the N-D recursion from `level` with B batches.
+int64_t wsnd(const hdc_plan_s* P, int level, int64_t B) {
+    const AxisPlan& A = P->ax[level];
+    if (level == P->ndim - 1) return ws1d(A, B, 1);
+    const int64_t Dg = std::min(A.d.D, A.d.q);
+    const int64_t inner_in = prod_L(P, level + 1), inner_out = prod_M(P, level + 1);
+    const int64_t nb = B * Dg * A.d.m;
+    return 2 * nb * inner_in + nb * inner_out + wsnd(P, level + 1, nb);
+}
+
+// Section 3.6: forward along the outer axis for a residue group, recurse on the
+// inner (N-1)-D problem for every residue row, backward along the outer axis.
+hdc_status convnd(const hdc_plan_s* P, int level, const void* xf, const void* xg, void* out, int64_t B, char* ws,
+                  hipStream_t s) {
+    const AxisPlan& A = P->ax[level];
+    const size_t eb = elem(P);
+    if (level == P->ndim - 1) return conv1d(A, xf, xg, out, B, A.d.L, A.d.M, 1, ws, eb, s);
+    const bool same = xf == xg;
+    const int64_t D = std::min(A.d.D, A.d.q);
+    const int64_t inner_in = prod_L(P, level + 1), inner_out = prod_M(P, level + 1);
+    const int64_t nbmax = B * D * A.d.m;
+    char* Xf = ws;
+    char* Xg = ws + (size_t)(nbmax * inner_in) * eb;
+    char* Y = Xg + (size_t)(nbmax * inner_in) * eb;
+    char* rest = Y + (size_t)(nbmax * inner_out) * eb;
+    for (int64_t r0 = 0; r0 < A.d.q; r0 += D) {
+        const int64_t Dg = std::min(D, A.d.q - r0);
+        const int64_t nb = B * Dg * A.d.m;
+        hdc_status st = run_col_fwd(A, xf, Xf, B, A.d.L * inner_in, Dg * A.d.m * inner_in, inner_in, r0, Dg, s);
+        if (st != HDC_OK) return st;
+        if (!same) {
+            st = run_col_fwd(A, xg, Xg, B, A.d.L * inner_in, Dg * A.d.m * inner_in, inner_in, r0, Dg, s);
+            if (st != HDC_OK) return st;
+        }
+        st = convnd(P, level + 1, Xf, same ? Xf : Xg, Y, nb, rest, s);
+        if (st != HDC_OK) return st;
+        st = run_col_bwd(A, Y, out, B, Dg * A.d.m * inner_out, A.d.M * inner_out, inner_out, r0, Dg, r0 > 0, s);
+        if (st != HDC_OK) return st;
+    }
+    return HDC_OK;
+}
+
+hdc_status finish_plan(hdc_plan_s* P) {
+    std::vector<unsigned char> blob;
+    for (int a = 0; a < P->ndim; ++a) stage_tables(P->ax[a], blob);
+    void* dev = nullptr;
+    hipError_t e = hipMalloc(&dev, std::max<size_t>(blob.size(), 256));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(twiddle tables)");
+    e = hipMemcpy(dev, blob.data(), blob.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(dev);
+        return hip_fail(e, "hipMemcpy(twiddle tables)");
+    }
+    P->tables = dev;
+    for (int a = 0; a < P->ndim; ++a) bind_tables(P->ax[a], (unsigned char*)dev);
+    if (P->ndim == 1) {
+        P->ws_bytes = (size_t)ws1d(P->ax[0], 1, P->ax[0].d.C) * elem(P);
+    } else {
+        P->ws_bytes = (size_t)wsnd(P, 0, 1) * elem(P);
+    }
+    return HDC_OK;
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+}  // namespace
+
+// ------------------------------------------------------------------- C-ABI --
+
+extern "C" {
+
+const char* hdc_last_error(void) { return g_err.c_str(); }
+const char* hdc_version(void) { return "hdc 0.1 (gfx950)"; }
+
+hdc_status hdc_derive(int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, int64_t C, int64_t D, hdc_dtype dtype,
+                      hdc_axis_desc* out) {
+    if (!out) return fail(HDC_ERR_INVALID_ARG, "out is NULL");
+    hdc_axis_desc d{};
+    hdc_status st = derive_axis(L, M, m, p, q, C, D, dtype, &d);
+    if (st != HDC_OK) return st;
+    *out = d;
+    return HDC_OK;
+}
+
+hdc_status hdc_plan(hdc_plan_t* out, int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, int64_t C, int64_t D,
+                    hdc_dtype dtype) {
+    if (!out) return fail(HDC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    hdc_plan_s* P = new hdc_plan_s();
+    P->ndim = 1;
+    P->dtype = dtype;
+    AxisPlan& A = P->ax[0];
+    hdc_status st = derive_axis(L, M, m, p, q, C, D, dtype, &A.d);
+    if (st == HDC_OK) {
+        A.dbl = dtype == HDC_C128;
+        st = geometry(A, false);
+    }
+    if (st == HDC_OK) st = finish_plan(P);
+    if (st != HDC_OK) {
+        delete P;
+        return st;
+    }
+    *out = P;
+    return HDC_OK;
+}
+
+hdc_status hdc_plan_nd(hdc_plan_t* out, int ndim, const int64_t* L, const int64_t* M, const int64_t* m,
+                       const int64_t* p, const int64_t* q, const int64_t* D, hdc_dtype dtype) {
+    if (!out || !L || !M || !m) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    if (ndim < 1 || ndim > 3) return fail(HDC_ERR_INVALID_ARG, "ndim = %d must be 1..3", ndim);
+    hdc_plan_s* P = new hdc_plan_s();
+    P->ndim = ndim;
+    P->dtype = dtype;
+    hdc_status st = HDC_OK;
+    for (int a = 0; a < ndim && st == HDC_OK; ++a) {
+        AxisPlan& A = P->ax[a];
+        st = derive_axis(L[a], M[a], m[a], p ? p[a] : 0, q ? q[a] : 0, 1, D ? D[a] : 0, dtype, &A.d);
+        if (st == HDC_OK) {
+            A.dbl = dtype == HDC_C128;
+            st = geometry(A, a < ndim - 1);
+        }
+    }
+    if (st == HDC_OK) st = finish_plan(P);
+    if (st != HDC_OK) {
+        delete P;
+        return st;
+    }
+    *out = P;
+    return HDC_OK;
+}
+
+hdc_status hdc_plan_destroy(hdc_plan_t P) {
+    if (!P) return HDC_OK;
+    if (P->tables) (void)hipFree(P->tables);
+    delete P;
+    return HDC_OK;
+}
+
+hdc_status hdc_plan_axis(hdc_plan_t P, int axis, int* ndim, hdc_axis_desc* out) {
+    if (!P) return fail(HDC_ERR_INVALID_ARG, "plan is NULL");
+    if (ndim) *ndim = P->ndim;
+    if (axis < 0 || axis >= P->ndim) return fail(HDC_ERR_INVALID_ARG, "axis %d out of range", axis);
+    if (out) *out = P->ax[axis].d;
+    return HDC_OK;
+}
+
+hdc_status hdc_workspace_size(hdc_plan_t P, size_t* bytes) {
+    if (!P || !bytes) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+    *bytes = P->ws_bytes;
+    return HDC_OK;
+}
+
+hdc_status hdc_residue_buffer_size(hdc_plan_t P, size_t* bytes) {
+    if (!P || !bytes) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+    if (P->ndim != 1) return fail(HDC_ERR_UNSUPPORTED, "residue buffers are defined for 1D plans");
+    const hdc_axis_desc& d = P->ax[0].d;
+    *bytes = (size_t)(std::min(d.D, d.q) * d.m * d.C) * elem(P);
+    return HDC_OK;
+}
+
+static hdc_status check_ptrs(hdc_plan_t P, const void* a, const void* b, const void* c) {
+    const size_t al = elem(P) == 16 ? 16 : 8;
+    if ((a && !aligned(a, al)) || (b && !aligned(b, al)) || (c && !aligned(c, al)))
+        return fail(HDC_ERR_INVALID_ARG, "data pointers must be %zu-byte aligned", al);
+    return HDC_OK;
+}
+
+hdc_status hdc_convolve(hdc_plan_t P, const void* f, const void* g, void* h, void* ws, hipStream_t s) {
+    if (!P || !f || !g || !h) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+    if (h == f || h == g) return fail(HDC_ERR_INVALID_ARG, "h must not alias f or g");
+    hdc_status st = check_ptrs(P, f, g, h);
+    if (st != HDC_OK) return st;
+    if (P->ws_bytes > 0 && !ws) return fail(HDC_ERR_WORKSPACE, "workspace of %zu bytes required", P->ws_bytes);
+    if (P->ndim == 1) {
+        const AxisPlan& A = P->ax[0];
+        return conv1d(A, f, g, h, 1, 0, 0, A.d.C, (char*)ws, elem(P), s);
+    }
+    return convnd(P, 0, f, g, h, 1, (char*)ws, s);
+}
+
+static hdc_status group_check(hdc_plan_t P, int64_t r0, int64_t* Dg) {
+    if (P->ndim != 1) return fail(HDC_ERR_UNSUPPORTED, "forward/multiply/backward are defined for 1D plans");
+    const hdc_axis_desc& d = P->ax[0].d;
+    const int64_t D = std::min(d.D, d.q);
+    if (r0 < 0 || r0 >= d.q || r0 % D != 0)
+        return fail(HDC_ERR_INVALID_ARG, "r0 = %lld must be a multiple of D = %lld below q = %lld", (long long)r0,
+                    (long long)D, (long long)d.q);
+    *Dg = std::min(D, d.q - r0);
+    return HDC_OK;
+}
+
+hdc_status hdc_forward(hdc_plan_t P, const void* f, void* F, int64_t r0, void* ws, hipStream_t s) {
+    (void)ws;
+    if (!P || !f || !F) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+    int64_t Dg = 0;
+    hdc_status st = group_check(P, r0, &Dg);
+    if (st == HDC_OK) st = check_ptrs(P, f, F, nullptr);
+    if (st != HDC_OK) return st;
+    const AxisPlan& A = P->ax[0];
+    const int64_t C = A.d.C;
+    st = run_col_fwd(A, f, F, 1, 0, 0, C, r0, Dg, s);
+    if (st != HDC_OK) return st;
+    return run_rows(A, F, F, F, Dg * A.d.m1 * C, C, MODE_FWD, s);
+}
+
+hdc_status hdc_multiply(hdc_plan_t P, void* F, const void* G, int64_t r0, hipStream_t s) {
+    if (!P || !F || !G) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+    int64_t Dg = 0;
+    hdc_status st = group_check(P, r0, &Dg);
+    if (st == HDC_OK) st = check_ptrs(P, F, G, nullptr);
+    if (st != HDC_OK) return st;
+    const hdc_axis_desc& d = P->ax[0].d;
+    hipError_t e = launch_mul(P->dtype == HDC_C128, F, G, Dg * d.m * d.C, s);
+    if (e != hipSuccess) return hip_fail(e, "multiply launch");
+    return HDC_OK;
+}
+
+hdc_status hdc_backward(hdc_plan_t P, void* F, void* h, int64_t r0, void* ws, hipStream_t s) {
+    (void)ws;
+    if (!P || !F || !h) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+    int64_t Dg = 0;
+    hdc_status st = group_check(P, r0, &Dg);
+    if (st == HDC_OK) st = check_ptrs(P, F, h, nullptr);
+    if (st != HDC_OK) return st;
+    const AxisPlan& A = P->ax[0];
+    const int64_t C = A.d.C;
+    st = run_rows(A, F, F, F, Dg * A.d.m1 * C, C, MODE_INV, s);
+    if (st != HDC_OK) return st;
+    return run_col_bwd(A, F, h, 1, 0, 0, C, r0, Dg, r0 > 0, s);
+}
+
+hdc_status hdc_residues_natural(hdc_plan_t P, const void* F, int64_t r0, void* out, hipStream_t s) {
+    if (!P || !F || !out) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+    int64_t Dg = 0;
+    hdc_status st = group_check(P, r0, &Dg);
+    if (st != HDC_OK) return st;
+    const hdc_axis_desc& d = P->ax[0].d;
+    hipError_t e = launch_natural(P->dtype == HDC_C128, F, out, Dg, d.m1, d.m2, d.C, s);
+    if (e != hipSuccess) return hip_fail(e, "natural-order launch");
+    return HDC_OK;
+}
+
+hdc_status hdc_time_convolve(hdc_plan_t P, const void* f, const void* g, void* h, void* ws, hipStream_t s, int warmup,
+                             int reps, float* ms_out) {
+    if (!P || !ms_out || reps < 1 || warmup < 0) return fail(HDC_ERR_INVALID_ARG, "bad timing arguments");
+    for (int i = 0; i < warmup; ++i) {
+        hdc_status st = hdc_convolve(P, f, g, h, ws, s);
+        if (st != HDC_OK) return st;
+    }
+    std::vector<hipEvent_t> ev(2 * (size_t)reps);
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    hdc_status st = HDC_OK;
+    for (int i = 0; i < reps && st == HDC_OK; ++i) {
+        HIP_TRY(hipEventRecord(ev[2 * i], s));
+        st = hdc_convolve(P, f, g, h, ws, s);
+        HIP_TRY(hipEventRecord(ev[2 * i + 1], s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < reps; ++i) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
+        ms_out[i] = ms;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    return st;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches --
+//
+// n independent 1D convolutions of uneven lengths.  Problems that share the
+// FFT size m and the derived (p, q) form a bucket with one set of twiddle
+// tables; every launch of a bucket covers all of its problems, the kernels
+// reading each problem's offsets and lengths from a descriptor array.
+
+namespace {
+
+struct Bucket {
+    AxisPlan A;
+    int64_t count = 0;
+    // host descriptors, uploaded into the batch's device block
+    std::vector<int64_t> fused_desc;  // {f_off, h_off, L, M} per problem
+    std::vector<int64_t> fwd_desc;    // {f_off, L} per problem
+    std::vector<int64_t> bwd_desc;    // {h_off, M} per problem
+    size_t off_fused = 0, off_fwd = 0, off_bwd = 0;
+    const int64_t* d_fused = nullptr;
+    const int64_t* d_fwd = nullptr;
+    const int64_t* d_bwd = nullptr;
+};
+
+}  // namespace
+
+struct hdc_batch_s {
+    hdc_dtype dtype = HDC_C64;
+    int64_t n = 0, total_L = 0, total_M = 0;
+    std::vector<Bucket> buckets;
+    void* block = nullptr;
+    size_t ws_bytes = 0;
+    // captured graph and the arguments it was captured with
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipStream_t g_stream = nullptr;
+    const void *g_f = nullptr, *g_g = nullptr;
+    void *g_h = nullptr, *g_ws = nullptr;
+};
+
+namespace {
+
+// Default FFT size for a problem of length L: the smallest power of two >= L
+// (p = 1, q = 2 for M = 2L-1), i.e. explicit padding to m, implicit to 2m.
+int64_t default_m(int64_t L) {
+    int64_t m = 1;
+    while (m < L) m <<= 1;
+    return m;
+}
+
+hdc_status batch_launch(hdc_batch_s* Bt, const void* f, const void* g, void* h, void* ws, hipStream_t s) {
+    const size_t eb = elem_bytes(Bt->dtype);
+    const bool same = f == g;
+    for (const Bucket& bk : Bt->buckets) {
+        const AxisPlan& A = bk.A;
+        if (A.d.variant == 0) {
+            RowAddr in{1, 0, 0, 1}, out{1, 0, 0, 1};
+            hdc_status st = run_fused(A, f, g, h, bk.count, in, out, bk.d_fused, s);
+            if (st != HDC_OK) return st;
+            continue;
+        }
+        const int64_t D = std::min(A.d.D, A.d.q);
+        char* Xf = (char*)ws;
+        char* Xg = same ? Xf : Xf + (size_t)(bk.count * D * A.d.m) * eb;
+        for (int64_t r0 = 0; r0 < A.d.q; r0 += D) {
+            const int64_t Dg = std::min(D, A.d.q - r0);
+            const int64_t xbs = Dg * A.d.m;
+            for (int64_t b0 = 0; b0 < bk.count; b0 += 65535) {
+                const int64_t nb = std::min<int64_t>(65535, bk.count - b0);
+                char* xf = Xf + (size_t)(b0 * xbs) * eb;
+                char* xg = Xg + (size_t)(b0 * xbs) * eb;
+                hdc_status st = run_col_fwd(A, f, xf, nb, 0, xbs, 1, r0, Dg, s, bk.d_fwd + 2 * b0);
+                if (st == HDC_OK && !same) st = run_col_fwd(A, g, xg, nb, 0, xbs, 1, r0, Dg, s, bk.d_fwd + 2 * b0);
+                if (st == HDC_OK) st = run_rows(A, xf, xg, xf, nb * Dg * A.d.m1, 1, MODE_CONV, s);
+                if (st == HDC_OK)
+                    st = run_col_bwd(A, xf, h, nb, xbs, 0, 1, r0, Dg, r0 > 0, s, bk.d_bwd + 2 * b0);
+                if (st != HDC_OK) return st;
+            }
+        }
+    }
+    return HDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hdc_status hdc_batch_plan(hdc_batch_t* out, int64_t n, const int64_t* L, const int64_t* M, const int64_t* bucket_m,
+                          hdc_dtype dtype) {
+    if (!out || !L || n < 1) return fail(HDC_ERR_INVALID_ARG, "bad batch arguments");
+    *out = nullptr;
+    if (dtype != HDC_C64 && dtype != HDC_C128) return fail(HDC_ERR_INVALID_ARG, "bad dtype");
+    hdc_batch_s* Bt = new hdc_batch_s();
+    Bt->dtype = dtype;
+    Bt->n = n;
+    struct Key {
+        int64_t m, p, q;
+        bool operator==(const Key& o) const { return m == o.m && p == o.p && q == o.q; }
+    };
+    std::vector<Key> keys;
+    std::vector<std::vector<int64_t>> members;
+    std::vector<int64_t> foff(n), hoff(n);
+    int64_t fo = 0, ho = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t Li = L[i];
+        const int64_t Mi = M ? M[i] : 2 * Li - 1;
+        const int64_t mi = (bucket_m && bucket_m[i] > 0) ? bucket_m[i] : default_m(Li);
+        hdc_axis_desc d{};
+        hdc_status st = derive_axis(Li, Mi, mi, 0, 0, 1, 0, dtype, &d);
+        if (st != HDC_OK) {
+            delete Bt;
+            return fail(st, "problem %lld: %s", (long long)i, g_err.c_str());
+        }
+        foff[i] = fo;
+        hoff[i] = ho;
+        fo += Li;
+        ho += Mi;
+        Key k{mi, d.p, d.q};
+        size_t b = 0;
+        while (b < keys.size() && !(keys[b] == k)) ++b;
+        if (b == keys.size()) {
+            keys.push_back(k);
+            members.emplace_back();
+        }
+        members[b].push_back(i);
+    }
+    Bt->total_L = fo;
+    Bt->total_M = ho;
+    std::vector<unsigned char> blob;
+    size_t ws_elems = 0;
+    for (size_t b = 0; b < keys.size(); ++b) {
+        Bucket bk;
+        int64_t Lmax = 0, Mmax = 0;
+        for (int64_t i : members[b]) {
+            Lmax = std::max(Lmax, L[i]);
+            Mmax = std::max(Mmax, M ? M[i] : 2 * L[i] - 1);
+        }
+        hdc_status st = derive_axis(Lmax, Mmax, keys[b].m, keys[b].p, keys[b].q, 1, 0, dtype, &bk.A.d);
+        if (st == HDC_OK) {
+            bk.A.dbl = dtype == HDC_C128;
+            st = geometry(bk.A, false);
+        }
+        if (st != HDC_OK) {
+            delete Bt;
+            return st;
+        }
+        bk.count = (int64_t)members[b].size();
+        for (int64_t i : members[b]) {
+            const int64_t Mi = M ? M[i] : 2 * L[i] - 1;
+            bk.fused_desc.insert(bk.fused_desc.end(), {foff[i], hoff[i], L[i], Mi});
+            bk.fwd_desc.insert(bk.fwd_desc.end(), {foff[i], L[i]});
+            bk.bwd_desc.insert(bk.bwd_desc.end(), {hoff[i], Mi});
+        }
+        stage_tables(bk.A, blob);
+        auto put = [&](const std::vector<int64_t>& v) {
+            while (blob.size() % 256) blob.push_back(0);
+            size_t off = blob.size();
+            blob.insert(blob.end(), (const unsigned char*)v.data(), (const unsigned char*)(v.data() + v.size()));
+            return off;
+        };
+        bk.off_fused = put(bk.fused_desc);
+        bk.off_fwd = put(bk.fwd_desc);
+        bk.off_bwd = put(bk.bwd_desc);
+        if (bk.A.d.variant != 0) ws_elems = std::max<size_t>(ws_elems, (size_t)ws1d(bk.A, bk.count, 1));
+        Bt->buckets.push_back(std::move(bk));
+    }
+    void* dev = nullptr;
+    hipError_t e = hipMalloc(&dev, std::max<size_t>(blob.size(), 256));
+    if (e == hipSuccess) e = hipMemcpy(dev, blob.data(), blob.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (dev) (void)hipFree(dev);
+        delete Bt;
+        return hip_fail(e, "batch tables");
+    }
+    Bt->block = dev;
+    for (Bucket& bk : Bt->buckets) {
+        bind_tables(bk.A, (unsigned char*)dev);
+        bk.d_fused = (const int64_t*)((unsigned char*)dev + bk.off_fused);
+        bk.d_fwd = (const int64_t*)((unsigned char*)dev + bk.off_fwd);
+        bk.d_bwd = (const int64_t*)((unsigned char*)dev + bk.off_bwd);
+    }
+    Bt->ws_bytes = ws_elems * elem_bytes(dtype);
+    *out = Bt;
+    return HDC_OK;
+}
+
+hdc_status hdc_batch_workspace_size(hdc_batch_t Bt, size_t* bytes) {
+    if (!Bt || !bytes) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+    *bytes = Bt->ws_bytes;
+    return HDC_OK;
+}
+
+hdc_status hdc_batch_info(hdc_batch_t Bt, int64_t* n_buckets, int64_t* total_L, int64_t* total_M) {
+    if (!Bt) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+    if (n_buckets) *n_buckets = (int64_t)Bt->buckets.size();
+    if (total_L) *total_L = Bt->total_L;
+    if (total_M) *total_M = Bt->total_M;
+    return HDC_OK;
+}
+
+static hdc_status batch_args(hdc_batch_t Bt, const void* f, const void* g, void* h, void* ws) {
+    if (!Bt || !f || !g || !h) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+    if (h == f || h == g) return fail(HDC_ERR_INVALID_ARG, "h must not alias f or g");
+    if (Bt->ws_bytes > 0 && !ws) return fail(HDC_ERR_WORKSPACE, "workspace of %zu bytes required", Bt->ws_bytes);
+    return HDC_OK;
+}
+
+hdc_status hdc_batch_convolve_eager(hdc_batch_t Bt, const void* f, const void* g, void* h, void* ws, hipStream_t s) {
+    hdc_status st = batch_args(Bt, f, g, h, ws);
+    if (st != HDC_OK) return st;
+    return batch_launch(Bt, f, g, h, ws, s);
+}
+
+hdc_status hdc_batch_convolve(hdc_batch_t Bt, const void* f, const void* g, void* h, void* ws, hipStream_t s) {
+    hdc_status st = batch_args(Bt, f, g, h, ws);
+    if (st != HDC_OK) return st;
+    const bool hit = Bt->exec && Bt->g_stream == s && Bt->g_f == f && Bt->g_g == g && Bt->g_h == h && Bt->g_ws == ws;
+    if (!hit) {
+        if (Bt->exec) {
+            (void)hipGraphExecDestroy(Bt->exec);
+            Bt->exec = nullptr;
+        }
+        if (Bt->graph) {
+            (void)hipGraphDestroy(Bt->graph);
+            Bt->graph = nullptr;
+        }
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        st = batch_launch(Bt, f, g, h, ws, s);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &graph);
+        if (st != HDC_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&Bt->exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        Bt->graph = graph;
+        Bt->g_stream = s;
+        Bt->g_f = f;
+        Bt->g_g = g;
+        Bt->g_h = h;
+        Bt->g_ws = ws;
+    }
+    HIP_TRY(hipGraphLaunch(Bt->exec, s));
+    return HDC_OK;
+}
+
+hdc_status hdc_batch_destroy(hdc_batch_t Bt) {
+    if (!Bt) return HDC_OK;
+    if (Bt->exec) (void)hipGraphExecDestroy(Bt->exec);
+    if (Bt->graph) (void)hipGraphDestroy(Bt->graph);
+    if (Bt->block) (void)hipFree(Bt->block);
+    delete Bt;
+    return HDC_OK;
+}
+
+}  // extern "C"

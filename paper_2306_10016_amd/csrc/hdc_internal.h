@@ -1,0 +1,109 @@
+// Internal interface between the host plan code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hdc {
+
+// zeta_N^e = lo[e & mask] * hi[e >> lgB]  (two-level table of exp(+2 pi i e / N), FP64).
+struct TwN {
+    const double2* lo;
+    const double2* hi;
+    int32_t lgB;
+    int32_t mask;
+};
+
+// Addressing of independent rows: base(row) = (row / inner_cnt) * outer_stride
+// + (row % inner_cnt) * inner_stride, element j of the row at base + j * es.
+struct RowAddr {
+    int64_t inner_cnt;
+    int64_t outer_stride;
+    int64_t inner_stride;
+    int64_t es;
+};
+
+// Fused small-transform convolution: every residue of one row in one workgroup.
+struct FusedArgs {
+    const void* f;
+    const void* g;
+    void* h;
+    int64_t nrows;
+    RowAddr in;   // f and g
+    RowAddr out;  // h
+    const int64_t* desc;  // optional per-row {f_off, h_off, L, M}; in/out then give es only
+    int32_t L, M;         // uniform lengths when desc == nullptr
+    int32_t p, q, qout;   // qout = max output blocks ceil(M/m)
+    int32_t N;            // q * m
+    int32_t Dc;           // residues processed concurrently
+    int32_t rpw;          // rows per workgroup
+    int32_t same;         // f == g
+    int32_t hiprec;       // FP64 twiddle products for complex64
+    TwN tw;
+    const void* twm;      // zeta_m^e, e < m, in the data type
+    double invN;
+};
+
+struct ColFwdArgs {
+    const void* x;
+    void* X;
+    int64_t B, in_bs, out_bs;  // batch count and strides (elements)
+    int32_t L, Ccols, C1, m2, m, q, p, N;
+    int32_t r0, Dg;            // residues [r0, r0 + Dg)
+    int32_t tile, ntiles;
+    int32_t hiprec;
+    TwN tw;
+    const void* tw1;           // zeta_{m1}^e, e < m1, data type
+    const int64_t* desc;       // optional per-batch {input offset, L}; replaces b*in_bs and L
+};
+
+struct ColBwdArgs {
+    const void* Y;
+    void* h;
+    int64_t B, in_bs, out_bs;
+    int32_t M, Ccols, C1, m2, m, q, N, qout;
+    int32_t r0, Dg, accumulate;
+    int32_t tile, ntiles;
+    int32_t hiprec;
+    TwN tw;
+    const void* tw1;
+    double invN;
+    const int64_t* desc;  // optional per-batch {output offset, M}; replaces b*out_bs and M
+};
+
+struct RowArgs {
+    const void* a;
+    const void* b;
+    void* out;
+    int64_t nrows;
+    RowAddr addr;
+    int32_t mode;  // 0 forward DFT, 1 inverse DFT, 2 forward a and b, product, inverse
+    int32_t same;
+    int32_t rpw;
+    const void* tw;  // zeta_{m2}^e, e < m2
+};
+
+enum { MODE_FWD = 0, MODE_INV = 1, MODE_CONV = 2 };
+
+// Launchers (return hipSuccess or the launch error).  `dbl` selects complex128.
+hipError_t launch_fused(bool dbl, int m, const FusedArgs& a, int threads, int64_t blocks, size_t lds,
+                        hipStream_t s);
+hipError_t launch_col_fwd(bool dbl, int m1, const ColFwdArgs& a, int threads, int64_t gx, int64_t gy,
+                          size_t lds, hipStream_t s);
+hipError_t launch_col_bwd(bool dbl, int m1, const ColBwdArgs& a, int threads, int64_t gx, int64_t gy,
+                          size_t lds, hipStream_t s);
+hipError_t launch_row(bool dbl, int m2, const RowArgs& a, int threads, int64_t blocks, size_t lds,
+                      hipStream_t s);
+hipError_t launch_mul(bool dbl, void* F, const void* G, int64_t n, hipStream_t s);
+hipError_t launch_natural(bool dbl, const void* F, void* out, int64_t Dg, int64_t m1, int64_t m2, int64_t C,
+                          hipStream_t s);
+
+// Points per thread of the Stockham transforms for size n.
+inline int ppt_for(int n) { return n >= 8 ? 8 : n; }
+
+// Largest column-stage transform and row-stage transform the kernels implement.
+constexpr int kMaxM1 = 1024;
+constexpr int kMaxRow = 4096;
+constexpr int kMaxFused = 4096;
+
+}  // namespace hdc

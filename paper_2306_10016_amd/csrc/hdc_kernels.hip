@@ -1,0 +1,708 @@
+// HIP kernels of the hybrid dealiased convolution, written for gfx950 (CDNA4).
+//
+// Notation (section 2.2, eq. (1)): N = q m, residue r < q, block t < p,
+// column s < m, frequency l < m; zeta_n = exp(+2 pi i / n).
+//
+//   forward   F_{q l + r} = sum_s zeta_m^{l s} [ zeta_N^{r s} sum_t zeta_q^{r t} f_{t m + s} ]
+//   backward  h_{t m + s} = (1/N) sum_r zeta_q^{-t r} zeta_N^{-s r} sum_l zeta_m^{-s l} H_{q l + r}
+//
+// The m-point DFTs are radix-8 Stockham autosort passes (plus one radix-2 or
+// radix-4 pass) with every thread owning PPT = 8 points at positions
+// lane + v*(n/8).  With that ownership the inputs of every pass and the
+// outputs of the last pass sit in the same registers, so
+//   * the block sum of eq. (1) is computed straight into the registers of the
+//     first radix pass (it never touches LDS or HBM), and
+//   * the pointwise product F.G sits between the last forward pass and the
+//     first inverse pass in registers (section 2.4, the convolution theorem).
+// LDS only carries the exchanges between passes.
+//
+// Large m is split m = m1 * m2 (the four-step factorisation of the m-point
+// DFT): a column kernel does the block sum, the m1-point DFTs down strided
+// columns and the twiddle zeta_m^{l1 s2}; a row kernel does the contiguous
+// m2-point DFTs, the product and the inverse; a second column kernel does the
+// inverse m1-point DFTs and the backward post-processing over residues.  The
+// same column kernels serve the outer axes of 2D/3D problems, whose copies
+// are the inner extents (section 2.5's C).
+#include "hdc_internal.h"
+
+namespace hdc {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cplx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> mk(T a, T b) {
+    cplx<T> r;
+    r.x = a;
+    r.y = b;
+    return r;
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> operator+(cplx<T> a, cplx<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ cplx<T> operator-(cplx<T> a, cplx<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ cplx<T> operator*(cplx<T> a, cplx<T> b) {
+    return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> scale(cplx<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+
+// a * (sign * i)
+template <int SIGN, typename T>
+__device__ __forceinline__ cplx<T> mul_i(cplx<T> a) {
+    return SIGN > 0 ? mk<T>(-a.y, a.x) : mk<T>(a.y, -a.x);
+}
+
+// zeta_N^e from the two-level FP64 table.
+__device__ __forceinline__ double2 tw_n(const TwN& t, uint32_t e) {
+    const double2 a = t.lo[e & (uint32_t)t.mask];
+    const double2 b = t.hi[e >> t.lgB];
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// v * z (CONJ: v * conj(z)); complex64 data use an FP64 product when hp is set.
+template <bool CONJ, typename T>
+__device__ __forceinline__ cplx<T> mul_tw(cplx<T> v, double2 z, bool hp);
+
+template <>
+__device__ __forceinline__ cplx<double> mul_tw<false, double>(cplx<double> v, double2 z, bool) {
+    return mk<double>(v.x * z.x - v.y * z.y, v.x * z.y + v.y * z.x);
+}
+template <>
+__device__ __forceinline__ cplx<double> mul_tw<true, double>(cplx<double> v, double2 z, bool) {
+    return mk<double>(v.x * z.x + v.y * z.y, v.y * z.x - v.x * z.y);
+}
+template <>
+__device__ __forceinline__ cplx<float> mul_tw<false, float>(cplx<float> v, double2 z, bool hp) {
+    if (hp) {
+        const double x = v.x, y = v.y;
+        return mk<float>((float)(x * z.x - y * z.y), (float)(x * z.y + y * z.x));
+    }
+    const float zx = (float)z.x, zy = (float)z.y;
+    return mk<float>(v.x * zx - v.y * zy, v.x * zy + v.y * zx);
+}
+template <>
+__device__ __forceinline__ cplx<float> mul_tw<true, float>(cplx<float> v, double2 z, bool hp) {
+    if (hp) {
+        const double x = v.x, y = v.y;
+        return mk<float>((float)(x * z.x + y * z.y), (float)(y * z.x - x * z.y));
+    }
+    const float zx = (float)z.x, zy = (float)z.y;
+    return mk<float>(v.x * zx + v.y * zy, v.y * zx - v.x * zy);
+}
+
+// ------------------------------------------------------------ Stockham DFT --
+
+constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
+
+template <int NSZ>
+struct FP {
+    static constexpr int LG = ilog2c(NSZ);
+    static constexpr int PPT = NSZ >= 8 ? 8 : NSZ;
+    static constexpr int TPF = NSZ / PPT;  // threads per transform
+    static constexpr int R0 = NSZ < 8 ? NSZ : ((LG % 3) == 0 ? 8 : (1 << (LG % 3)));
+    static constexpr int NPASS = NSZ <= 1 ? 0 : (NSZ < 8 ? 1 : ((LG % 3) == 0 ? LG / 3 : LG / 3 + 1));
+};
+
+template <int R, int SIGN, typename T>
+__device__ __forceinline__ void dft_r(cplx<T>* x) {
+    if constexpr (R == 2) {
+        const cplx<T> a = x[0];
+        x[0] = a + x[1];
+        x[1] = a - x[1];
+    } else if constexpr (R == 4) {
+        const cplx<T> a = x[0] + x[2], b = x[0] - x[2], c = x[1] + x[3];
+        const cplx<T> d = mul_i<SIGN>(x[1] - x[3]);
+        x[0] = a + c;
+        x[2] = a - c;
+        x[1] = b + d;
+        x[3] = b - d;
+    } else if constexpr (R == 8) {
+        cplx<T> a[4] = {x[0], x[2], x[4], x[6]};
+        cplx<T> b[4] = {x[1], x[3], x[5], x[7]};
+        dft_r<4, SIGN>(a);
+        dft_r<4, SIGN>(b);
+        const T rh = (T)0.70710678118654752440;
+        const T s = (T)SIGN;
+        b[1] = mk<T>((b[1].x - s * b[1].y) * rh, (s * b[1].x + b[1].y) * rh);
+        b[2] = mul_i<SIGN>(b[2]);
+        b[3] = mk<T>((-b[3].x - s * b[3].y) * rh, (s * b[3].x - b[3].y) * rh);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            x[k] = a[k] + b[k];
+            x[k + 4] = a[k] - b[k];
+        }
+    }
+}
+
+// One radix-R pass over sub-transforms of length Ns -> Ns*R.  Register v[w]
+// holds position lane + w*TPF.  Non-final passes write to LDS (element
+// stride bstride); the final pass leaves its outputs in v.
+template <typename T, int NSZ, int R, int SIGN, bool LAST>
+__device__ __forceinline__ void stock_pass(cplx<T> (&v)[FP<NSZ>::PPT], int Ns, cplx<T>* buf, int bstride, int lane,
+                                           const cplx<T>* tw, bool act) {
+    constexpr int PPT = FP<NSZ>::PPT;
+    constexpr int Q = FP<NSZ>::TPF;
+    constexpr int NB = PPT / R;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const int j = lane + u * Q;
+        const int k = j & (Ns - 1);
+        cplx<T> x[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) x[i] = v[u + i * NB];
+        if (Ns > 1) {
+            const int step = NSZ / (Ns * R);
+#pragma unroll
+            for (int i = 1; i < R; ++i) {
+                cplx<T> w = tw[i * k * step];
+                if (SIGN < 0) w.y = -w.y;
+                x[i] = x[i] * w;
+            }
+        }
+        dft_r<R, SIGN>(x);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int a = 0; a < R; ++a) v[u + a * NB] = x[a];
+        } else {
+            if (act) {
+                const int base = (j - k) * R + k;
+#pragma unroll
+                for (int a = 0; a < R; ++a) buf[(base + a * Ns) * bstride] = x[a];
+            }
+        }
+    }
+}
+
+template <typename T, int NSZ>
+__device__ __forceinline__ void lds_reload(cplx<T> (&v)[FP<NSZ>::PPT], const cplx<T>* buf, int bstride, int lane,
+                                           bool act) {
+    constexpr int PPT = FP<NSZ>::PPT;
+    constexpr int Q = FP<NSZ>::TPF;
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int w = 0; w < PPT; ++w) v[w] = buf[(lane + w * Q) * bstride];
+    }
+    __syncthreads();
+}
+
+// NSZ-point DFT with zeta_NSZ^{SIGN}, registers in and out (positions lane + w*TPF).
+// Every thread of the workgroup must call it (it contains barriers).
+template <typename T, int NSZ, int SIGN>
+__device__ __forceinline__ void fft_regs(cplx<T> (&v)[FP<NSZ>::PPT], cplx<T>* buf, int bstride, int lane,
+                                         const cplx<T>* tw, bool act) {
+    using P = FP<NSZ>;
+    if constexpr (P::NPASS == 1) {
+        stock_pass<T, NSZ, P::R0, SIGN, true>(v, 1, buf, bstride, lane, tw, act);
+    } else if constexpr (P::NPASS > 1) {
+        stock_pass<T, NSZ, P::R0, SIGN, false>(v, 1, buf, bstride, lane, tw, act);
+        int Ns = P::R0;
+#pragma unroll
+        for (int ps = 1; ps < P::NPASS - 1; ++ps) {
+            lds_reload<T, NSZ>(v, buf, bstride, lane, act);
+            stock_pass<T, NSZ, 8, SIGN, false>(v, Ns, buf, bstride, lane, tw, act);
+            Ns *= 8;
+        }
+        lds_reload<T, NSZ>(v, buf, bstride, lane, act);
+        stock_pass<T, NSZ, 8, SIGN, true>(v, Ns, buf, bstride, lane, tw, act);
+    }
+}
+
+__device__ __forceinline__ int64_t row_base(const RowAddr& a, int64_t row) {
+    const int64_t o = row / a.inner_cnt;
+    return o * a.outer_stride + (row - o * a.inner_cnt) * a.inner_stride;
+}
+
+// ------------------------------------------------------------- fused kernel --
+//
+// One row (an independent 1D convolution) per group of TPF*Dc threads; its
+// q residues are processed Dc at a time.  Residue r uses LDS region U[r]
+// (m values) as its exchange buffer and finally stores
+//     u^(r)_s zeta_N^{-r s} / N
+// there.  After all residues, the output blocks t < ceil(M/m) are the
+// q-point sums over r with zeta_q^{-t r}.  LDS: rows * N values + q twiddles.
+
+template <typename T, int MSZ>
+__global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
+    using P = FP<MSZ>;
+    constexpr int PPT = P::PPT;
+    constexpr int TPF = P::TPF;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T>* smem = reinterpret_cast<cplx<T>*>(smem_raw);
+    double2* twq = reinterpret_cast<double2*>(smem_raw + ((size_t)a.rpw * a.N * sizeof(cplx<T>) + 15) / 16 * 16);
+
+    const int rowthreads = TPF * a.Dc;
+    const int tid = threadIdx.x;
+    const int rloc = tid / rowthreads;
+    const int lt = tid - rloc * rowthreads;
+    const int grp = lt / TPF;
+    const int lane = lt - grp * TPF;
+    const int64_t row = (int64_t)blockIdx.x * a.rpw + rloc;
+    const bool rowok = row < a.nrows;
+
+    // zeta_q^e, e < q, shared by the block sums and the output sums.
+    for (int e = tid; e < a.q; e += blockDim.x) twq[e] = tw_n(a.tw, (uint32_t)e * (uint32_t)MSZ);
+    __syncthreads();
+
+    int L = a.L, M = a.M;
+    int64_t fbase, hbase;
+    if (a.desc != nullptr) {
+        const int64_t* d = a.desc + 4 * (rowok ? row : 0);
+        fbase = d[0];
+        hbase = d[1];
+        L = (int)d[2];
+        M = (int)d[3];
+    } else {
+        fbase = row_base(a.in, rowok ? row : 0);
+        hbase = row_base(a.out, rowok ? row : 0);
+    }
+    const int64_t ies = a.in.es, oes = a.out.es;
+    const cplx<T>* f = reinterpret_cast<const cplx<T>*>(a.f) + fbase;
+    const cplx<T>* g = reinterpret_cast<const cplx<T>*>(a.g) + fbase;
+    cplx<T>* h = reinterpret_cast<cplx<T>*>(a.h) + hbase;
+    const cplx<T>* twm = reinterpret_cast<const cplx<T>*>(a.twm);
+    cplx<T>* U = smem + (size_t)rloc * a.N;
+    const T invN = (T)a.invN;
+
+    for (int rb = 0; rb < a.q; rb += a.Dc) {
+        const int r = rb + grp;
+        const bool act = rowok && r < a.q;
+        cplx<T>* buf = U + (size_t)(act ? r : 0) * MSZ;
+
+        // block sums of eq. (1) for f and g, straight into the first radix pass
+        cplx<T> F[PPT], G[PPT];
+#pragma unroll
+        for (int v = 0; v < PPT; ++v) {
+            F[v] = mk<T>(0, 0);
+            G[v] = mk<T>(0, 0);
+        }
+        if (act) {
+            int e = 0;  // (r t) mod q
+            for (int t = 0; t < a.p; ++t) {
+                const double2 z = twq[e];
+                e += r;
+                if (e >= a.q) e -= a.q;
+#pragma unroll
+                for (int v = 0; v < PPT; ++v) {
+                    const int j = t * MSZ + lane + v * TPF;
+                    if (j < L) {
+                        F[v] = F[v] + mul_tw<false>(f[(int64_t)j * ies], z, false);
+                        if (!a.same) G[v] = G[v] + mul_tw<false>(g[(int64_t)j * ies], z, false);
+                    }
+                }
+            }
+        }
+        const uint32_t ru = (uint32_t)(act ? r : 0);
+#pragma unroll
+        for (int v = 0; v < PPT; ++v) {  // zeta_N^{r s}
+            const double2 z = tw_n(a.tw, ru * (uint32_t)(lane + v * TPF));
+            F[v] = mul_tw<false>(F[v], z, a.hiprec);
+            if (!a.same) G[v] = mul_tw<false>(G[v], z, a.hiprec);
+        }
+        fft_regs<T, MSZ, +1>(F, buf, 1, lane, twm, act);
+        if (!a.same) {
+            fft_regs<T, MSZ, +1>(G, buf, 1, lane, twm, act);
+#pragma unroll
+            for (int v = 0; v < PPT; ++v) F[v] = F[v] * G[v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < PPT; ++v) F[v] = F[v] * F[v];
+        }
+        fft_regs<T, MSZ, -1>(F, buf, 1, lane, twm, act);
+        if (act) {
+#pragma unroll
+            for (int v = 0; v < PPT; ++v) {
+                const int s = lane + v * TPF;
+                buf[s] = scale(mul_tw<true>(F[v], tw_n(a.tw, ru * (uint32_t)s), a.hiprec), invN);
+            }
+        }
+    }
+    __syncthreads();
+    if (!rowok) return;
+    // h_{t m + s} = sum_r zeta_q^{-t r} U[r][s]
+    for (int k = lt; k < M; k += rowthreads) {
+        const int t = k / MSZ;
+        const int s = k - t * MSZ;
+        cplx<T> acc = mk<T>(0, 0);
+        int e = 0;  // (t r) mod q
+        for (int r = 0; r < a.q; ++r) {
+            acc = acc + mul_tw<true>(U[(size_t)r * MSZ + s], twq[e], false);
+            e += t;
+            if (e >= a.q) e -= a.q;
+        }
+        h[(int64_t)k * oes] = acc;
+    }
+}
+
+// ------------------------------------------------------- column kernels --
+//
+// A workgroup owns `tile` adjacent columns c' (coalesced) and all m1 rows of
+// one residue (forward) or all residues of a group (backward).  LDS holds an
+// m1 x tile block, element (pos, cc) at pos*tile + cc.
+//
+// Column c' = s2*C1 + c1 (s2 < m2 the four-step column, c1 < C1 the copy);
+// axis index j = t*m + s1*m2 + s2 lives at element (t*m1 + s1)*Ccols + c'.
+
+template <typename T, int M1>
+__global__ void __launch_bounds__(1024) k_col_fwd(ColFwdArgs a) {
+    using P = FP<M1>;
+    constexpr int PPT = P::PPT;
+    constexpr int TPF = P::TPF;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+
+    const int tile = a.tile;
+    const int tid = threadIdx.x;
+    const int cc = tid % tile;
+    const int lane = tid / tile;
+    const int d = blockIdx.x % a.Dg;
+    const int tl = blockIdx.x / a.Dg;
+    const int64_t b = blockIdx.y;
+    const int cp = tl * tile + cc;
+    const bool ok = cp < a.Ccols;
+    const int s2 = ok ? cp / a.C1 : 0;
+    const int r = a.r0 + d;
+    int64_t xoff = b * a.in_bs;
+    int64_t L = a.L;
+    if (a.desc != nullptr) {
+        xoff = a.desc[2 * b];
+        L = a.desc[2 * b + 1];
+    }
+    const cplx<T>* x = reinterpret_cast<const cplx<T>*>(a.x) + xoff;
+
+    cplx<T> w[PPT];
+#pragma unroll
+    for (int v = 0; v < PPT; ++v) w[v] = mk<T>(0, 0);
+    for (int t = 0; t < a.p; ++t) {
+        const uint32_t e = (uint32_t)(((int64_t)r * t) % a.q) * (uint32_t)a.m;
+        const double2 z = tw_n(a.tw, e);
+#pragma unroll
+        for (int v = 0; v < PPT; ++v) {
+            const int s1 = lane + v * TPF;
+            const int64_t j = ((int64_t)t * M1 + s1) * a.m2 + s2;
+            if (ok && j < L) {
+                const cplx<T> xv = x[((int64_t)t * M1 + s1) * a.Ccols + cp];
+                w[v] = w[v] + mul_tw<false>(xv, z, a.hiprec);
+            }
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < PPT; ++v) {
+        const int s1 = lane + v * TPF;
+        const uint32_t s = (uint32_t)s1 * (uint32_t)a.m2 + (uint32_t)s2;
+        w[v] = mul_tw<false>(w[v], tw_n(a.tw, (uint32_t)r * s), a.hiprec);
+    }
+    fft_regs<T, M1, +1>(w, lds + cc, tile, lane, reinterpret_cast<const cplx<T>*>(a.tw1), true);
+    cplx<T>* X = reinterpret_cast<cplx<T>*>(a.X) + b * a.out_bs;
+#pragma unroll
+    for (int v = 0; v < PPT; ++v) {
+        const int l1 = lane + v * TPF;
+        cplx<T> o = w[v];
+        if (a.m2 > 1) o = mul_tw<false>(o, tw_n(a.tw, (uint32_t)l1 * (uint32_t)s2 * (uint32_t)a.q), a.hiprec);
+        if (ok) X[((int64_t)d * M1 + l1) * a.Ccols + cp] = o;
+    }
+}
+
+template <typename T, int M1, int DMAX>
+__global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
+    using P = FP<M1>;
+    constexpr int PPT = P::PPT;
+    constexpr int TPF = P::TPF;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+
+    const int tile = a.tile;
+    const int tid = threadIdx.x;
+    const int cc = tid % tile;
+    const int lane = tid / tile;
+    const int64_t b = blockIdx.y;
+    const int cp = blockIdx.x * tile + cc;
+    const bool ok = cp < a.Ccols;
+    const int s2 = ok ? cp / a.C1 : 0;
+    int64_t hoff = b * a.out_bs;
+    int64_t M = a.M;
+    if (a.desc != nullptr) {
+        hoff = a.desc[2 * b];
+        M = a.desc[2 * b + 1];
+    }
+    const cplx<T>* Y = reinterpret_cast<const cplx<T>*>(a.Y) + b * a.in_bs;
+    cplx<T>* h = reinterpret_cast<cplx<T>*>(a.h) + hoff;
+    const cplx<T>* tw1 = reinterpret_cast<const cplx<T>*>(a.tw1);
+    const T invN = (T)a.invN;
+
+    for (int db = 0; db < a.Dg; db += DMAX) {
+        const int nd = min(DMAX, a.Dg - db);
+        cplx<T> V[DMAX][PPT];
+#pragma unroll
+        for (int dd = 0; dd < DMAX; ++dd) {
+            const int d = db + dd;
+            if (dd < nd) {
+                cplx<T> w[PPT];
+#pragma unroll
+                for (int v = 0; v < PPT; ++v) {
+                    const int l1 = lane + v * TPF;
+                    cplx<T> y = ok ? Y[((int64_t)d * M1 + l1) * a.Ccols + cp] : mk<T>(0, 0);
+                    if (a.m2 > 1)
+                        y = mul_tw<true>(y, tw_n(a.tw, (uint32_t)l1 * (uint32_t)s2 * (uint32_t)a.q), a.hiprec);
+                    w[v] = y;
+                }
+                fft_regs<T, M1, -1>(w, lds + cc, tile, lane, tw1, true);
+                const int r = a.r0 + d;
+#pragma unroll
+                for (int v = 0; v < PPT; ++v) {
+                    const int s1 = lane + v * TPF;
+                    const uint32_t s = (uint32_t)s1 * (uint32_t)a.m2 + (uint32_t)s2;
+                    V[dd][v] = scale(mul_tw<true>(w[v], tw_n(a.tw, (uint32_t)r * s), a.hiprec), invN);
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < PPT; ++v) V[dd][v] = mk<T>(0, 0);
+            }
+        }
+        const bool add = a.accumulate || db > 0;
+        for (int t = 0; t < a.qout; ++t) {
+            double2 z[DMAX];
+#pragma unroll
+            for (int dd = 0; dd < DMAX; ++dd) {
+                const int64_t r = a.r0 + db + dd;
+                z[dd] = tw_n(a.tw, (uint32_t)(((int64_t)t * r) % a.q) * (uint32_t)a.m);
+            }
+#pragma unroll
+            for (int v = 0; v < PPT; ++v) {
+                const int s1 = lane + v * TPF;
+                const int64_t k = (int64_t)t * a.m + (int64_t)s1 * a.m2 + s2;
+                if (!ok || k >= M) continue;
+                cplx<T> acc = mk<T>(0, 0);
+#pragma unroll
+                for (int dd = 0; dd < DMAX; ++dd)
+                    if (dd < nd) acc = acc + mul_tw<true>(V[dd][v], z[dd], false);
+                const int64_t idx = ((int64_t)t * M1 + s1) * a.Ccols + cp;
+                if (add) acc = acc + h[idx];
+                h[idx] = acc;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- rows --
+
+template <typename T, int MSZ>
+__global__ void __launch_bounds__(512) k_row(RowArgs a) {
+    using P = FP<MSZ>;
+    constexpr int PPT = P::PPT;
+    constexpr int TPF = P::TPF;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T>* smem = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int rloc = tid / TPF;
+    const int lane = tid - rloc * TPF;
+    const int64_t row = (int64_t)blockIdx.x * a.rpw + rloc;
+    const bool ok = row < a.nrows;
+    cplx<T>* buf = smem + (size_t)rloc * MSZ;
+    const int64_t base = row_base(a.addr, ok ? row : 0);
+    const int64_t es = a.addr.es;
+    const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(a.tw);
+    const cplx<T>* A = reinterpret_cast<const cplx<T>*>(a.a) + base;
+    cplx<T>* O = reinterpret_cast<cplx<T>*>(a.out) + base;
+
+    cplx<T> v[PPT];
+#pragma unroll
+    for (int w = 0; w < PPT; ++w) v[w] = ok ? A[(int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
+    if (a.mode == MODE_INV) {
+        fft_regs<T, MSZ, -1>(v, buf, 1, lane, tw, ok);
+    } else {
+        fft_regs<T, MSZ, +1>(v, buf, 1, lane, tw, ok);
+        if (a.mode == MODE_CONV) {
+            if (a.same) {
+#pragma unroll
+                for (int w = 0; w < PPT; ++w) v[w] = v[w] * v[w];
+            } else {
+                const cplx<T>* B = reinterpret_cast<const cplx<T>*>(a.b) + base;
+                cplx<T> u[PPT];
+#pragma unroll
+                for (int w = 0; w < PPT; ++w) u[w] = ok ? B[(int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
+                fft_regs<T, MSZ, +1>(u, buf, 1, lane, tw, ok);
+#pragma unroll
+                for (int w = 0; w < PPT; ++w) v[w] = v[w] * u[w];
+            }
+            fft_regs<T, MSZ, -1>(v, buf, 1, lane, tw, ok);
+        }
+    }
+    if (ok) {
+#pragma unroll
+        for (int w = 0; w < PPT; ++w) O[(int64_t)(lane + w * TPF) * es] = v[w];
+    }
+}
+
+// ------------------------------------------------------------ elementwise --
+
+template <typename T>
+__global__ void k_mul(cplx<T>* F, const cplx<T>* G, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) F[i] = F[i] * G[i];
+}
+
+// out[((d m) + l) C + c] = F[((d m1 + l1) m2 + l2) C + c] with l = l1 + m1 l2.
+template <typename T>
+__global__ void k_natural(const cplx<T>* F, cplx<T>* out, int64_t Dg, int64_t m1, int64_t m2, int64_t C) {
+    const int64_t m = m1 * m2;
+    const int64_t n = Dg * m * C;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int64_t c = i % C;
+        const int64_t l = (i / C) % m;
+        const int64_t d = i / (C * m);
+        const int64_t l1 = l % m1, l2 = l / m1;
+        out[i] = F[((d * m1 + l1) * m2 + l2) * C + c];
+    }
+}
+
+// --------------------------------------------------------------- launchers --
+
+namespace {
+
+template <typename K>
+hipError_t allow_lds(K kernel, size_t lds) {
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds);
+}
+
+template <typename T, int MSZ>
+hipError_t fused_t(const FusedArgs& a, int threads, int64_t blocks, size_t lds, hipStream_t s) {
+    hipError_t e = allow_lds(k_fused<T, MSZ>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_fused<T, MSZ>), dim3((unsigned)blocks), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int M1>
+hipError_t colf_t(const ColFwdArgs& a, int threads, int64_t gx, int64_t gy, size_t lds, hipStream_t s) {
+    hipError_t e = allow_lds(k_col_fwd<T, M1>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_col_fwd<T, M1>), dim3((unsigned)gx, (unsigned)gy), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int M1>
+hipError_t colb_t(const ColBwdArgs& a, int threads, int64_t gx, int64_t gy, size_t lds, hipStream_t s) {
+    constexpr int DMAX = sizeof(T) == 8 ? 2 : 4;
+    hipError_t e = allow_lds(k_col_bwd<T, M1, DMAX>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_col_bwd<T, M1, DMAX>), dim3((unsigned)gx, (unsigned)gy), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int MSZ>
+hipError_t row_t(const RowArgs& a, int threads, int64_t blocks, size_t lds, hipStream_t s) {
+    hipError_t e = allow_lds(k_row<T, MSZ>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_row<T, MSZ>), dim3((unsigned)blocks), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+#define HDC_POW2_CASES(F, ...)             \
+    case 1: return F<T, 1>(__VA_ARGS__);       \
+    case 2: return F<T, 2>(__VA_ARGS__);       \
+    case 4: return F<T, 4>(__VA_ARGS__);       \
+    case 8: return F<T, 8>(__VA_ARGS__);       \
+    case 16: return F<T, 16>(__VA_ARGS__);     \
+    case 32: return F<T, 32>(__VA_ARGS__);     \
+    case 64: return F<T, 64>(__VA_ARGS__);     \
+    case 128: return F<T, 128>(__VA_ARGS__);   \
+    case 256: return F<T, 256>(__VA_ARGS__);   \
+    case 512: return F<T, 512>(__VA_ARGS__);   \
+    case 1024: return F<T, 1024>(__VA_ARGS__);
+
+template <typename T>
+static hipError_t fused_disp(int m, const FusedArgs& a, int th, int64_t bl, size_t lds, hipStream_t s) {
+    switch (m) {
+        HDC_POW2_CASES(fused_t, a, th, bl, lds, s)
+        case 2048: return fused_t<T, 2048>(a, th, bl, lds, s);
+        case 4096: return fused_t<T, 4096>(a, th, bl, lds, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+static hipError_t row_disp(int m, const RowArgs& a, int th, int64_t bl, size_t lds, hipStream_t s) {
+    switch (m) {
+        HDC_POW2_CASES(row_t, a, th, bl, lds, s)
+        case 2048: return row_t<T, 2048>(a, th, bl, lds, s);
+        case 4096: return row_t<T, 4096>(a, th, bl, lds, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+static hipError_t colf_disp(int m1, const ColFwdArgs& a, int th, int64_t gx, int64_t gy, size_t lds, hipStream_t s) {
+    switch (m1) {
+        HDC_POW2_CASES(colf_t, a, th, gx, gy, lds, s)
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+static hipError_t colb_disp(int m1, const ColBwdArgs& a, int th, int64_t gx, int64_t gy, size_t lds, hipStream_t s) {
+    switch (m1) {
+        HDC_POW2_CASES(colb_t, a, th, gx, gy, lds, s)
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fused(bool dbl, int m, const FusedArgs& a, int threads, int64_t blocks, size_t lds,
+                        hipStream_t s) {
+    return dbl ? fused_disp<double>(m, a, threads, blocks, lds, s) : fused_disp<float>(m, a, threads, blocks, lds, s);
+}
+
+hipError_t launch_row(bool dbl, int m2, const RowArgs& a, int threads, int64_t blocks, size_t lds, hipStream_t s) {
+    return dbl ? row_disp<double>(m2, a, threads, blocks, lds, s) : row_disp<float>(m2, a, threads, blocks, lds, s);
+}
+
+hipError_t launch_col_fwd(bool dbl, int m1, const ColFwdArgs& a, int threads, int64_t gx, int64_t gy, size_t lds,
+                          hipStream_t s) {
+    return dbl ? colf_disp<double>(m1, a, threads, gx, gy, lds, s)
+               : colf_disp<float>(m1, a, threads, gx, gy, lds, s);
+}
+
+hipError_t launch_col_bwd(bool dbl, int m1, const ColBwdArgs& a, int threads, int64_t gx, int64_t gy, size_t lds,
+                          hipStream_t s) {
+    return dbl ? colb_disp<double>(m1, a, threads, gx, gy, lds, s)
+               : colb_disp<float>(m1, a, threads, gx, gy, lds, s);
+}
+
+hipError_t launch_mul(bool dbl, void* F, const void* G, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    if (dbl)
+        hipLaunchKernelGGL(k_mul<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           reinterpret_cast<cplx<double>*>(F), reinterpret_cast<const cplx<double>*>(G), n);
+    else
+        hipLaunchKernelGGL(k_mul<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           reinterpret_cast<cplx<float>*>(F), reinterpret_cast<const cplx<float>*>(G), n);
+    return hipGetLastError();
+}
+
+hipError_t launch_natural(bool dbl, const void* F, void* out, int64_t Dg, int64_t m1, int64_t m2, int64_t C,
+                          hipStream_t s) {
+    const int64_t n = Dg * m1 * m2 * C;
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    if (dbl)
+        hipLaunchKernelGGL(k_natural<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           reinterpret_cast<const cplx<double>*>(F), reinterpret_cast<cplx<double>*>(out), Dg, m1,
+                           m2, C);
+    else
+        hipLaunchKernelGGL(k_natural<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           reinterpret_cast<const cplx<float>*>(F), reinterpret_cast<cplx<float>*>(out), Dg, m1, m2,
+                           C);
+    return hipGetLastError();
+}
+
+}  // namespace hdc

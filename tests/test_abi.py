@@ -1,0 +1,78 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports every
+symbol the headers declare, and hdc_derive implements the admissibility rules
+of section 2.5 (p = ceil(L/m), q = ceil(M/m), pm >= L, qm >= M, q >= p)."""
+import glob
+import os
+
+import pytest
+
+import paper_2306_10016_amd as hdc
+from paper_2306_10016_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    L = hdc.lib()
+    assert L.hdc_version().startswith(b"hdc")
+    for hdr in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        syms = _lib.header_symbols(hdr)
+        assert syms, hdr
+        missing = [s for s in syms if not hasattr(L, s)]
+        assert not missing, (hdr, missing)
+
+
+@pytest.mark.parametrize("L,M,m,p,q", [(6, 11, 4, 2, 3), (1024, 2047, 256, 4, 8), (1, 1, 1, 1, 1),
+                                       (37, 80, 64, 1, 2), (100, 199, 1, 100, 199), (1 << 22, (1 << 23) - 1,
+                                                                                     1 << 22, 1, 2)])
+def test_derive_ceilings(L, M, m, p, q):
+    d = hdc.derive(L, M, m)
+    assert (d["p"], d["q"], d["N"], d["D"]) == (p, q, p * 0 + q * m, q)
+    assert d["p"] * m >= L and d["q"] * m >= M and d["q"] >= d["p"]
+    assert d["q_out"] == -(-M // m)
+    assert d["m1"] * d["m2"] == m
+
+
+def test_derive_fig2_shape():
+    """Section 2.5, Fig. 2: L=6, M=11, m=4 gives p=2 (explicit pad to 8) and q=3 (implicit to 12)."""
+    d = hdc.derive(6, 11, 4)
+    assert d["p"] == 2 and d["q"] == 3 and d["N"] == 12
+
+
+@pytest.mark.parametrize("args,status", [
+    ((10, 18, 4), 1),            # M < 2L-1: aliasing
+    ((0, 5, 4), 1),              # L < 1
+    ((10, 19, 0), 1),            # m < 1
+    ((10, 19, 4, 2, 0), 1),      # p m < L
+    ((10, 19, 4, 0, 4), 1),      # q m < M
+    ((10, 19, 4, 5, 4), 1),      # q < p (and qm < M)
+    ((10, 19, 6), 2),            # m not a power of two: unsupported by the kernels
+    ((10, 19, 4, 0, 0, 0), 1),   # C < 1
+    ((1 << 23, (1 << 24) - 1, 1 << 24), 2),  # m beyond the column x row limit
+])
+def test_derive_rejects(args, status):
+    with pytest.raises(hdc.HdcError) as e:
+        hdc.derive(*args)
+    assert e.value.status == status
+    assert len(str(e.value)) > 10
+
+
+def test_derive_clamps_D():
+    assert hdc.derive(100, 199, 16, D=100)["D"] == hdc.derive(100, 199, 16)["q"]
+    assert hdc.derive(100, 199, 16, D=3)["D"] == 3
+
+
+def test_variant_choice_by_lds_budget():
+    # whole transform fits the fused kernel's LDS budget (N values of 8 or 16 bytes within 64 KiB)
+    assert hdc.derive(1024, 2047, 256, dtype="c128")["variant"] == 0
+    assert hdc.derive(2048, 4095, 4096, dtype="c128")["variant"] == 1
+    assert hdc.derive(2048, 4095, 4096, dtype="c64")["variant"] == 0
+    assert hdc.derive(1 << 20, (1 << 21) - 1, 1 << 20, dtype="c64")["variant"] == 1
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+    with pytest.raises((TypeError, hdc.HdcError, RuntimeError)):
+        p = hdc.Plan.__new__(hdc.Plan)
+        p.dtype = 1
+        hdc._check_tensor(torch.zeros(4, dtype=torch.complex128), 1, 4, "f")
