@@ -1,0 +1,277 @@
+#!/usr/bin/env python3
+"""Benchmark of the hybrid dealiased convolution on one MI355X.
+
+Workload (one "step"): the 1D sweep -- one linear convolution for every
+L in {2^6 .. 2^22} U {3^a 5^b 7^c in [64, 4e6]} (263 sizes), M = 2L-1,
+complex128 by default, inputs re/im ~ U[-1, 1] from the seeded generator,
+each with the (m, p, q, D) chosen by the experience autotuner.  Every step
+runs the whole hot path for every size: block sums, residue DFTs, products,
+inverse DFTs, backward accumulation.  Inputs are resident in HBM before the
+timed region starts.
+
+Printed (one JSON line): convs/s over the sweep, the roofline object of the
+dominant kernel (event-timed inside the timed region, algorithmic bytes per
+launch), the explicit-padding comparator on the same GPU (torch.fft, pad to
+2L), the accuracy against it, and the CPU oracle's rate on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--dtype c128|c64]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "convs/s & % HBM roofline vs explicit-pad conv at rel err ≤1e-12; tuner regret"
+
+
+def sweep_sizes(lo: int = 64, hi: float = 4e6):
+    S = {1 << k for k in range(6, 23)}
+    a = 1
+    while a <= hi:
+        b = a
+        while b <= hi:
+            c = b
+            while c <= hi:
+                if c >= lo:
+                    S.add(c)
+                c *= 7
+            b *= 5
+        a *= 3
+    return sorted(S)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(sizes, dtype, budget_s: float = 20.0):
+    """The oracle (explicit zero-padded FFT, FP64 C) on a stratified sample of the sweep,
+    run by a thread pool over the host cores; extrapolated to the whole sweep by
+    N log2 N work weights."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    import oracle
+    import synth
+    oracle.build(force=False)
+    np_dt = np.complex128 if dtype == "c128" else np.complex64
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    cores = max(1, min(cores, os.cpu_count() or 1, 16))
+    os.environ["OMP_NUM_THREADS"] = "1"
+
+    def w(L):
+        N = 2 * L
+        return N * math.log2(N)
+    cand = [L for L in sizes if L <= (1 << 20)]
+    sample = cand[::4]
+    # keep the sample within the budget: assume ~25 ns per N log2 N unit per core
+    while sample and sum(w(L) for L in sample) * 25e-9 / cores > budget_s:
+        sample = sample[:-1]
+
+    def one(i_L):
+        i, L = i_L
+        f, g = synth.pair(L, 2, i, np_dt)
+        f = f.astype(np.complex128)
+        g = g.astype(np.complex128)
+        t = time.perf_counter()
+        oracle.padded_1d(f, g, 2 * L - 1)
+        return time.perf_counter() - t
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        list(ex.map(one, enumerate(sample)))
+    wall = time.perf_counter() - t0
+    scale = sum(w(L) for L in sizes) / sum(w(L) for L in sample)
+    est_sweep_s = wall * scale
+    return {"value": len(sizes) / est_sweep_s, "unit": "convs/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(sample)} of {len(sizes)} sweep sizes (every 4th with L <= 2^20, L = {sample[0]}.."
+                      f"{sample[-1]}), FP64 explicit-padded FFT oracle, {cores} threads, wall {wall:.2f} s, "
+                      f"extrapolated to the full sweep by N log2 N weights (x{scale:.1f})"}
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM traffic per launch from the committed counter summary, if it matches the current kernels."""
+    import hashlib
+    path = os.path.join(HERE, "profiles", "traffic.json")
+    src = os.path.join(HERE, "paper_2306_10016_amd", "csrc", "hdc_kernels.hip")
+    try:
+        data = json.load(open(path))
+        h = hashlib.sha1(open(src, "rb").read()).hexdigest()[:16]
+        ent = data.get(f"{workload}|{kernel}")
+        if ent and ent.get("kernels_sha1") == h:
+            return ent["bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
+    ap.add_argument("--max-sizes", type=int, default=0, help="use only the largest N sizes (profiling runs)")
+    ap.add_argument("--tune-db", default=os.path.join(HERE, "gpurun_out", "tune_db.jsonl"))
+    ap.add_argument("--no-tune", action="store_true", help="default parameters m = 2^ceil(log2 L), p = 1, q = 2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-comparator", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain device copy of 512 MiB first (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU only; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2306_10016_amd as hdc
+    import synth
+    from paper_2306_10016_amd import tune
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    dt = args.dtype
+    np_dt = np.complex128 if dt == "c128" else np.complex64
+    td = torch.complex128 if dt == "c128" else torch.complex64
+    eb = 16 if dt == "c128" else 8
+
+    if args.copy_calibration:
+        x = torch.empty(1 << 29, dtype=torch.uint8, device=dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+
+    sizes = sweep_sizes()
+    if args.max_sizes:
+        sizes = sizes[-args.max_sizes:]
+    n = len(sizes)
+    log(f"[bench] {n} sizes, {dt}, steps={args.steps} warmup={args.warmup}")
+
+    # resident inputs and outputs
+    t0 = time.time()
+    F, G, H = [], [], []
+    for i, L in enumerate(sizes):
+        f, g = synth.pair(L, 2, i, np_dt)
+        F.append(torch.from_numpy(f).to(dev))
+        G.append(torch.from_numpy(g).to(dev))
+        H.append(torch.empty(2 * L - 1, dtype=td, device=dev))
+    torch.cuda.synchronize()
+    log(f"[bench] inputs resident ({time.time() - t0:.1f} s)")
+
+    # parameters: experience autotuner (A1) with a persistent timing database
+    t0 = time.time()
+    db = tune.TuneDB(None if args.no_tune else args.tune_db, device=tune.device_name(), build=tune.build_hash())
+    tuner = tune.Tuner1D(db, reps=3, warmup=1)
+    params = []
+    for L in sizes:
+        M = 2 * L - 1
+        if args.no_tune:
+            params.append({"m": tune.pow2_ceil(L), "D": 2})
+        else:
+            params.append(tuner.a1(L, M, dt).params)
+    log(f"[bench] parameters chosen ({time.time() - t0:.1f} s)")
+
+    plans = [hdc.Plan(L, 2 * L - 1, p["m"], 0, 0, 1, p["D"], dt) for L, p in zip(sizes, params)]
+    ws_bytes = max(pl.workspace_bytes for pl in plans)
+    ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        for pl, f, g, h in zip(plans, F, G, H):
+            pl.convolve(f, g, h, ws=ws, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # dominant plan: the largest transform
+    big = max(range(n), key=lambda i: (plans[i].axes[0]["N"], sizes[i]))
+    with hdc.Profile(plans[big]) as prof:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed / args.steps * 1e3
+    value = n * args.steps / elapsed
+    summ = prof.summary()
+    dom = max(summ, key=lambda k: summ[k]["ms"])
+    d = summ[dom]
+    ax = plans[big].axes[0]
+    workload_tag = f"1D {dt} L={sizes[big]} m={ax['m']} p={ax['p']} q={ax['q']} D={ax['D']}"
+    achieved = d["GBps"]
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": load_traffic(dom, workload_tag),
+            "kernel": dom, "workload": workload_tag,
+            "mean_launch_ms": round(d["mean_ms"], 5), "algorithmic_bytes_per_launch": d["mean_bytes"],
+            "all_kernels": {k: {"mean_ms": round(v["mean_ms"], 5), "GBps": round(v["GBps"], 1),
+                                "launches_per_conv": v["launches"] // args.steps} for k, v in summ.items()}}
+    # whole-convolution bandwidth of the dominant plan against its compulsory bytes (2L + M) b
+    conv_ms = sum(v["ms"] for v in summ.values()) / args.steps
+    comp = (2 * sizes[big] + (2 * sizes[big] - 1)) * eb
+    roof["conv_ms"] = round(conv_ms, 4)
+    roof["conv_compulsory_GBps"] = round(comp / (conv_ms * 1e-3) / 1e9, 1)
+    log(f"[bench] {value:.1f} convs/s, {ms_per_step:.3f} ms/step; dominant {dom} {achieved:.0f} GB/s")
+
+    out = {"metric": METRIC, "value": round(value, 2), "unit": "convs/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64" if dt == "c128" else "f32",
+           "data": "synthetic",
+           "config": {"workload": f"1D hybrid dealiased convolution sweep, {n} sizes L in {{2^6..2^22}} U "
+                                  f"{{3^a5^b7^c in [64,4e6]}}, M=2L-1, {'complex128' if dt == 'c128' else 'complex64'}"
+                                  f", one convolution per size per step, autotuned (m,p,q,D)",
+                      "sizes": n, "complex": dt},
+           "roofline": roof}
+
+    # explicit-padding comparator on the same GPU (torch.fft = rocFFT), pad to N_e = 2L
+    if not args.no_comparator:
+        def explicit(f, g, L):
+            Ne = 2 * L
+            return torch.fft.ifft(torch.fft.fft(f, n=Ne) * torch.fft.fft(g, n=Ne))[: 2 * L - 1]
+        errs = []
+        for i, L in enumerate(sizes):
+            e = explicit(F[i], G[i], L)
+            errs.append(float(torch.linalg.vector_norm(H[i] - e) / torch.linalg.vector_norm(e)))
+        for _ in range(args.warmup):
+            for i, L in enumerate(sizes):
+                explicit(F[i], G[i], L)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for i, L in enumerate(sizes):
+                explicit(F[i], G[i], L)
+        torch.cuda.synchronize()
+        e_el = time.perf_counter() - t0
+        ev = n * args.steps / e_el
+        out["explicit_pad"] = {"value": round(ev, 2), "unit": "convs/s", "ms_per_step": round(e_el / args.steps * 1e3, 4),
+                               "impl": "torch.fft (rocFFT) pad to 2L, fft x2, product, ifft, slice"}
+        out["speedup_vs_explicit"] = round(value / ev, 3)
+        out["max_rel_err_vs_explicit"] = max(errs)
+        log(f"[bench] explicit pad {ev:.1f} convs/s; speedup {value / ev:.2f}; max rel err {max(errs):.2e}")
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sizes, dt)
+        log(f"[bench] cpu baseline {out['cpu_baseline']['value']:.2f} convs/s")
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

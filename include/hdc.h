@@ -166,6 +166,27 @@ hdc_status hdc_batch_destroy(hdc_batch_t batch);
 hdc_status hdc_time_convolve(hdc_plan_t plan, const void* f, const void* g, void* h, void* ws, hipStream_t stream,
                              int warmup, int reps, float* ms_out);
 
+/*
+ * Instrumented hdc_convolve: the same launches, each bracketed by HIP events on
+ * `stream`; synchronises the stream.  For launch i < min(*n_launches,
+ * max_launches): kinds[i] (0 fused, 1 forward column, 2 row, 3 backward
+ * column), ms[i] (event-measured duration) and bytes[i] (the launch's
+ * algorithmic HBM bytes: compulsory reads plus writes).  Any output array may
+ * be NULL.  *n_launches receives the total number of launches.
+ */
+hdc_status hdc_convolve_profiled(hdc_plan_t plan, const void* f, const void* g, void* h, void* ws, hipStream_t stream,
+                                 int max_launches, int* n_launches, int32_t* kinds, float* ms, double* bytes);
+
+/*
+ * Per-launch timing over a region of the caller's choosing: after
+ * hdc_profile_begin(filter), every kernel launched on this thread by
+ * hdc_convolve of plan `filter` (of any plan if filter is NULL) is bracketed
+ * by HIP events on its stream.  hdc_profile_end synchronises the device and
+ * reports the launches as hdc_convolve_profiled does.
+ */
+hdc_status hdc_profile_begin(hdc_plan_t filter);
+hdc_status hdc_profile_end(int max_launches, int* n_launches, int32_t* kinds, float* ms, double* bytes);
+
 /* Thread-local description of the last error (never NULL). */
 const char* hdc_last_error(void);
 

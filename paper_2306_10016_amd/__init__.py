@@ -198,6 +198,22 @@ class Plan:
                                           int(warmup), int(reps), ms))
         return list(ms)
 
+    KIND_NAMES = ("fused", "col_fwd", "row", "col_bwd")
+
+    def convolve_profiled(self, f, g, out, ws=None, stream=None, max_launches: int = 4096):
+        """hdc_convolve with per-launch HIP-event timing: list of (kind, ms, algorithmic bytes)."""
+        n = ctypes.c_int()
+        kinds = (ctypes.c_int32 * max_launches)()
+        ms = (ctypes.c_float * max_launches)()
+        by = (ctypes.c_double * max_launches)()
+        if ws is None:
+            ws = self.workspace(f.device)
+        check(self._lib.hdc_convolve_profiled(self._h, _ptr(f), _ptr(g), _ptr(out),
+                                              _ptr(ws) if ws is not None else None, _stream(stream),
+                                              max_launches, ctypes.byref(n), kinds, ms, by))
+        k = min(n.value, max_launches)
+        return [(self.KIND_NAMES[kinds[i]], ms[i], by[i]) for i in range(k)]
+
     def close(self):
         if getattr(self, "_h", None):
             self._lib.hdc_plan_destroy(self._h)
@@ -208,6 +224,43 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class Profile:
+    """Context manager around hdc_profile_begin/end: per-launch (kind, ms, bytes) of one plan."""
+
+    def __init__(self, plan: Optional[Plan] = None, max_launches: int = 1 << 16):
+        self.plan = plan
+        self.max = max_launches
+        self.launches = []
+
+    def __enter__(self):
+        check(lib().hdc_profile_begin(self.plan._h if self.plan is not None else None))
+        return self
+
+    def __exit__(self, *exc):
+        n = ctypes.c_int()
+        kinds = (ctypes.c_int32 * self.max)()
+        ms = (ctypes.c_float * self.max)()
+        by = (ctypes.c_double * self.max)()
+        check(lib().hdc_profile_end(self.max, ctypes.byref(n), kinds, ms, by))
+        k = min(n.value, self.max)
+        self.launches = [(Plan.KIND_NAMES[kinds[i]], ms[i], by[i]) for i in range(k)]
+        return False
+
+    def summary(self) -> dict:
+        """Per kernel kind: launches, total ms, mean ms, mean algorithmic bytes, GB/s."""
+        out = {}
+        for kind, ms, by in self.launches:
+            d = out.setdefault(kind, {"launches": 0, "ms": 0.0, "bytes": 0.0})
+            d["launches"] += 1
+            d["ms"] += ms
+            d["bytes"] += by
+        for d in out.values():
+            d["mean_ms"] = d["ms"] / d["launches"]
+            d["mean_bytes"] = d["bytes"] / d["launches"]
+            d["GBps"] = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
+        return out
 
 
 class Batch:

@@ -53,6 +53,12 @@ SIGNATURES = {
     "hdc_batch_info": [_P, _PI64, _PI64, _PI64],
     "hdc_batch_destroy": [_P],
     "hdc_time_convolve": [_P, _P, _P, _P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float)],
+    "hdc_convolve_profiled": [_P, _P, _P, _P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float),
+                              ctypes.POINTER(ctypes.c_double)],
+    "hdc_profile_begin": [_P],
+    "hdc_profile_end": [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int32),
+                        ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double)],
     "hdc_last_error": [],
     "hdc_version": [],
 }

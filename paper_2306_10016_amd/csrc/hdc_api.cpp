@@ -73,8 +73,46 @@ size_t device_lds_max() {
     return cached;
 }
 
-// LDS budget the fused kernel may use for one row (N values + q twiddles).
-constexpr size_t kFusedRowLds = 65536;
+// LDS budget the fused kernel may use for one row (q padded residues + q twiddles):
+// two such workgroups fit the 160 KiB of a gfx950 CU.
+constexpr size_t kFusedRowLds = 81920;
+
+int64_t round8(int64_t x) { return (x + 7) / 8 * 8; }
+
+// Optional per-launch timing: when a recorder is installed on this thread,
+// every kernel launch is bracketed by HIP events on its stream and its
+// algorithmic bytes (compulsory reads + writes of that launch) are noted.
+struct Recorder {
+    const void* filter = nullptr;  // record only launches of this plan (NULL: all)
+    std::vector<hipEvent_t> ev;
+    std::vector<int32_t> kind;
+    std::vector<double> bytes;
+};
+thread_local Recorder* g_rec = nullptr;
+thread_local const void* g_cur_plan = nullptr;  // plan whose launches are being issued
+
+struct LaunchScope {
+    bool on = false;
+    LaunchScope(hipStream_t s, int kind, double bytes) {
+        if (!g_rec) return;
+        if (g_rec->filter && g_rec->filter != g_cur_plan) return;
+        hipEvent_t a = nullptr, b = nullptr;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+        g_rec->ev.push_back(a);
+        g_rec->ev.push_back(b);
+        g_rec->kind.push_back(kind);
+        g_rec->bytes.push_back(bytes);
+        (void)hipEventRecord(a, s);
+        on = true;
+        end = b;
+        st = s;
+    }
+    ~LaunchScope() {
+        if (on) (void)hipEventRecord(end, st);
+    }
+    hipEvent_t end = nullptr;
+    hipStream_t st = nullptr;
+};
 
 }  // namespace
 
@@ -150,7 +188,7 @@ hdc_status derive_axis(int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, in
     o->m1 = m1;
     o->m2 = m2;
     const size_t b = elem_bytes(dtype);
-    const size_t fused_lds = (size_t)N * b + (size_t)q * 16 + 16;
+    const size_t fused_lds = (size_t)(q * padded_len(m)) * b + (size_t)q * 16 + 16;
     o->variant = (m <= kMaxFused && fused_lds <= kFusedRowLds) ? 0 : 1;
     o->reserved = 0;
     return HDC_OK;
@@ -182,7 +220,7 @@ hdc_status geometry(AxisPlan& A, bool outer) {
         int Dc = (int)std::min<int64_t>(d.D, d.q);
         Dc = std::max(1, std::min(Dc, 512 / tpf));
         const int rowthreads = tpf * Dc;
-        const size_t rowlds = (size_t)d.N * b;
+        const size_t rowlds = (size_t)(d.q * padded_len(d.m)) * b;
         int rpw = std::max(1, 256 / rowthreads);
         while (rpw > 1 && (size_t)rpw * rowlds > kFusedRowLds) rpw /= 2;
         A.Dc = Dc;
@@ -211,7 +249,7 @@ hdc_status geometry(AxisPlan& A, bool outer) {
         int rpw = std::max(1, 256 / tpf);
         A.r_rpw = rpw;
         A.r_threads = rpw * tpf;
-        A.r_lds = (size_t)rpw * d.m2 * b;
+        A.r_lds = (size_t)rpw * padded_len(d.m2) * b;
         if (A.r_lds > device_lds_max())
             return fail(HDC_ERR_UNSUPPORTED, "row stage m2 = %lld needs %zu bytes of LDS", (long long)d.m2, A.r_lds);
     }
@@ -303,6 +341,8 @@ hdc_status run_fused(const AxisPlan& A, const void* f, const void* g, void* h, i
     a.invN = 1.0 / (double)A.d.N;
     const int64_t blocks = ceil_div(nrows, A.f_rpw);
     if (blocks > 0x7fffffff) return fail(HDC_ERR_UNSUPPORTED, "too many rows");
+    const double eb = A.dbl ? 16.0 : 8.0;
+    LaunchScope ls(s, 0, eb * (double)nrows * ((a.same ? 1.0 : 2.0) * (double)A.d.L + (double)A.d.M));
     hipError_t e = launch_fused(A.dbl, (int)A.d.m, a, A.f_threads, blocks, A.f_lds, s);
     if (e != hipSuccess) return hip_fail(e, "fused convolution launch");
     return HDC_OK;
@@ -332,8 +372,10 @@ hdc_status run_col_fwd(const AxisPlan& A, const void* x, void* X, int64_t B, int
     a.hiprec = A.hiprec ? 1 : 0;
     a.tw = A.tw;
     a.tw1 = A.tw_m1;
-    const int64_t gx = (int64_t)a.ntiles * Dg;
+    const int64_t gx = round8((int64_t)a.ntiles * Dg);
     if (gx > 0x7fffffff || B > 65535) return fail(HDC_ERR_UNSUPPORTED, "column grid too large (B = %lld)", (long long)B);
+    const double eb = A.dbl ? 16.0 : 8.0;
+    LaunchScope ls(s, 1, eb * (double)B * (double)C1 * ((double)A.d.L + (double)(Dg * A.d.m)));
     hipError_t e = launch_col_fwd(A.dbl, (int)A.d.m1, a, A.cf_threads, gx, B, A.cf_lds, s);
     if (e != hipSuccess) return hip_fail(e, "column forward launch");
     return HDC_OK;
@@ -367,7 +409,9 @@ hdc_status run_col_bwd(const AxisPlan& A, const void* Y, void* h, int64_t B, int
     a.tw1 = A.tw_m1;
     a.invN = 1.0 / (double)A.d.N;
     if (B > 65535) return fail(HDC_ERR_UNSUPPORTED, "column grid too large");
-    hipError_t e = launch_col_bwd(A.dbl, (int)A.d.m1, a, A.cb_threads, a.ntiles, B, A.cb_lds, s);
+    const double eb = A.dbl ? 16.0 : 8.0;
+    LaunchScope ls(s, 3, eb * (double)B * (double)C1 * ((double)(Dg * A.d.m) + (accumulate ? 2.0 : 1.0) * (double)A.d.M));
+    hipError_t e = launch_col_bwd(A.dbl, (int)A.d.m1, a, A.cb_threads, round8(a.ntiles), B, A.cb_lds, s);
     if (e != hipSuccess) return hip_fail(e, "column backward launch");
     return HDC_OK;
 }
@@ -391,6 +435,9 @@ hdc_status run_rows(const AxisPlan& A, const void* a_, const void* b_, void* out
     a.tw = A.tw_m2;
     const int64_t blocks = ceil_div(nrows, A.r_rpw);
     if (blocks > 0x7fffffff) return fail(HDC_ERR_UNSUPPORTED, "too many rows");
+    const double eb = A.dbl ? 16.0 : 8.0;
+    const double nio = mode == MODE_CONV ? (a.same ? 2.0 : 3.0) : 2.0;
+    LaunchScope ls(s, 2, eb * nio * (double)nrows * (double)A.d.m2);
     hipError_t e = launch_row(A.dbl, (int)A.d.m2, a, A.r_threads, blocks, A.r_lds, s);
     if (e != hipSuccess) return hip_fail(e, "row launch");
     return HDC_OK;
@@ -619,6 +666,10 @@ hdc_status hdc_convolve(hdc_plan_t P, const void* f, const void* g, void* h, voi
     hdc_status st = check_ptrs(P, f, g, h);
     if (st != HDC_OK) return st;
     if (P->ws_bytes > 0 && !ws) return fail(HDC_ERR_WORKSPACE, "workspace of %zu bytes required", P->ws_bytes);
+    struct CurPlan {
+        explicit CurPlan(const void* p) { g_cur_plan = p; }
+        ~CurPlan() { g_cur_plan = nullptr; }
+    } cur(P);
     if (P->ndim == 1) {
         const AxisPlan& A = P->ax[0];
         return conv1d(A, f, g, h, 1, 0, 0, A.d.C, (char*)ws, elem(P), s);
@@ -686,6 +737,47 @@ hdc_status hdc_residues_natural(hdc_plan_t P, const void* F, int64_t r0, void* o
     hipError_t e = launch_natural(P->dtype == HDC_C128, F, out, Dg, d.m1, d.m2, d.C, s);
     if (e != hipSuccess) return hip_fail(e, "natural-order launch");
     return HDC_OK;
+}
+
+static thread_local Recorder* t_profile = nullptr;
+
+hdc_status hdc_profile_begin(hdc_plan_t filter) {
+    if (t_profile) return fail(HDC_ERR_INVALID_ARG, "profiling already active on this thread");
+    t_profile = new Recorder();
+    t_profile->filter = filter;
+    g_rec = t_profile;
+    return HDC_OK;
+}
+
+hdc_status hdc_profile_end(int max_launches, int* n_launches, int32_t* kinds, float* ms, double* bytes) {
+    if (!t_profile) return fail(HDC_ERR_INVALID_ARG, "profiling not active");
+    Recorder* rec = t_profile;
+    t_profile = nullptr;
+    g_rec = nullptr;
+    hipError_t e = hipDeviceSynchronize();
+    const int n = (int)rec->kind.size();
+    if (n_launches) *n_launches = n;
+    for (int i = 0; i < n && i < max_launches; ++i) {
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, rec->ev[2 * i], rec->ev[2 * i + 1]);
+        if (kinds) kinds[i] = rec->kind[i];
+        if (ms) ms[i] = t;
+        if (bytes) bytes[i] = rec->bytes[i];
+    }
+    for (auto& x : rec->ev) (void)hipEventDestroy(x);
+    delete rec;
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    return HDC_OK;
+}
+
+hdc_status hdc_convolve_profiled(hdc_plan_t P, const void* f, const void* g, void* h, void* ws, hipStream_t s,
+                                 int max_launches, int* n_launches, int32_t* kinds, float* ms, double* bytes) {
+    if (!n_launches || max_launches < 0) return fail(HDC_ERR_INVALID_ARG, "bad profiling arguments");
+    hdc_status st = hdc_profile_begin(nullptr);
+    if (st != HDC_OK) return st;
+    st = hdc_convolve(P, f, g, h, ws, s);
+    hdc_status st2 = hdc_profile_end(max_launches, n_launches, kinds, ms, bytes);
+    return st != HDC_OK ? st : st2;
 }
 
 hdc_status hdc_time_convolve(hdc_plan_t P, const void* f, const void* g, void* h, void* ws, hipStream_t s, int warmup,

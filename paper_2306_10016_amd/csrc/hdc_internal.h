@@ -98,6 +98,9 @@ hipError_t launch_mul(bool dbl, void* F, const void* G, int64_t n, hipStream_t s
 hipError_t launch_natural(bool dbl, const void* F, void* out, int64_t Dg, int64_t m1, int64_t m2, int64_t C,
                           hipStream_t s);
 
+// Slots of a contiguous n-point LDS buffer (one pad slot per 8 values).
+inline int64_t padded_len(int64_t n) { return n + (n >> 3); }
+
 // Points per thread of the Stockham transforms for size n.
 inline int ppt_for(int n) { return n >= 8 ? 8 : n; }
 

@@ -138,10 +138,23 @@ __device__ __forceinline__ void dft_r(cplx<T>* x) {
     }
 }
 
+// LDS address of transform position `pos`.  Contiguous layouts (PAD) insert
+// one slot after every 8 values, which keeps the stride-R writes of the first
+// pass and the stride-Ns writes of later passes on distinct banks; column
+// layouts (tile columns side by side) are already conflict-free.
+template <bool PAD>
+__device__ __forceinline__ int lds_at(int pos, int bstride) {
+    return PAD ? pos + (pos >> 3) : pos * bstride;
+}
+
+// Padded length of a contiguous n-point LDS buffer.
+__host__ __device__ constexpr int padded(int n) { return n + (n >> 3); }
+
 // One radix-R pass over sub-transforms of length Ns -> Ns*R.  Register v[w]
-// holds position lane + w*TPF.  Non-final passes write to LDS (element
-// stride bstride); the final pass leaves its outputs in v.
-template <typename T, int NSZ, int R, int SIGN, bool LAST>
+// holds position lane + w*TPF.  Non-final passes write to LDS; the final
+// pass leaves its outputs in v.  Twiddles zeta^{i k} come from three table
+// loads (i = 1, 2, 4) and four products.
+template <typename T, int NSZ, int R, int SIGN, bool LAST, bool PAD>
 __device__ __forceinline__ void stock_pass(cplx<T> (&v)[FP<NSZ>::PPT], int Ns, cplx<T>* buf, int bstride, int lane,
                                            const cplx<T>* tw, bool act) {
     constexpr int PPT = FP<NSZ>::PPT;
@@ -155,13 +168,24 @@ __device__ __forceinline__ void stock_pass(cplx<T> (&v)[FP<NSZ>::PPT], int Ns, c
 #pragma unroll
         for (int i = 0; i < R; ++i) x[i] = v[u + i * NB];
         if (Ns > 1) {
-            const int step = NSZ / (Ns * R);
-#pragma unroll
-            for (int i = 1; i < R; ++i) {
-                cplx<T> w = tw[i * k * step];
-                if (SIGN < 0) w.y = -w.y;
-                x[i] = x[i] * w;
+            const int e1 = k * (NSZ / (Ns * R));
+            cplx<T> w[8];
+            w[1] = tw[e1];
+            if (SIGN < 0) w[1].y = -w[1].y;
+            if constexpr (R >= 4) {
+                w[2] = tw[2 * e1];
+                if (SIGN < 0) w[2].y = -w[2].y;
+                w[3] = w[1] * w[2];
             }
+            if constexpr (R == 8) {
+                w[4] = tw[4 * e1];
+                if (SIGN < 0) w[4].y = -w[4].y;
+                w[5] = w[1] * w[4];
+                w[6] = w[2] * w[4];
+                w[7] = w[3] * w[4];
+            }
+#pragma unroll
+            for (int i = 1; i < R; ++i) x[i] = x[i] * w[i];
         }
         dft_r<R, SIGN>(x);
         if constexpr (LAST) {
@@ -171,13 +195,13 @@ __device__ __forceinline__ void stock_pass(cplx<T> (&v)[FP<NSZ>::PPT], int Ns, c
             if (act) {
                 const int base = (j - k) * R + k;
 #pragma unroll
-                for (int a = 0; a < R; ++a) buf[(base + a * Ns) * bstride] = x[a];
+                for (int a = 0; a < R; ++a) buf[lds_at<PAD>(base + a * Ns, bstride)] = x[a];
             }
         }
     }
 }
 
-template <typename T, int NSZ>
+template <typename T, int NSZ, bool PAD>
 __device__ __forceinline__ void lds_reload(cplx<T> (&v)[FP<NSZ>::PPT], const cplx<T>* buf, int bstride, int lane,
                                            bool act) {
     constexpr int PPT = FP<NSZ>::PPT;
@@ -185,31 +209,40 @@ __device__ __forceinline__ void lds_reload(cplx<T> (&v)[FP<NSZ>::PPT], const cpl
     __syncthreads();
     if (act) {
 #pragma unroll
-        for (int w = 0; w < PPT; ++w) v[w] = buf[(lane + w * Q) * bstride];
+        for (int w = 0; w < PPT; ++w) v[w] = buf[lds_at<PAD>(lane + w * Q, bstride)];
     }
     __syncthreads();
 }
 
 // NSZ-point DFT with zeta_NSZ^{SIGN}, registers in and out (positions lane + w*TPF).
 // Every thread of the workgroup must call it (it contains barriers).
-template <typename T, int NSZ, int SIGN>
+template <typename T, int NSZ, int SIGN, bool PAD>
 __device__ __forceinline__ void fft_regs(cplx<T> (&v)[FP<NSZ>::PPT], cplx<T>* buf, int bstride, int lane,
                                          const cplx<T>* tw, bool act) {
     using P = FP<NSZ>;
     if constexpr (P::NPASS == 1) {
-        stock_pass<T, NSZ, P::R0, SIGN, true>(v, 1, buf, bstride, lane, tw, act);
+        stock_pass<T, NSZ, P::R0, SIGN, true, PAD>(v, 1, buf, bstride, lane, tw, act);
     } else if constexpr (P::NPASS > 1) {
-        stock_pass<T, NSZ, P::R0, SIGN, false>(v, 1, buf, bstride, lane, tw, act);
+        stock_pass<T, NSZ, P::R0, SIGN, false, PAD>(v, 1, buf, bstride, lane, tw, act);
         int Ns = P::R0;
 #pragma unroll
         for (int ps = 1; ps < P::NPASS - 1; ++ps) {
-            lds_reload<T, NSZ>(v, buf, bstride, lane, act);
-            stock_pass<T, NSZ, 8, SIGN, false>(v, Ns, buf, bstride, lane, tw, act);
+            lds_reload<T, NSZ, PAD>(v, buf, bstride, lane, act);
+            stock_pass<T, NSZ, 8, SIGN, false, PAD>(v, Ns, buf, bstride, lane, tw, act);
             Ns *= 8;
         }
-        lds_reload<T, NSZ>(v, buf, bstride, lane, act);
-        stock_pass<T, NSZ, 8, SIGN, true>(v, Ns, buf, bstride, lane, tw, act);
+        lds_reload<T, NSZ, PAD>(v, buf, bstride, lane, act);
+        stock_pass<T, NSZ, 8, SIGN, true, PAD>(v, Ns, buf, bstride, lane, tw, act);
     }
+}
+
+// Workgroup -> task map that keeps consecutive tasks on one XCD: workgroups
+// are dealt to the 8 XCDs round-robin, so block b runs on XCD b % 8; XCD x
+// takes the contiguous task range [x*per, (x+1)*per).  Neighbouring column
+// tiles then share that XCD's L2 (partial cache lines, re-read inputs).
+__device__ __forceinline__ int xcd_task(int bid, int nblk) {
+    const int per = nblk >> 3;
+    return (bid & 7) * per + (bid >> 3);
 }
 
 __device__ __forceinline__ int64_t row_base(const RowAddr& a, int64_t row) {
@@ -233,8 +266,10 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
     constexpr int TPF = P::TPF;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* smem = reinterpret_cast<cplx<T>*>(smem_raw);
-    double2* twq = reinterpret_cast<double2*>(smem_raw + ((size_t)a.rpw * a.N * sizeof(cplx<T>) + 15) / 16 * 16);
+    double2* twq =
+        reinterpret_cast<double2*>(smem_raw + ((size_t)a.rpw * a.q * padded(MSZ) * sizeof(cplx<T>) + 15) / 16 * 16);
 
+    constexpr int RS = padded(MSZ);  // LDS slots per residue
     const int rowthreads = TPF * a.Dc;
     const int tid = threadIdx.x;
     const int rloc = tid / rowthreads;
@@ -265,13 +300,13 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
     const cplx<T>* g = reinterpret_cast<const cplx<T>*>(a.g) + fbase;
     cplx<T>* h = reinterpret_cast<cplx<T>*>(a.h) + hbase;
     const cplx<T>* twm = reinterpret_cast<const cplx<T>*>(a.twm);
-    cplx<T>* U = smem + (size_t)rloc * a.N;
+    cplx<T>* U = smem + (size_t)rloc * a.q * RS;
     const T invN = (T)a.invN;
 
     for (int rb = 0; rb < a.q; rb += a.Dc) {
         const int r = rb + grp;
         const bool act = rowok && r < a.q;
-        cplx<T>* buf = U + (size_t)(act ? r : 0) * MSZ;
+        cplx<T>* buf = U + (size_t)(act ? r : 0) * RS;
 
         // block sums of eq. (1) for f and g, straight into the first radix pass
         cplx<T> F[PPT], G[PPT];
@@ -303,21 +338,21 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
             F[v] = mul_tw<false>(F[v], z, a.hiprec);
             if (!a.same) G[v] = mul_tw<false>(G[v], z, a.hiprec);
         }
-        fft_regs<T, MSZ, +1>(F, buf, 1, lane, twm, act);
+        fft_regs<T, MSZ, +1, true>(F, buf, 1, lane, twm, act);
         if (!a.same) {
-            fft_regs<T, MSZ, +1>(G, buf, 1, lane, twm, act);
+            fft_regs<T, MSZ, +1, true>(G, buf, 1, lane, twm, act);
 #pragma unroll
             for (int v = 0; v < PPT; ++v) F[v] = F[v] * G[v];
         } else {
 #pragma unroll
             for (int v = 0; v < PPT; ++v) F[v] = F[v] * F[v];
         }
-        fft_regs<T, MSZ, -1>(F, buf, 1, lane, twm, act);
+        fft_regs<T, MSZ, -1, true>(F, buf, 1, lane, twm, act);
         if (act) {
 #pragma unroll
             for (int v = 0; v < PPT; ++v) {
                 const int s = lane + v * TPF;
-                buf[s] = scale(mul_tw<true>(F[v], tw_n(a.tw, ru * (uint32_t)s), a.hiprec), invN);
+                buf[lds_at<true>(s, 1)] = scale(mul_tw<true>(F[v], tw_n(a.tw, ru * (uint32_t)s), a.hiprec), invN);
             }
         }
     }
@@ -330,7 +365,7 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
         cplx<T> acc = mk<T>(0, 0);
         int e = 0;  // (t r) mod q
         for (int r = 0; r < a.q; ++r) {
-            acc = acc + mul_tw<true>(U[(size_t)r * MSZ + s], twq[e], false);
+            acc = acc + mul_tw<true>(U[(size_t)r * RS + lds_at<true>(s, 1)], twq[e], false);
             e += t;
             if (e >= a.q) e -= a.q;
         }
@@ -355,17 +390,20 @@ __global__ void __launch_bounds__(1024) k_col_fwd(ColFwdArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
 
+    // task = (tile, residue) with the residue fastest: the Dg residues of a
+    // tile run back to back on one XCD and re-read its input from that L2
+    const int task = xcd_task(blockIdx.x, gridDim.x);
+    if (task >= a.ntiles * a.Dg) return;
+    const int tl = task / a.Dg;
+    const int d = task - tl * a.Dg;
     const int tile = a.tile;
     const int tid = threadIdx.x;
     const int cc = tid % tile;
     const int lane = tid / tile;
-    const int d = blockIdx.x % a.Dg;
-    const int tl = blockIdx.x / a.Dg;
     const int64_t b = blockIdx.y;
     const int cp = tl * tile + cc;
     const bool ok = cp < a.Ccols;
     const int s2 = ok ? cp / a.C1 : 0;
-    const int r = a.r0 + d;
     int64_t xoff = b * a.in_bs;
     int64_t L = a.L;
     if (a.desc != nullptr) {
@@ -373,38 +411,50 @@ __global__ void __launch_bounds__(1024) k_col_fwd(ColFwdArgs a) {
         L = a.desc[2 * b + 1];
     }
     const cplx<T>* x = reinterpret_cast<const cplx<T>*>(a.x) + xoff;
+    cplx<T>* X = reinterpret_cast<cplx<T>*>(a.X) + b * a.out_bs;
+    const cplx<T>* tw1 = reinterpret_cast<const cplx<T>*>(a.tw1);
 
-    cplx<T> w[PPT];
+    // block t, point v of this thread: x[(t*m1 + s1)*Ccols + cp], zero beyond L
+#define HDC_LOAD(t, v)                                                                        \
+    ((ok && (((int64_t)(t) * M1 + lane + (v) * TPF) * a.m2 + s2) < L)                         \
+         ? x[((int64_t)(t) * M1 + lane + (v) * TPF) * a.Ccols + cp]                           \
+         : mk<T>(0, 0))
+
+    {
+        const int r = a.r0 + d;
+        cplx<T> w[PPT];
 #pragma unroll
-    for (int v = 0; v < PPT; ++v) w[v] = mk<T>(0, 0);
-    for (int t = 0; t < a.p; ++t) {
-        const uint32_t e = (uint32_t)(((int64_t)r * t) % a.q) * (uint32_t)a.m;
-        const double2 z = tw_n(a.tw, e);
+        for (int v = 0; v < PPT; ++v) w[v] = HDC_LOAD(0, v);
+        int e = r;  // (r t) mod q for t = 1
+        if (e >= a.q) e -= a.q;
+        for (int t = 1; t < a.p; ++t) {
+            const double2 z = tw_n(a.tw, (uint32_t)e * (uint32_t)a.m);
+            e += r;
+            if (e >= a.q) e -= a.q;
 #pragma unroll
-        for (int v = 0; v < PPT; ++v) {
-            const int s1 = lane + v * TPF;
-            const int64_t j = ((int64_t)t * M1 + s1) * a.m2 + s2;
-            if (ok && j < L) {
-                const cplx<T> xv = x[((int64_t)t * M1 + s1) * a.Ccols + cp];
-                w[v] = w[v] + mul_tw<false>(xv, z, a.hiprec);
+            for (int v = 0; v < PPT; ++v) {
+                w[v] = w[v] + mul_tw<false>(HDC_LOAD(t, v), z, a.hiprec);
             }
         }
-    }
+        if (r != 0) {
 #pragma unroll
-    for (int v = 0; v < PPT; ++v) {
-        const int s1 = lane + v * TPF;
-        const uint32_t s = (uint32_t)s1 * (uint32_t)a.m2 + (uint32_t)s2;
-        w[v] = mul_tw<false>(w[v], tw_n(a.tw, (uint32_t)r * s), a.hiprec);
-    }
-    fft_regs<T, M1, +1>(w, lds + cc, tile, lane, reinterpret_cast<const cplx<T>*>(a.tw1), true);
-    cplx<T>* X = reinterpret_cast<cplx<T>*>(a.X) + b * a.out_bs;
+            for (int v = 0; v < PPT; ++v) {
+                const int s1 = lane + v * TPF;
+                const uint32_t s = (uint32_t)s1 * (uint32_t)a.m2 + (uint32_t)s2;
+                w[v] = mul_tw<false>(w[v], tw_n(a.tw, (uint32_t)r * s), a.hiprec);
+            }
+        }
+        fft_regs<T, M1, +1, false>(w, lds + cc, tile, lane, tw1, true);
 #pragma unroll
-    for (int v = 0; v < PPT; ++v) {
-        const int l1 = lane + v * TPF;
-        cplx<T> o = w[v];
-        if (a.m2 > 1) o = mul_tw<false>(o, tw_n(a.tw, (uint32_t)l1 * (uint32_t)s2 * (uint32_t)a.q), a.hiprec);
-        if (ok) X[((int64_t)d * M1 + l1) * a.Ccols + cp] = o;
+        for (int v = 0; v < PPT; ++v) {
+            const int l1 = lane + v * TPF;
+            cplx<T> o = w[v];
+            if (a.m2 > 1 && s2 != 0)
+                o = mul_tw<false>(o, tw_n(a.tw, (uint32_t)l1 * (uint32_t)s2 * (uint32_t)a.q), a.hiprec);
+            if (ok) X[((int64_t)d * M1 + l1) * a.Ccols + cp] = o;
+        }
     }
+#undef HDC_LOAD
 }
 
 template <typename T, int M1, int DMAX>
@@ -415,12 +465,14 @@ __global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
 
+    const int tl = xcd_task(blockIdx.x, gridDim.x);
+    if (tl >= a.ntiles) return;
     const int tile = a.tile;
     const int tid = threadIdx.x;
     const int cc = tid % tile;
     const int lane = tid / tile;
     const int64_t b = blockIdx.y;
-    const int cp = blockIdx.x * tile + cc;
+    const int cp = tl * tile + cc;
     const bool ok = cp < a.Ccols;
     const int s2 = ok ? cp / a.C1 : 0;
     int64_t hoff = b * a.out_bs;
@@ -446,11 +498,11 @@ __global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
                 for (int v = 0; v < PPT; ++v) {
                     const int l1 = lane + v * TPF;
                     cplx<T> y = ok ? Y[((int64_t)d * M1 + l1) * a.Ccols + cp] : mk<T>(0, 0);
-                    if (a.m2 > 1)
+                    if (a.m2 > 1 && s2 != 0)
                         y = mul_tw<true>(y, tw_n(a.tw, (uint32_t)l1 * (uint32_t)s2 * (uint32_t)a.q), a.hiprec);
                     w[v] = y;
                 }
-                fft_regs<T, M1, -1>(w, lds + cc, tile, lane, tw1, true);
+                fft_regs<T, M1, -1, false>(w, lds + cc, tile, lane, tw1, true);
                 const int r = a.r0 + d;
 #pragma unroll
                 for (int v = 0; v < PPT; ++v) {
@@ -502,7 +554,7 @@ __global__ void __launch_bounds__(512) k_row(RowArgs a) {
     const int lane = tid - rloc * TPF;
     const int64_t row = (int64_t)blockIdx.x * a.rpw + rloc;
     const bool ok = row < a.nrows;
-    cplx<T>* buf = smem + (size_t)rloc * MSZ;
+    cplx<T>* buf = smem + (size_t)rloc * padded(MSZ);
     const int64_t base = row_base(a.addr, ok ? row : 0);
     const int64_t es = a.addr.es;
     const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(a.tw);
@@ -513,9 +565,9 @@ __global__ void __launch_bounds__(512) k_row(RowArgs a) {
 #pragma unroll
     for (int w = 0; w < PPT; ++w) v[w] = ok ? A[(int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
     if (a.mode == MODE_INV) {
-        fft_regs<T, MSZ, -1>(v, buf, 1, lane, tw, ok);
+        fft_regs<T, MSZ, -1, true>(v, buf, 1, lane, tw, ok);
     } else {
-        fft_regs<T, MSZ, +1>(v, buf, 1, lane, tw, ok);
+        fft_regs<T, MSZ, +1, true>(v, buf, 1, lane, tw, ok);
         if (a.mode == MODE_CONV) {
             if (a.same) {
 #pragma unroll
@@ -525,11 +577,11 @@ __global__ void __launch_bounds__(512) k_row(RowArgs a) {
                 cplx<T> u[PPT];
 #pragma unroll
                 for (int w = 0; w < PPT; ++w) u[w] = ok ? B[(int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
-                fft_regs<T, MSZ, +1>(u, buf, 1, lane, tw, ok);
+                fft_regs<T, MSZ, +1, true>(u, buf, 1, lane, tw, ok);
 #pragma unroll
                 for (int w = 0; w < PPT; ++w) v[w] = v[w] * u[w];
             }
-            fft_regs<T, MSZ, -1>(v, buf, 1, lane, tw, ok);
+            fft_regs<T, MSZ, -1, true>(v, buf, 1, lane, tw, ok);
         }
     }
     if (ok) {

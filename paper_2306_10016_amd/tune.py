@@ -1,0 +1,316 @@
+"""Experience-based autotuner for the hybrid-dealiasing parameters (section 4).
+
+Two searches, both scoring a parameter set by the measured time of the whole
+convolution (hdc_time_convolve: HIP events, median of the repetitions):
+
+* **A0** (section 4.1): exhaustive grid over the candidate FFT sizes m (each
+  fixing p = ceil(L/m), q = ceil(M/m)) and residues-per-pass D.  For N-D
+  problems each axis is searched on its own with the other axes held at
+  their defaults (the per-dimension separability argument of section 4.1).
+* **A1** (section 4.2, "experience"): (1) reuse the best entry of the timing
+  database for the same problem; (2) seed with the scale-free class (p, D)
+  that won on the nearest already-tuned problem, including the rectangle ->
+  square reuse of section 4.2's third heuristic; (3) a random subset of the
+  remaining candidates (random search); (4) local refinement around the best
+  so far (the neighbouring m and D), which biases sampling toward the region
+  that scored well (the Bayesian-search idea, without a surrogate model).
+
+All timings are appended to a JSON-lines database (section 5.1's "cache all
+the results"), keyed by problem, parameters, device and library build, so a
+killed run resumes where it stopped.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import math
+import os
+import random
+import time
+from dataclasses import dataclass, field
+from typing import Callable, Dict, List, Optional, Sequence, Tuple
+
+P_CLASSES = (1, 2, 3, 4, 6, 8, 12, 16)
+
+
+def pow2_ceil(x: int) -> int:
+    m = 1
+    while m < x:
+        m <<= 1
+    return m
+
+
+def candidates_1d(L: int, M: int, max_m: int = 1 << 22, p_classes: Sequence[int] = P_CLASSES,
+                  d_choices: str = "q") -> List[Tuple[int, int]]:
+    """(m, D) candidates: power-of-two m whose p = ceil(L/m) is in ``p_classes``,
+    plus the explicit-padding case q = 1 when m >= M fits.  ``d_choices`` = "q"
+    (all residues in one pass) or "all" (also D = 1, 2, 4, ...)."""
+    out = []
+    m = 1
+    while m <= max_m:
+        p = -(-L // m)
+        q = -(-M // m)
+        if p in p_classes or q == 1:
+            Ds = [q]
+            if d_choices == "all":
+                d = 1
+                while d < q:
+                    Ds.append(d)
+                    d *= 2
+            for D in sorted(set(Ds)):
+                out.append((m, D))
+        m <<= 1
+    return out
+
+
+def scale_class(L: int, M: int, m: int, D: int) -> Tuple[int, int]:
+    """Scale-free class of a parameter set: (p, D relative to q) -- section 6.4's rays."""
+    p = -(-L // m)
+    q = -(-M // m)
+    return (p, 0 if D >= q else D)
+
+
+def m_for_class(L: int, p: int) -> int:
+    """Smallest power-of-two m with ceil(L/m) <= p."""
+    return pow2_ceil(-(-L // p))
+
+
+def build_hash() -> str:
+    from ._lib import LIB_PATH
+    try:
+        st = os.stat(LIB_PATH)
+        return hashlib.sha1(f"{st.st_size}:{int(st.st_mtime)}".encode()).hexdigest()[:12]
+    except OSError:
+        return "none"
+
+
+def device_name() -> str:
+    try:
+        import torch
+        return torch.cuda.get_device_name(0)
+    except Exception:
+        return "unknown"
+
+
+def problem_key(L, M, dtype: str, batch: int = 1) -> str:
+    Ls = list(L) if isinstance(L, (list, tuple)) else [int(L)]
+    Ms = list(M) if isinstance(M, (list, tuple)) else [int(M)]
+    return json.dumps({"L": Ls, "M": Ms, "dtype": dtype, "batch": int(batch)}, sort_keys=True)
+
+
+class TuneDB:
+    """Append-only JSON-lines timing database."""
+
+    def __init__(self, path: Optional[str] = None, device: Optional[str] = None, build: Optional[str] = None):
+        self.path = path
+        self.device = device or "any"
+        self.build = build or "any"
+        self.rows: List[dict] = []
+        if path and os.path.exists(path):
+            with open(path) as fh:
+                for line in fh:
+                    line = line.strip()
+                    if not line:
+                        continue
+                    try:
+                        self.rows.append(json.loads(line))
+                    except json.JSONDecodeError:
+                        continue  # a line cut short by a kill
+
+    def add(self, key: str, params: dict, ms: float, extra: Optional[dict] = None):
+        row = {"key": key, "params": params, "ms": float(ms), "device": self.device, "build": self.build,
+               "t": time.time()}
+        if extra:
+            row.update(extra)
+        self.rows.append(row)
+        if self.path:
+            d = os.path.dirname(self.path)
+            if d:
+                os.makedirs(d, exist_ok=True)
+            with open(self.path, "a") as fh:
+                fh.write(json.dumps(row) + "\n")
+
+    def _mine(self, r):
+        return r.get("device") == self.device and r.get("build") == self.build
+
+    def timings(self, key: str) -> Dict[str, float]:
+        out = {}
+        for r in self.rows:
+            if r["key"] == key and self._mine(r):
+                pk = json.dumps(r["params"], sort_keys=True)
+                out[pk] = min(out.get(pk, math.inf), r["ms"])
+        return out
+
+    def best(self, key: str) -> Optional[Tuple[dict, float]]:
+        t = self.timings(key)
+        if not t:
+            return None
+        pk = min(t, key=lambda k: (t[k], k))
+        return json.loads(pk), t[pk]
+
+    def keys(self):
+        return sorted({r["key"] for r in self.rows if self._mine(r)})
+
+
+@dataclass
+class TuneResult:
+    params: dict
+    ms: float
+    table: List[Tuple[dict, float]] = field(default_factory=list)
+    source: str = "search"
+
+
+def _pick(table: List[Tuple[dict, float]]) -> Tuple[dict, float]:
+    """argmin with the tie rule: within 1 %, prefer the smaller m, then the smaller D."""
+    best_ms = min(ms for _, ms in table)
+    near = [(p, ms) for p, ms in table if ms <= best_ms * 1.01]
+    near.sort(key=lambda x: (x[0]["m"], x[0]["D"], x[1]))
+    return near[0]
+
+
+class Tuner1D:
+    """Tunes a 1D problem (L, M, dtype) on the GPU through the C-ABI."""
+
+    def __init__(self, db: Optional[TuneDB] = None, reps: int = 5, warmup: int = 2, max_m: int = 1 << 22,
+                 timer: Optional[Callable[[int, int, int, int, str], float]] = None, seed: int = 0):
+        self.db = db or TuneDB(None)
+        self.reps = reps
+        self.warmup = warmup
+        self.max_m = max_m
+        self.timer = timer  # (L, M, m, D, dtype) -> ms ; defaults to the GPU timer
+        self.rng = random.Random(seed)
+        self._bufs = {}
+
+    # -- timing backends
+    def _gpu_time(self, L, M, m, D, dtype):
+        import torch
+        from . import Plan, torch_dtype, dtype_code
+        key = (L, M, dtype)
+        if key not in self._bufs:
+            self._bufs.clear()
+            td = torch_dtype(dtype_code(dtype))
+            f = torch.randn(L, dtype=td, device="cuda")
+            g = torch.randn(L, dtype=td, device="cuda")
+            h = torch.empty(M, dtype=td, device="cuda")
+            self._bufs[key] = (f, g, h)
+        f, g, h = self._bufs[key]
+        plan = Plan(L, M, m, 0, 0, 1, D, dtype)
+        ws = _shared_ws(plan.workspace_bytes)
+        ms = plan.time_convolve(f, g, h, ws=ws, warmup=self.warmup, reps=self.reps)
+        plan.close()
+        ms.sort()
+        return ms[len(ms) // 2]
+
+    def measure(self, L, M, m, D, dtype) -> float:
+        if self.timer is not None:
+            return float(self.timer(L, M, m, D, dtype))
+        return self._gpu_time(L, M, m, D, dtype)
+
+    def _run(self, key, L, M, dtype, cands, table, seen):
+        for (m, D) in cands:
+            params = {"m": int(m), "D": int(D)}
+            pk = json.dumps(params, sort_keys=True)
+            if pk in seen:
+                continue
+            ms = self.measure(L, M, m, D, dtype)
+            seen[pk] = ms
+            table.append((params, ms))
+            self.db.add(key, params, ms)
+
+    # -- A0: exhaustive grid
+    def a0(self, L: int, M: int, dtype: str = "c128", d_choices: str = "all") -> TuneResult:
+        key = problem_key(L, M, dtype)
+        table: List[Tuple[dict, float]] = []
+        seen = dict(self.db.timings(key))
+        for pk, ms in seen.items():
+            table.append((json.loads(pk), ms))
+        self._run(key, L, M, dtype, candidates_1d(L, M, self.max_m, d_choices=d_choices), table, seen)
+        p, ms = _pick(table)
+        return TuneResult(p, ms, table, "A0")
+
+    # -- A1: experience
+    def a1(self, L: int, M: int, dtype: str = "c128", n_random: int = 2, reuse: bool = True) -> TuneResult:
+        key = problem_key(L, M, dtype)
+        if reuse:
+            hit = self.db.best(key)
+            if hit is not None:
+                return TuneResult(hit[0], hit[1], [hit], "db")
+        cands = candidates_1d(L, M, self.max_m, d_choices="q")
+        table: List[Tuple[dict, float]] = []
+        seen: Dict[str, float] = {}
+        # (2) experience: the winning (p, D) class of the nearest tuned problems of this dtype
+        seeds = []
+        for cls in self.experience_classes(L, dtype):
+            m = m_for_class(L, cls[0])
+            if m <= self.max_m:
+                q = -(-M // m)
+                seeds.append((m, q if cls[1] == 0 else min(cls[1], q)))
+        if not seeds:
+            seeds = [(pow2_ceil(L), 2)]
+        self._run(key, L, M, dtype, seeds, table, seen)
+        # (3) random search over the rest
+        rest = [c for c in cands if json.dumps({"m": c[0], "D": c[1]}, sort_keys=True) not in seen]
+        self.rng.shuffle(rest)
+        self._run(key, L, M, dtype, rest[:n_random], table, seen)
+        # (4) local refinement around the incumbent
+        for _ in range(3):
+            best, _ms = _pick(table)
+            m0, D0 = best["m"], best["D"]
+            neigh = []
+            for m in (m0 // 2, m0 * 2):
+                if 1 <= m <= self.max_m:
+                    q = -(-M // m)
+                    p = -(-L // m)
+                    if q >= p:
+                        neigh.append((m, q))
+            q0 = -(-M // m0)
+            if D0 < q0:
+                neigh.append((m0, q0))
+            before = len(table)
+            self._run(key, L, M, dtype, neigh, table, seen)
+            if len(table) == before:
+                break
+        p, ms = _pick(table)
+        return TuneResult(p, ms, table, "A1")
+
+    def experience_classes(self, L: int, dtype: str, k: int = 2):
+        """Winning (p, D) classes of the k tuned 1D problems of this dtype nearest in log2 L."""
+        scored = []
+        for key in self.db.keys():
+            d = json.loads(key)
+            if d["dtype"] != dtype or len(d["L"]) != 1 or d["batch"] != 1:
+                continue
+            b = self.db.best(key)
+            if b is None:
+                continue
+            Lk, Mk = d["L"][0], d["M"][0]
+            scored.append((abs(math.log2(Lk) - math.log2(L)), scale_class(Lk, Mk, b[0]["m"], b[0]["D"])))
+        scored.sort()
+        out = []
+        for _, c in scored:
+            if c not in out:
+                out.append(c)
+            if len(out) >= k:
+                break
+        return out
+
+
+_WS = {"buf": None}
+
+
+def _shared_ws(nbytes: int):
+    """One growing device workspace shared by every timed plan."""
+    import torch
+    if nbytes == 0:
+        return None
+    b = _WS["buf"]
+    if b is None or b.numel() < nbytes:
+        _WS["buf"] = None
+        b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        _WS["buf"] = b
+    return b
+
+
+def regret(chosen_ms: float, best_ms: float) -> float:
+    """T(chosen) / T(exhaustive best) - 1."""
+    return chosen_ms / best_ms - 1.0
