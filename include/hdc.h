@@ -143,8 +143,10 @@ hdc_status hdc_residues_natural(hdc_plan_t plan, const void* F, int64_t r0, void
  * f and g at offsets sum_{j<i} L[j], h at sum_{j<i} M[j].  Problems are grouped
  * into buckets that share (m, p, q, D); `bucket_m` (length n, may be NULL) gives
  * the FFT size chosen for each problem, 0 meaning the built-in default.
- * The first hdc_batch_convolve on a stream captures the launches in a HIP graph;
- * later calls with the same stream and buffers replay it.
+ * The first hdc_batch_convolve captures the launches in a HIP graph on a private
+ * stream of the batch; later calls with the same buffers replay it.  Every
+ * call is ordered after the work already on `stream`, and work enqueued on
+ * `stream` afterwards runs after it.
  */
 hdc_status hdc_batch_plan(hdc_batch_t* out, int64_t n, const int64_t* L, const int64_t* M, const int64_t* bucket_m,
                           hdc_dtype dtype);

@@ -840,9 +840,12 @@ struct hdc_batch_s {
     // captured graph and the arguments it was captured with
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
-    hipStream_t g_stream = nullptr;
     const void *g_f = nullptr, *g_g = nullptr;
     void *g_h = nullptr, *g_ws = nullptr;
+    // the graph is captured on and replayed from a private stream (default
+    // priority), ordered after and before the caller's stream with events
+    hipStream_t side = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
 
 namespace {
@@ -1021,7 +1024,12 @@ hdc_status hdc_batch_convolve_eager(hdc_batch_t Bt, const void* f, const void* g
 hdc_status hdc_batch_convolve(hdc_batch_t Bt, const void* f, const void* g, void* h, void* ws, hipStream_t s) {
     hdc_status st = batch_args(Bt, f, g, h, ws);
     if (st != HDC_OK) return st;
-    const bool hit = Bt->exec && Bt->g_stream == s && Bt->g_f == f && Bt->g_g == g && Bt->g_h == h && Bt->g_ws == ws;
+    if (!Bt->side) {
+        HIP_TRY(hipStreamCreateWithFlags(&Bt->side, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&Bt->ev_in, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&Bt->ev_out, hipEventDisableTiming));
+    }
+    const bool hit = Bt->exec && Bt->g_f == f && Bt->g_g == g && Bt->g_h == h && Bt->g_ws == ws;
     if (!hit) {
         if (Bt->exec) {
             (void)hipGraphExecDestroy(Bt->exec);
@@ -1031,10 +1039,10 @@ hdc_status hdc_batch_convolve(hdc_batch_t Bt, const void* f, const void* g, void
             (void)hipGraphDestroy(Bt->graph);
             Bt->graph = nullptr;
         }
-        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        st = batch_launch(Bt, f, g, h, ws, s);
+        HIP_TRY(hipStreamBeginCapture(Bt->side, hipStreamCaptureModeThreadLocal));
+        st = batch_launch(Bt, f, g, h, ws, Bt->side);
         hipGraph_t graph = nullptr;
-        hipError_t e = hipStreamEndCapture(s, &graph);
+        hipError_t e = hipStreamEndCapture(Bt->side, &graph);
         if (st != HDC_OK) {
             if (graph) (void)hipGraphDestroy(graph);
             return st;
@@ -1046,13 +1054,16 @@ hdc_status hdc_batch_convolve(hdc_batch_t Bt, const void* f, const void* g, void
             return hip_fail(e, "hipGraphInstantiate");
         }
         Bt->graph = graph;
-        Bt->g_stream = s;
         Bt->g_f = f;
         Bt->g_g = g;
         Bt->g_h = h;
         Bt->g_ws = ws;
     }
-    HIP_TRY(hipGraphLaunch(Bt->exec, s));
+    HIP_TRY(hipEventRecord(Bt->ev_in, s));
+    HIP_TRY(hipStreamWaitEvent(Bt->side, Bt->ev_in, 0));
+    HIP_TRY(hipGraphLaunch(Bt->exec, Bt->side));
+    HIP_TRY(hipEventRecord(Bt->ev_out, Bt->side));
+    HIP_TRY(hipStreamWaitEvent(s, Bt->ev_out, 0));
     return HDC_OK;
 }
 
@@ -1060,6 +1071,12 @@ hdc_status hdc_batch_destroy(hdc_batch_t Bt) {
     if (!Bt) return HDC_OK;
     if (Bt->exec) (void)hipGraphExecDestroy(Bt->exec);
     if (Bt->graph) (void)hipGraphDestroy(Bt->graph);
+    if (Bt->side) {
+        (void)hipStreamSynchronize(Bt->side);
+        (void)hipStreamDestroy(Bt->side);
+    }
+    if (Bt->ev_in) (void)hipEventDestroy(Bt->ev_in);
+    if (Bt->ev_out) (void)hipEventDestroy(Bt->ev_out);
     if (Bt->block) (void)hipFree(Bt->block);
     delete Bt;
     return HDC_OK;

@@ -63,10 +63,11 @@ def test_derive_clamps_D():
 
 
 def test_variant_choice_by_lds_budget():
-    # whole transform fits the fused kernel's LDS budget (N values of 8 or 16 bytes within 64 KiB)
+    # the fused kernel holds q residues of m padded values (+1 slot per 8) within 80 KiB of LDS
     assert hdc.derive(1024, 2047, 256, dtype="c128")["variant"] == 0
-    assert hdc.derive(2048, 4095, 4096, dtype="c128")["variant"] == 1
-    assert hdc.derive(2048, 4095, 4096, dtype="c64")["variant"] == 0
+    assert hdc.derive(4096, 8191, 4096, dtype="c128")["variant"] == 1
+    assert hdc.derive(4096, 8191, 4096, dtype="c64")["variant"] == 0
+    assert hdc.derive(8192, 16383, 8192, dtype="c64")["variant"] == 1
     assert hdc.derive(1 << 20, (1 << 21) - 1, 1 << 20, dtype="c64")["variant"] == 1
 
 

@@ -1,0 +1,132 @@
+"""GPU parity of the N-D passes (section 3.6) and of uneven-length batches."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import TOL, NP_DT, inputs, rel, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+hdc = pytest.importorskip("paper_2306_10016_amd")
+
+
+def _nd(L, M, m, dtype, D=None, cfg=300, idx=0, full=True, nsample=48):
+    say(f"nd L={L} M={M} m={m} D={D} {dtype}")
+    f, g, f64, g64 = inputs(tuple(L), cfg, idx, dtype)
+    plan = hdc.Plan.nd(L, M, m, D=D, dtype=dtype)
+    h = to_host(plan.convolve(to_dev(f), to_dev(g)))
+    assert h.shape == tuple(M)
+    if full:
+        ref = oracle.padded_nd(f64, g64, M)
+        err = rel(h, ref)
+    else:
+        r = synth.rng(cfg, idx, 5)
+        tot = int(np.prod(M))
+        ks = np.unique(np.concatenate([[0, tot - 1], r.integers(0, tot, nsample)]))
+        ref = oracle.direct_nd_sampled(f64, g64, M, ks)
+        err = rel(h.reshape(-1)[ks], ref)
+    say(f"   rel={err:.3e}")
+    assert err <= TOL[dtype], err
+    return plan, h
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("L,extra,m,D", [((6, 9), (0, 0), (4, 8), None), ((16, 24), (0, 3), (8, 16), None),
+                                         ((16, 24), (0, 0), (8, 16), (1, 2)), ((37, 50), (5, 0), (16, 32), (3, 0)),
+                                         ((1, 50), (0, 0), (1, 64), None), ((50, 1), (0, 0), (64, 1), None),
+                                         ((33, 700), (0, 0), (64, 1024), (1, 1))])
+def test_2d(L, extra, m, D, dtype):
+    M = tuple(2 * a - 1 + e for a, e in zip(L, extra))
+    _nd(L, M, m, dtype, D=D, idx=L[0])
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("L,m,D", [((8, 12, 10), (4, 8, 8), None), ((5, 6, 7), (2, 4, 8), (1, 2, 0)),
+                                   ((9, 4, 33), (16, 2, 64), None)])
+def test_3d(L, m, D, dtype):
+    M = tuple(2 * a - 1 for a in L)
+    _nd(L, M, m, dtype, D=D, idx=L[2])
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("L,m", [((256, 256), (256, 256)), ((512, 512), (512, 512)), ((1024, 1024), (1024, 1024)),
+                                 ((2048, 512), (1024, 512)), ((1024, 4096), (1024, 4096))])
+def test_2d_workload_sizes_sampled(L, m, dtype):
+    M = tuple(2 * a - 1 for a in L)
+    _nd(L, M, m, dtype, idx=L[0] + L[1], full=False)
+
+
+def test_3d_256_sampled():
+    L = (256, 256, 256)
+    _nd(L, tuple(2 * a - 1 for a in L), (256, 256, 256), "c64", idx=256, full=False, nsample=24)
+
+
+def test_2d_separable():
+    """f = a (x) b, g = c (x) d  =>  h = (a*c) (x) (b*d)."""
+    a, c = synth.uniform_complex(40, 301, 0, 0), synth.uniform_complex(40, 301, 1, 0)
+    b, d = synth.uniform_complex(70, 301, 2, 0), synth.uniform_complex(70, 301, 3, 0)
+    f, g = np.outer(a, b), np.outer(c, d)
+    plan = hdc.Plan.nd((40, 70), (79, 139), (32, 64), dtype="c128")
+    h = to_host(plan.convolve(to_dev(f), to_dev(g)))
+    want = np.outer(oracle.padded_1d(a, c, 79), oracle.padded_1d(b, d, 139))
+    assert rel(h, want) <= 1e-12
+
+
+def test_2d_autoconvolution():
+    f, _, f64, _ = inputs((60, 45), 302, 0, "c128")
+    plan = hdc.Plan.nd((60, 45), (119, 89), (64, 32), dtype="c128")
+    ft = to_dev(f)
+    h = to_host(plan.convolve(ft, ft))
+    assert rel(h, oracle.padded_nd(f64, f64, (119, 89))) <= 1e-12
+
+
+def _batch(Ls, dtype, bucket_m=None, graph=True, cfg=310, check_idx=None, replays=1):
+    Ls = [int(x) for x in Ls]
+    Ms = [2 * x - 1 for x in Ls]
+    fs = [synth.uniform_complex(L, cfg, i, 0, NP_DT[dtype]) for i, L in enumerate(Ls)]
+    gs = [synth.uniform_complex(L, cfg, i, 1, NP_DT[dtype]) for i, L in enumerate(Ls)]
+    fp, gp = to_dev(np.concatenate(fs)), to_dev(np.concatenate(gs))
+    B = hdc.Batch(Ls, bucket_m=bucket_m, dtype=dtype)
+    say(f"batch n={len(Ls)} buckets={B.n_buckets} {dtype} graph={graph}")
+    import torch
+    out = torch.empty(B.total_M, dtype=fp.dtype, device="cuda")
+    offs = np.concatenate([[0], np.cumsum(Ms)])
+    idx = range(len(Ls)) if check_idx is None else check_idx
+    refs = {i: oracle.padded_1d(fs[i].astype(np.complex128), gs[i].astype(np.complex128), Ms[i]) for i in idx}
+    for rep in range(replays):
+        out.fill_(float("nan"))
+        B.convolve(fp, gp, out, graph=graph)
+        h = to_host(out)
+        tmp = torch.ones(1000, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert float(tmp) == 1000.0
+        for i in idx:
+            err = rel(h[offs[i]:offs[i + 1]], refs[i])
+            assert err <= TOL[dtype], (rep, i, Ls[i], err)
+    return B
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_small_eager_and_graph(dtype):
+    Ls = synth.batch_lengths(64, 3, 13, cfg=311)
+    _batch(Ls, dtype, graph=False)
+    _batch(Ls, dtype, graph=True, replays=3)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_bucket_override(dtype):
+    Ls = synth.batch_lengths(40, 4, 12, cfg=312)
+    bm = [max(1, int(2 ** np.floor(np.log2(L))) // 2) for L in Ls]  # p = 2 or 3 classes
+    _batch(Ls, dtype, bucket_m=bm, graph=True, replays=2)
+
+
+def test_batch_edge_lengths():
+    _batch([1, 2, 3, 1, 64, 65, 4096, 4097, 9000], "c128", graph=True, replays=2)
+
+
+def test_batch_full_workload_sampled():
+    """4096 complex64 problems, L log-uniform in [64, 65536]; 40 problems checked in full."""
+    Ls = synth.batch_lengths(4096, 6, 16, cfg=3)
+    check = sorted(set(synth.rng(3, 0, 6).integers(0, 4096, 36).tolist()) | {int(np.argmax(Ls)), int(np.argmin(Ls))})
+    _batch(Ls, "c64", graph=True, cfg=3, check_idx=check, replays=2)
