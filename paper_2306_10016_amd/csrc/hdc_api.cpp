@@ -116,6 +116,8 @@ struct LaunchScope {
 
 }  // namespace
 
+hdc_status set_error(hdc_status st, const char* msg) { return fail(st, "%s", msg); }
+
 // ------------------------------------------------------------------ plans --
 
 struct AxisPlan {

@@ -4,6 +4,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/hdc.h"
+
+// Records the thread-local message returned by hdc_last_error(); returns st.
+hdc_status set_error(hdc_status st, const char* msg);
+
 namespace hdc {
 
 // zeta_N^e = lo[e & mask] * hi[e >> lgB]  (two-level table of exp(+2 pi i e / N), FP64).

@@ -1,0 +1,326 @@
+"""Learned parameter predictor (section 4.3 and sections 5-6): a small MLP that
+maps a problem axis to the scale-free class (p, D) of its best parameters.
+
+* Training data come from the project's own tuner: problems of at most 2^20
+  elements (1D with 1, 4 or 16 copies, 2D squares and rectangles, 3D boxes,
+  sides of the form 2^a 3^b 5^c 7^d, complex64 and complex128) are tuned one
+  axis at a time (the separable search of section 4.1) and every timing is
+  cached in the JSON-lines database (section 5.1).
+* Classes are scale-free (p, D-mode): p = ceil(L/m) in {1,2,3,4,6,8,12,16},
+  D-mode "all residues in one pass" or "one residue per pass".  A class maps
+  back to m = the smallest power of two with ceil(L/m) <= p, which is what
+  lets a network trained on sides <= 1024 speak about sides of 8192 (the
+  "three rays" of m against L in section 6.4.1 are classes of this kind).
+* Inference is per axis.  A prediction whose softmax confidence is below a
+  threshold falls back to exhaustive per-axis tuning (A0).
+* Regret = T(predicted parameters) / T(best of the exhaustive search) - 1.
+
+Run ``python -m paper_2306_10016_amd.predict --out results.json`` on a GPU to
+build the database, train the network with the HIP kernels, and evaluate it
+on 4096^2, 8192^2 and 256^3 complex64 problems.
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import math
+import os
+import sys
+import time
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import tune
+
+P_CLASSES = tune.P_CLASSES
+CLASSES: List[Tuple[int, int]] = [(p, dm) for p in P_CLASSES for dm in (0, 1)]  # dm 0: D = q, 1: D = 1
+D_IN = 11
+HIDDEN = (128, 128, 128)
+MAX_OUTER_M = 1024  # column-stage limit of the outer N-D axes
+
+
+def features(Ls: Sequence[int], axis: int, dtype: str, batch: int = 1) -> np.ndarray:
+    """log2 L of this axis, log2 L of the other axes (0 if absent), one-hot axis,
+    one-hot ndim, dtype bit, log2 batch; log-sizes scaled by 1/16."""
+    nd = len(Ls)
+    others = [Ls[a] for a in range(nd) if a != axis]
+    others += [1] * (2 - len(others))
+    v = [math.log2(Ls[axis]) / 16.0, math.log2(others[0]) / 16.0, math.log2(others[1]) / 16.0]
+    v += [1.0 if axis == a else 0.0 for a in range(3)]
+    v += [1.0 if nd == d else 0.0 for d in (1, 2, 3)]
+    v += [1.0 if dtype == "c128" else 0.0, math.log2(max(batch, 1)) / 16.0]
+    return np.asarray(v, np.float32)
+
+
+def class_index(L: int, M: int, m: int, D: int) -> int:
+    p = -(-L // m)
+    q = -(-M // m)
+    # map p to the class whose m is the same power of two
+    best = None
+    for ci, (pc, dm) in enumerate(CLASSES):
+        if tune.m_for_class(L, pc) == m and dm == (0 if D >= q else 1):
+            best = ci
+            break
+    if best is None:
+        pc = min(P_CLASSES, key=lambda c: abs(math.log2(c) - math.log2(p)))
+        best = CLASSES.index((pc, 0 if D >= q else 1))
+    return best
+
+
+def params_of(ci: int, L: int, M: int, outer: bool) -> Tuple[int, int]:
+    """(m, D) for class ci on an axis of length L (outer axes keep m <= 1024)."""
+    pc, dm = CLASSES[ci]
+    m = tune.m_for_class(L, pc)
+    if outer:
+        while m > MAX_OUTER_M:
+            m //= 2
+    q = -(-M // m)
+    p = -(-L // m)
+    while q < p:  # keep q >= p
+        m *= 2
+        q, p = -(-M // m), -(-L // m)
+    return m, (q if dm == 0 else 1)
+
+
+def axis_candidates(L: int, M: int, outer: bool) -> List[Tuple[int, int]]:
+    out = []
+    for ci in range(len(CLASSES)):
+        c = params_of(ci, L, M, outer)
+        if c not in out:
+            out.append(c)
+    return out
+
+
+# ----------------------------------------------------------- N-D timing --
+
+class NDTimer:
+    """Times hdc_convolve of an N-D (or 1D with copies) problem on the GPU."""
+
+    def __init__(self, reps: int = 3, warmup: int = 1):
+        self.reps = reps
+        self.warmup = warmup
+        self._key = None
+        self._bufs = None
+
+    def _buffers(self, Ls, Ms, dtype, batch):
+        import torch
+        from . import torch_dtype, dtype_code
+        key = (tuple(Ls), tuple(Ms), dtype, batch)
+        if key != self._key:
+            self._bufs = None
+            td = torch_dtype(dtype_code(dtype))
+            n_in = int(np.prod(Ls)) * batch
+            n_out = int(np.prod(Ms)) * batch
+            self._bufs = (torch.randn(n_in, dtype=td, device="cuda"), torch.randn(n_in, dtype=td, device="cuda"),
+                          torch.empty(n_out, dtype=td, device="cuda"))
+            self._key = key
+        return self._bufs
+
+    def __call__(self, Ls, Ms, ms, Ds, dtype, batch=1) -> float:
+        from . import Plan
+        f, g, h = self._buffers(Ls, Ms, dtype, batch)
+        if len(Ls) == 1:
+            plan = Plan(Ls[0], Ms[0], ms[0], 0, 0, batch, Ds[0], dtype)
+        else:
+            plan = Plan.nd(Ls, Ms, ms, D=Ds, dtype=dtype)
+        ws = tune._shared_ws(plan.workspace_bytes)
+        t = plan.time_convolve(f, g, h, ws=ws, warmup=self.warmup, reps=self.reps)
+        plan.close()
+        t.sort()
+        return t[len(t) // 2]
+
+
+def default_params(Ls, Ms):
+    """The method without the predictor: p = 1 (m = next power of two >= L), all residues at once."""
+    out = []
+    for a, (L, M) in enumerate(zip(Ls, Ms)):
+        out.append(params_of(CLASSES.index((1, 0)), L, M, outer=a < len(Ls) - 1))
+    return out
+
+
+def tune_separable(Ls, Ms, dtype, timer, batch=1, db: Optional[tune.TuneDB] = None):
+    """A0 per axis (section 4.1): each axis searched with the others at their defaults.
+    Returns (per-axis best (m, D), per-axis tables, time of the combined choice)."""
+    base = default_params(Ls, Ms)
+    best, tables = [], []
+    for a in range(len(Ls)):
+        rows = []
+        for c in axis_candidates(Ls[a], Ms[a], outer=a < len(Ls) - 1):
+            cur = list(base)
+            cur[a] = c
+            try:
+                t = timer(Ls, Ms, [x[0] for x in cur], [x[1] for x in cur], dtype, batch)
+            except Exception:
+                continue
+            rows.append((c, t))
+            if db is not None:
+                db.add(tune.problem_key(list(Ls), list(Ms), dtype, batch),
+                       {"axis": a, "m": [x[0] for x in cur], "D": [x[1] for x in cur]}, t)
+        rows.sort(key=lambda r: (r[1], r[0][0], r[0][1]))
+        best.append(rows[0][0])
+        tables.append(rows)
+    t = timer(Ls, Ms, [b[0] for b in best], [b[1] for b in best], dtype, batch)
+    return best, tables, t
+
+
+def tune_joint(Ls, Ms, dtype, timer, batch=1):
+    """Exhaustive search over the product of the per-axis candidate sets (the regret judge).
+    For 3D problems the product is limited to the all-residues mode (D = q) on every
+    axis, which keeps it at (#m)^3 combinations."""
+    cands = [axis_candidates(L, M, outer=a < len(Ls) - 1) for a, (L, M) in enumerate(zip(Ls, Ms))]
+    if len(Ls) == 3:
+        cands = [[c for c in cs if c[1] == -(-M // c[0])] for cs, M in zip(cands, Ms)]
+    rows = []
+    for combo in itertools.product(*cands):
+        try:
+            t = timer(Ls, Ms, [c[0] for c in combo], [c[1] for c in combo], dtype, batch)
+        except Exception:
+            continue
+        rows.append((list(combo), t))
+    rows.sort(key=lambda r: r[1])
+    return rows
+
+
+# ------------------------------------------------------------ predictor --
+
+class Predictor:
+    def __init__(self, seed: int = 0, threshold: float = 0.0):
+        from .mlp import MLP
+        self.net = MLP([D_IN, *HIDDEN, len(CLASSES)], seed=seed)
+        self.threshold = threshold
+        self.history: List[float] = []
+
+    def fit(self, X: np.ndarray, y: np.ndarray, epochs: int = 300, lr: float = 2e-3, batch: int = 128):
+        self.history = self.net.train(X, y, epochs=epochs, batch=batch, lr=lr)
+        return self.history
+
+    def predict_axes(self, Ls, Ms, dtype, batch=1):
+        """Per-axis (m, D), the per-axis confidence, and the class indices."""
+        X = np.stack([features(Ls, a, dtype, batch) for a in range(len(Ls))])
+        P = self.net.predict_proba(X)
+        out, conf, cls = [], [], []
+        for a in range(len(Ls)):
+            ci = int(np.argmax(P[a]))  # ties: lowest class index
+            out.append(params_of(ci, Ls[a], Ms[a], outer=a < len(Ls) - 1))
+            conf.append(float(P[a, ci]))
+            cls.append(ci)
+        return out, conf, cls
+
+    def choose(self, Ls, Ms, dtype, timer, batch=1):
+        """Predicted parameters, or exhaustive per-axis tuning when confidence is low."""
+        params, conf, _ = self.predict_axes(Ls, Ms, dtype, batch)
+        if min(conf) < self.threshold:
+            best, _, _ = tune_separable(Ls, Ms, dtype, timer, batch)
+            return best, "fallback"
+        return params, "predicted"
+
+
+def smooth_sides(lo: int, hi: int) -> List[int]:
+    out = []
+    for a in range(0, 21):
+        for b in range(0, 13):
+            for c in range(0, 9):
+                for d in range(0, 8):
+                    v = 2 ** a * 3 ** b * 5 ** c * 7 ** d
+                    if lo <= v <= hi:
+                        out.append(v)
+    return sorted(set(out))
+
+
+def training_problems(seed: int = 0, max_elems: int = 1 << 20):
+    """(Ls, batch, dtype) training problems of at most max_elems elements."""
+    r = np.random.Generator(np.random.PCG64(np.random.SeedSequence([230610016, 5, seed])))
+    probs = []
+    s1 = smooth_sides(64, max_elems)
+    for dt in ("c64", "c128"):
+        for L in r.choice(s1, size=min(40, len(s1)), replace=False):
+            for batch in (1, 4, 16):
+                if L * batch <= max_elems:
+                    probs.append(([int(L)], batch, dt))
+        s2 = smooth_sides(16, 1024)
+        for _ in range(36):
+            x, y = int(r.choice(s2)), int(r.choice(s2))
+            if x * y <= max_elems:
+                probs.append(([x, y], 1, dt))
+        for L in (128, 256, 512, 1024):  # squares and L_y = 32 rectangles (section 6.4)
+            probs.append(([L, L], 1, dt))
+            probs.append(([L, 32], 1, dt))
+        s3 = smooth_sides(8, 101)
+        for _ in range(12):
+            dims = [int(r.choice(s3)) for _ in range(3)]
+            if int(np.prod(dims)) <= max_elems:
+                probs.append((dims, 1, dt))
+    return probs
+
+
+EVAL_PROBLEMS = [([4096, 4096], "c64"), ([8192, 8192], "c64"), ([256, 256, 256], "c64")]
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--db", default="gpurun_out/predictor_db.jsonl")
+    ap.add_argument("--out", default="gpurun_out/predictor.json")
+    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--max-problems", type=int, default=0)
+    args = ap.parse_args(argv)
+    timer = NDTimer(reps=3, warmup=1)
+    db = tune.TuneDB(args.db, device=tune.device_name(), build=tune.build_hash())
+    probs = training_problems()
+    if args.max_problems:
+        probs = probs[:args.max_problems]
+    X, y, meta = [], [], []
+    t0 = time.time()
+    for i, (Ls, batch, dt) in enumerate(probs):
+        Ms = [2 * L - 1 for L in Ls]
+        best, tables, _ = tune_separable(Ls, Ms, dt, timer, batch, db)
+        for a in range(len(Ls)):
+            X.append(features(Ls, a, dt, batch))
+            y.append(class_index(Ls[a], Ms[a], best[a][0], best[a][1]))
+        meta.append({"L": Ls, "batch": batch, "dtype": dt, "best": best})
+        if i % 25 == 0:
+            print(f"[predict] tuned {i + 1}/{len(probs)} ({time.time() - t0:.0f} s)", flush=True)
+    X = np.stack(X)
+    y = np.asarray(y, np.int32)
+    pred = Predictor(seed=0)
+    hist = pred.fit(X, y, epochs=args.epochs)
+    train_acc = float(np.mean(np.argmax(pred.net.predict_proba(X), 1) == y))
+    print(f"[predict] trained: loss {hist[0]:.3f} -> {hist[-1]:.3f}, train accuracy {train_acc:.3f}", flush=True)
+    results = {"train": {"problems": len(probs), "rows": int(len(y)), "loss_first": hist[0], "loss_last": hist[-1],
+                         "accuracy": train_acc, "class_counts": np.bincount(y, minlength=len(CLASSES)).tolist()},
+               "eval": []}
+    for Ls, dt in EVAL_PROBLEMS:
+        Ms = [2 * L - 1 for L in Ls]
+        joint = tune_joint(Ls, Ms, dt, timer)
+        best_p, best_t = joint[0]
+        params, conf, cls = pred.predict_axes(Ls, Ms, dt)
+        t_pred = timer(Ls, Ms, [p[0] for p in params], [p[1] for p in params], dt)
+        dflt = default_params(Ls, Ms)
+        t_def = timer(Ls, Ms, [p[0] for p in dflt], [p[1] for p in dflt], dt)
+        sep, _, t_sep = tune_separable(Ls, Ms, dt, timer)
+        # section 6.4's heuristic: tune the L_x x 32 rectangle and reuse its x-axis choice
+        # (same L_x, so the same m and D apply); the y axis keeps the default
+        rect, t_rect = None, None
+        if len(Ls) == 2:
+            rb, _, _ = tune_separable([Ls[0], 32], [Ms[0], 63], dt, timer)
+            rect = [rb[0], dflt[1]]
+            t_rect = timer(Ls, Ms, [p[0] for p in rect], [p[1] for p in rect], dt)
+        ent = {"L": Ls, "dtype": dt, "joint_best": {"params": best_p, "ms": best_t}, "joint_candidates": len(joint),
+               "predicted": {"params": params, "confidence": conf, "ms": t_pred,
+                             "regret": tune.regret(t_pred, best_t)},
+               "default": {"params": dflt, "ms": t_def, "regret": tune.regret(t_def, best_t)},
+               "separable_A0": {"params": sep, "ms": t_sep, "regret": tune.regret(t_sep, best_t)}}
+        if t_rect is not None:
+            ent["rect32"] = {"params": rect, "ms": t_rect, "regret": tune.regret(t_rect, best_t)}
+        results["eval"].append(ent)
+        print(f"[predict] {Ls} {dt}: best {best_t:.3f} ms, predicted {t_pred:.3f} ms "
+              f"(regret {ent['predicted']['regret']:.3f}), default regret {ent['default']['regret']:.3f}", flush=True)
+    os.makedirs(os.path.dirname(args.out) or ".", exist_ok=True)
+    json.dump(results, open(args.out, "w"), indent=1)
+    print(json.dumps({"eval": [{"L": e["L"], "regret": round(e["predicted"]["regret"], 4),
+                                "default_regret": round(e["default"]["regret"], 4)} for e in results["eval"]]}))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,120 @@
+"""Host logic of the autotuner (section 4) and of the predictor's encoding, run
+against a deterministic synthetic cost model instead of GPU timings.  The
+timings themselves are machine-dependent: parity unpinned for those; here the
+searches are pinned to the known argmin of the synthetic model."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import paper_2306_10016_amd as hdc
+from paper_2306_10016_amd import predict, tune
+
+
+def cost_model(L, M, m, D, dtype):
+    """A bowl in log2(m) with its minimum at m* = 2^ceil(log2 L) / 4, plus a penalty for D < q."""
+    q = -(-M // m)
+    mstar = tune.pow2_ceil(L) / 4
+    return 1.0 + (math.log2(m) - math.log2(mstar)) ** 2 + (0.5 if D < q else 0.0)
+
+
+@pytest.mark.parametrize("L", [37, 1000, 4096, 100000, 3 ** 13])
+def test_candidates_are_admissible(L):
+    M = 2 * L - 1
+    cands = tune.candidates_1d(L, M, d_choices="all")
+    assert cands
+    for m, D in cands:
+        d = hdc.derive(L, M, m, D=D)
+        assert d["p"] * m >= L and d["q"] * m >= M and d["q"] >= d["p"]
+        assert d["p"] in tune.P_CLASSES or d["q"] == 1
+
+
+def test_a0_finds_the_model_argmin():
+    t = tune.Tuner1D(tune.TuneDB(None), timer=cost_model)
+    r = t.a0(5000, 9999, "c64")
+    assert r.params["m"] == tune.pow2_ceil(5000) // 4 and r.params["D"] == -(-9999 // r.params["m"])
+    assert r.source == "A0"
+
+
+def test_a1_uses_experience_and_matches_a0_with_fewer_timings():
+    calls = []
+
+    def counting(L, M, m, D, dt):
+        calls.append((L, m, D))
+        return cost_model(L, M, m, D, dt)
+    db = tune.TuneDB(None)
+    t = tune.Tuner1D(db, timer=counting, seed=1)
+    for L in (2000, 4000, 8000):  # experience accumulates
+        t.a1(L, 2 * L - 1, "c64")
+    calls.clear()
+    r = t.a1(16000, 31999, "c64")
+    a0 = tune.Tuner1D(tune.TuneDB(None), timer=cost_model).a0(16000, 31999, "c64")
+    assert r.params == a0.params
+    assert len(calls) < len(tune.candidates_1d(16000, 31999, d_choices="all"))
+
+
+def test_db_reuse_and_resume(tmp_path):
+    path = str(tmp_path / "db.jsonl")
+    t = tune.Tuner1D(tune.TuneDB(path, device="dev", build="b1"), timer=cost_model)
+    r1 = t.a1(3000, 5999, "c128")
+    # a run killed mid-line leaves a partial record: the reader skips it
+    with open(path, "a") as fh:
+        fh.write('{"key": "trunc')
+    db2 = tune.TuneDB(path, device="dev", build="b1")
+    r2 = tune.Tuner1D(db2, timer=lambda *a: pytest.fail("should not time")).a1(3000, 5999, "c128")
+    assert r2.source == "db" and r2.params == r1.params
+    # another build does not reuse the timings
+    db3 = tune.TuneDB(path, device="dev", build="b2")
+    assert db3.best(tune.problem_key(3000, 5999, "c128")) is None
+
+
+def test_tie_rule_prefers_smaller_m_then_D():
+    table = [({"m": 64, "D": 2}, 1.000), ({"m": 32, "D": 4}, 1.005), ({"m": 32, "D": 1}, 1.009),
+             ({"m": 16, "D": 8}, 1.5)]
+    p, ms = tune._pick(table)
+    assert p == {"m": 32, "D": 1}
+
+
+def test_regret():
+    assert tune.regret(1.1, 1.0) == pytest.approx(0.1)
+    assert tune.regret(1.0, 1.0) == 0.0
+
+
+@pytest.mark.parametrize("L", [64, 1000, 8192, 100000])
+def test_predictor_classes_round_trip(L):
+    M = 2 * L - 1
+    seen = set()
+    for ci, (pc, dm) in enumerate(predict.CLASSES):
+        m, D = predict.params_of(ci, L, M, outer=False)
+        q = -(-M // m)
+        assert -(-L // m) <= pc
+        assert D == (q if dm == 0 else 1)
+        if (m, D) in seen:
+            continue
+        seen.add((m, D))
+        back = predict.class_index(L, M, m, D)
+        assert predict.params_of(back, L, M, outer=False) == (m, D)
+
+
+def test_outer_axes_respect_column_limit():
+    for ci in range(len(predict.CLASSES)):
+        m, _ = predict.params_of(ci, 8192, 16383, outer=True)
+        assert m <= predict.MAX_OUTER_M
+
+
+def test_features_encoding():
+    f = predict.features([4096, 256], 1, "c128", batch=4)
+    assert f.shape == (predict.D_IN,)
+    assert f[0] == pytest.approx(8 / 16) and f[1] == pytest.approx(12 / 16) and f[2] == 0.0
+    assert list(f[3:6]) == [0, 1, 0] and list(f[6:9]) == [0, 1, 0]
+    assert f[9] == 1.0 and f[10] == pytest.approx(2 / 16)
+
+
+def test_training_problems_within_bound():
+    probs = predict.training_problems()
+    assert len(probs) > 100
+    for Ls, batch, dt in probs:
+        assert int(np.prod(Ls)) * batch <= (1 << 20)
+        assert dt in ("c64", "c128") and 1 <= len(Ls) <= 3
