@@ -234,10 +234,14 @@ hdc_status geometry(AxisPlan& A, bool outer) {
     {
         const int ppt = ppt_for((int)d.m1);
         const int tpf = (int)d.m1 / ppt;
+        // the backward kernel keeps at most 64 KiB of LDS per workgroup; narrower
+        // tiles still fetch whole cache lines once, because the XCD map runs
+        // neighbouring tiles on the same L2
         A.cf_tile = tile_for(tpf, tmin, 1024);
         A.cf_threads = A.cf_tile * tpf;
         A.cf_lds = (size_t)d.m1 * A.cf_tile * b;
         A.cb_tile = tile_for(tpf, tmin, 512);
+        while (A.cb_tile > 1 && (size_t)d.m1 * A.cb_tile * b > 65536) A.cb_tile /= 2;
         A.cb_threads = A.cb_tile * tpf;
         A.cb_lds = (size_t)d.m1 * A.cb_tile * b;
         if (A.cf_lds > device_lds_max() || A.cb_lds > device_lds_max())

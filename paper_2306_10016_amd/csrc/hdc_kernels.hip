@@ -150,13 +150,33 @@ __device__ __forceinline__ int lds_at(int pos, int bstride) {
 // Padded length of a contiguous n-point LDS buffer.
 __host__ __device__ constexpr int padded(int n) { return n + (n >> 3); }
 
+// zeta_n^e for the Stockham passes from a two-level table in LDS:
+// zeta_n^e = lo[e mod B] * hi[e / B], B = 2^ceil(log2(n)/2).  Keeping the
+// per-pass twiddles out of global memory lets a kernel keep prefetched global
+// loads in flight across a whole transform (vector loads retire in order).
+template <typename T>
+struct TwLds {
+    const cplx<T>* lo;
+    const cplx<T>* hi;
+    int mask;
+    int lg;
+    __device__ __forceinline__ cplx<T> operator[](int e) const { return lo[e & mask] * hi[e >> lg]; }
+};
+
+template <int NSZ>
+struct TwSplit {
+    static constexpr int LG = (ilog2c(NSZ) + 1) / 2;
+    static constexpr int LO = 1 << LG;
+    static constexpr int HI = NSZ / LO > 0 ? NSZ / LO : 1;
+};
+
 // One radix-R pass over sub-transforms of length Ns -> Ns*R.  Register v[w]
 // holds position lane + w*TPF.  Non-final passes write to LDS; the final
 // pass leaves its outputs in v.  Twiddles zeta^{i k} come from three table
 // loads (i = 1, 2, 4) and four products.
-template <typename T, int NSZ, int R, int SIGN, bool LAST, bool PAD>
+template <typename T, int NSZ, int R, int SIGN, bool LAST, bool PAD, class TW>
 __device__ __forceinline__ void stock_pass(cplx<T> (&v)[FP<NSZ>::PPT], int Ns, cplx<T>* buf, int bstride, int lane,
-                                           const cplx<T>* tw, bool act) {
+                                           const TW& tw, bool act) {
     constexpr int PPT = FP<NSZ>::PPT;
     constexpr int Q = FP<NSZ>::TPF;
     constexpr int NB = PPT / R;
@@ -216,9 +236,9 @@ __device__ __forceinline__ void lds_reload(cplx<T> (&v)[FP<NSZ>::PPT], const cpl
 
 // NSZ-point DFT with zeta_NSZ^{SIGN}, registers in and out (positions lane + w*TPF).
 // Every thread of the workgroup must call it (it contains barriers).
-template <typename T, int NSZ, int SIGN, bool PAD>
+template <typename T, int NSZ, int SIGN, bool PAD, class TW>
 __device__ __forceinline__ void fft_regs(cplx<T> (&v)[FP<NSZ>::PPT], cplx<T>* buf, int bstride, int lane,
-                                         const cplx<T>* tw, bool act) {
+                                         const TW& tw, bool act) {
     using P = FP<NSZ>;
     if constexpr (P::NPASS == 1) {
         stock_pass<T, NSZ, P::R0, SIGN, true, PAD>(v, 1, buf, bstride, lane, tw, act);
@@ -266,8 +286,11 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
     constexpr int TPF = P::TPF;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* smem = reinterpret_cast<cplx<T>*>(smem_raw);
+    using S = TwSplit<MSZ>;
     double2* twq =
         reinterpret_cast<double2*>(smem_raw + ((size_t)a.rpw * a.q * padded(MSZ) * sizeof(cplx<T>) + 15) / 16 * 16);
+    cplx<T>* tlo = reinterpret_cast<cplx<T>*>(twq + a.q);
+    cplx<T>* thi = tlo + S::LO;
 
     constexpr int RS = padded(MSZ);  // LDS slots per residue
     const int rowthreads = TPF * a.Dc;
@@ -279,9 +302,16 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
     const int64_t row = (int64_t)blockIdx.x * a.rpw + rloc;
     const bool rowok = row < a.nrows;
 
-    // zeta_q^e, e < q, shared by the block sums and the output sums.
+    // zeta_q^e, e < q, shared by the block sums and the output sums; the
+    // two-level table of zeta_m for the transform passes
     for (int e = tid; e < a.q; e += blockDim.x) twq[e] = tw_n(a.tw, (uint32_t)e * (uint32_t)MSZ);
+    {
+        const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.twm);
+        for (int e = tid; e < S::LO; e += blockDim.x) tlo[e] = twg[e];
+        for (int e = tid; e < S::HI; e += blockDim.x) thi[e] = twg[e * S::LO];
+    }
     __syncthreads();
+    const TwLds<T> twm{tlo, thi, S::LO - 1, S::LG};
 
     int L = a.L, M = a.M;
     int64_t fbase, hbase;
@@ -299,7 +329,6 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
     const cplx<T>* f = reinterpret_cast<const cplx<T>*>(a.f) + fbase;
     const cplx<T>* g = reinterpret_cast<const cplx<T>*>(a.g) + fbase;
     cplx<T>* h = reinterpret_cast<cplx<T>*>(a.h) + hbase;
-    const cplx<T>* twm = reinterpret_cast<const cplx<T>*>(a.twm);
     cplx<T>* U = smem + (size_t)rloc * a.q * RS;
     const T invN = (T)a.invN;
 
@@ -332,11 +361,17 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
             }
         }
         const uint32_t ru = (uint32_t)(act ? r : 0);
+        // zeta_N^{r s} for s = lane + v TPF, as z0 zs^v
+        const double2 z0 = tw_n(a.tw, ru * (uint32_t)lane);
+        const double2 zs = tw_n(a.tw, ru * (uint32_t)TPF);
+        {
+            double2 z = z0;
 #pragma unroll
-        for (int v = 0; v < PPT; ++v) {  // zeta_N^{r s}
-            const double2 z = tw_n(a.tw, ru * (uint32_t)(lane + v * TPF));
-            F[v] = mul_tw<false>(F[v], z, a.hiprec);
-            if (!a.same) G[v] = mul_tw<false>(G[v], z, a.hiprec);
+            for (int v = 0; v < PPT; ++v) {
+                F[v] = mul_tw<false>(F[v], z, a.hiprec);
+                if (!a.same) G[v] = mul_tw<false>(G[v], z, a.hiprec);
+                z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
+            }
         }
         fft_regs<T, MSZ, +1, true>(F, buf, 1, lane, twm, act);
         if (!a.same) {
@@ -349,10 +384,12 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
         }
         fft_regs<T, MSZ, -1, true>(F, buf, 1, lane, twm, act);
         if (act) {
+            double2 z = z0;
 #pragma unroll
             for (int v = 0; v < PPT; ++v) {
                 const int s = lane + v * TPF;
-                buf[lds_at<true>(s, 1)] = scale(mul_tw<true>(F[v], tw_n(a.tw, ru * (uint32_t)s), a.hiprec), invN);
+                buf[lds_at<true>(s, 1)] = scale(mul_tw<true>(F[v], z, a.hiprec), invN);
+                z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
             }
         }
     }
@@ -387,8 +424,18 @@ __global__ void __launch_bounds__(1024) k_col_fwd(ColFwdArgs a) {
     using P = FP<M1>;
     constexpr int PPT = P::PPT;
     constexpr int TPF = P::TPF;
+    using S = TwSplit<M1>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* tlo = lds + (size_t)M1 * a.tile;
+    cplx<T>* thi = tlo + S::LO;
+    {
+        const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.tw1);
+        for (int e = threadIdx.x; e < S::LO; e += blockDim.x) tlo[e] = twg[e];
+        for (int e = threadIdx.x; e < S::HI; e += blockDim.x) thi[e] = twg[e * S::LO];
+        __syncthreads();
+    }
+    const TwLds<T> tw1{tlo, thi, S::LO - 1, S::LG};
 
     // task = (tile, residue) with the residue fastest: the Dg residues of a
     // tile run back to back on one XCD and re-read its input from that L2
@@ -412,7 +459,6 @@ __global__ void __launch_bounds__(1024) k_col_fwd(ColFwdArgs a) {
     }
     const cplx<T>* x = reinterpret_cast<const cplx<T>*>(a.x) + xoff;
     cplx<T>* X = reinterpret_cast<cplx<T>*>(a.X) + b * a.out_bs;
-    const cplx<T>* tw1 = reinterpret_cast<const cplx<T>*>(a.tw1);
 
     // block t, point v of this thread: x[(t*m1 + s1)*Ccols + cp], zero beyond L
 #define HDC_LOAD(t, v)                                                                        \
@@ -437,21 +483,31 @@ __global__ void __launch_bounds__(1024) k_col_fwd(ColFwdArgs a) {
             }
         }
         if (r != 0) {
+            // zeta_N^{r s}, s = (lane + v TPF) m2 + s2: z0 zs^v
+            const uint32_t N = (uint32_t)a.N;
+            double2 z = tw_n(a.tw, (uint32_t)(((uint64_t)r * ((uint64_t)lane * a.m2 + s2)) % N));
+            const double2 zs = tw_n(a.tw, (uint32_t)(((uint64_t)r * a.m2 * TPF) % N));
 #pragma unroll
             for (int v = 0; v < PPT; ++v) {
-                const int s1 = lane + v * TPF;
-                const uint32_t s = (uint32_t)s1 * (uint32_t)a.m2 + (uint32_t)s2;
-                w[v] = mul_tw<false>(w[v], tw_n(a.tw, (uint32_t)r * s), a.hiprec);
+                w[v] = mul_tw<false>(w[v], z, a.hiprec);
+                z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
             }
         }
         fft_regs<T, M1, +1, false>(w, lds + cc, tile, lane, tw1, true);
+        if (a.m2 > 1 && s2 != 0) {
+            // four-step twiddle zeta_m^{l1 s2}, l1 = lane + v TPF: z0 zs^v
+            double2 z = tw_n(a.tw, (uint32_t)lane * (uint32_t)s2 * (uint32_t)a.q);
+            const double2 zs = tw_n(a.tw, (uint32_t)TPF * (uint32_t)s2 * (uint32_t)a.q);
+#pragma unroll
+            for (int v = 0; v < PPT; ++v) {
+                w[v] = mul_tw<false>(w[v], z, a.hiprec);
+                z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
+            }
+        }
 #pragma unroll
         for (int v = 0; v < PPT; ++v) {
             const int l1 = lane + v * TPF;
-            cplx<T> o = w[v];
-            if (a.m2 > 1 && s2 != 0)
-                o = mul_tw<false>(o, tw_n(a.tw, (uint32_t)l1 * (uint32_t)s2 * (uint32_t)a.q), a.hiprec);
-            if (ok) X[((int64_t)d * M1 + l1) * a.Ccols + cp] = o;
+            if (ok) X[((int64_t)d * M1 + l1) * a.Ccols + cp] = w[v];
         }
     }
 #undef HDC_LOAD
@@ -460,10 +516,20 @@ __global__ void __launch_bounds__(1024) k_col_fwd(ColFwdArgs a) {
 template <typename T, int M1, int DMAX>
 __global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
     using P = FP<M1>;
+    using S = TwSplit<M1>;
     constexpr int PPT = P::PPT;
     constexpr int TPF = P::TPF;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* tlo = lds + (size_t)M1 * a.tile;
+    cplx<T>* thi = tlo + S::LO;
+    {
+        const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.tw1);
+        for (int e = threadIdx.x; e < S::LO; e += blockDim.x) tlo[e] = twg[e];
+        for (int e = threadIdx.x; e < S::HI; e += blockDim.x) thi[e] = twg[e * S::LO];
+        __syncthreads();
+    }
+    const TwLds<T> tw1{tlo, thi, S::LO - 1, S::LG};
 
     const int tl = xcd_task(blockIdx.x, gridDim.x);
     if (tl >= a.ntiles) return;
@@ -483,8 +549,11 @@ __global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
     }
     const cplx<T>* Y = reinterpret_cast<const cplx<T>*>(a.Y) + b * a.in_bs;
     cplx<T>* h = reinterpret_cast<cplx<T>*>(a.h) + hoff;
-    const cplx<T>* tw1 = reinterpret_cast<const cplx<T>*>(a.tw1);
     const T invN = (T)a.invN;
+    // four-step twiddle conj(zeta_m^{l1 s2}), l1 = lane + v TPF, as z0 zs^v
+    const bool fs = a.m2 > 1 && s2 != 0;
+    const double2 fz0 = fs ? tw_n(a.tw, (uint32_t)lane * (uint32_t)s2 * (uint32_t)a.q) : make_double2(1.0, 0.0);
+    const double2 fzs = fs ? tw_n(a.tw, (uint32_t)TPF * (uint32_t)s2 * (uint32_t)a.q) : make_double2(1.0, 0.0);
 
     for (int db = 0; db < a.Dg; db += DMAX) {
         const int nd = min(DMAX, a.Dg - db);
@@ -497,18 +566,26 @@ __global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
 #pragma unroll
                 for (int v = 0; v < PPT; ++v) {
                     const int l1 = lane + v * TPF;
-                    cplx<T> y = ok ? Y[((int64_t)d * M1 + l1) * a.Ccols + cp] : mk<T>(0, 0);
-                    if (a.m2 > 1 && s2 != 0)
-                        y = mul_tw<true>(y, tw_n(a.tw, (uint32_t)l1 * (uint32_t)s2 * (uint32_t)a.q), a.hiprec);
-                    w[v] = y;
+                    w[v] = ok ? Y[((int64_t)d * M1 + l1) * a.Ccols + cp] : mk<T>(0, 0);
+                }
+                if (fs) {
+                    double2 z = fz0;
+#pragma unroll
+                    for (int v = 0; v < PPT; ++v) {
+                        w[v] = mul_tw<true>(w[v], z, a.hiprec);
+                        z = make_double2(z.x * fzs.x - z.y * fzs.y, z.x * fzs.y + z.y * fzs.x);
+                    }
                 }
                 fft_regs<T, M1, -1, false>(w, lds + cc, tile, lane, tw1, true);
                 const int r = a.r0 + d;
+                // conj(zeta_N^{r s}), s = (lane + v TPF) m2 + s2, as z0 zs^v
+                const uint32_t N = (uint32_t)a.N;
+                double2 z = tw_n(a.tw, (uint32_t)(((uint64_t)r * ((uint64_t)lane * a.m2 + s2)) % N));
+                const double2 zs = tw_n(a.tw, (uint32_t)(((uint64_t)r * a.m2 * TPF) % N));
 #pragma unroll
                 for (int v = 0; v < PPT; ++v) {
-                    const int s1 = lane + v * TPF;
-                    const uint32_t s = (uint32_t)s1 * (uint32_t)a.m2 + (uint32_t)s2;
-                    V[dd][v] = scale(mul_tw<true>(w[v], tw_n(a.tw, (uint32_t)r * s), a.hiprec), invN);
+                    V[dd][v] = scale(mul_tw<true>(w[v], z, a.hiprec), invN);
+                    z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
                 }
             } else {
 #pragma unroll
@@ -542,51 +619,87 @@ __global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
 
 // ---------------------------------------------------------------- rows --
 
-template <typename T, int MSZ>
+// Persistent row kernel: the workgroup walks rows base, base + stride, ...
+// with a skewed software pipeline: the g row of iteration i is loaded when
+// the iteration starts (hidden behind the f transform), and the f row of
+// iteration i+1 is loaded before the g transform (hidden behind the g
+// transform, the product and the inverse), so HBM traffic overlaps the LDS
+// passes while only three rows of registers are live.
+template <typename T, int MSZ, int MODE, bool TWO>
 __global__ void __launch_bounds__(512) k_row(RowArgs a) {
     using P = FP<MSZ>;
+    using S = TwSplit<MSZ>;
     constexpr int PPT = P::PPT;
     constexpr int TPF = P::TPF;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* smem = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* tlo = smem + (size_t)a.rpw * padded(MSZ);
+    cplx<T>* thi = tlo + S::LO;
     const int tid = threadIdx.x;
+    const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.tw);
+    for (int e = tid; e < S::LO; e += blockDim.x) tlo[e] = twg[e];
+    for (int e = tid; e < S::HI; e += blockDim.x) thi[e] = twg[e * S::LO];
+    __syncthreads();
+    const TwLds<T> tw{tlo, thi, S::LO - 1, S::LG};
+
     const int rloc = tid / TPF;
     const int lane = tid - rloc * TPF;
-    const int64_t row = (int64_t)blockIdx.x * a.rpw + rloc;
-    const bool ok = row < a.nrows;
     cplx<T>* buf = smem + (size_t)rloc * padded(MSZ);
-    const int64_t base = row_base(a.addr, ok ? row : 0);
     const int64_t es = a.addr.es;
-    const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(a.tw);
-    const cplx<T>* A = reinterpret_cast<const cplx<T>*>(a.a) + base;
-    cplx<T>* O = reinterpret_cast<cplx<T>*>(a.out) + base;
+    const int64_t stride = (int64_t)gridDim.x * a.rpw;
+    constexpr bool conv = MODE == MODE_CONV;
+    constexpr bool two = conv && TWO;
+    const cplx<T>* Ag = reinterpret_cast<const cplx<T>*>(a.a);
+    const cplx<T>* Bg = reinterpret_cast<const cplx<T>*>(a.b);
+    cplx<T>* Og = reinterpret_cast<cplx<T>*>(a.out);
 
+    int64_t base = (int64_t)blockIdx.x * a.rpw;  // uniform over the workgroup
     cplx<T> v[PPT];
+    {
+        const int64_t row = base + rloc;
+        const bool ok = row < a.nrows;
+        const int64_t rb = row_base(a.addr, ok ? row : 0);
 #pragma unroll
-    for (int w = 0; w < PPT; ++w) v[w] = ok ? A[(int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
-    if (a.mode == MODE_INV) {
-        fft_regs<T, MSZ, -1, true>(v, buf, 1, lane, tw, ok);
-    } else {
-        fft_regs<T, MSZ, +1, true>(v, buf, 1, lane, tw, ok);
-        if (a.mode == MODE_CONV) {
-            if (a.same) {
-#pragma unroll
-                for (int w = 0; w < PPT; ++w) v[w] = v[w] * v[w];
-            } else {
-                const cplx<T>* B = reinterpret_cast<const cplx<T>*>(a.b) + base;
-                cplx<T> u[PPT];
-#pragma unroll
-                for (int w = 0; w < PPT; ++w) u[w] = ok ? B[(int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
-                fft_regs<T, MSZ, +1, true>(u, buf, 1, lane, tw, ok);
-#pragma unroll
-                for (int w = 0; w < PPT; ++w) v[w] = v[w] * u[w];
-            }
-            fft_regs<T, MSZ, -1, true>(v, buf, 1, lane, tw, ok);
-        }
+        for (int w = 0; w < PPT; ++w) v[w] = ok ? Ag[rb + (int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
     }
-    if (ok) {
+    for (; base < a.nrows; base += stride) {
+        const int64_t row = base + rloc;
+        const bool ok = row < a.nrows;
+        const int64_t rb = row_base(a.addr, ok ? row : 0);
+        const int64_t nrow = row + stride;
+        const bool nok = nrow < a.nrows;
+        const int64_t nrb = row_base(a.addr, nok ? nrow : 0);
+        cplx<T> u[PPT], pv[PPT];
+        if constexpr (two) {
 #pragma unroll
-        for (int w = 0; w < PPT; ++w) O[(int64_t)(lane + w * TPF) * es] = v[w];
+            for (int w = 0; w < PPT; ++w) u[w] = ok ? Bg[rb + (int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
+        }
+        if constexpr (MODE == MODE_INV) {
+#pragma unroll
+            for (int w = 0; w < PPT; ++w) pv[w] = nok ? Ag[nrb + (int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
+            fft_regs<T, MSZ, -1, true>(v, buf, 1, lane, tw, ok);
+        } else {
+            fft_regs<T, MSZ, +1, true>(v, buf, 1, lane, tw, ok);
+#pragma unroll
+            for (int w = 0; w < PPT; ++w) pv[w] = nok ? Ag[nrb + (int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
+            if constexpr (conv) {
+                if constexpr (two) {
+                    fft_regs<T, MSZ, +1, true>(u, buf, 1, lane, tw, ok);
+#pragma unroll
+                    for (int w = 0; w < PPT; ++w) v[w] = v[w] * u[w];
+                } else {
+#pragma unroll
+                    for (int w = 0; w < PPT; ++w) v[w] = v[w] * v[w];
+                }
+                fft_regs<T, MSZ, -1, true>(v, buf, 1, lane, tw, ok);
+            }
+        }
+        if (ok) {
+#pragma unroll
+            for (int w = 0; w < PPT; ++w) Og[rb + (int64_t)(lane + w * TPF) * es] = v[w];
+        }
+#pragma unroll
+        for (int w = 0; w < PPT; ++w) v[w] = pv[w];
     }
 }
 
@@ -626,6 +739,7 @@ hipError_t allow_lds(K kernel, size_t lds) {
 
 template <typename T, int MSZ>
 hipError_t fused_t(const FusedArgs& a, int threads, int64_t blocks, size_t lds, hipStream_t s) {
+    lds += (size_t)(TwSplit<MSZ>::LO + TwSplit<MSZ>::HI) * sizeof(cplx<T>);
     hipError_t e = allow_lds(k_fused<T, MSZ>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_fused<T, MSZ>), dim3((unsigned)blocks), dim3(threads), lds, s, a);
@@ -634,6 +748,7 @@ hipError_t fused_t(const FusedArgs& a, int threads, int64_t blocks, size_t lds, 
 
 template <typename T, int M1>
 hipError_t colf_t(const ColFwdArgs& a, int threads, int64_t gx, int64_t gy, size_t lds, hipStream_t s) {
+    lds += (size_t)(TwSplit<M1>::LO + TwSplit<M1>::HI) * sizeof(cplx<T>);
     hipError_t e = allow_lds(k_col_fwd<T, M1>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_col_fwd<T, M1>), dim3((unsigned)gx, (unsigned)gy), dim3(threads), lds, s, a);
@@ -643,18 +758,50 @@ hipError_t colf_t(const ColFwdArgs& a, int threads, int64_t gx, int64_t gy, size
 template <typename T, int M1>
 hipError_t colb_t(const ColBwdArgs& a, int threads, int64_t gx, int64_t gy, size_t lds, hipStream_t s) {
     constexpr int DMAX = sizeof(T) == 8 ? 2 : 4;
+    lds += (size_t)(TwSplit<M1>::LO + TwSplit<M1>::HI) * sizeof(cplx<T>);
     hipError_t e = allow_lds(k_col_bwd<T, M1, DMAX>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_col_bwd<T, M1, DMAX>), dim3((unsigned)gx, (unsigned)gy), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
+int cu_count() {
+    static int n = 0;
+    if (n == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            n = v;
+        else
+            n = 256;
+    }
+    return n;
+}
+
+template <typename T, int MSZ, int MODE, bool TWO>
+hipError_t row_mode(const RowArgs& a, int threads, int64_t blocks, size_t lds, hipStream_t s) {
+    auto kern = k_row<T, MSZ, MODE, TWO>;
+    hipError_t e = allow_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, threads, lds) != hipSuccess || occ < 1) occ = 1;
+    const int64_t resident = (int64_t)occ * cu_count();
+    const int64_t grid = blocks < resident ? blocks : resident;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
 template <typename T, int MSZ>
 hipError_t row_t(const RowArgs& a, int threads, int64_t blocks, size_t lds, hipStream_t s) {
-    hipError_t e = allow_lds(k_row<T, MSZ>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_row<T, MSZ>), dim3((unsigned)blocks), dim3(threads), lds, s, a);
-    return hipGetLastError();
+    using S = TwSplit<MSZ>;
+    lds += (size_t)(S::LO + S::HI) * sizeof(cplx<T>);
+    switch (a.mode) {
+        case MODE_FWD: return row_mode<T, MSZ, MODE_FWD, false>(a, threads, blocks, lds, s);
+        case MODE_INV: return row_mode<T, MSZ, MODE_INV, false>(a, threads, blocks, lds, s);
+        default:
+            return a.same ? row_mode<T, MSZ, MODE_CONV, false>(a, threads, blocks, lds, s)
+                          : row_mode<T, MSZ, MODE_CONV, true>(a, threads, blocks, lds, s);
+    }
 }
 
 }  // namespace
