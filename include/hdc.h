@@ -89,8 +89,9 @@ hdc_status hdc_plan(hdc_plan_t* out, int64_t L, int64_t M, int64_t m, int64_t p,
 
 /* N-D plan, ndim = 1..3 (section 3.6): per-axis L, M, m, p, q, D (p, q, D may
  * be 0 to derive).  The outer axes are transformed as strided column passes
- * whose copies are the inner extents (section 2.5's C copies); the innermost
- * axis is a 1D hybrid convolution per outer-residue row. */
+ * whose copies are the inner extents (section 2.5's C copies; outer m up to
+ * 2^20, split into two column stages when above 1024); the innermost axis is a
+ * 1D hybrid convolution per outer-residue row. */
 hdc_status hdc_plan_nd(hdc_plan_t* out, int ndim, const int64_t* L, const int64_t* M, const int64_t* m,
                        const int64_t* p, const int64_t* q, const int64_t* D, hdc_dtype dtype);
 

@@ -130,6 +130,9 @@ struct AxisPlan {
     // column/row geometry
     int cf_tile = 1, cf_threads = 1, cb_tile = 1, cb_threads = 1, r_rpw = 1, r_threads = 1;
     size_t cf_lds = 0, cb_lds = 0, r_lds = 0;
+    // outer N-D axes with m2 > 1: plain strided m2-point DFT passes (column kernels)
+    int mf_tile = 1, mf_threads = 1, mb_tile = 1, mb_threads = 1;
+    size_t mf_lds = 0, mb_lds = 0;
     // device tables
     TwN tw{};
     const void* tw_m = nullptr;
@@ -204,15 +207,27 @@ int tile_for(int tpf, int tmin, int maxthreads) {
 
 // Geometry of every kernel for one axis; `outer` = transformed as a column
 // stage of an N-D problem (m1 = m, m2 = 1).
-hdc_status geometry(AxisPlan& A, bool outer) {
+hdc_status geometry(AxisPlan& A, bool outer, bool many_rows = false) {
     hdc_axis_desc& d = A.d;
     const size_t b = A.dbl ? 16 : 8;
     if (outer) {
-        if (d.m > kMaxM1)
-            return fail(HDC_ERR_UNSUPPORTED, "outer-axis m = %lld exceeds %d", (long long)d.m, kMaxM1);
-        d.m1 = d.m;
-        d.m2 = 1;
+        // an outer axis is transformed down strided columns: m = m1 * m2 with both
+        // factors column passes (the second one a plain strided m2-point DFT)
+        if (d.m > (int64_t)kMaxM1 * kMaxM1)
+            return fail(HDC_ERR_UNSUPPORTED, "outer-axis m = %lld exceeds %d", (long long)d.m, kMaxM1 * kMaxM1);
+        d.m1 = std::min<int64_t>(d.m, kMaxM1);
+        d.m2 = d.m / d.m1;
         d.variant = 1;
+        const int ppt = ppt_for((int)d.m2);
+        const int tpf = (int)d.m2 / ppt;
+        const int tmin0 = A.dbl ? 8 : 16;
+        A.mf_tile = tile_for(tpf, tmin0, 1024);
+        A.mf_threads = A.mf_tile * tpf;
+        A.mf_lds = (size_t)d.m2 * A.mf_tile * b;
+        A.mb_tile = tile_for(tpf, tmin0, 512);
+        while (A.mb_tile > 1 && (size_t)d.m2 * A.mb_tile * b > 65536) A.mb_tile /= 2;
+        A.mb_threads = A.mb_tile * tpf;
+        A.mb_lds = (size_t)d.m2 * A.mb_tile * b;
     }
     const int tmin = A.dbl ? 8 : 16;
     // fused
@@ -259,6 +274,10 @@ hdc_status geometry(AxisPlan& A, bool outer) {
         if (A.r_lds > device_lds_max())
             return fail(HDC_ERR_UNSUPPORTED, "row stage m2 = %lld needs %zu bytes of LDS", (long long)d.m2, A.r_lds);
     }
+    // with many independent rows (the innermost axis of an N-D problem) one
+    // workgroup per row keeps the machine busy, and the fused kernel may use all
+    // the LDS a workgroup can have instead of the 80 KiB that leaves room for two
+    if (many_rows && !outer && d.m <= kMaxFused && A.f_lds + 4096 <= device_lds_max()) d.variant = 0;
     if (d.variant == 0 && A.f_lds > device_lds_max()) d.variant = 1;
     A.hiprec = !A.dbl && d.N > (int64_t(1) << 20);
     return HDC_OK;
@@ -422,6 +441,70 @@ hdc_status run_col_bwd(const AxisPlan& A, const void* Y, void* h, int64_t B, int
     return HDC_OK;
 }
 
+// Plain strided m2-point DFTs of an outer axis split four-step: B slabs of
+// [m2][cols], in place; sign +1 uses the forward column kernel with one
+// residue and no twiddles, sign -1 the backward one with no 1/N scaling.
+hdc_status run_col_plain(const AxisPlan& A, void* x, int64_t B, int64_t cols, int sign, hipStream_t s) {
+    const int m2 = (int)A.d.m2;
+    const int64_t bs = (int64_t)m2 * cols;
+    if (B > 65535) return fail(HDC_ERR_UNSUPPORTED, "column grid too large (B = %lld)", (long long)B);
+    const double eb = A.dbl ? 16.0 : 8.0;
+    if (sign > 0) {
+        ColFwdArgs a{};
+        a.x = x;
+        a.X = x;
+        a.B = B;
+        a.in_bs = bs;
+        a.out_bs = bs;
+        a.L = m2;
+        a.Ccols = (int32_t)cols;
+        a.C1 = (int32_t)cols;
+        a.m2 = 1;
+        a.m = m2;
+        a.q = 1;
+        a.p = 1;
+        a.N = m2;
+        a.r0 = 0;
+        a.Dg = 1;
+        a.tile = A.mf_tile;
+        a.ntiles = (int32_t)ceil_div(cols, A.mf_tile);
+        a.hiprec = 0;
+        a.tw = A.tw;
+        a.tw1 = A.tw_m2;
+        LaunchScope ls(s, 1, eb * 2.0 * (double)B * (double)bs);
+        hipError_t e = launch_col_fwd(A.dbl, m2, a, A.mf_threads, round8(a.ntiles), B, A.mf_lds, s);
+        if (e != hipSuccess) return hip_fail(e, "strided DFT launch");
+        return HDC_OK;
+    }
+    ColBwdArgs a{};
+    a.Y = x;
+    a.h = x;
+    a.B = B;
+    a.in_bs = bs;
+    a.out_bs = bs;
+    a.M = m2;
+    a.Ccols = (int32_t)cols;
+    a.C1 = (int32_t)cols;
+    a.m2 = 1;
+    a.m = m2;
+    a.q = 1;
+    a.N = m2;
+    a.qout = 1;
+    a.r0 = 0;
+    a.Dg = 1;
+    a.accumulate = 0;
+    a.tile = A.mb_tile;
+    a.ntiles = (int32_t)ceil_div(cols, A.mb_tile);
+    a.hiprec = 0;
+    a.tw = A.tw;
+    a.tw1 = A.tw_m2;
+    a.invN = 1.0;
+    LaunchScope ls(s, 3, eb * 2.0 * (double)B * (double)bs);
+    hipError_t e = launch_col_bwd(A.dbl, m2, a, A.mb_threads, round8(a.ntiles), B, A.mb_lds, s);
+    if (e != hipSuccess) return hip_fail(e, "strided inverse DFT launch");
+    return HDC_OK;
+}
+
 // Rows of the residue buffer [B][Dg][m1][m2*C1]: row = ((b Dg + d) m1 + l1) C1 + c1.
 hdc_status run_rows(const AxisPlan& A, const void* a_, const void* b_, void* out, int64_t nrows, int64_t C1, int mode,
                     hipStream_t s) {
@@ -526,15 +609,19 @@ hdc_status convnd(const hdc_plan_s* P, int level, const void* xf, const void* xg
     for (int64_t r0 = 0; r0 < A.d.q; r0 += D) {
         const int64_t Dg = std::min(D, A.d.q - r0);
         const int64_t nb = B * Dg * A.d.m;
+        // block sums, m1-point DFTs and four-step twiddles (copies = the inner extent)
         hdc_status st = run_col_fwd(A, xf, Xf, B, A.d.L * inner_in, Dg * A.d.m * inner_in, inner_in, r0, Dg, s);
-        if (st != HDC_OK) return st;
-        if (!same) {
+        if (st == HDC_OK && !same)
             st = run_col_fwd(A, xg, Xg, B, A.d.L * inner_in, Dg * A.d.m * inner_in, inner_in, r0, Dg, s);
-            if (st != HDC_OK) return st;
+        // the remaining m2-point DFTs of a long outer axis, in place
+        if (st == HDC_OK && A.d.m2 > 1) {
+            st = run_col_plain(A, Xf, B * Dg * A.d.m1, inner_in, +1, s);
+            if (st == HDC_OK && !same) st = run_col_plain(A, Xg, B * Dg * A.d.m1, inner_in, +1, s);
         }
-        st = convnd(P, level + 1, Xf, same ? Xf : Xg, Y, nb, rest, s);
-        if (st != HDC_OK) return st;
-        st = run_col_bwd(A, Y, out, B, Dg * A.d.m * inner_out, A.d.M * inner_out, inner_out, r0, Dg, r0 > 0, s);
+        if (st == HDC_OK) st = convnd(P, level + 1, Xf, same ? Xf : Xg, Y, nb, rest, s);
+        if (st == HDC_OK && A.d.m2 > 1) st = run_col_plain(A, Y, B * Dg * A.d.m1, inner_out, -1, s);
+        if (st == HDC_OK)
+            st = run_col_bwd(A, Y, out, B, Dg * A.d.m * inner_out, A.d.M * inner_out, inner_out, r0, Dg, r0 > 0, s);
         if (st != HDC_OK) return st;
     }
     return HDC_OK;
@@ -618,7 +705,7 @@ hdc_status hdc_plan_nd(hdc_plan_t* out, int ndim, const int64_t* L, const int64_
         st = derive_axis(L[a], M[a], m[a], p ? p[a] : 0, q ? q[a] : 0, 1, D ? D[a] : 0, dtype, &A.d);
         if (st == HDC_OK) {
             A.dbl = dtype == HDC_C128;
-            st = geometry(A, a < ndim - 1);
+            st = geometry(A, a < ndim - 1, ndim > 1 && a == ndim - 1);
         }
     }
     if (st == HDC_OK) st = finish_plan(P);

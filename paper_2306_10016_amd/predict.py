@@ -38,7 +38,7 @@ P_CLASSES = tune.P_CLASSES
 CLASSES: List[Tuple[int, int]] = [(p, dm) for p in P_CLASSES for dm in (0, 1)]  # dm 0: D = q, 1: D = 1
 D_IN = 11
 HIDDEN = (128, 128, 128)
-MAX_OUTER_M = 1024  # column-stage limit of the outer N-D axes
+MAX_OUTER_M = 1 << 20  # limit of the outer N-D axes (two column stages of at most 1024)
 
 
 def features(Ls: Sequence[int], axis: int, dtype: str, batch: int = 1) -> np.ndarray:

@@ -130,3 +130,21 @@ def test_batch_full_workload_sampled():
     Ls = synth.batch_lengths(4096, 6, 16, cfg=3)
     check = sorted(set(synth.rng(3, 0, 6).integers(0, 4096, 36).tolist()) | {int(np.argmax(Ls)), int(np.argmin(Ls))})
     _batch(Ls, "c64", graph=True, cfg=3, check_idx=check, replays=2)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("L,m,D", [((3000, 40), (4096, 64), None), ((1500, 100), (2048, 128), (1, 0)),
+                                   ((1100, 6, 5), (2048, 8, 8), None), ((700, 33), (8192, 64), (3, 0))])
+def test_outer_axis_four_step(L, m, D, dtype):
+    """Outer axes with m > 1024 run as two column stages (m1 = 1024, then a strided m2-point pass)."""
+    M = tuple(2 * a - 1 for a in L)
+    plan, _ = _nd(L, M, m, dtype, D=D, idx=L[0] + 7)
+    assert plan.axes[0]["m1"] * plan.axes[0]["m2"] == m[0]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_inner_axis_fused_with_many_rows(dtype):
+    """Innermost axis with N beyond 80 KiB of LDS uses the fused kernel when rows are many."""
+    L = (64, 3000)
+    plan, _ = _nd(L, (127, 5999), (64, 4096), dtype, idx=11)
+    assert plan.axes[1]["variant"] == 0
