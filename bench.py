@@ -114,6 +114,96 @@ def load_traffic(kernel: str, workload: str):
     return None
 
 
+def secondary(args, dev, hdc, synth, log):
+    """Measured secondary workloads: the single small convolution, the uneven batch,
+    the 2D squares/rectangles and the 2D/3D evaluation sizes, each against
+    explicit padding (torch.fft) on the same GPU where one exists."""
+    import numpy as np
+    import torch
+
+    def timed(fn, reps, warm=2):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    out = {}
+    # small workload: L = 1024, M = 2047, m = 256, p = 4, q = 8, C = 1, D = 1, complex128
+    f, g = synth.pair(1024, 1, 0, np.complex128)
+    ft, gt = torch.from_numpy(f).to(dev), torch.from_numpy(g).to(dev)
+    plan = hdc.Plan(1024, 2047, 256, 4, 8, 1, 1, "c128")
+    h = torch.empty(2047, dtype=torch.complex128, device=dev)
+    t = timed(lambda: plan.convolve(ft, gt, h), 200)
+    plan8 = hdc.Plan(1024, 2047, 256, 4, 8, 1, 8, "c128")
+    t8 = timed(lambda: plan8.convolve(ft, gt, h), 200)
+    out["small_L1024_c128"] = {"us_per_conv_D1": round(t * 1e6, 2), "us_per_conv_D8": round(t8 * 1e6, 2),
+                               "note": "one convolution per launch; launch latency dominates"}
+
+    # uneven batch: 4096 complex64 problems, L = round(2^U[6,16])
+    Ls = synth.batch_lengths(4096, 6, 16, cfg=3)
+    B = hdc.Batch(Ls, dtype="c64")
+    fb = torch.from_numpy(np.concatenate([synth.uniform_complex(int(L), 3, i, 0, np.complex64)
+                                          for i, L in enumerate(Ls)])).to(dev)
+    gb = torch.from_numpy(np.concatenate([synth.uniform_complex(int(L), 3, i, 1, np.complex64)
+                                          for i, L in enumerate(Ls)])).to(dev)
+    hb = torch.empty(B.total_M, dtype=torch.complex64, device=dev)
+    tb = timed(lambda: B.convolve(fb, gb, hb), 10)
+    comp = (2 * B.total_L + B.total_M) * 8
+    out["batch_4096_c64"] = {"convs_per_s": round(4096 / tb, 1), "ms": round(tb * 1e3, 4), "buckets": B.n_buckets,
+                             "compulsory_GBps": round(comp / tb / 1e9, 1)}
+    del fb, gb, hb, B
+
+    # 2D squares and rectangles, and the 2D/3D evaluation sizes (parameters from the per-axis tuner)
+    shapes = [((256, 256), "c64"), ((512, 512), "c64"), ((1024, 1024), "c64"), ((2048, 512), "c64"),
+              ((1024, 4096), "c64"), ((1024, 1024), "c128"), ((1024, 4096), "c128"), ((4096, 4096), "c64"),
+              ((8192, 8192), "c64"), ((256, 256, 256), "c64")]
+    from paper_2306_10016_amd import predict
+    timer = predict.NDTimer(reps=3, warmup=1)
+    nd = {}
+    for Ls, dt in shapes:
+        Ms = tuple(2 * x - 1 for x in Ls)
+        best, _, _ = predict.tune_separable(list(Ls), list(Ms), dt, timer)  # A0 per axis
+        ms = tuple(b[0] for b in best)
+        Ds = tuple(b[1] for b in best)
+        np_dt = np.complex128 if dt == "c128" else np.complex64
+        td = torch.complex128 if dt == "c128" else torch.complex64
+        f, g = synth.pair(Ls, 4, sum(Ls), np_dt)
+        ft, gt = torch.from_numpy(f).to(dev), torch.from_numpy(g).to(dev)
+        plan = hdc.Plan.nd(Ls, Ms, ms, D=Ds, dtype=dt)
+        h = torch.empty(Ms, dtype=td, device=dev)
+        ws = plan.workspace(dev)
+        reps = 10 if np.prod(Ls) <= (1 << 22) else 3
+        t = timed(lambda: plan.convolve(ft, gt, h, ws=ws), reps, warm=1)
+        s2 = tuple(2 * x for x in Ls)
+        sl = tuple(slice(0, m) for m in Ms)
+
+        def explicit():
+            return torch.fft.ifftn(torch.fft.fftn(ft, s=s2) * torch.fft.fftn(gt, s=s2))[sl]
+        err = float(torch.linalg.vector_norm(h - explicit()) / torch.linalg.vector_norm(explicit()))
+        te = timed(explicit, reps, warm=1)
+        comp = (2 * int(np.prod(Ls)) + int(np.prod(Ms))) * (16 if dt == "c128" else 8)
+        key = "x".join(str(x) for x in Ls) + "_" + dt
+        nd[key] = {"params": {"m": list(ms), "D": list(Ds)}, "ms": round(t * 1e3, 4), "compulsory_GBps": round(comp / t / 1e9, 1),
+                   "explicit_ms": round(te * 1e3, 4), "speedup_vs_explicit": round(te / t, 3),
+                   "rel_err_vs_explicit": err}
+        log(f"[bench] {key}: {t * 1e3:.3f} ms (explicit {te * 1e3:.3f} ms), rel {err:.1e}")
+        del ft, gt, h, plan, ws
+        torch.cuda.empty_cache()
+    out["nd"] = nd
+    return out
+
+
+def tune_pow2(x):
+    m = 1
+    while m < x:
+        m <<= 1
+    return m
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +215,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="default parameters m = 2^ceil(log2 L), p = 1, q = 2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 512 MiB first (counter calibration)")
     args = ap.parse_args()
@@ -265,6 +356,11 @@ def main():
         out["speedup_vs_explicit"] = round(value / ev, 3)
         out["max_rel_err_vs_explicit"] = max(errs)
         log(f"[bench] explicit pad {ev:.1f} convs/s; speedup {value / ev:.2f}; max rel err {max(errs):.2e}")
+
+    if not args.no_extras:
+        del F, G, H, plans, ws
+        torch.cuda.empty_cache()
+        out["secondary"] = secondary(args, dev, hdc, synth, log)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sizes, dt)
