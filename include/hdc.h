@@ -95,6 +95,13 @@ hdc_status hdc_plan(hdc_plan_t* out, int64_t L, int64_t M, int64_t m, int64_t p,
 hdc_status hdc_plan_nd(hdc_plan_t* out, int ndim, const int64_t* L, const int64_t* M, const int64_t* m,
                        const int64_t* p, const int64_t* q, const int64_t* D, hdc_dtype dtype);
 
+/* Host-only check of an N-D plan (no device memory is touched): the
+ * admissibility of every axis and the kernel geometry (LDS needs against the
+ * device's, or gfx950's 160 KiB when no device is visible).  Fills
+ * out[0 .. ndim-1] when out is non-NULL. */
+hdc_status hdc_plan_nd_check(int ndim, const int64_t* L, const int64_t* M, const int64_t* m, const int64_t* p,
+                             const int64_t* q, const int64_t* D, hdc_dtype dtype, hdc_axis_desc* out);
+
 hdc_status hdc_plan_destroy(hdc_plan_t plan);
 
 /* Number of axes and the description of axis `axis`. */

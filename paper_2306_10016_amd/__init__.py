@@ -46,6 +46,18 @@ def derive(L: int, M: int, m: int, p: int = 0, q: int = 0, C: int = 1, D: int = 
     return d.as_dict()
 
 
+def check_nd(L, M, m, p=None, q=None, D=None, dtype="c64"):
+    """Host-only validation of an N-D plan (hdc_plan_nd_check); returns the axis descriptions."""
+    n = len(L)
+    arr = ctypes.c_int64 * n
+
+    def a(v):
+        return arr(*[int(x) for x in v]) if v is not None else None
+    out = (AxisDesc * n)()
+    check(lib().hdc_plan_nd_check(n, a(L), a(M), a(m), a(p), a(q), a(D), dtype_code(dtype), out))
+    return [d.as_dict() for d in out]
+
+
 def _stream(stream) -> ctypes.c_void_p:
     import torch
     if stream is None:

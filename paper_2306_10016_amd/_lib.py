@@ -37,6 +37,8 @@ SIGNATURES = {
     "hdc_derive": [_I64, _I64, _I64, _I64, _I64, _I64, _I64, ctypes.c_int, ctypes.POINTER(AxisDesc)],
     "hdc_plan": [_PP, _I64, _I64, _I64, _I64, _I64, _I64, _I64, ctypes.c_int],
     "hdc_plan_nd": [_PP, ctypes.c_int, _PI64, _PI64, _PI64, _PI64, _PI64, _PI64, ctypes.c_int],
+    "hdc_plan_nd_check": [ctypes.c_int, _PI64, _PI64, _PI64, _PI64, _PI64, _PI64, ctypes.c_int,
+                          ctypes.POINTER(AxisDesc)],
     "hdc_plan_destroy": [_P],
     "hdc_plan_axis": [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(AxisDesc)],
     "hdc_workspace_size": [_P, ctypes.POINTER(ctypes.c_size_t)],

@@ -65,7 +65,7 @@ size_t device_lds_max() {
     static std::once_flag once;
     std::call_once(once, [] {
         int dev = 0, v = 0;
-        cached = 65536;
+        cached = 163840;  // gfx950: 160 KiB of LDS per workgroup
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
             cached = (size_t)v;
@@ -78,6 +78,9 @@ size_t device_lds_max() {
 constexpr size_t kFusedRowLds = 81920;
 
 int64_t round8(int64_t x) { return (x + 7) / 8 * 8; }
+
+// Largest y extent of a launch grid; column launches over more batches are split.
+constexpr int64_t kMaxGridY = 65535;
 
 // Optional per-launch timing: when a recorder is installed on this thread,
 // every kernel launch is bracketed by HIP events on its stream and its
@@ -398,11 +401,19 @@ hdc_status run_col_fwd(const AxisPlan& A, const void* x, void* X, int64_t B, int
     a.tw = A.tw;
     a.tw1 = A.tw_m1;
     const int64_t gx = round8((int64_t)a.ntiles * Dg);
-    if (gx > 0x7fffffff || B > 65535) return fail(HDC_ERR_UNSUPPORTED, "column grid too large (B = %lld)", (long long)B);
+    if (gx > 0x7fffffff) return fail(HDC_ERR_UNSUPPORTED, "column grid too large");
     const double eb = A.dbl ? 16.0 : 8.0;
+    const size_t esz = A.dbl ? 16 : 8;
     LaunchScope ls(s, 1, eb * (double)B * (double)C1 * ((double)A.d.L + (double)(Dg * A.d.m)));
-    hipError_t e = launch_col_fwd(A.dbl, (int)A.d.m1, a, A.cf_threads, gx, B, A.cf_lds, s);
-    if (e != hipSuccess) return hip_fail(e, "column forward launch");
+    for (int64_t b0 = 0; b0 < B; b0 += kMaxGridY) {  // the grid's y extent is limited
+        ColFwdArgs c = a;
+        c.B = std::min<int64_t>(kMaxGridY, B - b0);
+        if (desc) c.desc = desc + 2 * b0;
+        else c.x = (const char*)x + (size_t)(b0 * in_bs) * esz;
+        c.X = (char*)X + (size_t)(b0 * out_bs) * esz;
+        hipError_t e = launch_col_fwd(A.dbl, (int)A.d.m1, c, A.cf_threads, gx, c.B, A.cf_lds, s);
+        if (e != hipSuccess) return hip_fail(e, "column forward launch");
+    }
     return HDC_OK;
 }
 
@@ -433,11 +444,18 @@ hdc_status run_col_bwd(const AxisPlan& A, const void* Y, void* h, int64_t B, int
     a.tw = A.tw;
     a.tw1 = A.tw_m1;
     a.invN = 1.0 / (double)A.d.N;
-    if (B > 65535) return fail(HDC_ERR_UNSUPPORTED, "column grid too large");
     const double eb = A.dbl ? 16.0 : 8.0;
+    const size_t esz = A.dbl ? 16 : 8;
     LaunchScope ls(s, 3, eb * (double)B * (double)C1 * ((double)(Dg * A.d.m) + (accumulate ? 2.0 : 1.0) * (double)A.d.M));
-    hipError_t e = launch_col_bwd(A.dbl, (int)A.d.m1, a, A.cb_threads, round8(a.ntiles), B, A.cb_lds, s);
-    if (e != hipSuccess) return hip_fail(e, "column backward launch");
+    for (int64_t b0 = 0; b0 < B; b0 += kMaxGridY) {  // the grid's y extent is limited
+        ColBwdArgs c = a;
+        c.B = std::min<int64_t>(kMaxGridY, B - b0);
+        c.Y = (const char*)Y + (size_t)(b0 * in_bs) * esz;
+        if (desc) c.desc = desc + 2 * b0;
+        else c.h = (char*)h + (size_t)(b0 * out_bs) * esz;
+        hipError_t e = launch_col_bwd(A.dbl, (int)A.d.m1, c, A.cb_threads, round8(a.ntiles), c.B, A.cb_lds, s);
+        if (e != hipSuccess) return hip_fail(e, "column backward launch");
+    }
     return HDC_OK;
 }
 
@@ -447,7 +465,15 @@ hdc_status run_col_bwd(const AxisPlan& A, const void* Y, void* h, int64_t B, int
 hdc_status run_col_plain(const AxisPlan& A, void* x, int64_t B, int64_t cols, int sign, hipStream_t s) {
     const int m2 = (int)A.d.m2;
     const int64_t bs = (int64_t)m2 * cols;
-    if (B > 65535) return fail(HDC_ERR_UNSUPPORTED, "column grid too large (B = %lld)", (long long)B);
+    if (B > kMaxGridY) {  // the grid's y extent is limited
+        const size_t esz = A.dbl ? 16 : 8;
+        for (int64_t b0 = 0; b0 < B; b0 += kMaxGridY) {
+            hdc_status st = run_col_plain(A, (char*)x + (size_t)(b0 * bs) * esz, std::min<int64_t>(kMaxGridY, B - b0),
+                                          cols, sign, s);
+            if (st != HDC_OK) return st;
+        }
+        return HDC_OK;
+    }
     const double eb = A.dbl ? 16.0 : 8.0;
     if (sign > 0) {
         ColFwdArgs a{};
@@ -708,12 +734,29 @@ hdc_status hdc_plan_nd(hdc_plan_t* out, int ndim, const int64_t* L, const int64_
             st = geometry(A, a < ndim - 1, ndim > 1 && a == ndim - 1);
         }
     }
+    if (st == HDC_OK) st = hdc_plan_nd_check(ndim, L, M, m, p, q, D, dtype, nullptr);
     if (st == HDC_OK) st = finish_plan(P);
     if (st != HDC_OK) {
         delete P;
         return st;
     }
     *out = P;
+    return HDC_OK;
+}
+
+hdc_status hdc_plan_nd_check(int ndim, const int64_t* L, const int64_t* M, const int64_t* m, const int64_t* p,
+                             const int64_t* q, const int64_t* D, hdc_dtype dtype, hdc_axis_desc* out) {
+    if (!L || !M || !m) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+    if (ndim < 1 || ndim > 3) return fail(HDC_ERR_INVALID_ARG, "ndim = %d must be 1..3", ndim);
+    AxisPlan ax[3];
+    for (int a = 0; a < ndim; ++a) {
+        hdc_status st = derive_axis(L[a], M[a], m[a], p ? p[a] : 0, q ? q[a] : 0, 1, D ? D[a] : 0, dtype, &ax[a].d);
+        if (st != HDC_OK) return st;
+        ax[a].dbl = dtype == HDC_C128;
+        st = geometry(ax[a], a < ndim - 1, ndim > 1 && a == ndim - 1);
+        if (st != HDC_OK) return st;
+        if (out) out[a] = ax[a].d;
+    }
     return HDC_OK;
 }
 

@@ -77,3 +77,11 @@ def test_binding_refuses_cpu_tensors():
         p = hdc.Plan.__new__(hdc.Plan)
         p.dtype = 1
         hdc._check_tensor(torch.zeros(4, dtype=torch.complex128), 1, 4, "f")
+
+
+def test_nd_check_is_host_only_and_reports_axes():
+    d = hdc.check_nd([1024, 4096], [2047, 8191], [2048, 4096], dtype="c64")
+    assert d[0]["m1"] * d[0]["m2"] == 2048 and d[0]["variant"] == 1
+    assert d[1]["p"] == 1 and d[1]["q"] == 2
+    with pytest.raises(hdc.HdcError):
+        hdc.check_nd([1024, 4096], [2047, 8191], [1 << 21, 4096], dtype="c64")  # outer m > 2^20

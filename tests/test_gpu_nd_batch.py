@@ -148,3 +148,9 @@ def test_inner_axis_fused_with_many_rows(dtype):
     L = (64, 3000)
     plan, _ = _nd(L, (127, 5999), (64, 4096), dtype, idx=11)
     assert plan.axes[1]["variant"] == 0
+
+
+def test_column_batches_beyond_grid_limit():
+    """(16, 4096, 16): the middle axis's strided pass runs 65536 column batches (> 65535 per launch)."""
+    L = (16, 4096, 16)
+    _nd(L, tuple(2 * a - 1 for a in L), (16, 4096, 16), "c64", idx=99, full=False, nsample=40)
