@@ -39,6 +39,11 @@ hdc_status hdc_mlp_relu_backward(float* dA, const float* A, int64_t n, hipStream
 hdc_status hdc_mlp_softmax_xent(const float* Z, const int32_t* y, float* P, float* dZ, float* loss, int64_t B,
                                 int64_t K, hipStream_t stream);
 
+/* As hdc_mlp_softmax_xent with target distributions T (B x K, rows summing to 1)
+ * instead of labels: dZ = (P - T) / B and *loss = mean_i -sum_k T[i,k] log P[i,k]. */
+hdc_status hdc_mlp_softmax_xent_soft(const float* Z, const float* T, float* P, float* dZ, float* loss, int64_t B,
+                                     int64_t K, hipStream_t stream);
+
 /* One Adam step over n parameters with step count t >= 1 (bias-corrected). */
 hdc_status hdc_mlp_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                         float eps, int64_t t, hipStream_t stream);

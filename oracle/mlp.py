@@ -48,18 +48,31 @@ def cross_entropy(z, y):
     return float(np.mean(lse - z[np.arange(z.shape[0]), y]))
 
 
-def loss(params, X, y):
-    return cross_entropy(forward(params, X)[1], y)
+def cross_entropy_soft(z, T):
+    """Mean over rows of -sum_k T[i, k] log softmax(z)[i, k] (T rows sum to 1)."""
+    z = np.asarray(z, np.float64)
+    m = z.max(axis=1, keepdims=True)
+    logp = z - m - np.log(np.exp(z - m).sum(axis=1, keepdims=True))
+    return float(np.mean(-(np.asarray(T, np.float64) * logp).sum(axis=1)))
 
 
-def backward(params, X, y):
-    """Gradients [(dW_l, db_l)] of the mean cross-entropy, and the loss."""
+def loss(params, X, y=None, T=None):
+    z = forward(params, X)[1]
+    return cross_entropy_soft(z, T) if T is not None else cross_entropy(z, y)
+
+
+def backward(params, X, y=None, T=None):
+    """Gradients [(dW_l, db_l)] of the mean cross-entropy against integer labels y
+    or against target distributions T, and the loss."""
     acts, z = forward(params, X)
     B = z.shape[0]
     p = softmax(z)
-    dz = p.copy()
-    dz[np.arange(B), y] -= 1.0
-    dz /= B
+    if T is not None:
+        dz = (p - np.asarray(T, np.float64)) / B
+    else:
+        dz = p.copy()
+        dz[np.arange(B), y] -= 1.0
+        dz /= B
     grads = [None] * len(params)
     for li in range(len(params) - 1, -1, -1):
         W, _ = params[li]
@@ -68,7 +81,7 @@ def backward(params, X, y):
         if li > 0:
             da = dz @ W
             dz = da * (acts[li] > 0)
-    return grads, cross_entropy(z, y)
+    return grads, (cross_entropy_soft(z, T) if T is not None else cross_entropy(z, y))
 
 
 def adam_step(params, grads, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

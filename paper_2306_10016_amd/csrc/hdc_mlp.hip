@@ -103,6 +103,48 @@ __global__ void __launch_bounds__(256) k_xent_mean(const float* __restrict__ Z, 
     if (threadIdx.x == 0) out[0] = sh[0] / (float)B;
 }
 
+// Soft targets: P = softmax(Z), dZ = (P - T) / B (one thread per row).
+__global__ void k_softmax_soft(const float* __restrict__ Z, const float* __restrict__ T, float* __restrict__ P,
+                               float* __restrict__ dZ, int B, int K) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const float* z = Z + (int64_t)b * K;
+    float mx = z[0];
+    for (int k = 1; k < K; ++k) mx = fmaxf(mx, z[k]);
+    float s = 0.f;
+    for (int k = 0; k < K; ++k) s += expf(z[k] - mx);
+    const float inv = 1.f / s;
+    const float invB = 1.f / (float)B;
+    for (int k = 0; k < K; ++k) {
+        const float pk = expf(z[k] - mx) * inv;
+        P[(int64_t)b * K + k] = pk;
+        if (dZ) dZ[(int64_t)b * K + k] = (pk - T[(int64_t)b * K + k]) * invB;
+    }
+}
+
+// loss = mean_b sum_k -T[b,k] (Z[b,k] - logsumexp(Z_b)); one workgroup, fixed-order sums.
+__global__ void __launch_bounds__(256) k_soft_mean(const float* __restrict__ Z, const float* __restrict__ T,
+                                                  float* __restrict__ out, int B, int K) {
+    __shared__ float sh[256];
+    float s = 0.f;
+    for (int b = threadIdx.x; b < B; b += 256) {
+        const float* z = Z + (int64_t)b * K;
+        float mx = z[0];
+        for (int k = 1; k < K; ++k) mx = fmaxf(mx, z[k]);
+        float e = 0.f;
+        for (int k = 0; k < K; ++k) e += expf(z[k] - mx);
+        const float lse = logf(e) + mx;
+        for (int k = 0; k < K; ++k) s += T[(int64_t)b * K + k] * (lse - z[k]);
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0] / (float)B;
+}
+
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
                        float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float bc1,
                        float bc2) {
@@ -176,6 +218,18 @@ hdc_status hdc_mlp_softmax_xent(const float* Z, const int32_t* y, float* P, floa
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && y && loss) {
         hipLaunchKernelGGL(k_xent_mean, dim3(1), dim3(256), 0, s, Z, y, loss, (int)B, (int)K);
+        e = hipGetLastError();
+    }
+    return e == hipSuccess ? HDC_OK : set_error(HDC_ERR_HIP, hipGetErrorString(e));
+}
+
+hdc_status hdc_mlp_softmax_xent_soft(const float* Z, const float* T, float* P, float* dZ, float* loss, int64_t B,
+                                     int64_t K, hipStream_t s) {
+    if (!Z || !T || !P || !sizes_ok(B, K, 1)) return set_error(HDC_ERR_INVALID_ARG, "mlp soft softmax: bad arguments");
+    hipLaunchKernelGGL(k_softmax_soft, dim3(blocks_for(B)), dim3(256), 0, s, Z, T, P, dZ, (int)B, (int)K);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && loss) {
+        hipLaunchKernelGGL(k_soft_mean, dim3(1), dim3(256), 0, s, Z, T, loss, (int)B, (int)K);
         e = hipGetLastError();
     }
     return e == hipSuccess ? HDC_OK : set_error(HDC_ERR_HIP, hipGetErrorString(e));

@@ -20,6 +20,7 @@ SIGNATURES = {
     "hdc_mlp_linear_backward": [_F, _F, _F, _F, _F, _F, _I, _I, _I, _F],
     "hdc_mlp_relu_backward": [_F, _F, _I, _F],
     "hdc_mlp_softmax_xent": [_F, _F, _F, _F, _F, _I, _I, _F],
+    "hdc_mlp_softmax_xent_soft": [_F, _F, _F, _F, _F, _I, _I, _F],
     "hdc_mlp_adam": [_F, _F, _F, _F, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _I, _F],
 }
 
@@ -91,8 +92,9 @@ class MLP:
                                                    self._stream()))
         return P
 
-    def gradients(self, X, y):
-        """(loss tensor[1], [(dW, db)]) of the mean cross-entropy, all on the device."""
+    def gradients(self, X, y=None, T=None):
+        """(loss tensor[1], [(dW, db)]) of the mean cross-entropy against labels y (int32)
+        or target distributions T (float32, B x K), all on the device."""
         import torch
         Z, acts = self.forward(X)
         B, K = Z.shape
@@ -100,7 +102,10 @@ class MLP:
         P = torch.empty_like(Z)
         dZ = torch.empty_like(Z)
         loss = torch.empty(1, dtype=torch.float32, device=self.device)
-        self._check(self._lib.hdc_mlp_softmax_xent(_p(Z), _p(y), _p(P), _p(dZ), _p(loss), B, K, s))
+        if T is not None:
+            self._check(self._lib.hdc_mlp_softmax_xent_soft(_p(Z), _p(T), _p(P), _p(dZ), _p(loss), B, K, s))
+        else:
+            self._check(self._lib.hdc_mlp_softmax_xent(_p(Z), _p(y), _p(P), _p(dZ), _p(loss), B, K, s))
         grads: List = [None] * len(self.W)
         d = dZ
         for li in range(len(self.W) - 1, -1, -1):
@@ -124,12 +129,13 @@ class MLP:
                 self._check(self._lib.hdc_mlp_adam(_p(P), _p(G), _p(M), _p(V), P.numel(), lr, b1, b2, eps, self.t, s))
 
     def train(self, X, y, epochs: int = 200, batch: int = 256, lr: float = 1e-3, seed: int = 0,
-              log_every: int = 0) -> List[float]:
-        """Mini-batch Adam over host arrays X (n x d) and integer labels y (n,); every batch is
-        shuffled on the host and uploaded.  Returns the mean loss of each epoch."""
+              log_every: int = 0, soft: bool = False) -> List[float]:
+        """Mini-batch Adam over host arrays X (n x d) and integer labels y (n,), or target
+        distributions y (n x K) when soft; every batch is shuffled on the host and
+        uploaded.  Returns the mean loss of each epoch."""
         import torch
         X = np.ascontiguousarray(X, np.float32)
-        y = np.ascontiguousarray(y, np.int32)
+        y = np.ascontiguousarray(y, np.float32 if soft else np.int32)
         n = X.shape[0]
         r = np.random.Generator(np.random.PCG64(seed))
         hist = []
@@ -140,7 +146,7 @@ class MLP:
                 idx = order[i:i + batch]
                 xb = torch.from_numpy(X[idx]).to(self.device)
                 yb = torch.from_numpy(y[idx]).to(self.device)
-                loss, g = self.gradients(xb, yb)
+                loss, g = self.gradients(xb, T=yb) if soft else self.gradients(xb, yb)
                 self.adam(g, lr=lr)
                 losses.append(loss)
             hist.append(float(np.mean([float(v) for v in losses])))

@@ -36,14 +36,16 @@ from . import tune
 
 P_CLASSES = tune.P_CLASSES
 CLASSES: List[Tuple[int, int]] = [(p, dm) for p in P_CLASSES for dm in (0, 1)]  # dm 0: D = q, 1: D = 1
-D_IN = 11
+D_IN = 12
+SOFT_TAU = 0.03  # soft targets: a class 3 % slower than the best gets weight e^-1
 HIDDEN = (128, 128, 128)
 MAX_OUTER_M = 1 << 20  # limit of the outer N-D axes (two column stages of at most 1024)
 
 
 def features(Ls: Sequence[int], axis: int, dtype: str, batch: int = 1) -> np.ndarray:
     """log2 L of this axis, log2 L of the other axes (0 if absent), one-hot axis,
-    one-hot ndim, dtype bit, log2 batch; log-sizes scaled by 1/16."""
+    one-hot ndim, dtype bit, log2 batch (log-sizes scaled by 1/16), and log2 of the
+    total element count (scaled by 1/32)."""
     nd = len(Ls)
     others = [Ls[a] for a in range(nd) if a != axis]
     others += [1] * (2 - len(others))
@@ -51,7 +53,23 @@ def features(Ls: Sequence[int], axis: int, dtype: str, batch: int = 1) -> np.nda
     v += [1.0 if axis == a else 0.0 for a in range(3)]
     v += [1.0 if nd == d else 0.0 for d in (1, 2, 3)]
     v += [1.0 if dtype == "c128" else 0.0, math.log2(max(batch, 1)) / 16.0]
+    v += [math.log2(max(1, int(np.prod(Ls)) * max(batch, 1))) / 32.0]
     return np.asarray(v, np.float32)
+
+
+def soft_target(L: int, M: int, table, outer: bool, tau: float = SOFT_TAU) -> np.ndarray:
+    """Target distribution over classes from one axis's timing table [((m, D), ms)]:
+    weight exp(-(t/t_best - 1)/tau) for every class whose parameters were timed."""
+    times = {c: t for c, t in table}
+    if not times:
+        return np.full(len(CLASSES), 1.0 / len(CLASSES), np.float32)
+    tb = min(times.values())
+    w = np.zeros(len(CLASSES))
+    for ci in range(len(CLASSES)):
+        c = params_of(ci, L, M, outer)
+        if c in times:
+            w[ci] = math.exp(-(times[c] / tb - 1.0) / tau)
+    return (w / w.sum()).astype(np.float32)
 
 
 def class_index(L: int, M: int, m: int, D: int) -> int:
@@ -196,7 +214,9 @@ class Predictor:
         self.history: List[float] = []
 
     def fit(self, X: np.ndarray, y: np.ndarray, epochs: int = 300, lr: float = 2e-3, batch: int = 128):
-        self.history = self.net.train(X, y, epochs=epochs, batch=batch, lr=lr)
+        """Train on labels y (n,) or on target distributions y (n x K)."""
+        soft = y.ndim == 2
+        self.history = self.net.train(X, y, epochs=epochs, batch=batch, lr=lr, soft=soft)
         return self.history
 
     def predict_axes(self, Ls, Ms, dtype, batch=1):
@@ -210,6 +230,22 @@ class Predictor:
             conf.append(float(P[a, ci]))
             cls.append(ci)
         return out, conf, cls
+
+    def shortlist(self, Ls, Ms, dtype, k=2, batch=1):
+        """Per axis, the parameters of the k most probable distinct classes."""
+        X = np.stack([features(Ls, a, dtype, batch) for a in range(len(Ls))])
+        P = self.net.predict_proba(X)
+        out = []
+        for a in range(len(Ls)):
+            cands = []
+            for ci in np.argsort(-P[a], kind="stable"):
+                c = params_of(int(ci), Ls[a], Ms[a], outer=a < len(Ls) - 1)
+                if c not in cands:
+                    cands.append(c)
+                if len(cands) == k:
+                    break
+            out.append(cands)
+        return out
 
     def choose(self, Ls, Ms, dtype, timer, batch=1):
         """Predicted parameters, or exhaustive per-axis tuning when confidence is low."""
@@ -286,7 +322,7 @@ def main(argv=None):
     probs = training_problems()
     if args.max_problems:
         probs = probs[:args.max_problems]
-    X, y, meta = [], [], []
+    X, y, T, meta = [], [], [], []
     t0 = time.time()
     for i, (Ls, batch, dt) in enumerate(probs):
         Ms = [2 * L - 1 for L in Ls]
@@ -294,13 +330,15 @@ def main(argv=None):
         for a in range(len(Ls)):
             X.append(features(Ls, a, dt, batch))
             y.append(class_index(Ls[a], Ms[a], best[a][0], best[a][1]))
+            T.append(soft_target(Ls[a], Ms[a], tables[a], outer=a < len(Ls) - 1))
         meta.append({"L": Ls, "batch": batch, "dtype": dt, "best": best})
         if i % 25 == 0:
             print(f"[predict] tuned {i + 1}/{len(probs)} ({time.time() - t0:.0f} s)", flush=True)
     X = np.stack(X)
     y = np.asarray(y, np.int32)
+    T = np.stack(T)
     pred = Predictor(seed=0)
-    hist = pred.fit(X, y, epochs=args.epochs)
+    hist = pred.fit(X, T, epochs=args.epochs)  # soft targets from the timing tables
     train_acc = float(np.mean(np.argmax(pred.net.predict_proba(X), 1) == y))
     print(f"[predict] trained: loss {hist[0]:.3f} -> {hist[-1]:.3f}, train accuracy {train_acc:.3f}", flush=True)
     results = {"train": {"problems": len(probs), "rows": int(len(y)), "loss_first": hist[0], "loss_last": hist[-1],
@@ -322,7 +360,17 @@ def main(argv=None):
             rb, _, _ = tune_separable([Ls[0], 32], [Ms[0], 63], dt, timer)
             rect = [rb[0], dflt[1]]
             t_rect = timer(Ls, Ms, [p[0] for p in rect], [p[1] for p in rect], dt)
+        # the network's top-2 classes per axis, verified by timing at the target size
+        short = pred.shortlist(Ls, Ms, dt, k=2)
+        srows = []
+        for combo in itertools.product(*short):
+            srows.append((list(combo), timer(Ls, Ms, [c[0] for c in combo], [c[1] for c in combo], dt)))
+        srows.sort(key=lambda r: r[1])
+        ent_short = {"params": srows[0][0], "timings": len(srows)}
+        t_short = timer(Ls, Ms, [c[0] for c in srows[0][0]], [c[1] for c in srows[0][0]], dt)
+        ent_short.update({"ms": t_short, "regret": tune.regret(t_short, best_t)})
         ent = {"L": Ls, "dtype": dt, "joint_best": {"params": best_p, "ms": best_t}, "joint_candidates": len(joint),
+               "predicted_top2_verified": ent_short,
                "predicted": {"params": params, "confidence": conf, "ms": t_pred,
                              "regret": tune.regret(t_pred, best_t)},
                "default": {"params": dflt, "ms": t_def, "regret": tune.regret(t_def, best_t)},
@@ -330,8 +378,10 @@ def main(argv=None):
         if t_rect is not None:
             ent["rect32"] = {"params": rect, "ms": t_rect, "regret": tune.regret(t_rect, best_t)}
         results["eval"].append(ent)
-        print(f"[predict] {Ls} {dt}: best {best_t:.3f} ms, predicted {t_pred:.3f} ms "
-              f"(regret {ent['predicted']['regret']:.3f}), default regret {ent['default']['regret']:.3f}", flush=True)
+        print(f"[predict] {Ls} {dt}: best {best_t:.3f} ms ({len(joint)} timings), predicted {t_pred:.3f} ms "
+              f"(regret {ent['predicted']['regret']:.3f}), top-2 verified {t_short:.3f} ms (regret "
+              f"{ent_short['regret']:.3f}, {len(srows)} timings), default regret {ent['default']['regret']:.3f}",
+              flush=True)
     # the autotuner's own regret: A1 (experience) against A0 (exhaustive) on 1D sizes
     # it has not seen, re-timed under the same conditions
     t1 = tune.Tuner1D(tune.TuneDB(None), reps=5, warmup=2, seed=3)
@@ -352,6 +402,7 @@ def main(argv=None):
     os.makedirs(os.path.dirname(args.out) or ".", exist_ok=True)
     json.dump(results, open(args.out, "w"), indent=1)
     print(json.dumps({"eval": [{"L": e["L"], "regret": round(e["predicted"]["regret"], 4),
+                                "top2_verified_regret": round(e["predicted_top2_verified"]["regret"], 4),
                                 "default_regret": round(e["default"]["regret"], 4)} for e in results["eval"]]}))
 
 

@@ -77,3 +77,17 @@ def test_training_learns_a_separable_rule():
     acc = float(np.mean(np.argmax(net.predict_proba(X), 1) == y))
     say(f"mlp toy: loss {hist[0]:.3f} -> {hist[-1]:.3f}, accuracy {acc:.3f}")
     assert hist[-1] < 0.3 * hist[0] and acc > 0.9
+
+
+def test_soft_targets_match_reference():
+    import torch
+    net, Xt, yt, params64, X64, y = _setup([11, 32, 32, 32, 16], 64, seed=7)
+    r = synth.rng(502, 0, 0)
+    T = r.random((64, 16))
+    T /= T.sum(1, keepdims=True)
+    Tt = torch.tensor(T, dtype=torch.float32, device="cuda")
+    loss, grads = net.gradients(Xt, T=Tt)
+    g_ref, l_ref = ref.backward(params64, X64, T=T.astype(np.float32).astype(np.float64))
+    assert abs(float(loss) - l_ref) <= 1e-5 * max(1.0, abs(l_ref))
+    for (dW, db), (rW, rb) in zip(grads, g_ref):
+        assert _rel(dW.cpu().numpy(), rW) < 1e-4 and _rel(db.cpu().numpy(), rb) < 1e-4

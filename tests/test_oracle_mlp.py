@@ -90,3 +90,27 @@ def test_training_decreases_loss():
         g, _ = mlp.backward(params, X, y)
         params, m, v = mlp.adam_step(params, g, m, v, t, lr=1e-2)
     assert mlp.loss(params, X, y) < 0.5 * l0
+
+
+def test_soft_targets_reduce_to_hard_labels_and_match_differences():
+    X, y = _data(11, 5, 4, seed=21)
+    params = _net([5, 8, 8, 8, 4], seed=21)
+    onehot = np.eye(4)[y]
+    g_hard, l_hard = mlp.backward(params, X, y=y)
+    g_soft, l_soft = mlp.backward(params, X, T=onehot)
+    assert abs(l_hard - l_soft) < 1e-14
+    for (a, b), (c, d) in zip(g_hard, g_soft):
+        assert np.allclose(a, c, atol=1e-15) and np.allclose(b, d, atol=1e-15)
+    T = synth.rng(404, 0, 0).random((11, 4))
+    T /= T.sum(1, keepdims=True)
+    g, _ = mlp.backward(params, X, T=T)
+    W = params[1][0]
+    h = 1e-6
+    for idx in [(0, 0), (3, 5), (7, 2)]:
+        old = W[idx]
+        W[idx] = old + h
+        lp = mlp.loss(params, X, T=T)
+        W[idx] = old - h
+        lm = mlp.loss(params, X, T=T)
+        W[idx] = old
+        assert abs((lp - lm) / (2 * h) - g[1][0][idx]) < 1e-8

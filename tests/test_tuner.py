@@ -110,6 +110,16 @@ def test_features_encoding():
     assert f[0] == pytest.approx(8 / 16) and f[1] == pytest.approx(12 / 16) and f[2] == 0.0
     assert list(f[3:6]) == [0, 1, 0] and list(f[6:9]) == [0, 1, 0]
     assert f[9] == 1.0 and f[10] == pytest.approx(2 / 16)
+    assert f[11] == pytest.approx(np.log2(4096 * 256 * 4) / 32)
+
+
+def test_soft_target_weights():
+    table = [((1024, 2), 1.00), ((512, 4), 1.03), ((256, 8), 1.5)]
+    t = predict.soft_target(1000, 1999, table, outer=False)
+    assert t.sum() == pytest.approx(1.0)
+    i1 = predict.class_index(1000, 1999, 1024, 2)
+    i2 = predict.class_index(1000, 1999, 512, 4)
+    assert t[i1] > t[i2] > 0 and t[i1] / t[i2] == pytest.approx(np.e, rel=1e-3)
 
 
 def test_training_problems_within_bound():
