@@ -60,8 +60,6 @@ struct ColFwdArgs {
     TwN tw;
     const void* tw1;           // zeta_{m1}^e, e < m1, data type
     const int64_t* desc;       // optional per-batch {input offset, L}; replaces b*in_bs and L
-    const void* x2;            // second operand for the dual-operand kernel (NULL: one operand)
-    void* X2;
 };
 
 struct ColBwdArgs {
@@ -97,8 +95,6 @@ hipError_t launch_fused(bool dbl, int m, const FusedArgs& a, int threads, int64_
                         hipStream_t s);
 hipError_t launch_col_fwd(bool dbl, int m1, const ColFwdArgs& a, int threads, int64_t gx, int64_t gy,
                           size_t lds, hipStream_t s);
-hipError_t launch_col_fwd2(bool dbl, int m1, const ColFwdArgs& a, int threads, int64_t gx, int64_t gy,
-                           size_t lds, hipStream_t s);
 hipError_t launch_col_bwd(bool dbl, int m1, const ColBwdArgs& a, int threads, int64_t gx, int64_t gy,
                           size_t lds, hipStream_t s);
 hipError_t launch_row(bool dbl, int m2, const RowArgs& a, int threads, int64_t blocks, size_t lds,

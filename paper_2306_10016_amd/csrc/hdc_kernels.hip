@@ -513,99 +513,6 @@ __global__ void __launch_bounds__(1024) k_col_fwd(ColFwdArgs a) {
 #undef HDC_LOAD
 }
 
-// Forward column stage for both operands in one workgroup, 16 points per
-// thread (512 threads for m1 = 1024): the g tile's loads are issued together
-// with the f tile's, so they are in flight while f is transformed.
-template <typename T, int M1>
-__global__ void __launch_bounds__(512) k_col_fwd2(ColFwdArgs a) {
-    constexpr int PPT = 16;
-    using S = TwSplit<M1>;
-    constexpr int TPF = M1 / PPT;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-    cplx<T>* tlo = lds + (size_t)M1 * a.tile;
-    cplx<T>* thi = tlo + S::LO;
-    {
-        const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.tw1);
-        for (int e = threadIdx.x; e < S::LO; e += blockDim.x) tlo[e] = twg[e];
-        for (int e = threadIdx.x; e < S::HI; e += blockDim.x) thi[e] = twg[e * S::LO];
-        __syncthreads();
-    }
-    const TwLds<T> tw1{tlo, thi, S::LO - 1, S::LG};
-
-    const int task = xcd_task(blockIdx.x, gridDim.x);
-    if (task >= a.ntiles * a.Dg) return;
-    const int tl = task / a.Dg;
-    const int d = task - tl * a.Dg;
-    const int tile = a.tile;
-    const int tid = threadIdx.x;
-    const int cc = tid % tile;
-    const int lane = tid / tile;
-    const int64_t b = blockIdx.y;
-    const int cp = tl * tile + cc;
-    const bool ok = cp < a.Ccols;
-    const int s2 = ok ? cp / a.C1 : 0;
-    const int64_t L = a.L;
-    const int r = a.r0 + d;
-    const bool two = a.x2 != nullptr;
-    const cplx<T>* xs[2] = {reinterpret_cast<const cplx<T>*>(a.x) + b * a.in_bs,
-                            reinterpret_cast<const cplx<T>*>(two ? a.x2 : a.x) + b * a.in_bs};
-    cplx<T>* Xs[2] = {reinterpret_cast<cplx<T>*>(a.X) + b * a.out_bs,
-                      reinterpret_cast<cplx<T>*>(two ? a.X2 : a.X) + b * a.out_bs};
-#define HDC_LOAD2(src, t, v)                                                                  \
-    ((ok && (((int64_t)(t) * M1 + lane + (v) * TPF) * a.m2 + s2) < L)                         \
-         ? (src)[((int64_t)(t) * M1 + lane + (v) * TPF) * a.Ccols + cp]                       \
-         : mk<T>(0, 0))
-    // twiddle seeds first, then both tiles' first blocks: everything in flight at once
-    const uint32_t N = (uint32_t)a.N;
-    const double2 z0 = tw_n(a.tw, (uint32_t)(((uint64_t)r * ((uint64_t)lane * a.m2 + s2)) % N));
-    const double2 zs = tw_n(a.tw, (uint32_t)(((uint64_t)r * a.m2 * TPF) % N));
-    const bool fs = a.m2 > 1 && s2 != 0;
-    const double2 f0 = tw_n(a.tw, fs ? (uint32_t)lane * (uint32_t)s2 * (uint32_t)a.q : 0u);
-    const double2 fz = tw_n(a.tw, fs ? (uint32_t)TPF * (uint32_t)s2 * (uint32_t)a.q : 0u);
-    cplx<T> w[2][PPT];
-#pragma unroll
-    for (int o = 0; o < 2; ++o)
-#pragma unroll
-        for (int v = 0; v < PPT; ++v) w[o][v] = (o == 0 || two) ? HDC_LOAD2(xs[o], 0, v) : mk<T>(0, 0);
-#pragma unroll
-    for (int o = 0; o < 2; ++o) {
-        if (o == 1 && !two) break;
-        int e = r;  // (r t) mod q for t = 1
-        if (e >= a.q) e -= a.q;
-        for (int t = 1; t < a.p; ++t) {
-            const double2 z = tw_n(a.tw, (uint32_t)e * (uint32_t)a.m);
-            e += r;
-            if (e >= a.q) e -= a.q;
-#pragma unroll
-            for (int v = 0; v < PPT; ++v) w[o][v] = w[o][v] + mul_tw<false>(HDC_LOAD2(xs[o], t, v), z, a.hiprec);
-        }
-        if (r != 0) {
-            double2 z = z0;
-#pragma unroll
-            for (int v = 0; v < PPT; ++v) {
-                w[o][v] = mul_tw<false>(w[o][v], z, a.hiprec);
-                z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
-            }
-        }
-        fft_regs<T, M1, +1, false, PPT>(w[o], lds + cc, tile, lane, tw1, true);
-        if (fs) {
-            double2 z = f0;
-#pragma unroll
-            for (int v = 0; v < PPT; ++v) {
-                w[o][v] = mul_tw<false>(w[o][v], z, a.hiprec);
-                z = make_double2(z.x * fz.x - z.y * fz.y, z.x * fz.y + z.y * fz.x);
-            }
-        }
-#pragma unroll
-        for (int v = 0; v < PPT; ++v) {
-            const int l1 = lane + v * TPF;
-            if (ok) Xs[o][((int64_t)d * M1 + l1) * a.Ccols + cp] = w[o][v];
-        }
-    }
-#undef HDC_LOAD2
-}
-
 template <typename T, int M1, int DMAX>
 __global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
     using P = FP<M1>;
@@ -849,19 +756,6 @@ hipError_t colf_t(const ColFwdArgs& a, int threads, int64_t gx, int64_t gy, size
 }
 
 template <typename T, int M1>
-hipError_t colf2_t(const ColFwdArgs& a, int threads, int64_t gx, int64_t gy, size_t lds, hipStream_t s) {
-    if constexpr (M1 < 16) {
-        return hipErrorInvalidValue;
-    } else {
-        lds += (size_t)(TwSplit<M1>::LO + TwSplit<M1>::HI) * sizeof(cplx<T>);
-        hipError_t e = allow_lds(k_col_fwd2<T, M1>, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_col_fwd2<T, M1>), dim3((unsigned)gx, (unsigned)gy), dim3(threads), lds, s, a);
-        return hipGetLastError();
-    }
-}
-
-template <typename T, int M1>
 hipError_t colb_t(const ColBwdArgs& a, int threads, int64_t gx, int64_t gy, size_t lds, hipStream_t s) {
     constexpr int DMAX = sizeof(T) == 8 ? 2 : 4;
     lds += (size_t)(TwSplit<M1>::LO + TwSplit<M1>::HI) * sizeof(cplx<T>);
@@ -954,20 +848,6 @@ static hipError_t colf_disp(int m1, const ColFwdArgs& a, int th, int64_t gx, int
 }
 
 template <typename T>
-static hipError_t colf2_disp(int m1, const ColFwdArgs& a, int th, int64_t gx, int64_t gy, size_t lds, hipStream_t s) {
-    switch (m1) {
-        case 16: return colf2_t<T, 16>(a, th, gx, gy, lds, s);
-        case 32: return colf2_t<T, 32>(a, th, gx, gy, lds, s);
-        case 64: return colf2_t<T, 64>(a, th, gx, gy, lds, s);
-        case 128: return colf2_t<T, 128>(a, th, gx, gy, lds, s);
-        case 256: return colf2_t<T, 256>(a, th, gx, gy, lds, s);
-        case 512: return colf2_t<T, 512>(a, th, gx, gy, lds, s);
-        case 1024: return colf2_t<T, 1024>(a, th, gx, gy, lds, s);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename T>
 static hipError_t colb_disp(int m1, const ColBwdArgs& a, int th, int64_t gx, int64_t gy, size_t lds, hipStream_t s) {
     switch (m1) {
         HDC_POW2_CASES(colb_t, a, th, gx, gy, lds, s)
@@ -988,12 +868,6 @@ hipError_t launch_col_fwd(bool dbl, int m1, const ColFwdArgs& a, int threads, in
                           hipStream_t s) {
     return dbl ? colf_disp<double>(m1, a, threads, gx, gy, lds, s)
                : colf_disp<float>(m1, a, threads, gx, gy, lds, s);
-}
-
-hipError_t launch_col_fwd2(bool dbl, int m1, const ColFwdArgs& a, int threads, int64_t gx, int64_t gy, size_t lds,
-                           hipStream_t s) {
-    return dbl ? colf2_disp<double>(m1, a, threads, gx, gy, lds, s)
-               : colf2_disp<float>(m1, a, threads, gx, gy, lds, s);
 }
 
 hipError_t launch_col_bwd(bool dbl, int m1, const ColBwdArgs& a, int threads, int64_t gx, int64_t gy, size_t lds,
