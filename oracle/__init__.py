@@ -55,6 +55,8 @@ def _load():
         lib.oracle_direct_1d_sampled.argtypes = [_I64, _I64, _P, _P, _P, _I64, _P]
         lib.oracle_direct_nd_sampled.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P, _I64, _P]
         lib.oracle_padded_1d.argtypes = [_I64, _I64, _I64, _P, _P, _P]
+        lib.oracle_direct_1d_uneq.argtypes = [_I64, _I64, _I64, _I64, _P, _P, _P]
+        lib.oracle_padded_1d_uneq.argtypes = [_I64, _I64, _I64, _I64, _P, _P, _P]
         lib.oracle_padded_nd.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P]
         lib.oracle_dft.argtypes = [_I64, _P, ctypes.c_int]
         lib.oracle_padded_dft.argtypes = [_I64, _I64, _P, _P]
@@ -93,14 +95,16 @@ def _check(rc, name):
 
 
 def direct_1d(f, g, M: int) -> np.ndarray:
-    """h_k = sum_j f_j g_{k-j} for k < M (eq. (4)); f, g of shape (L,) or (L, C)."""
+    """h_k = sum_j f_j g_{k-j} for k < M (eq. (4)); f of shape (Lf,) or (Lf, C), g of
+    shape (Lg,) or (Lg, C) (Lf and Lg may differ: the unequal case of section 3.5)."""
     f2, flat = _as_2d(f)
     g2, _ = _as_2d(g)
-    if f2.shape != g2.shape:
-        raise ValueError("f and g must have the same shape")
-    L, C = f2.shape
+    if f2.shape[1] != g2.shape[1]:
+        raise ValueError("f and g must have the same number of copies")
+    Lf, C = f2.shape
     h = np.empty((int(M), C), np.complex128)
-    _check(_load().oracle_direct_1d(L, int(M), C, f2.ctypes.data, g2.ctypes.data, h.ctypes.data), "direct_1d")
+    _check(_load().oracle_direct_1d_uneq(Lf, g2.shape[0], int(M), C, f2.ctypes.data, g2.ctypes.data, h.ctypes.data),
+           "direct_1d")
     return h.reshape(-1) if flat else h
 
 
@@ -138,14 +142,16 @@ def direct_nd(f, g, M) -> np.ndarray:
 
 
 def padded_1d(f, g, M: int) -> np.ndarray:
-    """Explicitly zero-padded FFT convolution (section 3.1), output length M."""
+    """Explicitly zero-padded FFT convolution (section 3.1), output length M; f and g may
+    have different lengths (padding to the smallest friendly size >= Lf + Lg - 1)."""
     f2, flat = _as_2d(f)
     g2, _ = _as_2d(g)
-    if f2.shape != g2.shape:
-        raise ValueError("f and g must have the same shape")
-    L, C = f2.shape
+    if f2.shape[1] != g2.shape[1]:
+        raise ValueError("f and g must have the same number of copies")
+    Lf, C = f2.shape
     h = np.empty((int(M), C), np.complex128)
-    _check(_load().oracle_padded_1d(L, int(M), C, f2.ctypes.data, g2.ctypes.data, h.ctypes.data), "padded_1d")
+    _check(_load().oracle_padded_1d_uneq(Lf, g2.shape[0], int(M), C, f2.ctypes.data, g2.ctypes.data, h.ctypes.data),
+           "padded_1d")
     return h.reshape(-1) if flat else h
 
 

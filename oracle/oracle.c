@@ -9,6 +9,8 @@
  *   the linear convolution of two length-L sequences, eq. (4) of section 2.3,
  *       h_k = sum_{j} f_j g_{k-j},   0 <= j < L, 0 <= k-j < L,
  *   reported over the output length M (M >= 2L-1); entries k >= 2L-1 are 0.
+ *   Unequal lengths (section 3.5): f of length Lf, g of length Lg, the same sum
+ *   with 0 <= j < Lf, 0 <= k-j < Lg, over M >= Lf + Lg - 1.
  *   N-D: the same sum per axis over the box [0, M_1) x ... x [0, M_d).
  *
  * Two independent routes, deliberately plain:
@@ -48,9 +50,11 @@ int oracle_num_threads(void) {
 
 /* ---------------------------------------------------------------- direct -- */
 
-/* eq. (4), all copies, all k < M. */
-int oracle_direct_1d(int64_t L, int64_t M, int64_t C, const double* f_, const double* g_, double* h_) {
-    if (L < 0 || M < 0 || C < 1) return 1;
+/* eq. (4) for operands of lengths Lf and Lg (f_j = 0 for j >= Lf, g_j = 0 for
+ * j >= Lg, the unequal case of section 3.5), all copies, all k < M. */
+int oracle_direct_1d_uneq(int64_t Lf, int64_t Lg, int64_t M, int64_t C, const double* f_, const double* g_,
+                          double* h_) {
+    if (Lf < 0 || Lg < 0 || M < 0 || C < 1) return 1;
     const cd* f = (const cd*)f_;
     const cd* g = (const cd*)g_;
     cd* h = (cd*)h_;
@@ -58,13 +62,18 @@ int oracle_direct_1d(int64_t L, int64_t M, int64_t C, const double* f_, const do
     for (int64_t k = 0; k < M; ++k) {
         for (int64_t c = 0; c < C; ++c) {
             cd acc = {0.0, 0.0};
-            int64_t jlo = k - (L - 1) > 0 ? k - (L - 1) : 0;
-            int64_t jhi = k < L - 1 ? k : L - 1;
+            int64_t jlo = k - (Lg - 1) > 0 ? k - (Lg - 1) : 0;
+            int64_t jhi = k < Lf - 1 ? k : Lf - 1;
             for (int64_t j = jlo; j <= jhi; ++j) acc = cadd(acc, cmul(f[j * C + c], g[(k - j) * C + c]));
             h[k * C + c] = acc;
         }
     }
     return 0;
+}
+
+/* eq. (4), all copies, all k < M. */
+int oracle_direct_1d(int64_t L, int64_t M, int64_t C, const double* f_, const double* g_, double* h_) {
+    return oracle_direct_1d_uneq(L, L, M, C, f_, g_, h_);
 }
 
 /* eq. (4) for the listed output indices only (copy 0 .. C-1 of each). */
@@ -198,14 +207,16 @@ int oracle_dft(int64_t n, double* x_, int sign) {
 
 /* -------------------------------------------------------- explicit padding -- */
 
-/* Explicitly zero-padded FFT convolution, 1D with C copies (section 3.1). */
-int oracle_padded_1d(int64_t L, int64_t M, int64_t C, const double* f_, const double* g_, double* h_) {
-    if (L < 1 || M < 1 || C < 1) return 1;
+/* Explicitly zero-padded FFT convolution of lengths Lf and Lg, 1D with C copies
+ * (section 3.1; padding to the smallest friendly size >= Lf + Lg - 1). */
+int oracle_padded_1d_uneq(int64_t Lf, int64_t Lg, int64_t M, int64_t C, const double* f_, const double* g_,
+                          double* h_) {
+    if (Lf < 1 || Lg < 1 || M < 1 || C < 1) return 1;
     const cd* f = (const cd*)f_;
     const cd* g = (const cd*)g_;
     cd* h = (cd*)h_;
-    int64_t Ne = oracle_friendly_size(2 * L - 1);
-    int64_t Kmax = 2 * L - 1 < M ? 2 * L - 1 : M;
+    int64_t Ne = oracle_friendly_size(Lf + Lg - 1);
+    int64_t Kmax = Lf + Lg - 1 < M ? Lf + Lg - 1 : M;
     cd* rp = root_table(Ne, +1);
     cd* rm = root_table(Ne, -1);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -214,7 +225,8 @@ int oracle_padded_1d(int64_t L, int64_t M, int64_t C, const double* f_, const do
         cd* b = (cd*)calloc((size_t)Ne, sizeof(cd));
         cd* o = (cd*)malloc(sizeof(cd) * (size_t)Ne);
         cd* s = (cd*)malloc(sizeof(cd) * (size_t)Ne);
-        for (int64_t j = 0; j < L; ++j) { a[j] = f[j * C + c]; b[j] = g[j * C + c]; }
+        for (int64_t j = 0; j < Lf; ++j) a[j] = f[j * C + c];
+        for (int64_t j = 0; j < Lg; ++j) b[j] = g[j * C + c];
         dft_rec(a, 1, Ne, o, rp, Ne, s); memcpy(a, o, sizeof(cd) * (size_t)Ne);
         dft_rec(b, 1, Ne, o, rp, Ne, s); memcpy(b, o, sizeof(cd) * (size_t)Ne);
         for (int64_t k = 0; k < Ne; ++k) a[k] = cmul(a[k], b[k]);
@@ -228,6 +240,11 @@ int oracle_padded_1d(int64_t L, int64_t M, int64_t C, const double* f_, const do
     }
     free(rp); free(rm);
     return 0;
+}
+
+/* Explicitly zero-padded FFT convolution, 1D with C copies (section 3.1). */
+int oracle_padded_1d(int64_t L, int64_t M, int64_t C, const double* f_, const double* g_, double* h_) {
+    return oracle_padded_1d_uneq(L, L, M, C, f_, g_, h_);
 }
 
 /* DFT along one axis of a row-major array with extents ext[0..nd-1]. */

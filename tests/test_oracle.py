@@ -248,3 +248,25 @@ def test_golden_fixtures_exact(name):
     assert np.array_equal(h, _exact_int_conv(f, g, M))
     assert np.array_equal(oracle.direct_1d(f, g, M), h)
     assert np.array_equal(np.round(oracle.padded_1d(f, g, M)), h)
+
+
+
+@pytest.mark.parametrize("Lf,Lg", [(1, 9), (2, 100), (12, 100), (12, 1000), (37, 38), (100, 2187)])
+def test_unequal_lengths_match_numpy_convolve(Lf, Lg):
+    """The unequal case (section 3.5): operands of different lengths."""
+    f = synth.uniform_complex(Lf, 103, Lf, 0)
+    g = synth.uniform_complex(Lg, 103, Lg, 1)
+    ref = np.convolve(f, g)
+    for M in (Lf + Lg - 1, Lf + Lg + 5):
+        for h in (oracle.direct_1d(f, g, M), oracle.padded_1d(f, g, M)):
+            assert oracle.rel_l2(h[:Lf + Lg - 1], ref) < 1e-14
+            assert np.all(h[Lf + Lg - 1:] == 0)
+
+
+def test_unequal_lengths_integer_exact():
+    f = synth.gaussian_integers(12, 8, 104, 0, 0)
+    g = synth.gaussian_integers(777, 8, 104, 0, 1)
+    exact = np.array([sum(complex(int(f[j].real), int(f[j].imag)) * complex(int(g[k - j].real), int(g[k - j].imag))
+                          for j in range(max(0, k - 776), min(k, 11) + 1)) for k in range(788)])
+    assert np.array_equal(oracle.direct_1d(f, g, 788), exact)
+    assert np.array_equal(np.round(oracle.padded_1d(f, g, 788)), exact)
