@@ -102,6 +102,40 @@ hdc_status hdc_plan_nd(hdc_plan_t* out, int ndim, const int64_t* L, const int64_
 hdc_status hdc_plan_nd_check(int ndim, const int64_t* L, const int64_t* M, const int64_t* m, const int64_t* p,
                              const int64_t* q, const int64_t* D, hdc_dtype dtype, hdc_axis_desc* out);
 
+/*
+ * Unequal operand lengths (section 3.5): h = f * g for f of length Lf and g of
+ * length Lg, k = 0 .. M-1 with M >= Lf + Lg - 1, C copies.  Roles follow the
+ * lengths: the shorter operand is cut into m-point residues and the longer
+ * into Lambda m-point residues,
+ *     p_f = ceil(Ls/m), p_g = ceil(Ll/(Lambda m)), q_g = ceil(M/(Lambda m)), q_f = Lambda q_g,
+ * both of transform length N = q_g Lambda m.  Residue r_g of the longer operand
+ * meets, at its point l_g, point floor(l_g/Lambda) of the shorter operand's
+ * residue r_f = q_g (l_g mod Lambda) + r_g; the product and the backward run in
+ * the longer operand's geometry, D residues of it per pass.
+ * m = 0 derives m (and Lambda if 0) so that both operands fit one block
+ * (p_f = p_g = 1) within the limits below; Lambda = 0 with m > 0 derives Lambda
+ * the same way.  Admissible: Lf, Lg, C >= 1, M >= Lf + Lg - 1, D >= 0.
+ * HDC_ERR_UNSUPPORTED unless m and Lambda are powers of two with
+ * Lambda <= 1024 and Lambda m <= 2^22.
+ *
+ * hdc_uneq_derive is host-only: it fills the shorter operand's description
+ * (m, p_f, q_f, its four-step split) and the longer one's (Lambda m, p_g, q_g,
+ * D, q_out), and *swapped = 1 when Lf > Lg (then g plays the shorter role).
+ * Any output pointer may be NULL.
+ */
+hdc_status hdc_uneq_derive(int64_t Lf, int64_t Lg, int64_t M, int64_t m, int64_t Lambda, int64_t C, int64_t D,
+                           hdc_dtype dtype, hdc_axis_desc* short_out, hdc_axis_desc* long_out, int* swapped);
+
+/* Plan of the unequal-length convolution above (allocates its twiddle tables).
+ * hdc_convolve(plan, f, g, h, ws, s) then reads Lf x C values of f and
+ * Lg x C of g.  hdc_plan_axis reports ndim = 1, axis 0 the longer operand's
+ * description and axis 1 the shorter one's.  hdc_forward is rejected for such
+ * a plan (use hdc_forward_operand); hdc_multiply, hdc_backward,
+ * hdc_residues_natural and hdc_residue_buffer_size use the longer operand's
+ * geometry. */
+hdc_status hdc_plan_uneq(hdc_plan_t* out, int64_t Lf, int64_t Lg, int64_t M, int64_t m, int64_t Lambda, int64_t C,
+                         int64_t D, hdc_dtype dtype);
+
 hdc_status hdc_plan_destroy(hdc_plan_t plan);
 
 /* Number of axes and the description of axis `axis`. */
@@ -128,6 +162,18 @@ hdc_status hdc_convolve(hdc_plan_t plan, const void* f, const void* g, void* h, 
  * r0 must be a multiple of D.  ws: hdc_workspace_size bytes.
  */
 hdc_status hdc_forward(hdc_plan_t plan, const void* f, void* F, int64_t r0, void* ws, hipStream_t stream);
+
+/*
+ * hdc_forward for one operand: operand 0 is f, 1 is g.  For an equal-length
+ * plan it is hdc_forward.  For an unequal-length plan it fills the residue
+ * buffer of group [r0, r0 + D') of the longer operand's geometry (D' x Lambda m
+ * x C values): for the longer operand its Lambda m-point residues; for the
+ * shorter one the matching values of its m-point residues (section 3.5),
+ * which sit at the same indices k = q_g l_g + r of the length-N transform, so
+ * hdc_multiply pairs them point by point.
+ */
+hdc_status hdc_forward_operand(hdc_plan_t plan, int operand, const void* x, void* F, int64_t r0, void* ws,
+                               hipStream_t stream);
 
 /* Pointwise product of two residue buffers of the same group: F <- F . G. */
 hdc_status hdc_multiply(hdc_plan_t plan, void* F, const void* G, int64_t r0, hipStream_t stream);

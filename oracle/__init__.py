@@ -56,6 +56,7 @@ def _load():
         lib.oracle_direct_nd_sampled.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P, _I64, _P]
         lib.oracle_padded_1d.argtypes = [_I64, _I64, _I64, _P, _P, _P]
         lib.oracle_direct_1d_uneq.argtypes = [_I64, _I64, _I64, _I64, _P, _P, _P]
+        lib.oracle_direct_1d_uneq_sampled.argtypes = [_I64, _I64, _I64, _P, _P, _P, _I64, _P]
         lib.oracle_padded_1d_uneq.argtypes = [_I64, _I64, _I64, _I64, _P, _P, _P]
         lib.oracle_padded_nd.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P]
         lib.oracle_dft.argtypes = [_I64, _P, ctypes.c_int]
@@ -109,14 +110,16 @@ def direct_1d(f, g, M: int) -> np.ndarray:
 
 
 def direct_1d_sampled(f, g, ks) -> np.ndarray:
-    """eq. (4) evaluated only at the output indices ``ks``."""
+    """eq. (4) evaluated only at the output indices ``ks`` (f and g may differ in length)."""
     f2, flat = _as_2d(f)
     g2, _ = _as_2d(g)
-    L, C = f2.shape
+    if f2.shape[1] != g2.shape[1]:
+        raise ValueError("f and g must have the same number of copies")
+    Lf, C = f2.shape
     ks = np.ascontiguousarray(ks, dtype=np.int64)
     out = np.empty((ks.size, C), np.complex128)
-    _load().oracle_direct_1d_sampled(L, C, f2.ctypes.data, g2.ctypes.data, ks.ctypes.data, ks.size,
-                                     out.ctypes.data)
+    _check(_load().oracle_direct_1d_uneq_sampled(Lf, g2.shape[0], C, f2.ctypes.data, g2.ctypes.data, ks.ctypes.data,
+                                                 ks.size, out.ctypes.data), "direct_1d_sampled")
     return out.reshape(-1) if flat else out
 
 

@@ -76,9 +76,11 @@ int oracle_direct_1d(int64_t L, int64_t M, int64_t C, const double* f_, const do
     return oracle_direct_1d_uneq(L, L, M, C, f_, g_, h_);
 }
 
-/* eq. (4) for the listed output indices only (copy 0 .. C-1 of each). */
-int oracle_direct_1d_sampled(int64_t L, int64_t C, const double* f_, const double* g_,
-                             const int64_t* ks, int64_t nk, double* out_) {
+/* eq. (4) for the listed output indices only (copy 0 .. C-1 of each), operands
+ * of lengths Lf and Lg (section 3.5; Lf = Lg is the equal case). */
+int oracle_direct_1d_uneq_sampled(int64_t Lf, int64_t Lg, int64_t C, const double* f_, const double* g_,
+                                  const int64_t* ks, int64_t nk, double* out_) {
+    if (Lf < 0 || Lg < 0 || C < 1 || nk < 0) return 1;
     const cd* f = (const cd*)f_;
     const cd* g = (const cd*)g_;
     cd* out = (cd*)out_;
@@ -87,13 +89,19 @@ int oracle_direct_1d_sampled(int64_t L, int64_t C, const double* f_, const doubl
         int64_t k = ks[i];
         for (int64_t c = 0; c < C; ++c) {
             cd acc = {0.0, 0.0};
-            int64_t jlo = k - (L - 1) > 0 ? k - (L - 1) : 0;
-            int64_t jhi = k < L - 1 ? k : L - 1;
+            int64_t jlo = k - (Lg - 1) > 0 ? k - (Lg - 1) : 0;
+            int64_t jhi = k < Lf - 1 ? k : Lf - 1;
             for (int64_t j = jlo; j <= jhi; ++j) acc = cadd(acc, cmul(f[j * C + c], g[(k - j) * C + c]));
             out[i * C + c] = acc;
         }
     }
     return 0;
+}
+
+/* eq. (4) for the listed output indices only (copy 0 .. C-1 of each). */
+int oracle_direct_1d_sampled(int64_t L, int64_t C, const double* f_, const double* g_,
+                             const int64_t* ks, int64_t nk, double* out_) {
+    return oracle_direct_1d_uneq_sampled(L, L, C, f_, g_, ks, nk, out_);
 }
 
 static void unravel(int ndim, const int64_t* ext, int64_t lin, int64_t* idx) {

@@ -12,7 +12,10 @@ Names follow ``include/hdc.h``:
   ``residues_natural``;
 * :class:`Batch` wraps ``hdc_batch_*`` (uneven-length batches, replayed
   from a captured HIP graph);
-* :func:`derive` is the host-only admissibility check (``hdc_derive``).
+* :class:`UneqPlan` wraps ``hdc_plan_uneq`` (operands of different lengths,
+  section 3.5) and adds ``forward_operand`` (``hdc_forward_operand``);
+* :func:`derive` / :func:`uneq_derive` are the host-only admissibility checks
+  (``hdc_derive`` / ``hdc_uneq_derive``).
 """
 from __future__ import annotations
 
@@ -236,6 +239,64 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def uneq_derive(Lf: int, Lg: int, M: int, m: int = 0, lam: int = 0, C: int = 1, D: int = 0, dtype="c128"):
+    """Host-only derivation of an unequal-length plan (hdc_uneq_derive):
+    (shorter operand's description, longer operand's description, swapped)."""
+    s, lg, sw = AxisDesc(), AxisDesc(), ctypes.c_int()
+    check(lib().hdc_uneq_derive(int(Lf), int(Lg), int(M), int(m), int(lam), int(C), int(D), dtype_code(dtype),
+                                ctypes.byref(s), ctypes.byref(lg), ctypes.byref(sw)))
+    return s.as_dict(), lg.as_dict(), bool(sw.value)
+
+
+class UneqPlan(Plan):
+    """Unequal operand lengths (hdc_plan_uneq, section 3.5): f of length Lf, g of
+    length Lg, output length M >= Lf + Lg - 1; the shorter operand uses m-point
+    residues and the longer Lambda m-point ones.  ``axes[0]`` describes the
+    longer operand (the geometry of the product and the backward),
+    ``short_axis`` the shorter one."""
+
+    def __init__(self, Lf: int, Lg: int, M: Optional[int] = None, m: int = 0, lam: int = 0, C: int = 1, D: int = 0,
+                 dtype="c128"):
+        M = int(Lf) + int(Lg) - 1 if M is None else int(M)
+        h = ctypes.c_void_p()
+        check(lib().hdc_plan_uneq(ctypes.byref(h), int(Lf), int(Lg), M, int(m), int(lam), int(C), int(D),
+                                  dtype_code(dtype)))
+        super().__init__(0, 0, 0, dtype=dtype, _handle=h)
+        d = AxisDesc()
+        check(self._lib.hdc_plan_axis(self._h, 1, None, ctypes.byref(d)))
+        self.short_axis = d.as_dict()
+        self.Lf, self.Lg = int(Lf), int(Lg)
+        self.lam = self.axes[0]["m"] // self.short_axis["m"]
+
+    @property
+    def L(self):
+        return (self.Lf, self.Lg)
+
+    def convolve(self, f, g, out=None, ws=None, stream=None):
+        """h = f * g (hdc_convolve of the unequal-length plan)."""
+        import torch
+        _check_tensor(f, self.dtype, self.Lf * self.C, "f")
+        _check_tensor(g, self.dtype, self.Lg * self.C, "g")
+        if out is None:
+            out = torch.empty(self.out_shape(), dtype=torch_dtype(self.dtype), device=f.device)
+        _check_tensor(out, self.dtype, self.out_numel(), "out")
+        if ws is None:
+            ws = self.workspace(f.device)
+        check(self._lib.hdc_convolve(self._h, _ptr(f), _ptr(g), _ptr(out),
+                                     _ptr(ws) if ws is not None else None, _stream(stream)))
+        return out
+
+    def forward_operand(self, operand: int, x, F, r0: int, stream=None):
+        """hdc_forward_operand: residues of group r0 of f (operand 0) or g (operand 1),
+        in the longer operand's geometry."""
+        _check_tensor(x, self.dtype, (self.Lf if operand == 0 else self.Lg) * self.C, "x")
+        check(self._lib.hdc_forward_operand(self._h, int(operand), _ptr(x), _ptr(F), int(r0), None, _stream(stream)))
+        return F
+
+    def forward(self, f, F, r0: int, stream=None):
+        raise HdcError(1, "unequal-length plan: use forward_operand")
 
 
 class Profile:

@@ -151,20 +151,28 @@ struct hdc_plan_s {
     int ndim = 1;
     hdc_dtype dtype = HDC_C128;
     AxisPlan ax[3];
+    // unequal lengths (section 3.5): ax[0] is the longer operand's geometry
+    // (Lambda m-point residues), fx the shorter operand's (m-point residues)
+    bool uneq = false;
+    bool swap = false;  // the caller's f is the longer operand
+    int64_t lam = 1;
+    AxisPlan fx;
     void* tables = nullptr;
     size_t ws_bytes = 0;
 };
 
 namespace {
 
-// Derivation and admissibility (section 2.5, section 2.2's q >= p).
+// Derivation and admissibility (section 2.5, section 2.2's q >= p).  `Mmin`
+// is the shortest output that does not alias: 2L-1 for equal lengths.
 hdc_status derive_axis(int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, int64_t C, int64_t D, hdc_dtype dtype,
-                       hdc_axis_desc* o) {
+                       hdc_axis_desc* o, int64_t Mmin = -1) {
     if (dtype != HDC_C64 && dtype != HDC_C128) return fail(HDC_ERR_INVALID_ARG, "dtype must be HDC_C64 or HDC_C128");
     if (L < 1) return fail(HDC_ERR_INVALID_ARG, "L = %lld must be >= 1", (long long)L);
-    if (M < 2 * L - 1)
-        return fail(HDC_ERR_INVALID_ARG, "M = %lld < 2L-1 = %lld: the output would alias", (long long)M,
-                    (long long)(2 * L - 1));
+    if (Mmin < 0) Mmin = 2 * L - 1;
+    if (M < Mmin)
+        return fail(HDC_ERR_INVALID_ARG, "M = %lld < %lld: the output would alias", (long long)M,
+                    (long long)Mmin);
     if (m < 1) return fail(HDC_ERR_INVALID_ARG, "m = %lld must be >= 1", (long long)m);
     if (C < 1) return fail(HDC_ERR_INVALID_ARG, "C = %lld must be >= 1", (long long)C);
     if (p < 0 || q < 0 || D < 0) return fail(HDC_ERR_INVALID_ARG, "p, q, D must be >= 0 (0 derives)");
@@ -287,6 +295,68 @@ hdc_status geometry(AxisPlan& A, bool outer, bool many_rows = false) {
     return HDC_OK;
 }
 
+int64_t pow2_ceil(int64_t x) {
+    int64_t v = 1;
+    while (v < x) v <<= 1;
+    return v;
+}
+
+// Section 3.5: the shorter operand (length Ls) is cut into m-point residues,
+// the longer one (length Ll) into Lambda m-point residues, with
+//   p_f = ceil(Ls/m), p_g = ceil(Ll/(Lambda m)), q_g = ceil(M/(Lambda m)),
+//   q_f = Lambda q_g,
+// so both transforms have length N = q_g Lambda m = q_f m.  The longer
+// operand's four-step split m1g x m2g takes m1g a multiple of Lambda; the
+// shorter one's is (m1g/Lambda) x m2g, so its row l1f of residue r_f is the
+// longer operand's row Lambda l1f + lambda of residue r_f - q_g lambda.
+hdc_status derive_uneq(int64_t Lf, int64_t Lg, int64_t M, int64_t m, int64_t lam, int64_t C, int64_t D,
+                       hdc_dtype dtype, hdc_axis_desc* fo, hdc_axis_desc* go, bool* swapped) {
+    if (Lf < 1 || Lg < 1) return fail(HDC_ERR_INVALID_ARG, "Lf = %lld and Lg = %lld must be >= 1", (long long)Lf,
+                                      (long long)Lg);
+    const bool sw = Lf > Lg;
+    const int64_t Ls = sw ? Lg : Lf, Ll = sw ? Lf : Lg;
+    if (M < Ls + Ll - 1)
+        return fail(HDC_ERR_INVALID_ARG, "M = %lld < Lf + Lg - 1 = %lld: the output would alias", (long long)M,
+                    (long long)(Ls + Ll - 1));
+    if (m < 0 || lam < 0) return fail(HDC_ERR_INVALID_ARG, "m and Lambda must be >= 0 (0 derives)");
+    const int64_t mg_max = int64_t(kMaxM1) * kMaxRow;
+    if (m == 0) {  // one block per operand, Lambda as large as the column stage allows
+        const int64_t mg = std::min(pow2_ceil(Ll), mg_max);
+        if (lam == 0) lam = std::min<int64_t>(kMaxM1, std::max<int64_t>(1, mg / pow2_ceil(Ls)));
+        m = std::max<int64_t>(1, mg / lam);
+    } else if (lam == 0) {
+        lam = std::min<int64_t>(kMaxM1, std::max<int64_t>(1, std::min(pow2_ceil(Ll), mg_max) / m));
+    }
+    if (!is_pow2(m) || !is_pow2(lam))
+        return fail(HDC_ERR_UNSUPPORTED, "m = %lld and Lambda = %lld: only powers of two are implemented",
+                    (long long)m, (long long)lam);
+    if (lam > kMaxM1)
+        return fail(HDC_ERR_UNSUPPORTED, "Lambda = %lld exceeds the column stage's %d", (long long)lam, kMaxM1);
+    hdc_axis_desc g{};
+    hdc_status st = derive_axis(Ll, M, lam * m, 0, 0, C, D, dtype, &g, Ls + Ll - 1);
+    if (st != HDC_OK) return st;
+    // split with Lambda | m1g
+    g.m1 = std::max<int64_t>(lam, g.m / kMaxRow);
+    g.m2 = g.m / g.m1;
+    if (g.m1 > kMaxM1)
+        return fail(HDC_ERR_UNSUPPORTED, "Lambda m = %lld exceeds %lld", (long long)g.m,
+                    (long long)(int64_t(kMaxM1) * kMaxRow));
+    g.variant = 1;
+    hdc_axis_desc f = g;
+    f.L = Ls;
+    f.m = m;
+    f.p = ceil_div(Ls, m);
+    f.q = lam * g.q;
+    f.D = lam * g.D;
+    f.q_out = ceil_div(M, m);
+    f.m1 = g.m1 / lam;
+    f.m2 = g.m2;
+    if (fo) *fo = f;
+    if (go) *go = g;
+    if (swapped) *swapped = sw;
+    return HDC_OK;
+}
+
 // Append tables for one axis to the host staging blob.
 void stage_tables(AxisPlan& A, std::vector<unsigned char>& blob) {
     auto align = [&](size_t a) {
@@ -377,8 +447,12 @@ hdc_status run_fused(const AxisPlan& A, const void* f, const void* g, void* h, i
     return HDC_OK;
 }
 
+// Forward column stage of residues r0 + d (d < Dg).  With lam > 1 (section 3.5)
+// every d also yields residues r0 + d + li rstride, li < lam, interleaved so
+// that slot (d, l1, li) lands on row (d m1 + l1) lam + li.
 hdc_status run_col_fwd(const AxisPlan& A, const void* x, void* X, int64_t B, int64_t in_bs, int64_t out_bs,
-                       int64_t C1, int64_t r0, int64_t Dg, hipStream_t s, const int64_t* desc = nullptr) {
+                       int64_t C1, int64_t r0, int64_t Dg, hipStream_t s, const int64_t* desc = nullptr,
+                       int64_t lam = 1, int64_t rstride = 0) {
     ColFwdArgs a{};
     a.desc = desc;
     a.x = x;
@@ -395,17 +469,19 @@ hdc_status run_col_fwd(const AxisPlan& A, const void* x, void* X, int64_t B, int
     a.p = (int32_t)A.d.p;
     a.N = (int32_t)A.d.N;
     a.r0 = (int32_t)r0;
-    a.Dg = (int32_t)Dg;
+    a.Dg = (int32_t)(Dg * lam);
+    a.lam = (int32_t)lam;
+    a.rstride = (int32_t)rstride;
     a.tile = A.cf_tile;
     a.ntiles = (int32_t)ceil_div(a.Ccols, A.cf_tile);
     a.hiprec = A.hiprec ? 1 : 0;
     a.tw = A.tw;
     a.tw1 = A.tw_m1;
-    const int64_t gx = round8((int64_t)a.ntiles * Dg);
+    const int64_t gx = round8((int64_t)a.ntiles * a.Dg);
     if (gx > 0x7fffffff) return fail(HDC_ERR_UNSUPPORTED, "column grid too large");
     const double eb = A.dbl ? 16.0 : 8.0;
     const size_t esz = A.dbl ? 16 : 8;
-    LaunchScope ls(s, 1, eb * (double)B * (double)C1 * ((double)A.d.L + (double)(Dg * A.d.m)));
+    LaunchScope ls(s, 1, eb * (double)B * (double)C1 * ((double)A.d.L + (double)(a.Dg * A.d.m)));
     for (int64_t b0 = 0; b0 < B; b0 += kMaxGridY) {  // the grid's y extent is limited
         ColFwdArgs c = a;
         c.B = std::min<int64_t>(kMaxGridY, B - b0);
@@ -493,6 +569,8 @@ hdc_status run_col_plain(const AxisPlan& A, void* x, int64_t B, int64_t cols, in
         a.N = m2;
         a.r0 = 0;
         a.Dg = 1;
+        a.lam = 1;
+        a.rstride = 0;
         a.tile = A.mf_tile;
         a.ntiles = (int32_t)ceil_div(cols, A.mf_tile);
         a.hiprec = 0;
@@ -654,9 +732,34 @@ hdc_status convnd(const hdc_plan_s* P, int level, const void* xf, const void* xg
     return HDC_OK;
 }
 
+// Section 3.5: for every residue group of the longer operand, the shorter
+// operand's matching residues r_f = q_g lambda + r_g (lambda < Lambda) are
+// formed by its own column stage, stored row-interleaved so that the row pass
+// multiplies row by row; the backward runs in the longer operand's geometry.
+hdc_status conv_uneq(const hdc_plan_s* P, const void* xs, const void* xl, void* out, char* ws, hipStream_t s) {
+    const AxisPlan& G = P->ax[0];
+    const AxisPlan& F = P->fx;
+    const int64_t C = G.d.C;
+    const size_t eb = elem(P);
+    const int64_t D = std::min(G.d.D, G.d.q);
+    char* Xf = ws;
+    char* Xg = ws + (size_t)(D * G.d.m * C) * eb;
+    for (int64_t r0 = 0; r0 < G.d.q; r0 += D) {
+        const int64_t Dg = std::min(D, G.d.q - r0);
+        const int64_t xbs = Dg * G.d.m * C;
+        hdc_status st = run_col_fwd(F, xs, Xf, 1, 0, xbs, C, r0, Dg, s, nullptr, P->lam, G.d.q);
+        if (st == HDC_OK) st = run_col_fwd(G, xl, Xg, 1, 0, xbs, C, r0, Dg, s);
+        if (st == HDC_OK) st = run_rows(G, Xf, Xg, Xf, Dg * G.d.m1 * C, C, MODE_CONV, s);
+        if (st == HDC_OK) st = run_col_bwd(G, Xf, out, 1, xbs, 0, C, r0, Dg, r0 > 0, s);
+        if (st != HDC_OK) return st;
+    }
+    return HDC_OK;
+}
+
 hdc_status finish_plan(hdc_plan_s* P) {
     std::vector<unsigned char> blob;
     for (int a = 0; a < P->ndim; ++a) stage_tables(P->ax[a], blob);
+    if (P->uneq) stage_tables(P->fx, blob);
     void* dev = nullptr;
     hipError_t e = hipMalloc(&dev, std::max<size_t>(blob.size(), 256));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(twiddle tables)");
@@ -667,6 +770,7 @@ hdc_status finish_plan(hdc_plan_s* P) {
     }
     P->tables = dev;
     for (int a = 0; a < P->ndim; ++a) bind_tables(P->ax[a], (unsigned char*)dev);
+    if (P->uneq) bind_tables(P->fx, (unsigned char*)dev);
     if (P->ndim == 1) {
         P->ws_bytes = (size_t)ws1d(P->ax[0], 1, P->ax[0].d.C) * elem(P);
     } else {
@@ -708,6 +812,45 @@ hdc_status hdc_plan(hdc_plan_t* out, int64_t L, int64_t M, int64_t m, int64_t p,
     if (st == HDC_OK) {
         A.dbl = dtype == HDC_C128;
         st = geometry(A, false);
+    }
+    if (st == HDC_OK) st = finish_plan(P);
+    if (st != HDC_OK) {
+        delete P;
+        return st;
+    }
+    *out = P;
+    return HDC_OK;
+}
+
+hdc_status hdc_uneq_derive(int64_t Lf, int64_t Lg, int64_t M, int64_t m, int64_t Lambda, int64_t C, int64_t D,
+                           hdc_dtype dtype, hdc_axis_desc* short_out, hdc_axis_desc* long_out, int* swapped) {
+    bool sw = false;
+    hdc_axis_desc f{}, g{};
+    hdc_status st = derive_uneq(Lf, Lg, M, m, Lambda, C, D, dtype, &f, &g, &sw);
+    if (st != HDC_OK) return st;
+    if (short_out) *short_out = f;
+    if (long_out) *long_out = g;
+    if (swapped) *swapped = sw ? 1 : 0;
+    return HDC_OK;
+}
+
+hdc_status hdc_plan_uneq(hdc_plan_t* out, int64_t Lf, int64_t Lg, int64_t M, int64_t m, int64_t Lambda, int64_t C,
+                         int64_t D, hdc_dtype dtype) {
+    if (!out) return fail(HDC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    hdc_plan_s* P = new hdc_plan_s();
+    P->ndim = 1;
+    P->dtype = dtype;
+    P->uneq = true;
+    bool sw = false;
+    hdc_status st = derive_uneq(Lf, Lg, M, m, Lambda, C, D, dtype, &P->fx.d, &P->ax[0].d, &sw);
+    if (st == HDC_OK) {
+        P->swap = sw;
+        P->lam = P->ax[0].d.m / P->fx.d.m;
+        P->ax[0].dbl = P->fx.dbl = dtype == HDC_C128;
+        st = geometry(P->ax[0], false);
+        if (st == HDC_OK) st = geometry(P->fx, false);
+        P->ax[0].d.variant = P->fx.d.variant = 1;
     }
     if (st == HDC_OK) st = finish_plan(P);
     if (st != HDC_OK) {
@@ -771,6 +914,10 @@ hdc_status hdc_plan_destroy(hdc_plan_t P) {
 hdc_status hdc_plan_axis(hdc_plan_t P, int axis, int* ndim, hdc_axis_desc* out) {
     if (!P) return fail(HDC_ERR_INVALID_ARG, "plan is NULL");
     if (ndim) *ndim = P->ndim;
+    if (P->uneq && axis == 1) {
+        if (out) *out = P->fx.d;
+        return HDC_OK;
+    }
     if (axis < 0 || axis >= P->ndim) return fail(HDC_ERR_INVALID_ARG, "axis %d out of range", axis);
     if (out) *out = P->ax[axis].d;
     return HDC_OK;
@@ -807,6 +954,7 @@ hdc_status hdc_convolve(hdc_plan_t P, const void* f, const void* g, void* h, voi
         explicit CurPlan(const void* p) { g_cur_plan = p; }
         ~CurPlan() { g_cur_plan = nullptr; }
     } cur(P);
+    if (P->uneq) return P->swap ? conv_uneq(P, g, f, h, (char*)ws, s) : conv_uneq(P, f, g, h, (char*)ws, s);
     if (P->ndim == 1) {
         const AxisPlan& A = P->ax[0];
         return conv1d(A, f, g, h, 1, 0, 0, A.d.C, (char*)ws, elem(P), s);
@@ -825,9 +973,28 @@ static hdc_status group_check(hdc_plan_t P, int64_t r0, int64_t* Dg) {
     return HDC_OK;
 }
 
+hdc_status hdc_forward_operand(hdc_plan_t P, int operand, const void* x, void* F, int64_t r0, void* ws,
+                               hipStream_t s) {
+    if (!P || !x || !F) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+    if (operand != 0 && operand != 1) return fail(HDC_ERR_INVALID_ARG, "operand = %d must be 0 (f) or 1 (g)", operand);
+    if (!P->uneq) return hdc_forward(P, x, F, r0, ws, s);
+    int64_t Dg = 0;
+    hdc_status st = group_check(P, r0, &Dg);
+    if (st == HDC_OK) st = check_ptrs(P, x, F, nullptr);
+    if (st != HDC_OK) return st;
+    const AxisPlan& G = P->ax[0];
+    const int64_t C = G.d.C;
+    const bool shorter = (operand == 0) != P->swap;
+    st = shorter ? run_col_fwd(P->fx, x, F, 1, 0, 0, C, r0, Dg, s, nullptr, P->lam, G.d.q)
+                 : run_col_fwd(G, x, F, 1, 0, 0, C, r0, Dg, s);
+    if (st != HDC_OK) return st;
+    return run_rows(G, F, F, F, Dg * G.d.m1 * C, C, MODE_FWD, s);
+}
+
 hdc_status hdc_forward(hdc_plan_t P, const void* f, void* F, int64_t r0, void* ws, hipStream_t s) {
     (void)ws;
     if (!P || !f || !F) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+    if (P->uneq) return fail(HDC_ERR_INVALID_ARG, "unequal-length plan: use hdc_forward_operand");
     int64_t Dg = 0;
     hdc_status st = group_check(P, r0, &Dg);
     if (st == HDC_OK) st = check_ptrs(P, f, F, nullptr);

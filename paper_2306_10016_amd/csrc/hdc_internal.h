@@ -54,7 +54,8 @@ struct ColFwdArgs {
     void* X;
     int64_t B, in_bs, out_bs;  // batch count and strides (elements)
     int32_t L, Ccols, C1, m2, m, q, p, N;
-    int32_t r0, Dg;            // residues [r0, r0 + Dg)
+    int32_t r0, Dg;            // Dg residue slots; slot d lam + li is residue r0 + d + li rstride
+    int32_t lam, rstride;      // lam = 1 (rstride unused): residues [r0, r0 + Dg)
     int32_t tile, ntiles;
     int32_t hiprec;
     TwN tw;

@@ -442,7 +442,11 @@ __global__ void __launch_bounds__(1024) k_col_fwd(ColFwdArgs a) {
     const int task = xcd_task(blockIdx.x, gridDim.x);
     if (task >= a.ntiles * a.Dg) return;
     const int tl = task / a.Dg;
-    const int d = task - tl * a.Dg;
+    const int dd = task - tl * a.Dg;
+    // residue slot dd = d lam + li holds r = r0 + d + li rstride, stored at row
+    // block (d m1 + l1) lam + li (section 3.5's matching when lam > 1)
+    const int d = dd / a.lam;
+    const int li = dd - d * a.lam;
     const int tile = a.tile;
     const int tid = threadIdx.x;
     const int cc = tid % tile;
@@ -467,7 +471,7 @@ __global__ void __launch_bounds__(1024) k_col_fwd(ColFwdArgs a) {
          : mk<T>(0, 0))
 
     {
-        const int r = a.r0 + d;
+        const int r = a.r0 + d + li * a.rstride;
         cplx<T> w[PPT];
 #pragma unroll
         for (int v = 0; v < PPT; ++v) w[v] = HDC_LOAD(0, v);
@@ -507,7 +511,7 @@ __global__ void __launch_bounds__(1024) k_col_fwd(ColFwdArgs a) {
 #pragma unroll
         for (int v = 0; v < PPT; ++v) {
             const int l1 = lane + v * TPF;
-            if (ok) X[((int64_t)d * M1 + l1) * a.Ccols + cp] = w[v];
+            if (ok) X[(((int64_t)d * M1 + l1) * a.lam + li) * a.Ccols + cp] = w[v];
         }
     }
 #undef HDC_LOAD

@@ -85,3 +85,39 @@ def test_nd_check_is_host_only_and_reports_axes():
     assert d[1]["p"] == 1 and d[1]["q"] == 2
     with pytest.raises(hdc.HdcError):
         hdc.check_nd([1024, 4096], [2047, 8191], [1 << 21, 4096], dtype="c64")  # outer m > 2^20
+
+
+@pytest.mark.parametrize("Lf,Lg,m,lam", [(12, 1000, 16, 4), (37, 38, 8, 2), (5, 20000, 4, 1024), (1000, 100000, 32768, 4),
+                                         (3000, 40, 64, 8), (12, 1 << 22, 4096, 1024), (7, 9, 0, 0), (12, 1000, 0, 0)])
+def test_uneq_derive_rules(Lf, Lg, m, lam):
+    """Section 3.5's parameters: p_f = ceil(Ls/m), p_g = ceil(Ll/(Lambda m)),
+    q_g = ceil(M/(Lambda m)), q_f = Lambda q_g, one transform length N, and the
+    four-step splits that let row l1f of the shorter operand meet row
+    Lambda l1f + lambda of the longer one."""
+    M = Lf + Lg - 1
+    s, l, sw = hdc.uneq_derive(Lf, Lg, M, m, lam)
+    Ls, Ll = min(Lf, Lg), max(Lf, Lg)
+    assert sw == (Lf > Lg) and s["L"] == Ls and l["L"] == Ll
+    ms, ml = s["m"], l["m"]
+    L_ = ml // ms
+    assert ml == L_ * ms and (m == 0 or ms == m) and (lam == 0 or L_ == lam)
+    assert s["p"] == -(-Ls // ms) and l["p"] == -(-Ll // ml)
+    assert l["q"] == -(-M // ml) and s["q"] == L_ * l["q"]
+    assert s["N"] == l["N"] == l["q"] * ml >= M
+    assert l["m1"] % L_ == 0 and s["m1"] == l["m1"] // L_ and s["m2"] == l["m2"]
+    assert l["m1"] * l["m2"] == ml and s["m1"] * s["m2"] == ms
+    assert l["m1"] <= 1024 and l["m2"] <= 4096 and l["variant"] == 1
+    if m == 0:
+        assert s["p"] == 1 and (l["p"] == 1 or L_ == 1024)
+
+
+def test_uneq_derive_errors():
+    with pytest.raises(hdc.HdcError) as e:
+        hdc.uneq_derive(12, 1000, 1010)
+    assert e.value.status == 1
+    for m, lam in ((24, 2), (16, 3), (16, 2048), (8192, 1024)):
+        with pytest.raises(hdc.HdcError) as e:
+            hdc.uneq_derive(12, 1000, 1011, m, lam)
+        assert e.value.status == 2
+    with pytest.raises(hdc.HdcError):
+        hdc.uneq_derive(0, 1000, 1011)

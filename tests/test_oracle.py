@@ -270,3 +270,12 @@ def test_unequal_lengths_integer_exact():
                           for j in range(max(0, k - 776), min(k, 11) + 1)) for k in range(788)])
     assert np.array_equal(oracle.direct_1d(f, g, 788), exact)
     assert np.array_equal(np.round(oracle.padded_1d(f, g, 788)), exact)
+
+
+def test_unequal_sampled_matches_full():
+    f = synth.uniform_complex(7, 105, 7, 0)
+    g = synth.uniform_complex(300, 105, 300, 1)
+    full = oracle.direct_1d(f, g, 320)
+    ks = np.array([0, 1, 6, 7, 150, 299, 305, 306, 319])
+    assert np.array_equal(oracle.direct_1d_sampled(f, g, ks), full[ks])
+    assert np.array_equal(oracle.direct_1d_sampled(g, f, ks), oracle.direct_1d(g, f, 320)[ks])
