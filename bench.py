@@ -194,6 +194,49 @@ def secondary(args, dev, hdc, synth, log):
         del ft, gt, h, plan, ws
         torch.cuda.empty_cache()
     out["nd"] = nd
+
+    # unequal lengths (section 3.5): a short filter against a long signal, tuned over
+    # (m, Lambda, D), against explicit padding and against the equal-length plan with
+    # the filter zero-padded to the signal's length
+    from paper_2306_10016_amd import tune
+    db = tune.TuneDB(None if args.no_tune else args.tune_db, device=tune.device_name(), build=tune.build_hash())
+    tu = tune.TunerUneq(db, reps=3, warmup=1)
+    un = {}
+    for Lf, Lg, dt in ((2, 1 << 22, "c128"), (12, 1 << 22, "c128"), (12, 3 ** 13, "c128"), (1000, 1 << 20, "c128"),
+                       (12, 1 << 22, "c64"), (12, 1 << 16, "c128")):
+        M = Lf + Lg - 1
+        np_dt = np.complex128 if dt == "c128" else np.complex64
+        td = torch.complex128 if dt == "c128" else torch.complex64
+        ft = torch.from_numpy(synth.uniform_complex(Lf, 5, Lg, 0, np_dt)).to(dev)
+        gt = torch.from_numpy(synth.uniform_complex(Lg, 5, Lg, 1, np_dt)).to(dev)
+        h = torch.empty(M, dtype=td, device=dev)
+        r = tu.a1(Lf, Lg, M, dt)
+        plan = hdc.UneqPlan(Lf, Lg, M, m=r.params["m"], lam=r.params["lam"], D=r.params["D"], dtype=dt)
+        ws = plan.workspace(dev)
+        t = timed(lambda: plan.convolve(ft, gt, h, ws=ws), 20)
+        n2 = tune.pow2_ceil(M)
+
+        def explicit():
+            return torch.fft.ifft(torch.fft.fft(ft, n2) * torch.fft.fft(gt, n2))[:M]
+        ref = explicit()
+        err = float(torch.linalg.vector_norm(h - ref) / torch.linalg.vector_norm(ref))
+        te = timed(explicit, 20)
+        fp = torch.zeros(Lg, dtype=td, device=dev)
+        fp[:Lf] = ft
+        eq = hdc.Plan(Lg, 2 * Lg - 1, tune.pow2_ceil(Lg), dtype=dt)
+        he = torch.empty(2 * Lg - 1, dtype=td, device=dev)
+        wse = eq.workspace(dev)
+        tq = timed(lambda: eq.convolve(fp, gt, he, ws=wse), 20)
+        comp = (Lf + Lg + M) * (16 if dt == "c128" else 8)
+        key = f"Lf{Lf}_Lg{Lg}_{dt}"
+        un[key] = {"params": r.params, "tuned_by": r.source, "ms": round(t * 1e3, 4),
+                   "compulsory_GBps": round(comp / t / 1e9, 1), "explicit_ms": round(te * 1e3, 4),
+                   "speedup_vs_explicit": round(te / t, 3), "equal_padded_ms": round(tq * 1e3, 4),
+                   "speedup_vs_equal_padded": round(tq / t, 3), "rel_err_vs_explicit": err}
+        log(f"[bench] {key}: {t * 1e3:.3f} ms (explicit {te * 1e3:.3f}, equal-padded {tq * 1e3:.3f}), rel {err:.1e}")
+        del ft, gt, h, plan, ws, fp, eq, he, wse
+        torch.cuda.empty_cache()
+    out["uneq"] = un
     return out
 
 

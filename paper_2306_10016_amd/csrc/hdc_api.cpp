@@ -320,12 +320,35 @@ hdc_status derive_uneq(int64_t Lf, int64_t Lg, int64_t M, int64_t m, int64_t lam
                     (long long)(Ls + Ll - 1));
     if (m < 0 || lam < 0) return fail(HDC_ERR_INVALID_ARG, "m and Lambda must be >= 0 (0 derives)");
     const int64_t mg_max = int64_t(kMaxM1) * kMaxRow;
-    if (m == 0) {  // one block per operand, Lambda as large as the column stage allows
-        const int64_t mg = std::min(pow2_ceil(Ll), mg_max);
-        if (lam == 0) lam = std::min<int64_t>(kMaxM1, std::max<int64_t>(1, mg / pow2_ceil(Ls)));
-        m = std::max<int64_t>(1, mg / lam);
-    } else if (lam == 0) {
-        lam = std::min<int64_t>(kMaxM1, std::max<int64_t>(1, std::min(pow2_ceil(Ll), mg_max) / m));
+    if (m == 0 || lam == 0) {
+        // Lambda m: up to 2^17 output points a single block (q_g = 1: one
+        // residue, the fewest launches); beyond, the power of two with at most
+        // four blocks of the longer operand and the shortest transform
+        // N = ceil(M/(Lambda m)) Lambda m (ties: the larger)
+        int64_t best = 0, bestN = 0;
+        for (int64_t mg = 1; mg <= mg_max; mg <<= 1) {
+            if (m > 0 && (mg < m || mg / m > kMaxM1)) continue;
+            if (lam > 0 && mg < lam) continue;
+            if (mg * 4 < Ll && mg < mg_max) continue;
+            if (M <= 131072 && mg < M && mg < mg_max) continue;
+            const int64_t N = ceil_div(M, mg) * mg;
+            if (best == 0 || N <= bestN) {
+                if (best != 0 && M <= 131072 && N == bestN) continue;
+                best = mg, bestN = N;
+            }
+        }
+        if (best == 0) return fail(HDC_ERR_UNSUPPORTED, "no admissible Lambda m for m = %lld", (long long)m);
+        if (m > 0) lam = best / m;
+        else if (lam > 0) m = best / lam;
+        else {
+            // a balanced four-step split m1g x m2g, m2g = 2^ceil(lg(Lambda m)/2),
+            // with the shorter operand's column stage trivial: m = m2g, Lambda = m1g
+            int64_t m2 = 1;
+            while (m2 * m2 < best) m2 <<= 1;
+            m2 = std::min<int64_t>(m2, kMaxRow);
+            lam = std::min<int64_t>(kMaxM1, best / m2);
+            m = best / lam;
+        }
     }
     if (!is_pow2(m) || !is_pow2(lam))
         return fail(HDC_ERR_UNSUPPORTED, "m = %lld and Lambda = %lld: only powers of two are implemented",
@@ -341,7 +364,9 @@ hdc_status derive_uneq(int64_t Lf, int64_t Lg, int64_t M, int64_t m, int64_t lam
     if (g.m1 > kMaxM1)
         return fail(HDC_ERR_UNSUPPORTED, "Lambda m = %lld exceeds %lld", (long long)g.m,
                     (long long)(int64_t(kMaxM1) * kMaxRow));
-    g.variant = 1;
+    // Lambda = 1 keeps the single-kernel variant when it fits (both operands
+    // then share m and differ only in their lengths)
+    if (lam > 1) g.variant = 1;
     hdc_axis_desc f = g;
     f.L = Ls;
     f.m = m;
@@ -414,8 +439,9 @@ void bind_tables(AxisPlan& A, unsigned char* base) {
 
 // ---------------------------------------------------------------- launches --
 
+// Lf >= 0: f has length Lf and g the axis length (section 3.5 with Lambda = 1).
 hdc_status run_fused(const AxisPlan& A, const void* f, const void* g, void* h, int64_t nrows, RowAddr in, RowAddr out,
-                     const int64_t* desc, hipStream_t s) {
+                     const int64_t* desc, hipStream_t s, int64_t Lf = -1) {
     if (nrows <= 0) return HDC_OK;
     FusedArgs a{};
     a.f = f;
@@ -433,7 +459,11 @@ hdc_status run_fused(const AxisPlan& A, const void* f, const void* g, void* h, i
     a.N = (int32_t)A.d.N;
     a.Dc = A.Dc;
     a.rpw = A.f_rpw;
-    a.same = (f == g) ? 1 : 0;
+    a.same = (f == g && Lf < 0) ? 1 : 0;
+    if (Lf >= 0) {
+        a.L = (int32_t)Lf;
+        a.Lg = (int32_t)A.d.L;
+    }
     a.hiprec = A.hiprec ? 1 : 0;
     a.tw = A.tw;
     a.twm = A.tw_m;
@@ -441,7 +471,8 @@ hdc_status run_fused(const AxisPlan& A, const void* f, const void* g, void* h, i
     const int64_t blocks = ceil_div(nrows, A.f_rpw);
     if (blocks > 0x7fffffff) return fail(HDC_ERR_UNSUPPORTED, "too many rows");
     const double eb = A.dbl ? 16.0 : 8.0;
-    LaunchScope ls(s, 0, eb * (double)nrows * ((a.same ? 1.0 : 2.0) * (double)A.d.L + (double)A.d.M));
+    const double lin = Lf >= 0 ? (double)(Lf + A.d.L) : (a.same ? 1.0 : 2.0) * (double)A.d.L;
+    LaunchScope ls(s, 0, eb * (double)nrows * (lin + (double)A.d.M));
     hipError_t e = launch_fused(A.dbl, (int)A.d.m, a, A.f_threads, blocks, A.f_lds, s);
     if (e != hipSuccess) return hip_fail(e, "fused convolution launch");
     return HDC_OK;
@@ -637,6 +668,45 @@ hdc_status run_rows(const AxisPlan& A, const void* a_, const void* b_, void* out
     return HDC_OK;
 }
 
+// Row pass of section 3.5 whose first operand is formed from the raw shorter
+// operand xs (plan F, column stage trivial) for the group at r0; the second is
+// the longer operand's column-stage output Xg (plan G); the product's inverse
+// rows go to out.
+hdc_status run_rows_raw(const AxisPlan& G, const AxisPlan& F, const void* xs, const void* Xg, void* out, int64_t nrows,
+                        int64_t C1, int64_t r0, hipStream_t s) {
+    if (nrows <= 0) return HDC_OK;
+    RowArgs a{};
+    a.a = nullptr;
+    a.b = Xg;
+    a.out = out;
+    a.nrows = nrows;
+    a.addr.inner_cnt = C1;
+    a.addr.outer_stride = G.d.m2 * C1;
+    a.addr.inner_stride = 1;
+    a.addr.es = C1;
+    a.mode = MODE_CONV;
+    a.same = 0;
+    a.rpw = G.r_rpw;
+    a.tw = G.tw_m2;
+    a.fraw = xs;
+    a.twN = F.tw;
+    a.Lf = (int32_t)F.d.L;
+    a.pf = (int32_t)F.d.p;
+    a.qf = (int32_t)F.d.q;
+    a.N = (int32_t)F.d.N;
+    a.r0 = (int32_t)r0;
+    a.qg = (int32_t)G.d.q;
+    a.m1g = (int32_t)G.d.m1;
+    a.hiprec = F.hiprec ? 1 : 0;
+    const int64_t blocks = ceil_div(nrows, G.r_rpw);
+    if (nrows > 0x7fffffff) return fail(HDC_ERR_UNSUPPORTED, "too many rows");
+    const double eb = G.dbl ? 16.0 : 8.0;
+    LaunchScope ls(s, 2, eb * (2.0 * (double)nrows * (double)G.d.m2 + (double)(F.d.L * C1)));
+    hipError_t e = launch_row(G.dbl, (int)G.d.m2, a, G.r_threads, blocks, G.r_lds, s);
+    if (e != hipSuccess) return hip_fail(e, "row launch");
+    return HDC_OK;
+}
+
 size_t elem(const hdc_plan_s* P) { return elem_bytes(P->dtype); }
 
 // Workspace (elements) of a 1D convolution of B rows x C1 copies on axis A.
@@ -736,21 +806,36 @@ hdc_status convnd(const hdc_plan_s* P, int level, const void* xf, const void* xg
 // operand's matching residues r_f = q_g lambda + r_g (lambda < Lambda) are
 // formed by its own column stage, stored row-interleaved so that the row pass
 // multiplies row by row; the backward runs in the longer operand's geometry.
+// With Lambda = 1 and a transform that fits one workgroup, the single fused
+// kernel runs instead (both operands share m); with the shorter operand's column
+// stage trivial (m1f = 1), the row pass forms its rows from the raw input.
 hdc_status conv_uneq(const hdc_plan_s* P, const void* xs, const void* xl, void* out, char* ws, hipStream_t s) {
     const AxisPlan& G = P->ax[0];
     const AxisPlan& F = P->fx;
     const int64_t C = G.d.C;
+    if (G.d.variant == 0) {
+        RowAddr io{C, 0, 1, C};
+        return run_fused(G, xs, xl, out, C, io, io, nullptr, s, F.d.L);
+    }
     const size_t eb = elem(P);
     const int64_t D = std::min(G.d.D, G.d.q);
-    char* Xf = ws;
-    char* Xg = ws + (size_t)(D * G.d.m * C) * eb;
+    const bool raw = F.d.m1 == 1;
+    char* Xg = ws;
+    char* Xf = ws + (size_t)(D * G.d.m * C) * eb;
     for (int64_t r0 = 0; r0 < G.d.q; r0 += D) {
         const int64_t Dg = std::min(D, G.d.q - r0);
         const int64_t xbs = Dg * G.d.m * C;
-        hdc_status st = run_col_fwd(F, xs, Xf, 1, 0, xbs, C, r0, Dg, s, nullptr, P->lam, G.d.q);
-        if (st == HDC_OK) st = run_col_fwd(G, xl, Xg, 1, 0, xbs, C, r0, Dg, s);
-        if (st == HDC_OK) st = run_rows(G, Xf, Xg, Xf, Dg * G.d.m1 * C, C, MODE_CONV, s);
-        if (st == HDC_OK) st = run_col_bwd(G, Xf, out, 1, xbs, 0, C, r0, Dg, r0 > 0, s);
+        const int64_t rows = Dg * G.d.m1 * C;
+        hdc_status st = run_col_fwd(G, xl, Xg, 1, 0, xbs, C, r0, Dg, s);
+        if (st == HDC_OK) {
+            if (raw) {
+                st = run_rows_raw(G, F, xs, Xg, Xg, rows, C, r0, s);
+            } else {
+                st = run_col_fwd(F, xs, Xf, 1, 0, xbs, C, r0, Dg, s, nullptr, P->lam, G.d.q);
+                if (st == HDC_OK) st = run_rows(G, Xf, Xg, Xg, rows, C, MODE_CONV, s);
+            }
+        }
+        if (st == HDC_OK) st = run_col_bwd(G, Xg, out, 1, xbs, 0, C, r0, Dg, r0 > 0, s);
         if (st != HDC_OK) return st;
     }
     return HDC_OK;
@@ -771,7 +856,11 @@ hdc_status finish_plan(hdc_plan_s* P) {
     P->tables = dev;
     for (int a = 0; a < P->ndim; ++a) bind_tables(P->ax[a], (unsigned char*)dev);
     if (P->uneq) bind_tables(P->fx, (unsigned char*)dev);
-    if (P->ndim == 1) {
+    if (P->uneq) {
+        const AxisPlan& G = P->ax[0];
+        const int64_t one = std::min(G.d.D, G.d.q) * G.d.m * G.d.C;
+        P->ws_bytes = G.d.variant == 0 ? 0 : (size_t)(P->fx.d.m1 == 1 ? one : 2 * one) * elem(P);
+    } else if (P->ndim == 1) {
         P->ws_bytes = (size_t)ws1d(P->ax[0], 1, P->ax[0].d.C) * elem(P);
     } else {
         P->ws_bytes = (size_t)wsnd(P, 0, 1) * elem(P);
@@ -848,9 +937,11 @@ hdc_status hdc_plan_uneq(hdc_plan_t* out, int64_t Lf, int64_t Lg, int64_t M, int
         P->swap = sw;
         P->lam = P->ax[0].d.m / P->fx.d.m;
         P->ax[0].dbl = P->fx.dbl = dtype == HDC_C128;
+        const int32_t var = P->ax[0].d.variant;
         st = geometry(P->ax[0], false);
         if (st == HDC_OK) st = geometry(P->fx, false);
-        P->ax[0].d.variant = P->fx.d.variant = 1;
+        P->ax[0].d.variant = (var == 0 && P->ax[0].d.variant == 0) ? 0 : 1;
+        P->fx.d.variant = 1;
     }
     if (st == HDC_OK) st = finish_plan(P);
     if (st != HDC_OK) {

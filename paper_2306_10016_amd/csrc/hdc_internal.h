@@ -38,6 +38,7 @@ struct FusedArgs {
     RowAddr out;  // h
     const int64_t* desc;  // optional per-row {f_off, h_off, L, M}; in/out then give es only
     int32_t L, M;         // uniform lengths when desc == nullptr
+    int32_t Lg;           // g's length when it differs from f's (section 3.5 with Lambda = 1), else 0
     int32_t p, q, qout;   // qout = max output blocks ceil(M/m)
     int32_t N;            // q * m
     int32_t Dc;           // residues processed concurrently
@@ -87,6 +88,13 @@ struct RowArgs {
     int32_t same;
     int32_t rpw;
     const void* tw;  // zeta_{m2}^e, e < m2
+    // MODE_CONV with fraw != nullptr (section 3.5, shorter operand with a
+    // trivial column stage): operand a is formed from the raw input fraw
+    // (Lf x C1 values, pf blocks of m2) instead of being read; row
+    // (d m1g + l1g) C1 + c1 then holds residue r0 + d + l1g qg of length qf m2 = N
+    const void* fraw;
+    TwN twN;
+    int32_t Lf, pf, qf, N, r0, qg, m1g, hiprec;
 };
 
 enum { MODE_FWD = 0, MODE_INV = 1, MODE_CONV = 2 };

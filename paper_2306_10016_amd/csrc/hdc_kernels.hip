@@ -314,6 +314,7 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
     const TwLds<T> twm{tlo, thi, S::LO - 1, S::LG};
 
     int L = a.L, M = a.M;
+    int Lg = a.Lg > 0 ? a.Lg : a.L;
     int64_t fbase, hbase;
     if (a.desc != nullptr) {
         const int64_t* d = a.desc + 4 * (rowok ? row : 0);
@@ -321,6 +322,7 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
         hbase = d[1];
         L = (int)d[2];
         M = (int)d[3];
+        Lg = L;
     } else {
         fbase = row_base(a.in, rowok ? row : 0);
         hbase = row_base(a.out, rowok ? row : 0);
@@ -353,10 +355,8 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
 #pragma unroll
                 for (int v = 0; v < PPT; ++v) {
                     const int j = t * MSZ + lane + v * TPF;
-                    if (j < L) {
-                        F[v] = F[v] + mul_tw<false>(f[(int64_t)j * ies], z, false);
-                        if (!a.same) G[v] = G[v] + mul_tw<false>(g[(int64_t)j * ies], z, false);
-                    }
+                    if (j < L) F[v] = F[v] + mul_tw<false>(f[(int64_t)j * ies], z, false);
+                    if (!a.same && j < Lg) G[v] = G[v] + mul_tw<false>(g[(int64_t)j * ies], z, false);
                 }
             }
         }
@@ -623,13 +623,59 @@ __global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
 
 // ---------------------------------------------------------------- rows --
 
+// Operand a's row formed from the raw shorter operand (section 3.5, its column
+// stage trivial): row (d m1g + l1g) C1 + c1 holds residue r = r0 + d + l1g qg,
+//   w_s = zeta_N^{r s} sum_{t < pf} zeta_qf^{r t} f_{(t m2 + s) C1 + c1},  s < m2.
+template <typename T, int MSZ>
+__device__ __forceinline__ void raw_row(const RowArgs& a, int64_t row, bool ok, int lane, cplx<T>* v) {
+    constexpr int PPT = FP<MSZ>::PPT;
+    constexpr int TPF = FP<MSZ>::TPF;
+#pragma unroll
+    for (int w = 0; w < PPT; ++w) v[w] = mk<T>(0, 0);
+    if (!ok) return;
+    // the host keeps nrows below 2^31 for this mode
+    const uint32_t C1 = (uint32_t)a.addr.inner_cnt;
+    const uint32_t rw = (uint32_t)row;
+    const uint32_t c1 = rw % C1;
+    const uint32_t t1 = rw / C1;
+    const uint32_t l1 = t1 % (uint32_t)a.m1g;
+    const uint32_t r = (uint32_t)a.r0 + t1 / (uint32_t)a.m1g + l1 * (uint32_t)a.qg;
+    const cplx<T>* f = reinterpret_cast<const cplx<T>*>(a.fraw) + c1;
+#pragma unroll
+    for (int w = 0; w < PPT; ++w) {
+        const int j = lane + w * TPF;
+        if (j < a.Lf) v[w] = f[(int64_t)j * C1];
+    }
+    uint32_t e = r;  // (r t) mod qf for t = 1
+    for (int t = 1; t < a.pf; ++t) {
+        const double2 z = tw_n(a.twN, e * (uint32_t)MSZ);
+        e += r;
+        if (e >= (uint32_t)a.qf) e -= (uint32_t)a.qf;
+#pragma unroll
+        for (int w = 0; w < PPT; ++w) {
+            const int j = t * MSZ + lane + w * TPF;
+            if (j < a.Lf) v[w] = v[w] + mul_tw<false>(f[(int64_t)j * C1], z, a.hiprec);
+        }
+    }
+    if (r != 0) {
+        // r < qf and lane < TPF = m2 / PPT, so r lane and r TPF stay below N
+        double2 z = tw_n(a.twN, r * (uint32_t)lane);
+        const double2 zs = tw_n(a.twN, r * (uint32_t)TPF);
+#pragma unroll
+        for (int w = 0; w < PPT; ++w) {
+            v[w] = mul_tw<false>(v[w], z, a.hiprec);
+            z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
+        }
+    }
+}
+
 // Persistent row kernel: the workgroup walks rows base, base + stride, ...
 // with a skewed software pipeline: the g row of iteration i is loaded when
 // the iteration starts (hidden behind the f transform), and the f row of
 // iteration i+1 is loaded before the g transform (hidden behind the g
 // transform, the product and the inverse), so HBM traffic overlaps the LDS
 // passes while only three rows of registers are live.
-template <typename T, int MSZ, int MODE, bool TWO>
+template <typename T, int MSZ, int MODE, bool TWO, bool FRAW>
 __global__ void __launch_bounds__(512) k_row(RowArgs a) {
     using P = FP<MSZ>;
     using S = TwSplit<MSZ>;
@@ -659,7 +705,7 @@ __global__ void __launch_bounds__(512) k_row(RowArgs a) {
 
     int64_t base = (int64_t)blockIdx.x * a.rpw;  // uniform over the workgroup
     cplx<T> v[PPT];
-    {
+    if constexpr (!FRAW) {
         const int64_t row = base + rloc;
         const bool ok = row < a.nrows;
         const int64_t rb = row_base(a.addr, ok ? row : 0);
@@ -678,14 +724,19 @@ __global__ void __launch_bounds__(512) k_row(RowArgs a) {
 #pragma unroll
             for (int w = 0; w < PPT; ++w) u[w] = ok ? Bg[rb + (int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
         }
+        // a raw operand row is formed from L2-resident input while the b row
+        // is in flight, so it needs no prefetch
+        if constexpr (FRAW) raw_row<T, MSZ>(a, row, ok, lane, v);
         if constexpr (MODE == MODE_INV) {
 #pragma unroll
             for (int w = 0; w < PPT; ++w) pv[w] = nok ? Ag[nrb + (int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
             fft_regs<T, MSZ, -1, true>(v, buf, 1, lane, tw, ok);
         } else {
             fft_regs<T, MSZ, +1, true>(v, buf, 1, lane, tw, ok);
+            if constexpr (!FRAW) {
 #pragma unroll
-            for (int w = 0; w < PPT; ++w) pv[w] = nok ? Ag[nrb + (int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
+                for (int w = 0; w < PPT; ++w) pv[w] = nok ? Ag[nrb + (int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
+            }
             if constexpr (conv) {
                 if constexpr (two) {
                     fft_regs<T, MSZ, +1, true>(u, buf, 1, lane, tw, ok);
@@ -702,8 +753,10 @@ __global__ void __launch_bounds__(512) k_row(RowArgs a) {
 #pragma unroll
             for (int w = 0; w < PPT; ++w) Og[rb + (int64_t)(lane + w * TPF) * es] = v[w];
         }
+        if constexpr (!FRAW) {
 #pragma unroll
-        for (int w = 0; w < PPT; ++w) v[w] = pv[w];
+            for (int w = 0; w < PPT; ++w) v[w] = pv[w];
+        }
     }
 }
 
@@ -782,9 +835,9 @@ int cu_count() {
     return n;
 }
 
-template <typename T, int MSZ, int MODE, bool TWO>
+template <typename T, int MSZ, int MODE, bool TWO, bool FRAW = false>
 hipError_t row_mode(const RowArgs& a, int threads, int64_t blocks, size_t lds, hipStream_t s) {
-    auto kern = k_row<T, MSZ, MODE, TWO>;
+    auto kern = k_row<T, MSZ, MODE, TWO, FRAW>;
     hipError_t e = allow_lds(kern, lds);
     if (e != hipSuccess) return e;
     int occ = 0;
@@ -803,6 +856,7 @@ hipError_t row_t(const RowArgs& a, int threads, int64_t blocks, size_t lds, hipS
         case MODE_FWD: return row_mode<T, MSZ, MODE_FWD, false>(a, threads, blocks, lds, s);
         case MODE_INV: return row_mode<T, MSZ, MODE_INV, false>(a, threads, blocks, lds, s);
         default:
+            if (a.fraw != nullptr) return row_mode<T, MSZ, MODE_CONV, true, true>(a, threads, blocks, lds, s);
             return a.same ? row_mode<T, MSZ, MODE_CONV, false>(a, threads, blocks, lds, s)
                           : row_mode<T, MSZ, MODE_CONV, true>(a, threads, blocks, lds, s);
     }

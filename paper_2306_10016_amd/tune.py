@@ -314,3 +314,165 @@ def _shared_ws(nbytes: int):
 def regret(chosen_ms: float, best_ms: float) -> float:
     """T(chosen) / T(exhaustive best) - 1."""
     return chosen_ms / best_ms - 1.0
+
+
+# ------------------------------------------------------- unequal lengths --
+
+def uneq_key(Lf: int, Lg: int, M: int, dtype: str) -> str:
+    return json.dumps({"uneq": [int(Lf), int(Lg)], "M": int(M), "dtype": dtype}, sort_keys=True)
+
+
+def uneq_candidates(Lf: int, Lg: int, M: int, max_mg: int = 1 << 22, max_pg: int = 4, max_pf: int = 16,
+                    d_choices: str = "q") -> List[Tuple[int, int, int]]:
+    """(m, Lambda, D) candidates of section 3.5: the longer operand's Lambda m a
+    power of two with at most ``max_pg`` blocks (or a single residue), every
+    power-of-two Lambda the column stage takes (<= 1024), and the shorter
+    operand's m with at most ``max_pf`` blocks."""
+    from . import uneq_derive, HdcError
+    Ls, Ll = min(Lf, Lg), max(Lf, Lg)
+    out = []
+    mg = 1
+    while mg <= max_mg:
+        pg, qg = -(-Ll // mg), -(-M // mg)
+        if pg <= max_pg or qg == 1:
+            lam = 1
+            while lam <= min(1024, mg):
+                m = mg // lam
+                if -(-Ls // m) <= max_pf:
+                    Ds = [qg] + ([1 << i for i in range(20) if (1 << i) < qg] if d_choices == "all" else [])
+                    for D in Ds:
+                        try:
+                            uneq_derive(Lf, Lg, M, m, lam, 1, D)
+                        except HdcError:
+                            continue
+                        out.append((m, lam, D))
+                lam *= 2
+        mg *= 2
+    return out
+
+
+def _uneq_class(Lf, Lg, M, m, lam):
+    """Scale-free class: (p_g, log2 of the shorter operand's m over sqrt(Lambda m))."""
+    mg = m * lam
+    return (-(-max(Lf, Lg) // mg), int(round(math.log2(m) - math.log2(mg) / 2)))
+
+
+class TunerUneq:
+    """Tunes an unequal-length problem (Lf, Lg, M, dtype) over (m, Lambda, D) on the GPU."""
+
+    def __init__(self, db: Optional[TuneDB] = None, reps: int = 5, warmup: int = 2,
+                 timer: Optional[Callable[[int, int, int, int, int, int, str], float]] = None, seed: int = 0):
+        self.db = db or TuneDB(None)
+        self.reps, self.warmup = reps, warmup
+        self.timer = timer  # (Lf, Lg, M, m, lam, D, dtype) -> ms ; defaults to the GPU timer
+        self.rng = random.Random(seed)
+        self._bufs = {}
+
+    def _gpu_time(self, Lf, Lg, M, m, lam, D, dtype):
+        import torch
+        from . import UneqPlan, torch_dtype, dtype_code
+        key = (Lf, Lg, M, dtype)
+        if key not in self._bufs:
+            self._bufs.clear()
+            td = torch_dtype(dtype_code(dtype))
+            self._bufs[key] = (torch.randn(Lf, dtype=td, device="cuda"), torch.randn(Lg, dtype=td, device="cuda"),
+                               torch.empty(M, dtype=td, device="cuda"))
+        f, g, h = self._bufs[key]
+        plan = UneqPlan(Lf, Lg, M, m=m, lam=lam, D=D, dtype=dtype)
+        ms = plan.time_convolve(f, g, h, ws=_shared_ws(plan.workspace_bytes), warmup=self.warmup, reps=self.reps)
+        plan.close()
+        ms.sort()
+        return ms[len(ms) // 2]
+
+    def measure(self, Lf, Lg, M, m, lam, D, dtype) -> float:
+        if self.timer is not None:
+            return float(self.timer(Lf, Lg, M, m, lam, D, dtype))
+        return self._gpu_time(Lf, Lg, M, m, lam, D, dtype)
+
+    def _run(self, key, Lf, Lg, M, dtype, cands, table, seen):
+        for (m, lam, D) in cands:
+            params = {"m": int(m), "lam": int(lam), "D": int(D)}
+            pk = json.dumps(params, sort_keys=True)
+            if pk in seen:
+                continue
+            ms = self.measure(Lf, Lg, M, m, lam, D, dtype)
+            seen[pk] = ms
+            table.append((params, ms))
+            self.db.add(key, params, ms)
+
+    @staticmethod
+    def _pick(table):
+        """argmin; within 1 %: the shorter transform (smaller Lambda m), then the larger Lambda."""
+        best = min(ms for _, ms in table)
+        near = [(p, ms) for p, ms in table if ms <= best * 1.01]
+        near.sort(key=lambda x: (x[0]["m"] * x[0]["lam"], -x[0]["lam"], x[0]["D"], x[1]))
+        return near[0]
+
+    def a0(self, Lf: int, Lg: int, M: int, dtype: str = "c128", d_choices: str = "q") -> TuneResult:
+        key = uneq_key(Lf, Lg, M, dtype)
+        seen = dict(self.db.timings(key))
+        table = [(json.loads(pk), ms) for pk, ms in seen.items()]
+        self._run(key, Lf, Lg, M, dtype, uneq_candidates(Lf, Lg, M, d_choices=d_choices), table, seen)
+        p, ms = self._pick(table)
+        return TuneResult(p, ms, table, "A0")
+
+    def a1(self, Lf: int, Lg: int, M: int, dtype: str = "c128", n_random: int = 2, reuse: bool = True) -> TuneResult:
+        from . import uneq_derive
+        key = uneq_key(Lf, Lg, M, dtype)
+        if reuse:
+            hit = self.db.best(key)
+            if hit is not None:
+                return TuneResult(hit[0], hit[1], [hit], "db")
+        cands = uneq_candidates(Lf, Lg, M)
+        cset = set(cands)
+        table: List[Tuple[dict, float]] = []
+        seen: Dict[str, float] = {}
+        # (1) the derived default; (2) the class of the nearest tuned unequal problem
+        s, lg, _ = uneq_derive(Lf, Lg, M, 0, 0, 1, 0)
+        seeds = [(s["m"], lg["m"] // s["m"], lg["q"])]
+        for cls in self.experience_classes(Lf, Lg, dtype):
+            for c in cands:
+                if _uneq_class(Lf, Lg, M, c[0], c[1]) == cls and c not in seeds:
+                    seeds.append(c)
+                    break
+        self._run(key, Lf, Lg, M, dtype, seeds, table, seen)
+        rest = [c for c in cands if json.dumps({"m": c[0], "lam": c[1], "D": c[2]}, sort_keys=True) not in seen]
+        self.rng.shuffle(rest)
+        self._run(key, Lf, Lg, M, dtype, rest[:n_random], table, seen)
+        # (3) local refinement: Lambda m halved or doubled at the same Lambda, Lambda halved or doubled at the same Lambda m
+        for _ in range(4):
+            best, _ms = self._pick(table)
+            m0, l0 = best["m"], best["lam"]
+            neigh = []
+            for m, lam in ((m0 // 2, l0), (m0 * 2, l0), (m0 * 2, l0 // 2), (m0 // 2, l0 * 2)):
+                for c in cands:
+                    if c[0] == m and c[1] == lam and c in cset:
+                        neigh.append(c)
+                        break
+            before = len(table)
+            self._run(key, Lf, Lg, M, dtype, neigh, table, seen)
+            if len(table) == before:
+                break
+        p, ms = self._pick(table)
+        return TuneResult(p, ms, table, "A1")
+
+    def experience_classes(self, Lf: int, Lg: int, dtype: str, k: int = 2):
+        scored = []
+        for key in self.db.keys():
+            d = json.loads(key)
+            if "uneq" not in d or d["dtype"] != dtype:
+                continue
+            b = self.db.best(key)
+            if b is None:
+                continue
+            (lf, lg), M = d["uneq"], d["M"]
+            dist = abs(math.log2(max(lf, lg)) - math.log2(max(Lf, Lg))) + abs(math.log2(min(lf, lg)) - math.log2(min(Lf, Lg)))
+            scored.append((dist, _uneq_class(lf, lg, M, b[0]["m"], b[0]["lam"])))
+        scored.sort()
+        out = []
+        for _, c in scored:
+            if c not in out:
+                out.append(c)
+            if len(out) >= k:
+                break
+        return out

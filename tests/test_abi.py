@@ -106,9 +106,17 @@ def test_uneq_derive_rules(Lf, Lg, m, lam):
     assert s["N"] == l["N"] == l["q"] * ml >= M
     assert l["m1"] % L_ == 0 and s["m1"] == l["m1"] // L_ and s["m2"] == l["m2"]
     assert l["m1"] * l["m2"] == ml and s["m1"] * s["m2"] == ms
-    assert l["m1"] <= 1024 and l["m2"] <= 4096 and l["variant"] == 1
-    if m == 0:
-        assert s["p"] == 1 and (l["p"] == 1 or L_ == 1024)
+    assert l["m1"] <= 1024 and l["m2"] <= 4096 and (l["variant"] == 1 or L_ == 1)
+    if m == 0 and lam == 0:
+        # one block up to 2^17 outputs, else the shortest transform over Lambda m with
+        # at most four blocks of the longer operand; a trivial column stage for the
+        # shorter one
+        if M <= 131072:
+            assert l["q"] == 1 and l["m"] == 1 << (M - 1).bit_length()
+        else:
+            Ns = [-(-M // (1 << k)) * (1 << k) for k in range(23) if 4 * (1 << k) >= Ll or k == 22]
+            assert l["p"] <= 4 and l["N"] == min(Ns)
+        assert s["m1"] == 1
 
 
 def test_uneq_derive_errors():

@@ -41,7 +41,9 @@ SMALL = [
     (1, 500, 1, 64, 0, 1),
     (37, 38, 8, 2, 2, 1),
     (100, 2187, 32, 16, 5, 1),
-    (100, 2187, 128, 1, 0, 1),      # Lambda = 1: same m, different lengths
+    (100, 2187, 128, 1, 0, 1),      # Lambda = 1: same m, different lengths (single fused kernel)
+    (300, 1000, 256, 1, 0, 2),      # Lambda = 1 fused with copies and p_f > 1
+    (700, 6000, 2048, 1, 2, 1),     # Lambda = 1 too large to fuse: row pass with the raw operand
     (300, 5000, 64, 32, 0, 3),      # copies
     (513, 4097, 256, 16, 2, 2),
     (1000, 100000, 1024, 16, 0, 1),  # p_g > 1
@@ -154,3 +156,27 @@ def test_uneq_deterministic():
     plan, f, g, h1 = _run(12, 50000, m=64, lam=64, idx=70)
     h2 = to_host(plan.convolve(to_dev(f), to_dev(g)))
     assert np.array_equal(h1, h2)
+
+
+@pytest.mark.parametrize("case,path", [((100, 2187, 128, 1, 0, 1), "fused"), ((700, 6000, 2048, 1, 2, 1), "raw"),
+                                       ((12, 1000, 16, 4, 0, 1), "raw"), ((1000, 100000, 32768, 4, 0, 1), "general")])
+def test_uneq_execution_paths(case, path):
+    """Which kernels run: one fused kernel (Lambda = 1 and the transform fits a
+    workgroup), the row pass forming the shorter operand from its input (its
+    column stage trivial), or both column stages; the workspace follows."""
+    import paper_2306_10016_amd as hdc
+    Lf, Lg, m, lam, D, C = case
+    plan = hdc.UneqPlan(Lf, Lg, m=m, lam=lam, C=C, D=D)
+    G = plan.axes[0]
+    one = min(G["D"], G["q"]) * G["m"] * C * 16
+    want = {"fused": 0, "raw": one, "general": 2 * one}[path]
+    assert plan.workspace_bytes == want
+    f, g = _ops(Lf, Lg, C, "c128", 80)
+    fd, gd = to_dev(f), to_dev(g)
+    out = to_dev(np.zeros(Lf + Lg - 1, np.complex128))
+    kinds = [k for k, _, _ in plan.convolve_profiled(fd, gd, out)]
+    groups = -(-G["q"] // min(G["D"], G["q"]))
+    per = {"fused": ["fused"], "raw": ["col_fwd", "row", "col_bwd"],
+           "general": ["col_fwd", "col_fwd", "row", "col_bwd"]}[path]
+    assert kinds == ([] if path == "fused" else []) + per * (1 if path == "fused" else groups)
+    assert rel(to_host(out), oracle.direct_1d(f, g, Lf + Lg - 1)) < TOL["c128"]

@@ -128,3 +128,38 @@ def test_training_problems_within_bound():
     for Ls, batch, dt in probs:
         assert int(np.prod(Ls)) * batch <= (1 << 20)
         assert dt in ("c64", "c128") and 1 <= len(Ls) <= 3
+
+
+def uneq_cost(Lf, Lg, M, m, lam, D, dtype):
+    """A bowl with its minimum at Lambda m = 2^ceil(log2 Lg) / 2 and m = 64."""
+    mg = m * lam
+    return 1.0 + (math.log2(mg) - (math.log2(tune.pow2_ceil(Lg)) - 1)) ** 2 + 0.3 * (math.log2(m) - 6) ** 2
+
+
+def test_uneq_candidates_admissible():
+    cands = tune.uneq_candidates(12, 100000, 100011)
+    assert cands
+    for m, lam, D in cands:
+        s, l, _ = hdc.uneq_derive(12, 100000, 100011, m, lam, 1, D)
+        assert l["p"] <= 4 or l["q"] == 1
+        assert s["p"] <= 16 and lam <= 1024 and l["m"] == m * lam
+
+
+def test_uneq_a0_and_a1_find_the_model_argmin():
+    t0 = tune.TunerUneq(tune.TuneDB(None), timer=uneq_cost)
+    r0 = t0.a0(12, 100000, 100011)
+    assert r0.params["m"] == 64 and r0.params["m"] * r0.params["lam"] == 65536
+    calls = []
+
+    def counting(*a):
+        calls.append(a)
+        return uneq_cost(*a)
+    db = tune.TuneDB(None)
+    t1 = tune.TunerUneq(db, timer=counting, seed=3)
+    for Lg in (30000, 60000):
+        t1.a1(12, Lg, Lg + 11)
+    calls.clear()
+    r1 = t1.a1(12, 100000, 100011)
+    assert r1.params == r0.params
+    assert len(calls) < len(tune.uneq_candidates(12, 100000, 100011))
+    assert t1.a1(12, 100000, 100011).source == "db"
