@@ -1,7 +1,7 @@
 /*
  * hdc -- hybrid dealiased convolution for AMD MI355X (gfx950).
  *
- * The operation (section 2.2 eq. (1), section 2.3 eq. (4), section 3.3):
+ * The operation (section 2.2 eqs. (3)-(4), section 2.3 eq. (5), section 3.3):
  *   given f, g of length L, compute the linear convolution
  *       h_k = sum_j f_j g_{k-j},  k = 0 .. M-1,  M >= 2L-1,
  *   by hybrid dealiasing: choose an FFT size m, explicitly extend the inputs
@@ -9,8 +9,8 @@
  *   N = q*m >= M (q = ceil(M/m)), and compute the length-N transform as q
  *   "residues" r = 0..q-1, each an m-point DFT of the block sum
  *       w^(r)_s = zeta_N^{r s} sum_{t<p} zeta_q^{r t} f_{t m + s}
- *   (forward of eq. (1), zeta_n = exp(+2 pi i / n), unscaled).  The product
- *   H = F.G is taken residue by residue and the backward of eq. (1)
+ *   (forward, eq. (3), zeta_n = exp(+2 pi i / n), unscaled).  The product
+ *   H = F.G is taken residue by residue and the backward, eq. (4),
  *       h_{t m + s} = (1/N) sum_r zeta_q^{-t r} zeta_N^{-s r} sum_l zeta_m^{-s l} H_{q l + r}
  *   is accumulated over output blocks t < ceil(M/m).  Residues are taken D
  *   at a time (section 2.5); C copies are transformed together.
@@ -82,7 +82,7 @@ typedef struct {
 hdc_status hdc_derive(int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, int64_t C, int64_t D,
                       hdc_dtype dtype, hdc_axis_desc* out);
 
-/* 1D plan (eq. (1)).  Allocates the device twiddle tables on the current device
+/* 1D plan (eqs. (3)-(4)).  Allocates the device twiddle tables on the current device
  * (the only allocation a plan makes).  Errors as hdc_derive, plus HDC_ERR_HIP. */
 hdc_status hdc_plan(hdc_plan_t* out, int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, int64_t C,
                     int64_t D, hdc_dtype dtype);
@@ -157,7 +157,7 @@ hdc_status hdc_convolve(hdc_plan_t plan, const void* f, const void* g, void* h, 
 
 /*
  * Forward residues [r0, r0 + D') of a 1D plan, D' = min(D, q - r0): the m-point
- * DFTs of eq. (1).  F holds D' x m x C values; within a residue the order is
+ * DFTs of eq. (3).  F holds D' x m x C values; within a residue the order is
  * implementation-defined (hdc_residues_natural gives the natural order).
  * r0 must be a multiple of D.  ws: hdc_workspace_size bytes.
  */
@@ -179,7 +179,7 @@ hdc_status hdc_forward_operand(hdc_plan_t plan, int operand, const void* x, void
 hdc_status hdc_multiply(hdc_plan_t plan, void* F, const void* G, int64_t r0, hipStream_t stream);
 
 /*
- * Backward of eq. (1) for residues [r0, r0 + D'): inverse m-point DFTs,
+ * Backward, eq. (4), for residues [r0, r0 + D'): inverse m-point DFTs,
  * twiddle, and accumulation into the output blocks t < ceil(M/m) of h.
  * r0 == 0 overwrites h; r0 > 0 adds to it, so calling r0 = 0, D, 2D, ... in
  * order on one stream yields the convolution.  F is overwritten.
@@ -214,7 +214,7 @@ hdc_status hdc_batch_info(hdc_batch_t batch, int64_t* n_buckets, int64_t* total_
 hdc_status hdc_batch_destroy(hdc_batch_t batch);
 
 /*
- * Timing core for the autotuner (section 4.2's score R): runs hdc_convolve
+ * Timing core for the autotuner (sections 4.2-4.3): runs hdc_convolve
  * `warmup` times, then `reps` times each bracketed by HIP events on `stream`,
  * and writes the per-repetition milliseconds to ms_out[reps].  Synchronises
  * the stream.

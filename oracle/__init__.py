@@ -6,7 +6,7 @@ and shares no code with it.
 
 The convolution oracle is ``oracle.c`` (plain C, FP64, OpenMP), built into
 ``liboracle.so`` next to this file by :func:`build`.  It computes the linear
-convolution of eq. (4) (section 2.3) two independent ways:
+convolution of eq. (5) (section 2.3) two independent ways:
 
 * :func:`direct_1d`, :func:`direct_1d_sampled`, :func:`direct_nd_sampled` --
   the defining sum;
@@ -15,7 +15,7 @@ convolution of eq. (4) (section 2.3) two independent ways:
   zeta = e^{+2 pi i/n}, product, inverse DFT with 1/n, crop to M.
 
 :func:`padded_dft` is the zero-extended forward DFT whose entries the residues
-of eq. (1) (section 2.2) enumerate.  ``mlp.py`` holds the FP64 reference of
+of eq. (3) (section 2.2) enumerate.  ``mlp.py`` holds the FP64 reference of
 the parameter predictor's network.
 """
 from __future__ import annotations
@@ -96,7 +96,7 @@ def _check(rc, name):
 
 
 def direct_1d(f, g, M: int) -> np.ndarray:
-    """h_k = sum_j f_j g_{k-j} for k < M (eq. (4)); f of shape (Lf,) or (Lf, C), g of
+    """h_k = sum_j f_j g_{k-j} for k < M (eq. (5)); f of shape (Lf,) or (Lf, C), g of
     shape (Lg,) or (Lg, C) (Lf and Lg may differ: the unequal case of section 3.5)."""
     f2, flat = _as_2d(f)
     g2, _ = _as_2d(g)
@@ -110,7 +110,7 @@ def direct_1d(f, g, M: int) -> np.ndarray:
 
 
 def direct_1d_sampled(f, g, ks) -> np.ndarray:
-    """eq. (4) evaluated only at the output indices ``ks`` (f and g may differ in length)."""
+    """eq. (5) evaluated only at the output indices ``ks`` (f and g may differ in length)."""
     f2, flat = _as_2d(f)
     g2, _ = _as_2d(g)
     if f2.shape[1] != g2.shape[1]:
@@ -124,7 +124,7 @@ def direct_1d_sampled(f, g, ks) -> np.ndarray:
 
 
 def direct_nd_sampled(f, g, M, ks) -> np.ndarray:
-    """N-D eq. (4) at the row-major linear indices ``ks`` of the output box M."""
+    """N-D eq. (5) at the row-major linear indices ``ks`` of the output box M."""
     f = _c128(f)
     g = _c128(g)
     nd = f.ndim
@@ -138,7 +138,7 @@ def direct_nd_sampled(f, g, M, ks) -> np.ndarray:
 
 
 def direct_nd(f, g, M) -> np.ndarray:
-    """N-D eq. (4) over the whole output box (small problems only)."""
+    """N-D eq. (5) over the whole output box (small problems only)."""
     M = tuple(int(x) for x in M)
     ks = np.arange(int(np.prod(M)), dtype=np.int64)
     return direct_nd_sampled(f, g, M, ks).reshape(M)

@@ -6,7 +6,7 @@
  * baseline use it.  It shares no code with the GPU library.
  *
  * What it computes (the method reaches this result exactly, up to rounding):
- *   the linear convolution of two length-L sequences, eq. (4) of section 2.3,
+ *   the linear convolution of two length-L sequences, eq. (5) of section 2.3,
  *       h_k = sum_{j} f_j g_{k-j},   0 <= j < L, 0 <= k-j < L,
  *   reported over the output length M (M >= 2L-1); entries k >= 2L-1 are 0.
  *   Unequal lengths (section 3.5): f of length Lf, g of length Lg, the same sum
@@ -14,7 +14,7 @@
  *   N-D: the same sum per axis over the box [0, M_1) x ... x [0, M_d).
  *
  * Two independent routes, deliberately plain:
- *   1. direct summation of eq. (4)                           (O(L^2));
+ *   1. direct summation of eq. (5)                           (O(L^2));
  *   2. explicit dealiasing (section 3.1): zero-pad both operands to the
  *      smallest size 2^a 3^b 5^c 7^d >= 2L-1, forward DFT (zeta = e^{+2 pi i/n}),
  *      pointwise product, backward DFT with 1/n, crop.
@@ -50,7 +50,7 @@ int oracle_num_threads(void) {
 
 /* ---------------------------------------------------------------- direct -- */
 
-/* eq. (4) for operands of lengths Lf and Lg (f_j = 0 for j >= Lf, g_j = 0 for
+/* eq. (5) for operands of lengths Lf and Lg (f_j = 0 for j >= Lf, g_j = 0 for
  * j >= Lg, the unequal case of section 3.5), all copies, all k < M. */
 int oracle_direct_1d_uneq(int64_t Lf, int64_t Lg, int64_t M, int64_t C, const double* f_, const double* g_,
                           double* h_) {
@@ -71,12 +71,12 @@ int oracle_direct_1d_uneq(int64_t Lf, int64_t Lg, int64_t M, int64_t C, const do
     return 0;
 }
 
-/* eq. (4), all copies, all k < M. */
+/* eq. (5), all copies, all k < M. */
 int oracle_direct_1d(int64_t L, int64_t M, int64_t C, const double* f_, const double* g_, double* h_) {
     return oracle_direct_1d_uneq(L, L, M, C, f_, g_, h_);
 }
 
-/* eq. (4) for the listed output indices only (copy 0 .. C-1 of each), operands
+/* eq. (5) for the listed output indices only (copy 0 .. C-1 of each), operands
  * of lengths Lf and Lg (section 3.5; Lf = Lg is the equal case). */
 int oracle_direct_1d_uneq_sampled(int64_t Lf, int64_t Lg, int64_t C, const double* f_, const double* g_,
                                   const int64_t* ks, int64_t nk, double* out_) {
@@ -98,7 +98,7 @@ int oracle_direct_1d_uneq_sampled(int64_t Lf, int64_t Lg, int64_t C, const doubl
     return 0;
 }
 
-/* eq. (4) for the listed output indices only (copy 0 .. C-1 of each). */
+/* eq. (5) for the listed output indices only (copy 0 .. C-1 of each). */
 int oracle_direct_1d_sampled(int64_t L, int64_t C, const double* f_, const double* g_,
                              const int64_t* ks, int64_t nk, double* out_) {
     return oracle_direct_1d_uneq_sampled(L, L, C, f_, g_, ks, nk, out_);
@@ -108,7 +108,7 @@ static void unravel(int ndim, const int64_t* ext, int64_t lin, int64_t* idx) {
     for (int a = ndim - 1; a >= 0; --a) { idx[a] = lin % ext[a]; lin /= ext[a]; }
 }
 
-/* N-D eq. (4) for the listed output multi-indices (given as row-major linear
+/* N-D eq. (5) for the listed output multi-indices (given as row-major linear
  * indices into the M box). ndim <= 3. */
 int oracle_direct_nd_sampled(int ndim, const int64_t* L, const int64_t* M, const double* f_, const double* g_,
                              const int64_t* ks, int64_t nk, double* out_) {
@@ -320,7 +320,7 @@ int oracle_padded_nd(int ndim, const int64_t* L, const int64_t* M, const double*
 }
 
 /* Zero-extended forward DFT (the transform that the residues of section 2.2,
- * eq. (1), enumerate): X_k = sum_{j<L} zeta_N^{+kj} x_j for k < N. */
+ * eq. (3), enumerate): X_k = sum_{j<L} zeta_N^{+kj} x_j for k < N. */
 int oracle_padded_dft(int64_t L, int64_t N, const double* x_, double* X_) {
     if (L < 0 || N < 1 || L > N) return 1;
     cd* buf = (cd*)calloc((size_t)N, sizeof(cd));

@@ -246,7 +246,9 @@ hdc_status geometry(AxisPlan& A, bool outer, bool many_rows = false) {
     {
         const int ppt = ppt_for((int)d.m);
         const int tpf = (int)d.m / ppt;
-        int Dc = (int)std::min<int64_t>(d.D, d.q);
+        // every residue of a row stays in LDS whatever D is (D bounds the
+        // workspace of the multi-pass variant), so D does not limit concurrency
+        int Dc = (int)d.q;
         Dc = std::max(1, std::min(Dc, 512 / tpf));
         const int rowthreads = tpf * Dc;
         const size_t rowlds = (size_t)(d.q * padded_len(d.m)) * b;

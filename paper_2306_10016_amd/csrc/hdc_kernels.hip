@@ -1,6 +1,6 @@
 // HIP kernels of the hybrid dealiased convolution, written for gfx950 (CDNA4).
 //
-// Notation (section 2.2, eq. (1)): N = q m, residue r < q, block t < p,
+// Notation (section 2.2, eqs. (3)-(4)): N = q m, residue r < q, block t < p,
 // column s < m, frequency l < m; zeta_n = exp(+2 pi i / n).
 //
 //   forward   F_{q l + r} = sum_s zeta_m^{l s} [ zeta_N^{r s} sum_t zeta_q^{r t} f_{t m + s} ]
@@ -10,7 +10,7 @@
 // radix-4 pass) with every thread owning PPT = 8 points at positions
 // lane + v*(n/8).  With that ownership the inputs of every pass and the
 // outputs of the last pass sit in the same registers, so
-//   * the block sum of eq. (1) is computed straight into the registers of the
+//   * the block sum of eq. (3) is computed straight into the registers of the
 //     first radix pass (it never touches LDS or HBM), and
 //   * the pointwise product F.G sits between the last forward pass and the
 //     first inverse pass in registers (section 2.4, the convolution theorem).
@@ -339,7 +339,7 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
         const bool act = rowok && r < a.q;
         cplx<T>* buf = U + (size_t)(act ? r : 0) * RS;
 
-        // block sums of eq. (1) for f and g, straight into the first radix pass
+        // block sums of eq. (3) for f and g, straight into the first radix pass
         cplx<T> F[PPT], G[PPT];
 #pragma unroll
         for (int v = 0; v < PPT; ++v) {

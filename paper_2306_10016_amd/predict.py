@@ -1,10 +1,10 @@
-"""Learned parameter predictor (section 4.3 and sections 5-6): a small MLP that
+"""Learned parameter predictor (section 4.4 and sections 5-6): a small MLP that
 maps a problem axis to the scale-free class (p, D) of its best parameters.
 
 * Training data come from the project's own tuner: problems of at most 2^20
   elements (1D with 1, 4 or 16 copies, 2D squares and rectangles, 3D boxes,
   sides of the form 2^a 3^b 5^c 7^d, complex64 and complex128) are tuned one
-  axis at a time (the separable search of section 4.1) and every timing is
+  axis at a time (the separable search of section 4.2) and every timing is
   cached in the JSON-lines database (section 5.1).
 * Classes are scale-free (p, D-mode): p = ceil(L/m) in {1,2,3,4,6,8,12,16},
   D-mode "all residues in one pass" or "one residue per pass".  A class maps
@@ -159,7 +159,7 @@ def default_params(Ls, Ms):
 
 
 def tune_separable(Ls, Ms, dtype, timer, batch=1, db: Optional[tune.TuneDB] = None):
-    """A0 per axis (section 4.1): each axis searched with the others at their defaults.
+    """A0 per axis (section 4.2): each axis searched with the others at their defaults.
     Returns (per-axis best (m, D), per-axis tables, time of the combined choice)."""
     from . import HdcError
     base = default_params(Ls, Ms)

@@ -3,20 +3,20 @@
 Two searches, both scoring a parameter set by the measured time of the whole
 convolution (hdc_time_convolve: HIP events, median of the repetitions):
 
-* **A0** (section 4.1): exhaustive grid over the candidate FFT sizes m (each
+* **A0** (section 4.2): exhaustive grid over the candidate FFT sizes m (each
   fixing p = ceil(L/m), q = ceil(M/m)) and residues-per-pass D.  For N-D
   problems each axis is searched on its own with the other axes held at
-  their defaults (the per-dimension separability argument of section 4.1).
-* **A1** (section 4.2, "experience"): (1) reuse the best entry of the timing
+  their defaults (the per-dimension separability argument of section 4.2).
+* **A1** (section 4.3, "experience"): (1) reuse the best entry of the timing
   database for the same problem; (2) seed with the scale-free class (p, D)
   that won on the nearest already-tuned problem, including the rectangle ->
-  square reuse of section 4.2's third heuristic; (3) a random subset of the
+  square reuse of section 4.3's third heuristic; (3) a random subset of the
   remaining candidates (random search); (4) local refinement around the best
   so far (the neighbouring m and D), which biases sampling toward the region
   that scored well (the Bayesian-search idea, without a surrogate model).
 
-All timings are appended to a JSON-lines database (section 5.1's "cache all
-the results"), keyed by problem, parameters, device and library build, so a
+All timings are appended to a JSON-lines database (section 5.1 keeps every
+measured result), keyed by problem, parameters, device and library build, so a
 killed run resumes where it stopped.
 """
 from __future__ import annotations

@@ -1,7 +1,7 @@
 """Writes the stored expected values under tests/golden/.
 
 Calls only the oracle (and the seeded input generator).  Inputs are Gaussian
-integers, so the direct sum of eq. (4) is exact in FP64 and the stored
+integers, so the direct sum of eq. (5) is exact in FP64 and the stored
 outputs are exact integers.
 
 fig2_L6_M11.txt -- the worked shape of the paper's 1D parameter figure

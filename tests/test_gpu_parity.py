@@ -129,7 +129,7 @@ def test_bitwise_deterministic():
 @pytest.mark.parametrize("L,M,m,D,C", [(6, 11, 4, 1, 1), (100, 199, 32, 3, 1), (1000, 2047, 256, 8, 1),
                                        (5000, 9999, 8192, 1, 1), (300, 599, 64, 2, 3)])
 def test_forward_multiply_backward(L, M, m, D, C, dtype):
-    """Residues equal the zero-extended N-point DFT (eq. (1)); the group loop gives h."""
+    """Residues equal the zero-extended N-point DFT (eq. (3)); the group loop gives h."""
     import torch
     say(f"fwd/bwd L={L} M={M} m={m} D={D} C={C} {dtype}")
     shape = L if C == 1 else (L, C)

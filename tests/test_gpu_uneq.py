@@ -1,7 +1,7 @@
 """GPU parity of the unequal-length convolution (section 3.5): the shorter
 operand in m-point residues, the longer in Lambda m-point ones, matched by
 r_f = q_g lambda + r_g.  Every case compares hdc_plan_uneq / hdc_convolve with
-the FP64 oracle's direct sum of eq. (4) element by element."""
+the FP64 oracle's direct sum of eq. (5) element by element."""
 import numpy as np
 import pytest
 

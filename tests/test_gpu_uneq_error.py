@@ -1,6 +1,6 @@
 """Accuracy of the unequal-length convolution as the longer operand grows, for a
 fixed shorter operand of length 2 or 12 and several transform lengths: the
-study of the L2 error against the length of g (section 5.1's figure on padding
+study of the L2 error against the length of g (section 6.1's figure on padding
 sizes).  The reference is the oracle's FP64 direct sum; explicit padding
 (torch.fft on the GPU, the same dtype) is measured beside it.  The bar is the
 normwise bound of FFT-based convolution, a small multiple of eps log2 N."""

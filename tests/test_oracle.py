@@ -2,7 +2,7 @@
 
 Each test names what fixes the expected value: a library routine
 (numpy.convolve, numpy.fft, scipy.signal), exact integer arithmetic, a closed
-form of eq. (4) (section 2.3), the orthogonality relation of section 2.1, or
+form of eq. (5) (section 2.3), the orthogonality relation of section 2.1, or
 the structure of explicit dealiasing (section 3.1).
 """
 import numpy as np
@@ -20,7 +20,7 @@ def _gauss_int(L, C=None, seed=0, bound=8):
 
 
 def _exact_int_conv(f, g, M):
-    """Brute-force eq. (4) in Python integers (exact)."""
+    """Brute-force eq. (5) in Python integers (exact)."""
     fr = [(int(z.real), int(z.imag)) for z in f]
     gr = [(int(z.real), int(z.imag)) for z in g]
     L = len(fr)
@@ -61,7 +61,7 @@ def test_output_tail_beyond_2L_minus_1_is_exactly_zero(L, M):
 
 @pytest.mark.parametrize("L", [6, 37, 300])
 def test_gaussian_integers_exact(L):
-    """Integer inputs: eq. (4) by Python integer arithmetic is exact."""
+    """Integer inputs: eq. (5) by Python integer arithmetic is exact."""
     f, g = _gauss_int(L, seed=L)
     M = 2 * L - 1
     exact = _exact_int_conv(f, g, M)
