@@ -59,6 +59,8 @@ def _load():
         lib.oracle_direct_1d_uneq_sampled.argtypes = [_I64, _I64, _I64, _P, _P, _P, _I64, _P]
         lib.oracle_padded_1d_uneq.argtypes = [_I64, _I64, _I64, _I64, _P, _P, _P]
         lib.oracle_padded_nd.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P]
+        lib.oracle_direct_nd_uneq_sampled.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P, _P, _I64, _P]
+        lib.oracle_padded_nd_uneq.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P, _P]
         lib.oracle_dft.argtypes = [_I64, _P, ctypes.c_int]
         lib.oracle_padded_dft.argtypes = [_I64, _I64, _P, _P]
         lib.oracle_friendly_size.argtypes = [_I64]
@@ -124,16 +126,21 @@ def direct_1d_sampled(f, g, ks) -> np.ndarray:
 
 
 def direct_nd_sampled(f, g, M, ks) -> np.ndarray:
-    """N-D eq. (5) at the row-major linear indices ``ks`` of the output box M."""
+    """N-D eq. (5) at the row-major linear indices ``ks`` of the output box M; f and
+    g may have different extents (same number of axes)."""
     f = _c128(f)
     g = _c128(g)
     nd = f.ndim
-    Ls = np.ascontiguousarray(f.shape, dtype=np.int64)
+    if g.ndim != nd:
+        raise ValueError("f and g must have the same number of axes")
+    Lf = np.ascontiguousarray(f.shape, dtype=np.int64)
+    Lg = np.ascontiguousarray(g.shape, dtype=np.int64)
     Ms = np.ascontiguousarray(M, dtype=np.int64)
     ks = np.ascontiguousarray(ks, dtype=np.int64)
     out = np.empty(ks.size, np.complex128)
-    _check(_load().oracle_direct_nd_sampled(nd, Ls.ctypes.data, Ms.ctypes.data, f.ctypes.data, g.ctypes.data,
-                                            ks.ctypes.data, ks.size, out.ctypes.data), "direct_nd_sampled")
+    _check(_load().oracle_direct_nd_uneq_sampled(nd, Lf.ctypes.data, Lg.ctypes.data, Ms.ctypes.data, f.ctypes.data,
+                                                 g.ctypes.data, ks.ctypes.data, ks.size, out.ctypes.data),
+           "direct_nd_sampled")
     return out
 
 
@@ -159,14 +166,18 @@ def padded_1d(f, g, M: int) -> np.ndarray:
 
 
 def padded_nd(f, g, M) -> np.ndarray:
-    """Explicitly zero-padded FFT convolution in 1..3 dimensions."""
+    """Explicitly zero-padded FFT convolution in 1..3 dimensions (f and g may differ
+    in extent along any axis)."""
     f = _c128(f)
     g = _c128(g)
-    Ls = np.ascontiguousarray(f.shape, dtype=np.int64)
+    if g.ndim != f.ndim:
+        raise ValueError("f and g must have the same number of axes")
+    Lf = np.ascontiguousarray(f.shape, dtype=np.int64)
+    Lg = np.ascontiguousarray(g.shape, dtype=np.int64)
     Ms = np.ascontiguousarray(M, dtype=np.int64)
     h = np.empty(tuple(int(x) for x in M), np.complex128)
-    _check(_load().oracle_padded_nd(f.ndim, Ls.ctypes.data, Ms.ctypes.data, f.ctypes.data, g.ctypes.data,
-                                    h.ctypes.data), "padded_nd")
+    _check(_load().oracle_padded_nd_uneq(f.ndim, Lf.ctypes.data, Lg.ctypes.data, Ms.ctypes.data, f.ctypes.data,
+                                         g.ctypes.data, h.ctypes.data), "padded_nd")
     return h
 
 

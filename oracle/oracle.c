@@ -109,32 +109,36 @@ static void unravel(int ndim, const int64_t* ext, int64_t lin, int64_t* idx) {
 }
 
 /* N-D eq. (5) for the listed output multi-indices (given as row-major linear
- * indices into the M box). ndim <= 3. */
-int oracle_direct_nd_sampled(int ndim, const int64_t* L, const int64_t* M, const double* f_, const double* g_,
-                             const int64_t* ks, int64_t nk, double* out_) {
+ * indices into the M box), f of extents Lf and g of extents Lg (equal or not,
+ * section 3.6 with the lengths of section 3.5). ndim <= 3. */
+int oracle_direct_nd_uneq_sampled(int ndim, const int64_t* Lf, const int64_t* Lg, const int64_t* M, const double* f_,
+                                  const double* g_, const int64_t* ks, int64_t nk, double* out_) {
     if (ndim < 1 || ndim > 3) return 1;
     const cd* f = (const cd*)f_;
     const cd* g = (const cd*)g_;
     cd* out = (cd*)out_;
-    int64_t L3[3] = {1, 1, 1};
-    for (int a = 0; a < ndim; ++a) L3[3 - ndim + a] = L[a];
+    int64_t F3[3] = {1, 1, 1}, G3[3] = {1, 1, 1};
+    for (int a = 0; a < ndim; ++a) {
+        F3[3 - ndim + a] = Lf[a];
+        G3[3 - ndim + a] = Lg[a];
+    }
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t i = 0; i < nk; ++i) {
         int64_t k[3] = {0, 0, 0}, kk[3];
         unravel(ndim, M, ks[i], kk);
         for (int a = 0; a < ndim; ++a) k[3 - ndim + a] = kk[a];
         cd acc = {0.0, 0.0};
-        for (int64_t j0 = 0; j0 < L3[0]; ++j0) {
+        for (int64_t j0 = 0; j0 < F3[0]; ++j0) {
             int64_t d0 = k[0] - j0;
-            if (d0 < 0 || d0 >= L3[0]) continue;
-            for (int64_t j1 = 0; j1 < L3[1]; ++j1) {
+            if (d0 < 0 || d0 >= G3[0]) continue;
+            for (int64_t j1 = 0; j1 < F3[1]; ++j1) {
                 int64_t d1 = k[1] - j1;
-                if (d1 < 0 || d1 >= L3[1]) continue;
-                for (int64_t j2 = 0; j2 < L3[2]; ++j2) {
+                if (d1 < 0 || d1 >= G3[1]) continue;
+                for (int64_t j2 = 0; j2 < F3[2]; ++j2) {
                     int64_t d2 = k[2] - j2;
-                    if (d2 < 0 || d2 >= L3[2]) continue;
-                    int64_t a = (j0 * L3[1] + j1) * L3[2] + j2;
-                    int64_t b = (d0 * L3[1] + d1) * L3[2] + d2;
+                    if (d2 < 0 || d2 >= G3[2]) continue;
+                    int64_t a = (j0 * F3[1] + j1) * F3[2] + j2;
+                    int64_t b = (d0 * G3[1] + d1) * G3[2] + d2;
                     acc = cadd(acc, cmul(f[a], g[b]));
                 }
             }
@@ -142,6 +146,12 @@ int oracle_direct_nd_sampled(int ndim, const int64_t* L, const int64_t* M, const
         out[i] = acc;
     }
     return 0;
+}
+
+/* N-D eq. (5) for the listed output multi-indices, equal extents L. */
+int oracle_direct_nd_sampled(int ndim, const int64_t* L, const int64_t* M, const double* f_, const double* g_,
+                             const int64_t* ks, int64_t nk, double* out_) {
+    return oracle_direct_nd_uneq_sampled(ndim, L, L, M, f_, g_, ks, nk, out_);
 }
 
 /* ------------------------------------------------------------------- DFT -- */
@@ -280,25 +290,33 @@ static void dft_axis(cd* x, int nd, const int64_t* ext, int axis, int sign) {
 
 /* Explicitly zero-padded FFT convolution in 1..3 dimensions (per-axis padding
  * to the smallest friendly size >= 2 L_a - 1). */
-int oracle_padded_nd(int ndim, const int64_t* L, const int64_t* M, const double* f_, const double* g_, double* h_) {
+int oracle_padded_nd_uneq(int ndim, const int64_t* Lf, const int64_t* Lg, const int64_t* M, const double* f_,
+                          const double* g_, double* h_) {
     if (ndim < 1 || ndim > 3) return 1;
     const cd* f = (const cd*)f_;
     const cd* g = (const cd*)g_;
     cd* h = (cd*)h_;
-    int64_t Ne[3], tot = 1, totL = 1, totM = 1;
+    int64_t Ne[3], K[3], tot = 1, totF = 1, totG = 1, totM = 1;
     for (int a = 0; a < ndim; ++a) {
-        if (L[a] < 1 || M[a] < 1) return 1;
-        Ne[a] = oracle_friendly_size(2 * L[a] - 1);
-        tot *= Ne[a]; totL *= L[a]; totM *= M[a];
+        if (Lf[a] < 1 || Lg[a] < 1 || M[a] < 1) return 1;
+        K[a] = Lf[a] + Lg[a] - 1;
+        Ne[a] = oracle_friendly_size(K[a]);
+        tot *= Ne[a]; totF *= Lf[a]; totG *= Lg[a]; totM *= M[a];
     }
     cd* A = (cd*)calloc((size_t)tot, sizeof(cd));
     cd* B = (cd*)calloc((size_t)tot, sizeof(cd));
     int64_t idx[3];
-    for (int64_t lin = 0; lin < totL; ++lin) {
-        unravel(ndim, L, lin, idx);
+    for (int64_t lin = 0; lin < totF; ++lin) {
+        unravel(ndim, Lf, lin, idx);
         int64_t p = 0;
         for (int a = 0; a < ndim; ++a) p = p * Ne[a] + idx[a];
-        A[p] = f[lin]; B[p] = g[lin];
+        A[p] = f[lin];
+    }
+    for (int64_t lin = 0; lin < totG; ++lin) {
+        unravel(ndim, Lg, lin, idx);
+        int64_t p = 0;
+        for (int a = 0; a < ndim; ++a) p = p * Ne[a] + idx[a];
+        B[p] = g[lin];
     }
     for (int a = 0; a < ndim; ++a) { dft_axis(A, ndim, Ne, a, +1); dft_axis(B, ndim, Ne, a, +1); }
     for (int64_t i = 0; i < tot; ++i) A[i] = cmul(A[i], B[i]);
@@ -308,7 +326,7 @@ int oracle_padded_nd(int ndim, const int64_t* L, const int64_t* M, const double*
         int inside = 1;
         int64_t p = 0;
         for (int a = 0; a < ndim; ++a) {
-            if (idx[a] >= 2 * L[a] - 1) inside = 0;
+            if (idx[a] >= K[a]) inside = 0;
             p = p * Ne[a] + (inside ? idx[a] : 0);
         }
         cd v = {0.0, 0.0};
@@ -317,6 +335,11 @@ int oracle_padded_nd(int ndim, const int64_t* L, const int64_t* M, const double*
     }
     free(A); free(B);
     return 0;
+}
+
+/* Explicitly zero-padded FFT convolution in 1..3 dimensions, equal extents L. */
+int oracle_padded_nd(int ndim, const int64_t* L, const int64_t* M, const double* f_, const double* g_, double* h_) {
+    return oracle_padded_nd_uneq(ndim, L, L, M, f_, g_, h_);
 }
 
 /* Zero-extended forward DFT (the transform that the residues of section 2.2,

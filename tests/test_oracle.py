@@ -279,3 +279,23 @@ def test_unequal_sampled_matches_full():
     ks = np.array([0, 1, 6, 7, 150, 299, 305, 306, 319])
     assert np.array_equal(oracle.direct_1d_sampled(f, g, ks), full[ks])
     assert np.array_equal(oracle.direct_1d_sampled(g, f, ks), oracle.direct_1d(g, f, 320)[ks])
+
+
+
+@pytest.mark.parametrize("sf,sg", [((3, 5), (20, 17)), ((20, 2), (4, 30)), ((1, 7), (9, 1)), ((2, 3, 4), (5, 3, 6)),
+                                   ((6, 1, 2), (2, 7, 5))])
+def test_nd_unequal_matches_scipy(sf, sg):
+    """N-D with different extents per operand (section 3.6 with section 3.5's lengths),
+    including axes where f is the longer operand."""
+    from scipy import signal
+    f = synth.uniform_complex(sf, 106, len(sf), 0)
+    g = synth.uniform_complex(sg, 106, len(sf), 1)
+    ref = signal.convolve(f, g, method="direct")
+    K = ref.shape
+    M = tuple(k + 2 for k in K)
+    h = oracle.padded_nd(f, g, M)
+    assert oracle.rel_l2(h[tuple(slice(0, k) for k in K)], ref) < 1e-14
+    assert np.all(h[tuple(slice(k, None) if i == 0 else slice(None) for i, k in enumerate(K))] == 0)
+    ks = np.arange(int(np.prod(M)))
+    d = oracle.direct_nd_sampled(f, g, M, ks).reshape(M)
+    assert oracle.rel_l2(d[tuple(slice(0, k) for k in K)], ref) < 1e-14
