@@ -136,6 +136,30 @@ hdc_status hdc_uneq_derive(int64_t Lf, int64_t Lg, int64_t M, int64_t m, int64_t
 hdc_status hdc_plan_uneq(hdc_plan_t* out, int64_t Lf, int64_t Lg, int64_t M, int64_t m, int64_t Lambda, int64_t C,
                          int64_t D, hdc_dtype dtype);
 
+/*
+ * Unequal extents in 2D/3D (section 3.6 with section 3.5's lengths): f of
+ * extents Lf[0..ndim), g of extents Lg[0..ndim), both row-major with the last
+ * axis contiguous, output box M[a] >= Lf[a] + Lg[a] - 1.  Every axis follows
+ * the 1D rules above on its own, the roles too (f may be the shorter operand
+ * on one axis and the longer on another); m, Lambda and D may be NULL or hold
+ * 0 to derive.  Outer axes are column passes over the inner extents: there
+ * Lambda m <= 2^20, split into a first column stage of min(Lambda m, 1024)
+ * points and a second strided one.  The innermost axis is a batched 1D
+ * unequal convolution per row pair (the fused kernel when Lambda = 1 and it
+ * fits a workgroup's LDS).
+ *
+ * hdc_uneq_nd_check is host-only and fills, per axis, the shorter operand's
+ * description, the longer one's and whether f is the longer one (any output
+ * array may be NULL).  hdc_plan_axis on such a plan: axis a < ndim gives the
+ * longer operand's description, axis ndim + a the shorter one's.
+ * hdc_convolve(plan, f, g, h, ws, s) reads prod(Lf) and prod(Lg) values.
+ */
+hdc_status hdc_uneq_nd_check(int ndim, const int64_t* Lf, const int64_t* Lg, const int64_t* M, const int64_t* m,
+                             const int64_t* Lambda, const int64_t* D, hdc_dtype dtype, hdc_axis_desc* short_out,
+                             hdc_axis_desc* long_out, int* swapped);
+hdc_status hdc_plan_uneq_nd(hdc_plan_t* out, int ndim, const int64_t* Lf, const int64_t* Lg, const int64_t* M,
+                            const int64_t* m, const int64_t* Lambda, const int64_t* D, hdc_dtype dtype);
+
 hdc_status hdc_plan_destroy(hdc_plan_t plan);
 
 /* Number of axes and the description of axis `axis`. */

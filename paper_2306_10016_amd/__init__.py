@@ -250,35 +250,78 @@ def uneq_derive(Lf: int, Lg: int, M: int, m: int = 0, lam: int = 0, C: int = 1, 
     return s.as_dict(), lg.as_dict(), bool(sw.value)
 
 
+def uneq_nd_check(Lf, Lg, M=None, m=None, lam=None, D=None, dtype="c64"):
+    """Host-only check of an unequal-extent N-D plan (hdc_uneq_nd_check):
+    per axis (shorter operand's description, longer operand's, f is the longer)."""
+    n = len(Lf)
+    arr = ctypes.c_int64 * n
+    M = [int(a) + int(b) - 1 for a, b in zip(Lf, Lg)] if M is None else M
+
+    def a(v):
+        return arr(*[int(x) for x in v]) if v is not None else None
+    so, lo, sw = (AxisDesc * n)(), (AxisDesc * n)(), (ctypes.c_int * n)()
+    check(lib().hdc_uneq_nd_check(n, a(Lf), a(Lg), a(M), a(m), a(lam), a(D), dtype_code(dtype), so, lo, sw))
+    return [(so[i].as_dict(), lo[i].as_dict(), bool(sw[i])) for i in range(n)]
+
+
 class UneqPlan(Plan):
     """Unequal operand lengths (hdc_plan_uneq, section 3.5): f of length Lf, g of
     length Lg, output length M >= Lf + Lg - 1; the shorter operand uses m-point
-    residues and the longer Lambda m-point ones.  ``axes[0]`` describes the
-    longer operand (the geometry of the product and the backward),
-    ``short_axis`` the shorter one."""
+    residues and the longer Lambda m-point ones.  ``axes[a]`` describes the
+    longer operand on axis a (the geometry of the product and the backward),
+    ``short_axes[a]`` the shorter one (``short_axis`` for 1D).  ``UneqPlan.nd``
+    builds the 2D/3D form (hdc_plan_uneq_nd)."""
 
     def __init__(self, Lf: int, Lg: int, M: Optional[int] = None, m: int = 0, lam: int = 0, C: int = 1, D: int = 0,
-                 dtype="c128"):
-        M = int(Lf) + int(Lg) - 1 if M is None else int(M)
+                 dtype="c128", _handle=None, _shapes=None):
+        if _handle is None:
+            M = int(Lf) + int(Lg) - 1 if M is None else int(M)
+            h = ctypes.c_void_p()
+            check(lib().hdc_plan_uneq(ctypes.byref(h), int(Lf), int(Lg), M, int(m), int(lam), int(C), int(D),
+                                      dtype_code(dtype)))
+            _handle = h
+            _shapes = ((int(Lf),), (int(Lg),))
+        super().__init__(0, 0, 0, dtype=dtype, _handle=_handle)
+        self.short_axes = []
+        for a in range(self.ndim):
+            d = AxisDesc()
+            check(self._lib.hdc_plan_axis(self._h, self.ndim + a, None, ctypes.byref(d)))
+            self.short_axes.append(d.as_dict())
+        self.short_axis = self.short_axes[0]
+        self.f_shape, self.g_shape = _shapes
+        if self.ndim == 1:
+            self.Lf, self.Lg = self.f_shape[0], self.g_shape[0]
+        self.lams = [ax["m"] // sa["m"] for ax, sa in zip(self.axes, self.short_axes)]
+        self.lam = self.lams[0]
+
+    @classmethod
+    def nd(cls, Lf: Sequence[int], Lg: Sequence[int], M: Optional[Sequence[int]] = None, m=None, lam=None, D=None,
+           dtype="c64"):
+        n = len(Lf)
+        arr = ctypes.c_int64 * n
+        M = [int(a) + int(b) - 1 for a, b in zip(Lf, Lg)] if M is None else M
+
+        def a(v):
+            return arr(*[int(x) for x in v]) if v is not None else None
         h = ctypes.c_void_p()
-        check(lib().hdc_plan_uneq(ctypes.byref(h), int(Lf), int(Lg), M, int(m), int(lam), int(C), int(D),
-                                  dtype_code(dtype)))
-        super().__init__(0, 0, 0, dtype=dtype, _handle=h)
-        d = AxisDesc()
-        check(self._lib.hdc_plan_axis(self._h, 1, None, ctypes.byref(d)))
-        self.short_axis = d.as_dict()
-        self.Lf, self.Lg = int(Lf), int(Lg)
-        self.lam = self.axes[0]["m"] // self.short_axis["m"]
+        check(lib().hdc_plan_uneq_nd(ctypes.byref(h), n, a(Lf), a(Lg), a(M), a(m), a(lam), a(D), dtype_code(dtype)))
+        return cls(0, 0, dtype=dtype, _handle=h, _shapes=(tuple(int(x) for x in Lf), tuple(int(x) for x in Lg)))
 
     @property
     def L(self):
-        return (self.Lf, self.Lg)
+        return (self.f_shape, self.g_shape) if self.ndim > 1 else (self.Lf, self.Lg)
+
+    def _numel(self, shape):
+        n = 1
+        for x in shape:
+            n *= x
+        return n * (self.C if self.ndim == 1 else 1)
 
     def convolve(self, f, g, out=None, ws=None, stream=None):
         """h = f * g (hdc_convolve of the unequal-length plan)."""
         import torch
-        _check_tensor(f, self.dtype, self.Lf * self.C, "f")
-        _check_tensor(g, self.dtype, self.Lg * self.C, "g")
+        _check_tensor(f, self.dtype, self._numel(self.f_shape), "f")
+        _check_tensor(g, self.dtype, self._numel(self.g_shape), "g")
         if out is None:
             out = torch.empty(self.out_shape(), dtype=torch_dtype(self.dtype), device=f.device)
         _check_tensor(out, self.dtype, self.out_numel(), "out")
@@ -291,7 +334,7 @@ class UneqPlan(Plan):
     def forward_operand(self, operand: int, x, F, r0: int, stream=None):
         """hdc_forward_operand: residues of group r0 of f (operand 0) or g (operand 1),
         in the longer operand's geometry."""
-        _check_tensor(x, self.dtype, (self.Lf if operand == 0 else self.Lg) * self.C, "x")
+        _check_tensor(x, self.dtype, self._numel(self.f_shape if operand == 0 else self.g_shape), "x")
         check(self._lib.hdc_forward_operand(self._h, int(operand), _ptr(x), _ptr(F), int(r0), None, _stream(stream)))
         return F
 

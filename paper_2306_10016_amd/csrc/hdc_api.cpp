@@ -151,12 +151,14 @@ struct hdc_plan_s {
     int ndim = 1;
     hdc_dtype dtype = HDC_C128;
     AxisPlan ax[3];
-    // unequal lengths (section 3.5): ax[0] is the longer operand's geometry
-    // (Lambda m-point residues), fx the shorter operand's (m-point residues)
+    // unequal lengths (sections 3.5-3.6): per axis, ax[a] is the longer
+    // operand's geometry (Lambda m-point residues) and fx[a] the shorter one's
+    // (m-point residues); swap[a]: the caller's f is the longer one on axis a
     bool uneq = false;
-    bool swap = false;  // the caller's f is the longer operand
-    int64_t lam = 1;
-    AxisPlan fx;
+    bool swap[3] = {false, false, false};
+    int64_t lam[3] = {1, 1, 1};
+    int64_t Lf[3] = {1, 1, 1}, Lg[3] = {1, 1, 1};
+    AxisPlan fx[3];
     void* tables = nullptr;
     size_t ws_bytes = 0;
 };
@@ -219,7 +221,7 @@ int tile_for(int tpf, int tmin, int maxthreads) {
 
 // Geometry of every kernel for one axis; `outer` = transformed as a column
 // stage of an N-D problem (m1 = m, m2 = 1).
-hdc_status geometry(AxisPlan& A, bool outer, bool many_rows = false) {
+hdc_status geometry(AxisPlan& A, bool outer, bool many_rows = false, bool keep_split = false) {
     hdc_axis_desc& d = A.d;
     const size_t b = A.dbl ? 16 : 8;
     if (outer) {
@@ -227,8 +229,10 @@ hdc_status geometry(AxisPlan& A, bool outer, bool many_rows = false) {
         // factors column passes (the second one a plain strided m2-point DFT)
         if (d.m > (int64_t)kMaxM1 * kMaxM1)
             return fail(HDC_ERR_UNSUPPORTED, "outer-axis m = %lld exceeds %d", (long long)d.m, kMaxM1 * kMaxM1);
-        d.m1 = std::min<int64_t>(d.m, kMaxM1);
-        d.m2 = d.m / d.m1;
+        if (!keep_split) {
+            d.m1 = std::min<int64_t>(d.m, kMaxM1);
+            d.m2 = d.m / d.m1;
+        }
         d.variant = 1;
         const int ppt = ppt_for((int)d.m2);
         const int tpf = (int)d.m2 / ppt;
@@ -312,7 +316,7 @@ int64_t pow2_ceil(int64_t x) {
 // shorter one's is (m1g/Lambda) x m2g, so its row l1f of residue r_f is the
 // longer operand's row Lambda l1f + lambda of residue r_f - q_g lambda.
 hdc_status derive_uneq(int64_t Lf, int64_t Lg, int64_t M, int64_t m, int64_t lam, int64_t C, int64_t D,
-                       hdc_dtype dtype, hdc_axis_desc* fo, hdc_axis_desc* go, bool* swapped) {
+                       hdc_dtype dtype, hdc_axis_desc* fo, hdc_axis_desc* go, bool* swapped, bool outer = false) {
     if (Lf < 1 || Lg < 1) return fail(HDC_ERR_INVALID_ARG, "Lf = %lld and Lg = %lld must be >= 1", (long long)Lf,
                                       (long long)Lg);
     const bool sw = Lf > Lg;
@@ -321,7 +325,8 @@ hdc_status derive_uneq(int64_t Lf, int64_t Lg, int64_t M, int64_t m, int64_t lam
         return fail(HDC_ERR_INVALID_ARG, "M = %lld < Lf + Lg - 1 = %lld: the output would alias", (long long)M,
                     (long long)(Ls + Ll - 1));
     if (m < 0 || lam < 0) return fail(HDC_ERR_INVALID_ARG, "m and Lambda must be >= 0 (0 derives)");
-    const int64_t mg_max = int64_t(kMaxM1) * kMaxRow;
+    // an outer N-D axis is two column stages of at most kMaxM1 each
+    const int64_t mg_max = int64_t(kMaxM1) * (outer ? kMaxM1 : kMaxRow);
     if (m == 0 || lam == 0) {
         // Lambda m: up to 2^17 output points a single block (q_g = 1: one
         // residue, the fewest launches); beyond, the power of two with at most
@@ -360,15 +365,24 @@ hdc_status derive_uneq(int64_t Lf, int64_t Lg, int64_t M, int64_t m, int64_t lam
     hdc_axis_desc g{};
     hdc_status st = derive_axis(Ll, M, lam * m, 0, 0, C, D, dtype, &g, Ls + Ll - 1);
     if (st != HDC_OK) return st;
-    // split with Lambda | m1g
-    g.m1 = std::max<int64_t>(lam, g.m / kMaxRow);
+    if (g.m > mg_max)
+        return fail(HDC_ERR_UNSUPPORTED, "Lambda m = %lld exceeds %lld", (long long)g.m, (long long)mg_max);
+    // split with Lambda | m1g: a 1D axis (and the innermost N-D axis) puts at
+    // most kMaxRow points in the row stage; an outer axis puts up to kMaxM1 in
+    // its first column stage (Lambda <= kMaxM1 divides it)
+    if (outer) {
+        g.m1 = std::min<int64_t>(g.m, kMaxM1);
+        if (g.m1 < lam) g.m1 = lam;
+    } else {
+        g.m1 = std::max<int64_t>(lam, g.m / kMaxRow);
+    }
     g.m2 = g.m / g.m1;
-    if (g.m1 > kMaxM1)
-        return fail(HDC_ERR_UNSUPPORTED, "Lambda m = %lld exceeds %lld", (long long)g.m,
-                    (long long)(int64_t(kMaxM1) * kMaxRow));
+    if (g.m1 > kMaxM1 || (outer && g.m2 > kMaxM1))
+        return fail(HDC_ERR_UNSUPPORTED, "Lambda m = %lld does not split for Lambda = %lld", (long long)g.m,
+                    (long long)lam);
     // Lambda = 1 keeps the single-kernel variant when it fits (both operands
     // then share m and differ only in their lengths)
-    if (lam > 1) g.variant = 1;
+    if (lam > 1 || outer) g.variant = 1;
     hdc_axis_desc f = g;
     f.L = Ls;
     f.m = m;
@@ -441,9 +455,10 @@ void bind_tables(AxisPlan& A, unsigned char* base) {
 
 // ---------------------------------------------------------------- launches --
 
-// Lf >= 0: f has length Lf and g the axis length (section 3.5 with Lambda = 1).
+// Lf >= 0: f has length Lf and g the axis length, g's rows addressed by ing
+// (section 3.5 with Lambda = 1).
 hdc_status run_fused(const AxisPlan& A, const void* f, const void* g, void* h, int64_t nrows, RowAddr in, RowAddr out,
-                     const int64_t* desc, hipStream_t s, int64_t Lf = -1) {
+                     const int64_t* desc, hipStream_t s, int64_t Lf = -1, RowAddr ing = RowAddr{}) {
     if (nrows <= 0) return HDC_OK;
     FusedArgs a{};
     a.f = f;
@@ -465,6 +480,7 @@ hdc_status run_fused(const AxisPlan& A, const void* f, const void* g, void* h, i
     if (Lf >= 0) {
         a.L = (int32_t)Lf;
         a.Lg = (int32_t)A.d.L;
+        a.ing = ing;
     }
     a.hiprec = A.hiprec ? 1 : 0;
     a.tw = A.tw;
@@ -675,7 +691,7 @@ hdc_status run_rows(const AxisPlan& A, const void* a_, const void* b_, void* out
 // the longer operand's column-stage output Xg (plan G); the product's inverse
 // rows go to out.
 hdc_status run_rows_raw(const AxisPlan& G, const AxisPlan& F, const void* xs, const void* Xg, void* out, int64_t nrows,
-                        int64_t C1, int64_t r0, hipStream_t s) {
+                        int64_t C1, int64_t r0, int64_t Dg, int64_t xs_bs, hipStream_t s) {
     if (nrows <= 0) return HDC_OK;
     RowArgs a{};
     a.a = nullptr;
@@ -699,11 +715,14 @@ hdc_status run_rows_raw(const AxisPlan& G, const AxisPlan& F, const void* xs, co
     a.r0 = (int32_t)r0;
     a.qg = (int32_t)G.d.q;
     a.m1g = (int32_t)G.d.m1;
+    a.Dg = (int32_t)Dg;
+    a.fbs = xs_bs;
     a.hiprec = F.hiprec ? 1 : 0;
     const int64_t blocks = ceil_div(nrows, G.r_rpw);
     if (nrows > 0x7fffffff) return fail(HDC_ERR_UNSUPPORTED, "too many rows");
     const double eb = G.dbl ? 16.0 : 8.0;
-    LaunchScope ls(s, 2, eb * (2.0 * (double)nrows * (double)G.d.m2 + (double)(F.d.L * C1)));
+    const double batches = (double)nrows / (double)(Dg * G.d.m1 * C1);
+    LaunchScope ls(s, 2, eb * (2.0 * (double)nrows * (double)G.d.m2 + batches * (double)(F.d.L * C1)));
     hipError_t e = launch_row(G.dbl, (int)G.d.m2, a, G.r_threads, blocks, G.r_lds, s);
     if (e != hipSuccess) return hip_fail(e, "row launch");
     return HDC_OK;
@@ -808,45 +827,146 @@ hdc_status convnd(const hdc_plan_s* P, int level, const void* xf, const void* xg
 // operand's matching residues r_f = q_g lambda + r_g (lambda < Lambda) are
 // formed by its own column stage, stored row-interleaved so that the row pass
 // multiplies row by row; the backward runs in the longer operand's geometry.
-// With Lambda = 1 and a transform that fits one workgroup, the single fused
-// kernel runs instead (both operands share m); with the shorter operand's column
-// stage trivial (m1f = 1), the row pass forms its rows from the raw input.
-hdc_status conv_uneq(const hdc_plan_s* P, const void* xs, const void* xl, void* out, char* ws, hipStream_t s) {
-    const AxisPlan& G = P->ax[0];
-    const AxisPlan& F = P->fx;
-    const int64_t C = G.d.C;
+// Section 3.5 along one axis for B batches of C1 interleaved copies: xs is the
+// operand that is shorter on this axis (plan F, m-point residues), xl the
+// longer one (plan G, Lambda m-point residues), batch strides xs_bs, xl_bs and
+// out_bs.  With Lambda = 1 and a transform that fits one workgroup, the single
+// fused kernel runs (both operands share m); with the shorter operand's column
+// stage trivial (m1f = 1), the row pass forms its rows from the raw input;
+// otherwise both column stages run, the shorter one's residues r_f = q_g lambda
+// + r_g stored row-interleaved so that the row pass multiplies row by row.
+hdc_status conv_uneq(const AxisPlan& G, const AxisPlan& F, int64_t lam, const void* xs, const void* xl, void* out,
+                     int64_t B, int64_t xs_bs, int64_t xl_bs, int64_t out_bs, int64_t C1, char* ws, size_t eb,
+                     hipStream_t s) {
     if (G.d.variant == 0) {
-        RowAddr io{C, 0, 1, C};
-        return run_fused(G, xs, xl, out, C, io, io, nullptr, s, F.d.L);
+        RowAddr is{C1, xs_bs, 1, C1}, il{C1, xl_bs, 1, C1}, io{C1, out_bs, 1, C1};
+        return run_fused(G, xs, xl, out, B * C1, is, io, nullptr, s, F.d.L, il);
     }
-    const size_t eb = elem(P);
     const int64_t D = std::min(G.d.D, G.d.q);
     const bool raw = F.d.m1 == 1;
     char* Xg = ws;
-    char* Xf = ws + (size_t)(D * G.d.m * C) * eb;
+    char* Xf = ws + (size_t)(B * D * G.d.m * C1) * eb;
     for (int64_t r0 = 0; r0 < G.d.q; r0 += D) {
         const int64_t Dg = std::min(D, G.d.q - r0);
-        const int64_t xbs = Dg * G.d.m * C;
-        const int64_t rows = Dg * G.d.m1 * C;
-        hdc_status st = run_col_fwd(G, xl, Xg, 1, 0, xbs, C, r0, Dg, s);
+        const int64_t xbs = Dg * G.d.m * C1;
+        const int64_t rows = B * Dg * G.d.m1 * C1;
+        hdc_status st = run_col_fwd(G, xl, Xg, B, xl_bs, xbs, C1, r0, Dg, s);
         if (st == HDC_OK) {
             if (raw) {
-                st = run_rows_raw(G, F, xs, Xg, Xg, rows, C, r0, s);
+                st = run_rows_raw(G, F, xs, Xg, Xg, rows, C1, r0, Dg, xs_bs, s);
             } else {
-                st = run_col_fwd(F, xs, Xf, 1, 0, xbs, C, r0, Dg, s, nullptr, P->lam, G.d.q);
-                if (st == HDC_OK) st = run_rows(G, Xf, Xg, Xg, rows, C, MODE_CONV, s);
+                st = run_col_fwd(F, xs, Xf, B, xs_bs, xbs, C1, r0, Dg, s, nullptr, lam, G.d.q);
+                if (st == HDC_OK) st = run_rows(G, Xf, Xg, Xg, rows, C1, MODE_CONV, s);
             }
         }
-        if (st == HDC_OK) st = run_col_bwd(G, Xg, out, 1, xbs, 0, C, r0, Dg, r0 > 0, s);
+        if (st == HDC_OK) st = run_col_bwd(G, Xg, out, B, xbs, out_bs, C1, r0, Dg, r0 > 0, s);
         if (st != HDC_OK) return st;
     }
     return HDC_OK;
 }
 
+// Workspace (elements) of conv_uneq for B batches of C1 copies.
+int64_t ws_uneq(const AxisPlan& G, const AxisPlan& F, int64_t B, int64_t C1) {
+    if (G.d.variant == 0) return 0;
+    const int64_t one = B * std::min(G.d.D, G.d.q) * G.d.m * C1;
+    return F.d.m1 == 1 ? one : 2 * one;
+}
+
+int64_t prod3(const int64_t* L, int from, int ndim) {
+    int64_t v = 1;
+    for (int a = from; a < ndim; ++a) v *= L[a];
+    return v;
+}
+
+// Workspace (elements) of the unequal N-D recursion from `level` with B batches.
+int64_t wsnd_uneq(const hdc_plan_s* P, int level, int64_t B) {
+    const AxisPlan& G = P->ax[level];
+    if (level == P->ndim - 1) return ws_uneq(G, P->fx[level], B, 1);
+    const int64_t Dg = std::min(G.d.D, G.d.q);
+    const int64_t nb = B * Dg * G.d.m;
+    const int64_t inf = prod3(P->Lf, level + 1, P->ndim), ing = prod3(P->Lg, level + 1, P->ndim);
+    int64_t inner_out = 1;
+    for (int a = level + 1; a < P->ndim; ++a) inner_out *= P->ax[a].d.M;
+    return nb * (inf + ing + inner_out) + wsnd_uneq(P, level + 1, nb);
+}
+
+// Section 3.6 with section 3.5's lengths: along the outer axis, for each residue
+// group of the longer operand, the forward column stages of both operands (the
+// shorter one in its matching residue slots), the remaining strided m2-point
+// DFTs, the inner (N-1)-D unequal problem for every row pair, and the backward
+// along the outer axis in the longer operand's geometry.
+hdc_status convnd_uneq(const hdc_plan_s* P, int level, const void* xf, const void* xg, void* out, int64_t B, char* ws,
+                       hipStream_t s) {
+    const AxisPlan& G = P->ax[level];
+    const AxisPlan& F = P->fx[level];
+    const bool sw = P->swap[level];
+    const size_t eb = elem(P);
+    if (level == P->ndim - 1) {
+        const int64_t Lf = P->Lf[level], Lg = P->Lg[level];
+        return sw ? conv_uneq(G, F, P->lam[level], xg, xf, out, B, Lg, Lf, G.d.M, 1, ws, eb, s)
+                  : conv_uneq(G, F, P->lam[level], xf, xg, out, B, Lf, Lg, G.d.M, 1, ws, eb, s);
+    }
+    const int64_t D = std::min(G.d.D, G.d.q);
+    const int64_t inf = prod3(P->Lf, level + 1, P->ndim), ing = prod3(P->Lg, level + 1, P->ndim);
+    int64_t inner_out = 1;
+    for (int a = level + 1; a < P->ndim; ++a) inner_out *= P->ax[a].d.M;
+    const int64_t nbmax = B * D * G.d.m;
+    char* Xf = ws;
+    char* Xg = Xf + (size_t)(nbmax * inf) * eb;
+    char* Y = Xg + (size_t)(nbmax * ing) * eb;
+    char* rest = Y + (size_t)(nbmax * inner_out) * eb;
+    const AxisPlan& Af = sw ? G : F;  // plan of f on this axis
+    const AxisPlan& Ag = sw ? F : G;
+    for (int64_t r0 = 0; r0 < G.d.q; r0 += D) {
+        const int64_t Dg = std::min(D, G.d.q - r0);
+        const int64_t nb = B * Dg * G.d.m;
+        hdc_status st = sw ? run_col_fwd(Af, xf, Xf, B, P->Lf[level] * inf, Dg * G.d.m * inf, inf, r0, Dg, s)
+                           : run_col_fwd(Af, xf, Xf, B, P->Lf[level] * inf, Dg * G.d.m * inf, inf, r0, Dg, s, nullptr,
+                                         P->lam[level], G.d.q);
+        if (st == HDC_OK)
+            st = sw ? run_col_fwd(Ag, xg, Xg, B, P->Lg[level] * ing, Dg * G.d.m * ing, ing, r0, Dg, s, nullptr,
+                                  P->lam[level], G.d.q)
+                    : run_col_fwd(Ag, xg, Xg, B, P->Lg[level] * ing, Dg * G.d.m * ing, ing, r0, Dg, s);
+        if (st == HDC_OK && G.d.m2 > 1) {
+            st = run_col_plain(Af, Xf, B * Dg * G.d.m1, inf, +1, s);
+            if (st == HDC_OK) st = run_col_plain(Ag, Xg, B * Dg * G.d.m1, ing, +1, s);
+        }
+        if (st == HDC_OK) st = convnd_uneq(P, level + 1, Xf, Xg, Y, nb, rest, s);
+        if (st == HDC_OK && G.d.m2 > 1) st = run_col_plain(G, Y, B * Dg * G.d.m1, inner_out, -1, s);
+        if (st == HDC_OK)
+            st = run_col_bwd(G, Y, out, B, Dg * G.d.m * inner_out, G.d.M * inner_out, inner_out, r0, Dg, r0 > 0, s);
+        if (st != HDC_OK) return st;
+    }
+    return HDC_OK;
+}
+
+// Derivation and kernel geometry of axis a of an unequal-length plan.
+hdc_status uneq_axis(hdc_plan_s* P, int a, int64_t Lf, int64_t Lg, int64_t M, int64_t m, int64_t lam, int64_t C,
+                     int64_t D, bool outer, bool many_rows) {
+    bool sw = false;
+    AxisPlan& G = P->ax[a];
+    AxisPlan& F = P->fx[a];
+    hdc_status st = derive_uneq(Lf, Lg, M, m, lam, C, D, P->dtype, &F.d, &G.d, &sw, outer);
+    if (st != HDC_OK) return st;
+    P->swap[a] = sw;
+    P->lam[a] = G.d.m / F.d.m;
+    G.dbl = F.dbl = P->dtype == HDC_C128;
+    const int32_t var = G.d.variant;
+    st = geometry(G, outer, many_rows, true);
+    if (st == HDC_OK) st = geometry(F, outer, false, true);
+    // the fused kernel serves Lambda = 1 only; geometry() may have allowed it
+    // the whole LDS for the many rows of an innermost N-D axis
+    (void)var;
+    G.d.variant = (!outer && P->lam[a] == 1 && G.d.variant == 0) ? 0 : 1;
+    F.d.variant = 1;
+    return st;
+}
+
 hdc_status finish_plan(hdc_plan_s* P) {
     std::vector<unsigned char> blob;
     for (int a = 0; a < P->ndim; ++a) stage_tables(P->ax[a], blob);
-    if (P->uneq) stage_tables(P->fx, blob);
+    if (P->uneq)
+        for (int a = 0; a < P->ndim; ++a) stage_tables(P->fx[a], blob);
     void* dev = nullptr;
     hipError_t e = hipMalloc(&dev, std::max<size_t>(blob.size(), 256));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(twiddle tables)");
@@ -857,11 +977,11 @@ hdc_status finish_plan(hdc_plan_s* P) {
     }
     P->tables = dev;
     for (int a = 0; a < P->ndim; ++a) bind_tables(P->ax[a], (unsigned char*)dev);
-    if (P->uneq) bind_tables(P->fx, (unsigned char*)dev);
+    if (P->uneq)
+        for (int a = 0; a < P->ndim; ++a) bind_tables(P->fx[a], (unsigned char*)dev);
     if (P->uneq) {
-        const AxisPlan& G = P->ax[0];
-        const int64_t one = std::min(G.d.D, G.d.q) * G.d.m * G.d.C;
-        P->ws_bytes = G.d.variant == 0 ? 0 : (size_t)(P->fx.d.m1 == 1 ? one : 2 * one) * elem(P);
+        P->ws_bytes = (size_t)(P->ndim == 1 ? ws_uneq(P->ax[0], P->fx[0], 1, P->ax[0].d.C) : wsnd_uneq(P, 0, 1)) *
+                      elem(P);
     } else if (P->ndim == 1) {
         P->ws_bytes = (size_t)ws1d(P->ax[0], 1, P->ax[0].d.C) * elem(P);
     } else {
@@ -933,18 +1053,56 @@ hdc_status hdc_plan_uneq(hdc_plan_t* out, int64_t Lf, int64_t Lg, int64_t M, int
     P->ndim = 1;
     P->dtype = dtype;
     P->uneq = true;
-    bool sw = false;
-    hdc_status st = derive_uneq(Lf, Lg, M, m, Lambda, C, D, dtype, &P->fx.d, &P->ax[0].d, &sw);
-    if (st == HDC_OK) {
-        P->swap = sw;
-        P->lam = P->ax[0].d.m / P->fx.d.m;
-        P->ax[0].dbl = P->fx.dbl = dtype == HDC_C128;
-        const int32_t var = P->ax[0].d.variant;
-        st = geometry(P->ax[0], false);
-        if (st == HDC_OK) st = geometry(P->fx, false);
-        P->ax[0].d.variant = (var == 0 && P->ax[0].d.variant == 0) ? 0 : 1;
-        P->fx.d.variant = 1;
+    P->Lf[0] = Lf;
+    P->Lg[0] = Lg;
+    hdc_status st = uneq_axis(P, 0, Lf, Lg, M, m, Lambda, C, D, false, false);
+    if (st == HDC_OK) st = finish_plan(P);
+    if (st != HDC_OK) {
+        delete P;
+        return st;
     }
+    *out = P;
+    return HDC_OK;
+}
+
+static hdc_status uneq_nd_fill(hdc_plan_s* P, int ndim, const int64_t* Lf, const int64_t* Lg, const int64_t* M,
+                               const int64_t* m, const int64_t* Lambda, const int64_t* D) {
+    if (!Lf || !Lg || !M) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+    if (ndim < 1 || ndim > 3) return fail(HDC_ERR_INVALID_ARG, "ndim = %d must be 1..3", ndim);
+    P->ndim = ndim;
+    P->uneq = true;
+    for (int a = 0; a < ndim; ++a) {
+        P->Lf[a] = Lf[a];
+        P->Lg[a] = Lg[a];
+        hdc_status st = uneq_axis(P, a, Lf[a], Lg[a], M[a], m ? m[a] : 0, Lambda ? Lambda[a] : 0, 1, D ? D[a] : 0,
+                                  a < ndim - 1, ndim > 1 && a == ndim - 1);
+        if (st != HDC_OK) return st;
+    }
+    return HDC_OK;
+}
+
+hdc_status hdc_uneq_nd_check(int ndim, const int64_t* Lf, const int64_t* Lg, const int64_t* M, const int64_t* m,
+                             const int64_t* Lambda, const int64_t* D, hdc_dtype dtype, hdc_axis_desc* short_out,
+                             hdc_axis_desc* long_out, int* swapped) {
+    hdc_plan_s P;
+    P.dtype = dtype;
+    hdc_status st = uneq_nd_fill(&P, ndim, Lf, Lg, M, m, Lambda, D);
+    if (st != HDC_OK) return st;
+    for (int a = 0; a < ndim; ++a) {
+        if (short_out) short_out[a] = P.fx[a].d;
+        if (long_out) long_out[a] = P.ax[a].d;
+        if (swapped) swapped[a] = P.swap[a] ? 1 : 0;
+    }
+    return HDC_OK;
+}
+
+hdc_status hdc_plan_uneq_nd(hdc_plan_t* out, int ndim, const int64_t* Lf, const int64_t* Lg, const int64_t* M,
+                            const int64_t* m, const int64_t* Lambda, const int64_t* D, hdc_dtype dtype) {
+    if (!out) return fail(HDC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    hdc_plan_s* P = new hdc_plan_s();
+    P->dtype = dtype;
+    hdc_status st = uneq_nd_fill(P, ndim, Lf, Lg, M, m, Lambda, D);
     if (st == HDC_OK) st = finish_plan(P);
     if (st != HDC_OK) {
         delete P;
@@ -1007,8 +1165,8 @@ hdc_status hdc_plan_destroy(hdc_plan_t P) {
 hdc_status hdc_plan_axis(hdc_plan_t P, int axis, int* ndim, hdc_axis_desc* out) {
     if (!P) return fail(HDC_ERR_INVALID_ARG, "plan is NULL");
     if (ndim) *ndim = P->ndim;
-    if (P->uneq && axis == 1) {
-        if (out) *out = P->fx.d;
+    if (P->uneq && axis >= P->ndim && axis < 2 * P->ndim) {
+        if (out) *out = P->fx[axis - P->ndim].d;
         return HDC_OK;
     }
     if (axis < 0 || axis >= P->ndim) return fail(HDC_ERR_INVALID_ARG, "axis %d out of range", axis);
@@ -1047,7 +1205,13 @@ hdc_status hdc_convolve(hdc_plan_t P, const void* f, const void* g, void* h, voi
         explicit CurPlan(const void* p) { g_cur_plan = p; }
         ~CurPlan() { g_cur_plan = nullptr; }
     } cur(P);
-    if (P->uneq) return P->swap ? conv_uneq(P, g, f, h, (char*)ws, s) : conv_uneq(P, f, g, h, (char*)ws, s);
+    if (P->uneq) {
+        if (P->ndim > 1) return convnd_uneq(P, 0, f, g, h, 1, (char*)ws, s);
+        const AxisPlan& G = P->ax[0];
+        const int64_t C = G.d.C;
+        return P->swap[0] ? conv_uneq(G, P->fx[0], P->lam[0], g, f, h, 1, 0, 0, 0, C, (char*)ws, elem(P), s)
+                          : conv_uneq(G, P->fx[0], P->lam[0], f, g, h, 1, 0, 0, 0, C, (char*)ws, elem(P), s);
+    }
     if (P->ndim == 1) {
         const AxisPlan& A = P->ax[0];
         return conv1d(A, f, g, h, 1, 0, 0, A.d.C, (char*)ws, elem(P), s);
@@ -1077,8 +1241,8 @@ hdc_status hdc_forward_operand(hdc_plan_t P, int operand, const void* x, void* F
     if (st != HDC_OK) return st;
     const AxisPlan& G = P->ax[0];
     const int64_t C = G.d.C;
-    const bool shorter = (operand == 0) != P->swap;
-    st = shorter ? run_col_fwd(P->fx, x, F, 1, 0, 0, C, r0, Dg, s, nullptr, P->lam, G.d.q)
+    const bool shorter = (operand == 0) != P->swap[0];
+    st = shorter ? run_col_fwd(P->fx[0], x, F, 1, 0, 0, C, r0, Dg, s, nullptr, P->lam[0], G.d.q)
                  : run_col_fwd(G, x, F, 1, 0, 0, C, r0, Dg, s);
     if (st != HDC_OK) return st;
     return run_rows(G, F, F, F, Dg * G.d.m1 * C, C, MODE_FWD, s);

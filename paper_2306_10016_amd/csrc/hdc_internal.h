@@ -34,7 +34,8 @@ struct FusedArgs {
     const void* g;
     void* h;
     int64_t nrows;
-    RowAddr in;   // f and g
+    RowAddr in;   // f and g (f only when Lg > 0)
+    RowAddr ing;  // g when Lg > 0
     RowAddr out;  // h
     const int64_t* desc;  // optional per-row {f_off, h_off, L, M}; in/out then give es only
     int32_t L, M;         // uniform lengths when desc == nullptr
@@ -90,11 +91,13 @@ struct RowArgs {
     const void* tw;  // zeta_{m2}^e, e < m2
     // MODE_CONV with fraw != nullptr (section 3.5, shorter operand with a
     // trivial column stage): operand a is formed from the raw input fraw
-    // (Lf x C1 values, pf blocks of m2) instead of being read; row
-    // (d m1g + l1g) C1 + c1 then holds residue r0 + d + l1g qg of length qf m2 = N
+    // (batches fbs apart, Lf x C1 values each, pf blocks of m2) instead of being
+    // read; row ((b Dg + d) m1g + l1g) C1 + c1 then holds residue
+    // r0 + d + l1g qg of length qf m2 = N of batch b
     const void* fraw;
     TwN twN;
-    int32_t Lf, pf, qf, N, r0, qg, m1g, hiprec;
+    int64_t fbs;
+    int32_t Lf, pf, qf, N, r0, qg, m1g, Dg, hiprec;
 };
 
 enum { MODE_FWD = 0, MODE_INV = 1, MODE_CONV = 2 };

@@ -327,9 +327,10 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
         fbase = row_base(a.in, rowok ? row : 0);
         hbase = row_base(a.out, rowok ? row : 0);
     }
+    const int64_t gbase = (a.Lg > 0 && a.desc == nullptr) ? row_base(a.ing, rowok ? row : 0) : fbase;
     const int64_t ies = a.in.es, oes = a.out.es;
     const cplx<T>* f = reinterpret_cast<const cplx<T>*>(a.f) + fbase;
-    const cplx<T>* g = reinterpret_cast<const cplx<T>*>(a.g) + fbase;
+    const cplx<T>* g = reinterpret_cast<const cplx<T>*>(a.g) + gbase;
     cplx<T>* h = reinterpret_cast<cplx<T>*>(a.h) + hbase;
     cplx<T>* U = smem + (size_t)rloc * a.q * RS;
     const T invN = (T)a.invN;
@@ -639,8 +640,10 @@ __device__ __forceinline__ void raw_row(const RowArgs& a, int64_t row, bool ok, 
     const uint32_t c1 = rw % C1;
     const uint32_t t1 = rw / C1;
     const uint32_t l1 = t1 % (uint32_t)a.m1g;
-    const uint32_t r = (uint32_t)a.r0 + t1 / (uint32_t)a.m1g + l1 * (uint32_t)a.qg;
-    const cplx<T>* f = reinterpret_cast<const cplx<T>*>(a.fraw) + c1;
+    const uint32_t t2 = t1 / (uint32_t)a.m1g;
+    const uint32_t b = t2 / (uint32_t)a.Dg;
+    const uint32_t r = (uint32_t)a.r0 + (t2 - b * (uint32_t)a.Dg) + l1 * (uint32_t)a.qg;
+    const cplx<T>* f = reinterpret_cast<const cplx<T>*>(a.fraw) + (int64_t)b * a.fbs + c1;
 #pragma unroll
     for (int w = 0; w < PPT; ++w) {
         const int j = lane + w * TPF;

@@ -129,3 +129,30 @@ def test_uneq_derive_errors():
         assert e.value.status == 2
     with pytest.raises(hdc.HdcError):
         hdc.uneq_derive(0, 1000, 1011)
+
+
+@pytest.mark.parametrize("sf,sg,m,lam", [((12, 12), (4096, 4096), None, None), ((5, 8), (3000, 20), (8, 8), (512, 4)),
+                                         ((9, 3, 12), (4, 30, 5), None, None), ((100, 6), (2500, 40), (128, 8), (16, 8))])
+def test_uneq_nd_check_rules(sf, sg, m, lam):
+    """Per axis the 1D rules of section 3.5; outer axes split into two column stages
+    of at most 1024 with Lambda dividing the first, the shorter operand's split the
+    longer one's divided by Lambda."""
+    res = hdc.uneq_nd_check(sf, sg, m=m, lam=lam)
+    n = len(sf)
+    for a, (s, l, sw) in enumerate(res):
+        L_ = l["m"] // s["m"]
+        assert sw == (sf[a] > sg[a]) and s["L"] == min(sf[a], sg[a]) and l["L"] == max(sf[a], sg[a])
+        assert s["N"] == l["N"] >= sf[a] + sg[a] - 1 and s["q"] == L_ * l["q"]
+        assert l["m1"] % L_ == 0 and s["m1"] * L_ == l["m1"] and s["m2"] == l["m2"]
+        if a < n - 1:
+            assert l["m1"] == max(min(l["m"], 1024), L_) and l["m2"] <= 1024 and l["variant"] == 1
+        else:
+            assert l["m2"] <= 4096
+
+
+def test_uneq_nd_check_errors():
+    with pytest.raises(hdc.HdcError):
+        hdc.uneq_nd_check((4, 4), (10, 10), M=(12, 13))
+    with pytest.raises(hdc.HdcError) as e:  # outer Lambda m above 2^20
+        hdc.uneq_nd_check((4, 4), (3000000, 10), m=(4096, 4), lam=(512, 1))
+    assert e.value.status == 2
