@@ -315,8 +315,10 @@ int64_t pow2_ceil(int64_t x) {
 // operand's four-step split m1g x m2g takes m1g a multiple of Lambda; the
 // shorter one's is (m1g/Lambda) x m2g, so its row l1f of residue r_f is the
 // longer operand's row Lambda l1f + lambda of residue r_f - q_g lambda.
+// `outer`: an outer axis of an N-D problem; `inner_nd`: the innermost axis of one.
 hdc_status derive_uneq(int64_t Lf, int64_t Lg, int64_t M, int64_t m, int64_t lam, int64_t C, int64_t D,
-                       hdc_dtype dtype, hdc_axis_desc* fo, hdc_axis_desc* go, bool* swapped, bool outer = false) {
+                       hdc_dtype dtype, hdc_axis_desc* fo, hdc_axis_desc* go, bool* swapped, bool outer = false,
+                       bool inner_nd = false) {
     if (Lf < 1 || Lg < 1) return fail(HDC_ERR_INVALID_ARG, "Lf = %lld and Lg = %lld must be >= 1", (long long)Lf,
                                       (long long)Lg);
     const bool sw = Lf > Lg;
@@ -327,6 +329,26 @@ hdc_status derive_uneq(int64_t Lf, int64_t Lg, int64_t M, int64_t m, int64_t lam
     if (m < 0 || lam < 0) return fail(HDC_ERR_INVALID_ARG, "m and Lambda must be >= 0 (0 derives)");
     // an outer N-D axis is two column stages of at most kMaxM1 each
     const int64_t mg_max = int64_t(kMaxM1) * (outer ? kMaxM1 : kMaxRow);
+    if (m == 0 && lam == 0 && outer) {
+        // outer axes (measured): the smallest Lambda m with at most four blocks of
+        // the longer operand, and m the smallest power of two holding the shorter
+        // operand in one block
+        int64_t mg = 1;
+        while (mg * 4 < Ll && mg < mg_max) mg <<= 1;
+        lam = std::max<int64_t>(1, std::min<int64_t>({mg / pow2_ceil(Ls), kMaxM1, mg}));
+        m = mg / lam;
+    } else if (m == 0 && lam == 0 && inner_nd) {
+        // the innermost axis of an N-D problem (measured): Lambda = 1, so that its
+        // many rows run in the fused kernel when the transform fits, in as few
+        // blocks and residues as it allows (one residue, else one block)
+        int64_t best = pow2_ceil(M);
+        if (best > kMaxFused) best = pow2_ceil(Ll);
+        const size_t lds = (size_t)(ceil_div(M, best) * padded_len(best)) * elem_bytes(dtype) + 4096;
+        if (lds <= device_lds_max()) {
+            lam = 1;
+            m = best;
+        }
+    }
     if (m == 0 || lam == 0) {
         // Lambda m: up to 2^17 output points a single block (q_g = 1: one
         // residue, the fewest launches); beyond, the power of two with at most
@@ -946,7 +968,7 @@ hdc_status uneq_axis(hdc_plan_s* P, int a, int64_t Lf, int64_t Lg, int64_t M, in
     bool sw = false;
     AxisPlan& G = P->ax[a];
     AxisPlan& F = P->fx[a];
-    hdc_status st = derive_uneq(Lf, Lg, M, m, lam, C, D, P->dtype, &F.d, &G.d, &sw, outer);
+    hdc_status st = derive_uneq(Lf, Lg, M, m, lam, C, D, P->dtype, &F.d, &G.d, &sw, outer, many_rows);
     if (st != HDC_OK) return st;
     P->swap[a] = sw;
     P->lam[a] = G.d.m / F.d.m;

@@ -476,3 +476,64 @@ class TunerUneq:
             if len(out) >= k:
                 break
         return out
+
+
+def uneq_nd_candidates(sf, sg, M, axis: int, dtype: str = "c64", max_pg: int = 4):
+    """(m, Lambda) candidates of one axis of an unequal-extent N-D problem, the other
+    axes at their derived defaults: Lambda m a power of two with at most ``max_pg``
+    blocks of the longer operand (or a single residue), Lambda in powers of four."""
+    from . import uneq_nd_check, HdcError
+    n = len(sf)
+    Ll = max(sf[axis], sg[axis])
+    out = []
+    mg = 1
+    while mg <= (1 << 22):
+        if -(-Ll // mg) <= max_pg or -(-M[axis] // mg) == 1:
+            lam = 1
+            while lam <= min(1024, mg):
+                m = [0] * n
+                ll = [0] * n
+                m[axis], ll[axis] = mg // lam, lam
+                try:
+                    res = uneq_nd_check(sf, sg, M, m, ll, dtype=dtype)
+                except HdcError:
+                    res = None
+                if res is not None and res[axis][1]["N"] <= 4 * M[axis] + 64:
+                    out.append((mg // lam, lam))
+                lam *= 4
+        mg *= 2
+    return out
+
+
+def uneq_nd_separable(sf, sg, M, dtype: str = "c64", timer=None, reps: int = 3, warmup: int = 1):
+    """Separable A0 (section 4.2) for an unequal-extent N-D problem: each axis
+    searched over its (m, Lambda) candidates with the others at their defaults.
+    ``timer(m_list, lam_list) -> ms`` defaults to timing hdc_convolve on the GPU.
+    Returns (m per axis, Lambda per axis, number of timings)."""
+    n = len(sf)
+    if timer is None:
+        import torch
+        from . import UneqPlan, torch_dtype, dtype_code
+        td = torch_dtype(dtype_code(dtype))
+        f = torch.randn(tuple(sf), dtype=td, device="cuda")
+        g = torch.randn(tuple(sg), dtype=td, device="cuda")
+        h = torch.empty(tuple(M), dtype=td, device="cuda")
+
+        def timer(m, lam):
+            plan = UneqPlan.nd(sf, sg, M, m=m, lam=lam, dtype=dtype)
+            ms = plan.time_convolve(f, g, h, ws=_shared_ws(plan.workspace_bytes), warmup=warmup, reps=reps)
+            plan.close()
+            ms.sort()
+            return ms[len(ms) // 2]
+    best_m, best_l, count = [0] * n, [0] * n, 0
+    for axis in range(n):
+        best = None
+        for m, lam in uneq_nd_candidates(sf, sg, M, axis, dtype):
+            mm, ll = [0] * n, [0] * n
+            mm[axis], ll[axis] = m, lam
+            t = timer(mm, ll)
+            count += 1
+            if best is None or t < best[0]:
+                best = (t, m, lam)
+        best_m[axis], best_l[axis] = best[1], best[2]
+    return best_m, best_l, count

@@ -163,3 +163,21 @@ def test_uneq_a0_and_a1_find_the_model_argmin():
     assert r1.params == r0.params
     assert len(calls) < len(tune.uneq_candidates(12, 100000, 100011))
     assert t1.a1(12, 100000, 100011).source == "db"
+
+
+def test_uneq_nd_separable_finds_per_axis_argmin():
+    """With a cost separable over axes, the per-axis search returns each axis's argmin."""
+    sf, sg = (12, 12), (4096, 2000)
+    M = [a + b - 1 for a, b in zip(sf, sg)]
+    want = [(64, 16), (16, 64)]
+
+    def cost(m, lam):
+        t = 1.0
+        for ax in range(2):
+            if m[ax]:
+                t += (math.log2(m[ax]) - math.log2(want[ax][0])) ** 2 + (math.log2(lam[ax]) - math.log2(want[ax][1])) ** 2
+        return t
+    for ax in range(2):
+        assert want[ax] in tune.uneq_nd_candidates(sf, sg, M, ax)
+    m, lam, n = tune.uneq_nd_separable(sf, sg, M, timer=cost)
+    assert list(zip(m, lam)) == want and n > 4
