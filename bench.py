@@ -142,6 +142,28 @@ def secondary(args, dev, hdc, synth, log):
     out["small_L1024_c128"] = {"us_per_conv_D1": round(t * 1e6, 2), "us_per_conv_D8": round(t8 * 1e6, 2),
                                "note": "one convolution per launch; launch latency dominates"}
 
+    # first-outputs mode: M = L (the backward range t < p of section 2.2) against
+    # the full M = 2L - 1, same transform (L = 2^22, m = L, p = 1, q = 2, D = 2)
+    L = 1 << 22
+    f, g = synth.pair(L, 7, 0, np.complex128)
+    ft, gt = torch.from_numpy(f).to(dev), torch.from_numpy(g).to(dev)
+    fl = {}
+    for name, M in (("full", 2 * L - 1), ("first_L", L)):
+        plan = hdc.Plan(L, M, L, 0, 0, 1, 2, "c128")
+        h = torch.empty(M, dtype=torch.complex128, device=dev)
+        ws = plan.workspace(dev)
+        t = timed(lambda: plan.convolve(ft, gt, h, ws=ws), 20)
+        with hdc.Profile(plan) as prof:
+            plan.convolve(ft, gt, h, ws=ws)
+        fl[name] = {"M": M, "ms": round(t * 1e3, 4),
+                    "kernels_ms": {k: round(v["ms"], 4) for k, v in prof.summary().items()}}
+        del plan, h, ws
+    fl["saving"] = round(1 - fl["first_L"]["ms"] / fl["full"]["ms"], 3)
+    out["first_L_c128_L4194304"] = fl
+    log(f"[bench] first-L outputs: {fl['first_L']['ms']:.3f} ms vs full {fl['full']['ms']:.3f} ms")
+    del ft, gt
+    torch.cuda.empty_cache()
+
     # uneven batch: 4096 complex64 problems, L = round(2^U[6,16])
     Ls = synth.batch_lengths(4096, 6, 16, cfg=3)
     B = hdc.Batch(Ls, dtype="c64")

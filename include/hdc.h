@@ -3,10 +3,12 @@
  *
  * The operation (section 2.2 eqs. (3)-(4), section 2.3 eq. (5), section 3.3):
  *   given f, g of length L, compute the linear convolution
- *       h_k = sum_j f_j g_{k-j},  k = 0 .. M-1,  M >= 2L-1,
+ *       h_k = sum_j f_j g_{k-j},  k = 0 .. M-1,
+ *   (all 2L-1 terms and zeros beyond when M >= 2L-1; the first M terms when
+ *   M < 2L-1, e.g. M = L, the backward range t < p of section 2.2),
  *   by hybrid dealiasing: choose an FFT size m, explicitly extend the inputs
  *   to p*m >= L (p = ceil(L/m), zeros never stored), implicitly pad to
- *   N = q*m >= M (q = ceil(M/m)), and compute the length-N transform as q
+ *   N = q*m >= max(M, 2L-1) (q = ceil(max(M, 2L-1)/m)), and compute the length-N transform as q
  *   "residues" r = 0..q-1, each an m-point DFT of the block sum
  *       w^(r)_s = zeta_N^{r s} sum_{t<p} zeta_q^{r t} f_{t m + s}
  *   (forward, eq. (3), zeta_n = exp(+2 pi i / n), unscaled).  The product
@@ -73,8 +75,9 @@ typedef struct {
  * Admissibility and derivation, host only (no device is touched).
  * Section 2.5 defines p = ceil(L/m), q = ceil(M/m) as the smallest values with
  * p m >= L and q m >= M; section 2.2 requires q >= p.  Admissible means
- * m >= 1, L >= 1, p m >= L, q m >= M, q >= p, M >= 2L-1 (else the output
- * would alias), C >= 1, 1 <= D.  p or q = 0 derives the ceiling; D = 0
+ * m >= 1, L >= 1, M >= 1, p m >= L, q m >= max(M, 2L-1) (else the outputs
+ * alias), q >= p, C >= 1, 1 <= D.  p or q = 0 derives the ceiling (q from
+ * max(M, 2L-1)); M below 2L-1 writes the first M outputs only; D = 0
  * means D = q; D > q is clamped to q.  Returns HDC_ERR_INVALID_ARG for
  * inadmissible input and HDC_ERR_UNSUPPORTED when m is not a power of two,
  * m > 2^22, or the transform does not fit the kernels' index range.
@@ -104,7 +107,8 @@ hdc_status hdc_plan_nd_check(int ndim, const int64_t* L, const int64_t* M, const
 
 /*
  * Unequal operand lengths (section 3.5): h = f * g for f of length Lf and g of
- * length Lg, k = 0 .. M-1 with M >= Lf + Lg - 1, C copies.  Roles follow the
+ * length Lg, k = 0 .. M-1 (M >= 1; the transforms cover max(M, Lf + Lg - 1)
+ * points, so M < Lf + Lg - 1 writes the first M outputs), C copies.  Roles follow the
  * lengths: the shorter operand is cut into m-point residues and the longer
  * into Lambda m-point residues,
  *     p_f = ceil(Ls/m), p_g = ceil(Ll/(Lambda m)), q_g = ceil(M/(Lambda m)), q_f = Lambda q_g,
@@ -114,7 +118,7 @@ hdc_status hdc_plan_nd_check(int ndim, const int64_t* L, const int64_t* M, const
  * the longer operand's geometry, D residues of it per pass.
  * m = 0 derives m (and Lambda if 0) so that both operands fit one block
  * (p_f = p_g = 1) within the limits below; Lambda = 0 with m > 0 derives Lambda
- * the same way.  Admissible: Lf, Lg, C >= 1, M >= Lf + Lg - 1, D >= 0.
+ * the same way.  Admissible: Lf, Lg, C, M >= 1, D >= 0.
  * HDC_ERR_UNSUPPORTED unless m and Lambda are powers of two with
  * Lambda <= 1024 and Lambda m <= 2^22.
  *
@@ -139,7 +143,8 @@ hdc_status hdc_plan_uneq(hdc_plan_t* out, int64_t Lf, int64_t Lg, int64_t M, int
 /*
  * Unequal extents in 2D/3D (section 3.6 with section 3.5's lengths): f of
  * extents Lf[0..ndim), g of extents Lg[0..ndim), both row-major with the last
- * axis contiguous, output box M[a] >= Lf[a] + Lg[a] - 1.  Every axis follows
+ * axis contiguous, output box M[a] >= 1 (the first M[a] of the Lf[a] + Lg[a] - 1
+ * terms, zeros beyond).  Every axis follows
  * the 1D rules above on its own, the roles too (f may be the shorter operand
  * on one axis and the longer on another); m, Lambda and D may be NULL or hold
  * 0 to derive.  Outer axes are column passes over the inner extents: there

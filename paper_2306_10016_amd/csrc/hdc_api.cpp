@@ -165,23 +165,28 @@ struct hdc_plan_s {
 
 namespace {
 
-// Derivation and admissibility (section 2.5, section 2.2's q >= p).  `Mmin`
-// is the shortest output that does not alias: 2L-1 for equal lengths.
+// Derivation and admissibility (section 2.5, section 2.2's q >= p).  K is the
+// length of the linear convolution (2L-1 for equal lengths): the transform
+// length N = q m must reach max(M, K) or the outputs alias; M is the number of
+// outputs written, so M < K gives the first M outputs only (the backward range
+// t < p of section 2.2 gives the first L).
 hdc_status derive_axis(int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, int64_t C, int64_t D, hdc_dtype dtype,
-                       hdc_axis_desc* o, int64_t Mmin = -1) {
+                       hdc_axis_desc* o, int64_t K = -1) {
     if (dtype != HDC_C64 && dtype != HDC_C128) return fail(HDC_ERR_INVALID_ARG, "dtype must be HDC_C64 or HDC_C128");
     if (L < 1) return fail(HDC_ERR_INVALID_ARG, "L = %lld must be >= 1", (long long)L);
-    if (Mmin < 0) Mmin = 2 * L - 1;
-    if (M < Mmin)
-        return fail(HDC_ERR_INVALID_ARG, "M = %lld < %lld: the output would alias", (long long)M,
-                    (long long)Mmin);
+    if (K < 0) K = 2 * L - 1;
+    if (M < 1) return fail(HDC_ERR_INVALID_ARG, "M = %lld must be >= 1", (long long)M);
+    const int64_t Mt = std::max(M, K);
     if (m < 1) return fail(HDC_ERR_INVALID_ARG, "m = %lld must be >= 1", (long long)m);
     if (C < 1) return fail(HDC_ERR_INVALID_ARG, "C = %lld must be >= 1", (long long)C);
     if (p < 0 || q < 0 || D < 0) return fail(HDC_ERR_INVALID_ARG, "p, q, D must be >= 0 (0 derives)");
     if (p == 0) p = ceil_div(L, m);
-    if (q == 0) q = ceil_div(M, m);
+    if (q == 0) q = ceil_div(Mt, m);
     if (p * m < L) return fail(HDC_ERR_INVALID_ARG, "p m = %lld < L = %lld", (long long)(p * m), (long long)L);
     if (q * m < M) return fail(HDC_ERR_INVALID_ARG, "q m = %lld < M = %lld", (long long)(q * m), (long long)M);
+    if (q * m < K)
+        return fail(HDC_ERR_INVALID_ARG, "q m = %lld < %lld: the transform would alias the linear convolution",
+                    (long long)(q * m), (long long)K);
     if (q < p) return fail(HDC_ERR_INVALID_ARG, "q = %lld < p = %lld", (long long)q, (long long)p);
     if (D == 0 || D > q) D = q;
     if (!is_pow2(m)) return fail(HDC_ERR_UNSUPPORTED, "m = %lld: only powers of two are implemented", (long long)m);
@@ -323,9 +328,10 @@ hdc_status derive_uneq(int64_t Lf, int64_t Lg, int64_t M, int64_t m, int64_t lam
                                       (long long)Lg);
     const bool sw = Lf > Lg;
     const int64_t Ls = sw ? Lg : Lf, Ll = sw ? Lf : Lg;
-    if (M < Ls + Ll - 1)
-        return fail(HDC_ERR_INVALID_ARG, "M = %lld < Lf + Lg - 1 = %lld: the output would alias", (long long)M,
-                    (long long)(Ls + Ll - 1));
+    if (M < 1) return fail(HDC_ERR_INVALID_ARG, "M = %lld must be >= 1", (long long)M);
+    // the transform must reach the linear convolution's Lf + Lg - 1 terms
+    const int64_t Mo = M;
+    M = std::max(M, Ls + Ll - 1);
     if (m < 0 || lam < 0) return fail(HDC_ERR_INVALID_ARG, "m and Lambda must be >= 0 (0 derives)");
     // an outer N-D axis is two column stages of at most kMaxM1 each
     const int64_t mg_max = int64_t(kMaxM1) * (outer ? kMaxM1 : kMaxRow);
@@ -385,7 +391,7 @@ hdc_status derive_uneq(int64_t Lf, int64_t Lg, int64_t M, int64_t m, int64_t lam
     if (lam > kMaxM1)
         return fail(HDC_ERR_UNSUPPORTED, "Lambda = %lld exceeds the column stage's %d", (long long)lam, kMaxM1);
     hdc_axis_desc g{};
-    hdc_status st = derive_axis(Ll, M, lam * m, 0, 0, C, D, dtype, &g, Ls + Ll - 1);
+    hdc_status st = derive_axis(Ll, Mo, lam * m, 0, 0, C, D, dtype, &g, Ls + Ll - 1);
     if (st != HDC_OK) return st;
     if (g.m > mg_max)
         return fail(HDC_ERR_UNSUPPORTED, "Lambda m = %lld exceeds %lld", (long long)g.m, (long long)mg_max);
@@ -411,7 +417,7 @@ hdc_status derive_uneq(int64_t Lf, int64_t Lg, int64_t M, int64_t m, int64_t lam
     f.p = ceil_div(Ls, m);
     f.q = lam * g.q;
     f.D = lam * g.D;
-    f.q_out = ceil_div(M, m);
+    f.q_out = ceil_div(Mo, m);
     f.m1 = g.m1 / lam;
     f.m2 = g.m2;
     if (fo) *fo = f;

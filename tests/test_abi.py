@@ -40,7 +40,8 @@ def test_derive_fig2_shape():
 
 
 @pytest.mark.parametrize("args,status", [
-    ((10, 18, 4), 1),            # M < 2L-1: aliasing
+    ((10, 18, 4, 0, 4), 1),      # q m = 16 < 2L-1 = 19: the transform aliases
+    ((10, 0, 4), 1),             # M < 1
     ((0, 5, 4), 1),              # L < 1
     ((10, 19, 0), 1),            # m < 1
     ((10, 19, 4, 2, 0), 1),      # p m < L
@@ -121,7 +122,7 @@ def test_uneq_derive_rules(Lf, Lg, m, lam):
 
 def test_uneq_derive_errors():
     with pytest.raises(hdc.HdcError) as e:
-        hdc.uneq_derive(12, 1000, 1010)
+        hdc.uneq_derive(12, 1000, 0)
     assert e.value.status == 1
     for m, lam in ((24, 2), (16, 3), (16, 2048), (8192, 1024)):
         with pytest.raises(hdc.HdcError) as e:
@@ -152,7 +153,22 @@ def test_uneq_nd_check_rules(sf, sg, m, lam):
 
 def test_uneq_nd_check_errors():
     with pytest.raises(hdc.HdcError):
-        hdc.uneq_nd_check((4, 4), (10, 10), M=(12, 13))
+        hdc.uneq_nd_check((4, 4), (10, 10), M=(0, 13))
     with pytest.raises(hdc.HdcError) as e:  # outer Lambda m above 2^20
         hdc.uneq_nd_check((4, 4), (3000000, 10), m=(4096, 4), lam=(512, 1))
     assert e.value.status == 2
+
+
+
+@pytest.mark.parametrize("L,M,m", [(10, 10, 4), (1000, 1000, 256), (1000, 1, 64), (4096, 4096, 4096), (37, 50, 8)])
+def test_first_outputs_mode(L, M, m):
+    """M below 2L-1 (the backward range of section 2.2 gives the first L outputs):
+    the transform still covers 2L-1 points, the backward writes ceil(M/m) blocks."""
+    d = hdc.derive(L, M, m)
+    assert d["q"] == -(-(2 * L - 1) // m) and d["N"] >= 2 * L - 1
+    assert d["q_out"] == -(-M // m) and d["M"] == M
+
+
+def test_uneq_first_outputs_mode():
+    s, l, _ = hdc.uneq_derive(12, 1000, 500, 16, 4)
+    assert l["q"] == -(-1011 // 64) and l["q_out"] == -(-500 // 64) and l["M"] == 500
