@@ -57,6 +57,7 @@ def _load():
         lib.oracle_padded_1d.argtypes = [_I64, _I64, _I64, _P, _P, _P]
         lib.oracle_direct_1d_uneq.argtypes = [_I64, _I64, _I64, _I64, _P, _P, _P]
         lib.oracle_direct_1d_uneq_sampled.argtypes = [_I64, _I64, _I64, _P, _P, _P, _I64, _P]
+        lib.oracle_direct_1d_real.argtypes = [_I64, _I64, _I64, _P, _P, _P]
         lib.oracle_padded_1d_uneq.argtypes = [_I64, _I64, _I64, _I64, _P, _P, _P]
         lib.oracle_padded_nd.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P]
         lib.oracle_direct_nd_uneq_sampled.argtypes = [ctypes.c_int, _P, _P, _P, _P, _P, _P, _I64, _P]
@@ -108,6 +109,21 @@ def direct_1d(f, g, M: int) -> np.ndarray:
     h = np.empty((int(M), C), np.complex128)
     _check(_load().oracle_direct_1d_uneq(Lf, g2.shape[0], int(M), C, f2.ctypes.data, g2.ctypes.data, h.ctypes.data),
            "direct_1d")
+    return h.reshape(-1) if flat else h
+
+
+def direct_1d_real(f, g, M: int) -> np.ndarray:
+    """eq. (5) for real f, g of shape (L,) or (L, C), in real FP64 arithmetic."""
+    f2 = np.ascontiguousarray(np.asarray(f, dtype=np.float64))
+    g2 = np.ascontiguousarray(np.asarray(g, dtype=np.float64))
+    flat = f2.ndim == 1
+    f2, g2 = f2.reshape(f2.shape[0], -1), g2.reshape(g2.shape[0], -1)
+    if f2.shape != g2.shape:
+        raise ValueError("f and g must have the same shape")
+    L, C = f2.shape
+    h = np.empty((int(M), C), np.float64)
+    _check(_load().oracle_direct_1d_real(L, int(M), C, f2.ctypes.data, g2.ctypes.data, h.ctypes.data),
+           "direct_1d_real")
     return h.reshape(-1) if flat else h
 
 

@@ -71,6 +71,23 @@ int oracle_direct_1d_uneq(int64_t Lf, int64_t Lg, int64_t M, int64_t C, const do
     return 0;
 }
 
+/* eq. (5) for real sequences (the real case the paper leaves to future work,
+ * section 7): real arithmetic throughout, all copies, all k < M. */
+int oracle_direct_1d_real(int64_t L, int64_t M, int64_t C, const double* f, const double* g, double* h) {
+    if (L < 0 || M < 0 || C < 1) return 1;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < M; ++k) {
+        for (int64_t c = 0; c < C; ++c) {
+            double acc = 0.0;
+            int64_t jlo = k - (L - 1) > 0 ? k - (L - 1) : 0;
+            int64_t jhi = k < L - 1 ? k : L - 1;
+            for (int64_t j = jlo; j <= jhi; ++j) acc += f[j * C + c] * g[(k - j) * C + c];
+            h[k * C + c] = acc;
+        }
+    }
+    return 0;
+}
+
 /* eq. (5), all copies, all k < M. */
 int oracle_direct_1d(int64_t L, int64_t M, int64_t C, const double* f_, const double* g_, double* h_) {
     return oracle_direct_1d_uneq(L, L, M, C, f_, g_, h_);

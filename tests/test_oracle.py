@@ -299,3 +299,27 @@ def test_nd_unequal_matches_scipy(sf, sg):
     ks = np.arange(int(np.prod(M)))
     d = oracle.direct_nd_sampled(f, g, M, ks).reshape(M)
     assert oracle.rel_l2(d[tuple(slice(0, k) for k in K)], ref) < 1e-14
+
+
+
+@pytest.mark.parametrize("L", [1, 2, 7, 100, 1000])
+def test_real_matches_numpy_and_complex_oracle(L):
+    """The real-arithmetic direct sum against numpy.convolve and against the complex
+    oracle on the same data with zero imaginary parts (whose imaginary output is 0)."""
+    r = synth.rng(107, L, 0)
+    f, g = r.uniform(-1, 1, L), r.uniform(-1, 1, L)
+    h = oracle.direct_1d_real(f, g, 2 * L + 3)
+    assert np.max(np.abs(h[:2 * L - 1] - np.convolve(f, g))) < 1e-12 and np.all(h[2 * L - 1:] == 0)
+    hc = oracle.direct_1d(f.astype(complex), g.astype(complex), 2 * L + 3)
+    assert np.all(hc.imag == 0) and np.max(np.abs(hc.real - h)) < 1e-12
+    fc, gc = r.uniform(-1, 1, (L, 3)), r.uniform(-1, 1, (L, 3))
+    hc3 = oracle.direct_1d_real(fc, gc, 2 * L - 1)
+    for c in range(3):
+        assert np.max(np.abs(hc3[:, c] - np.convolve(fc[:, c], gc[:, c]))) < 1e-12
+
+
+def test_real_integer_exact():
+    r = synth.rng(108, 0, 0)
+    f, g = r.integers(-50, 51, 300).astype(float), r.integers(-50, 51, 300).astype(float)
+    exact = [sum(int(f[j]) * int(g[k - j]) for j in range(max(0, k - 299), min(k, 299) + 1)) for k in range(599)]
+    assert np.array_equal(oracle.direct_1d_real(f, g, 599), np.array(exact, dtype=float))
