@@ -131,178 +131,244 @@ def secondary(args, dev, hdc, synth, log):
         return (time.perf_counter() - t0) / reps
 
     out = {}
-    # small workload: L = 1024, M = 2047, m = 256, p = 4, q = 8, C = 1, D = 1, complex128
-    f, g = synth.pair(1024, 1, 0, np.complex128)
-    ft, gt = torch.from_numpy(f).to(dev), torch.from_numpy(g).to(dev)
-    plan = hdc.Plan(1024, 2047, 256, 4, 8, 1, 1, "c128")
-    h = torch.empty(2047, dtype=torch.complex128, device=dev)
-    t = timed(lambda: plan.convolve(ft, gt, h), 200)
-    plan8 = hdc.Plan(1024, 2047, 256, 4, 8, 1, 8, "c128")
-    t8 = timed(lambda: plan8.convolve(ft, gt, h), 200)
-    out["small_L1024_c128"] = {"us_per_conv_D1": round(t * 1e6, 2), "us_per_conv_D8": round(t8 * 1e6, 2),
-                               "note": "one convolution per launch; launch latency dominates"}
+    sel = [x for x in args.extras.split(",") if x]
 
-    # first-outputs mode: M = L (the backward range t < p of section 2.2) against
-    # the full M = 2L - 1, same transform (L = 2^22, m = L, p = 1, q = 2, D = 2)
-    L = 1 << 22
-    f, g = synth.pair(L, 7, 0, np.complex128)
-    ft, gt = torch.from_numpy(f).to(dev), torch.from_numpy(g).to(dev)
-    fl = {}
-    for name, M in (("full", 2 * L - 1), ("first_L", L)):
-        plan = hdc.Plan(L, M, L, 0, 0, 1, 2, "c128")
-        h = torch.empty(M, dtype=torch.complex128, device=dev)
-        ws = plan.workspace(dev)
-        t = timed(lambda: plan.convolve(ft, gt, h, ws=ws), 20)
-        with hdc.Profile(plan) as prof:
-            plan.convolve(ft, gt, h, ws=ws)
-        fl[name] = {"M": M, "ms": round(t * 1e3, 4),
-                    "kernels_ms": {k: round(v["ms"], 4) for k, v in prof.summary().items()}}
-        del plan, h, ws
-    fl["saving"] = round(1 - fl["first_L"]["ms"] / fl["full"]["ms"], 3)
-    out["first_L_c128_L4194304"] = fl
-    log(f"[bench] first-L outputs: {fl['first_L']['ms']:.3f} ms vs full {fl['full']['ms']:.3f} ms")
-    del ft, gt
-    torch.cuda.empty_cache()
+    def want(name):
+        return not sel or name in sel
 
-    # uneven batch: 4096 complex64 problems, L = round(2^U[6,16])
-    Ls = synth.batch_lengths(4096, 6, 16, cfg=3)
-    B = hdc.Batch(Ls, dtype="c64")
-    fb = torch.from_numpy(np.concatenate([synth.uniform_complex(int(L), 3, i, 0, np.complex64)
-                                          for i, L in enumerate(Ls)])).to(dev)
-    gb = torch.from_numpy(np.concatenate([synth.uniform_complex(int(L), 3, i, 1, np.complex64)
-                                          for i, L in enumerate(Ls)])).to(dev)
-    hb = torch.empty(B.total_M, dtype=torch.complex64, device=dev)
-    tb = timed(lambda: B.convolve(fb, gb, hb), 10)
-    comp = (2 * B.total_L + B.total_M) * 8
-    out["batch_4096_c64"] = {"convs_per_s": round(4096 / tb, 1), "ms": round(tb * 1e3, 4), "buckets": B.n_buckets,
-                             "compulsory_GBps": round(comp / tb / 1e9, 1)}
-    del fb, gb, hb, B
-
-    # 2D squares and rectangles, and the 2D/3D evaluation sizes (parameters from the per-axis tuner)
-    shapes = [((256, 256), "c64"), ((512, 512), "c64"), ((1024, 1024), "c64"), ((2048, 512), "c64"),
-              ((1024, 4096), "c64"), ((1024, 1024), "c128"), ((1024, 4096), "c128"), ((4096, 4096), "c64"),
-              ((8192, 8192), "c64"), ((256, 256, 256), "c64")]
-    from paper_2306_10016_amd import predict
-    timer = predict.NDTimer(reps=3, warmup=1)
-    nd = {}
-    for Ls, dt in shapes:
-        Ms = tuple(2 * x - 1 for x in Ls)
-        best, _, _ = predict.tune_separable(list(Ls), list(Ms), dt, timer)  # A0 per axis
-        ms = tuple(b[0] for b in best)
-        Ds = tuple(b[1] for b in best)
-        np_dt = np.complex128 if dt == "c128" else np.complex64
-        td = torch.complex128 if dt == "c128" else torch.complex64
-        f, g = synth.pair(Ls, 4, sum(Ls), np_dt)
+    if want("small"):
+        # small workload: L = 1024, M = 2047, m = 256, p = 4, q = 8, C = 1, D = 1, complex128
+        f, g = synth.pair(1024, 1, 0, np.complex128)
         ft, gt = torch.from_numpy(f).to(dev), torch.from_numpy(g).to(dev)
-        plan = hdc.Plan.nd(Ls, Ms, ms, D=Ds, dtype=dt)
-        h = torch.empty(Ms, dtype=td, device=dev)
-        ws = plan.workspace(dev)
-        reps = 10 if np.prod(Ls) <= (1 << 22) else 3
-        t = timed(lambda: plan.convolve(ft, gt, h, ws=ws), reps, warm=1)
-        s2 = tuple(2 * x for x in Ls)
-        sl = tuple(slice(0, m) for m in Ms)
+        plan = hdc.Plan(1024, 2047, 256, 4, 8, 1, 1, "c128")
+        h = torch.empty(2047, dtype=torch.complex128, device=dev)
+        t = timed(lambda: plan.convolve(ft, gt, h), 200)
+        plan8 = hdc.Plan(1024, 2047, 256, 4, 8, 1, 8, "c128")
+        t8 = timed(lambda: plan8.convolve(ft, gt, h), 200)
+        out["small_L1024_c128"] = {"us_per_conv_D1": round(t * 1e6, 2), "us_per_conv_D8": round(t8 * 1e6, 2),
+                                   "note": "one convolution per launch; launch latency dominates"}
 
-        def explicit():
-            return torch.fft.ifftn(torch.fft.fftn(ft, s=s2) * torch.fft.fftn(gt, s=s2))[sl]
-        err = float(torch.linalg.vector_norm(h - explicit()) / torch.linalg.vector_norm(explicit()))
-        te = timed(explicit, reps, warm=1)
-        comp = (2 * int(np.prod(Ls)) + int(np.prod(Ms))) * (16 if dt == "c128" else 8)
-        key = "x".join(str(x) for x in Ls) + "_" + dt
-        nd[key] = {"params": {"m": list(ms), "D": list(Ds)}, "ms": round(t * 1e3, 4), "compulsory_GBps": round(comp / t / 1e9, 1),
-                   "explicit_ms": round(te * 1e3, 4), "speedup_vs_explicit": round(te / t, 3),
-                   "rel_err_vs_explicit": err}
-        log(f"[bench] {key}: {t * 1e3:.3f} ms (explicit {te * 1e3:.3f} ms), rel {err:.1e}")
-        del ft, gt, h, plan, ws
+    if want("first_L"):
+        # first-outputs mode: M = L (the backward range t < p of section 2.2) against
+        # the full M = 2L - 1, same transform (L = 2^22, m = L, p = 1, q = 2, D = 2)
+        L = 1 << 22
+        f, g = synth.pair(L, 7, 0, np.complex128)
+        ft, gt = torch.from_numpy(f).to(dev), torch.from_numpy(g).to(dev)
+        fl = {}
+        for name, M in (("full", 2 * L - 1), ("first_L", L)):
+            plan = hdc.Plan(L, M, L, 0, 0, 1, 2, "c128")
+            h = torch.empty(M, dtype=torch.complex128, device=dev)
+            ws = plan.workspace(dev)
+            t = timed(lambda: plan.convolve(ft, gt, h, ws=ws), 20)
+            with hdc.Profile(plan) as prof:
+                plan.convolve(ft, gt, h, ws=ws)
+            fl[name] = {"M": M, "ms": round(t * 1e3, 4),
+                        "kernels_ms": {k: round(v["ms"], 4) for k, v in prof.summary().items()}}
+            del plan, h, ws
+        fl["saving"] = round(1 - fl["first_L"]["ms"] / fl["full"]["ms"], 3)
+        out["first_L_c128_L4194304"] = fl
+        log(f"[bench] first-L outputs: {fl['first_L']['ms']:.3f} ms vs full {fl['full']['ms']:.3f} ms")
+        del ft, gt
         torch.cuda.empty_cache()
-    out["nd"] = nd
 
-    # unequal lengths (section 3.5): a short filter against a long signal, tuned over
-    # (m, Lambda, D), against explicit padding and against the equal-length plan with
-    # the filter zero-padded to the signal's length
-    from paper_2306_10016_amd import tune
-    db = tune.TuneDB(None if args.no_tune else args.tune_db, device=tune.device_name(), build=tune.build_hash())
-    tu = tune.TunerUneq(db, reps=3, warmup=1)
-    un = {}
-    for Lf, Lg, dt in ((2, 1 << 22, "c128"), (12, 1 << 22, "c128"), (12, 3 ** 13, "c128"), (1000, 1 << 20, "c128"),
-                       (12, 1 << 22, "c64"), (12, 1 << 16, "c128")):
-        M = Lf + Lg - 1
-        np_dt = np.complex128 if dt == "c128" else np.complex64
-        td = torch.complex128 if dt == "c128" else torch.complex64
-        ft = torch.from_numpy(synth.uniform_complex(Lf, 5, Lg, 0, np_dt)).to(dev)
-        gt = torch.from_numpy(synth.uniform_complex(Lg, 5, Lg, 1, np_dt)).to(dev)
-        h = torch.empty(M, dtype=td, device=dev)
-        r = tu.a1(Lf, Lg, M, dt)
-        plan = hdc.UneqPlan(Lf, Lg, M, m=r.params["m"], lam=r.params["lam"], D=r.params["D"], dtype=dt)
-        ws = plan.workspace(dev)
-        t = timed(lambda: plan.convolve(ft, gt, h, ws=ws), 20)
-        n2 = tune.pow2_ceil(M)
+    if want("real"):
+        # real data (the real case of section 7): f, g and h real, z = f + i g transformed
+        # once and only the residues r <= q/2 inverted; against the complex plan on the
+        # same (real-valued) data and against explicit padding with torch.fft.rfft
+        rl = {}
+        for L, dt in ((1 << 22, "r64"), (1 << 22, "r32"), (3 ** 13, "r64"), (1 << 16, "r64")):
+            M = 2 * L - 1
+            np_dt = np.float64 if dt == "r64" else np.float32
+            td = torch.float64 if dt == "r64" else torch.float32
+            cdt = "c128" if dt == "r64" else "c64"
+            ft = torch.from_numpy(synth.uniform_real(L, 8, L, 0, np_dt)).to(dev)
+            gt = torch.from_numpy(synth.uniform_real(L, 8, L, 1, np_dt)).to(dev)
+            fc, gc = ft.to(torch.complex128 if dt == "r64" else torch.complex64), gt.to(
+                torch.complex128 if dt == "r64" else torch.complex64)
+            m0 = 1
+            while m0 < L:
+                m0 *= 2
+            best = {}
+            for kind, dtype_, a_, b_ in (("real", dt, ft, gt), ("complex", cdt, fc, gc)):
+                for m in (m0, m0 // 2, m0 // 4):
+                    for D in (0, 1):
+                        try:
+                            plan = hdc.Plan(L, M, m, 0, 0, 1, D, dtype_)
+                        except hdc.HdcError:
+                            continue
+                        h = torch.empty(M, dtype=a_.dtype, device=dev)
+                        ws = plan.workspace(dev)
+                        t = timed(lambda: plan.convolve(a_, b_, h, ws=ws), 10)
+                        if kind not in best or t < best[kind][0]:
+                            best[kind] = (t, {"m": m, "D": plan.axes[0]["D"], "q": plan.axes[0]["q"]}, h)
+                        del plan, ws
+            n = 1
+            while n < M:
+                n *= 2
 
-        def explicit():
-            return torch.fft.ifft(torch.fft.fft(ft, n2) * torch.fft.fft(gt, n2))[:M]
-        ref = explicit()
-        err = float(torch.linalg.vector_norm(h - ref) / torch.linalg.vector_norm(ref))
-        te = timed(explicit, 20)
-        fp = torch.zeros(Lg, dtype=td, device=dev)
-        fp[:Lf] = ft
-        eq = hdc.Plan(Lg, 2 * Lg - 1, tune.pow2_ceil(Lg), dtype=dt)
-        he = torch.empty(2 * Lg - 1, dtype=td, device=dev)
-        wse = eq.workspace(dev)
-        tq = timed(lambda: eq.convolve(fp, gt, he, ws=wse), 20)
-        comp = (Lf + Lg + M) * (16 if dt == "c128" else 8)
-        key = f"Lf{Lf}_Lg{Lg}_{dt}"
-        un[key] = {"params": r.params, "tuned_by": r.source, "ms": round(t * 1e3, 4),
-                   "compulsory_GBps": round(comp / t / 1e9, 1), "explicit_ms": round(te * 1e3, 4),
-                   "speedup_vs_explicit": round(te / t, 3), "equal_padded_ms": round(tq * 1e3, 4),
-                   "speedup_vs_equal_padded": round(tq / t, 3), "rel_err_vs_explicit": err}
-        log(f"[bench] {key}: {t * 1e3:.3f} ms (explicit {te * 1e3:.3f}, equal-padded {tq * 1e3:.3f}), rel {err:.1e}")
-        del ft, gt, h, plan, ws, fp, eq, he, wse
-        torch.cuda.empty_cache()
-    out["uneq"] = un
+            def explicit():
+                return torch.fft.irfft(torch.fft.rfft(ft, n) * torch.fft.rfft(gt, n), n)[:M]
+            ref = explicit()
+            t, params, h = best["real"]
+            err = float(torch.linalg.vector_norm(h - ref) / torch.linalg.vector_norm(ref))
+            te = timed(explicit, 10)
+            tc = best["complex"][0]
+            key = f"L{L}_{dt}"
+            rb = 8 if dt == "r64" else 4
+            rl[key] = {"params": params, "ms": round(t * 1e3, 4), "compulsory_GBps": round((2 * L + M) * rb / t / 1e9, 1),
+                       "complex_plan_ms": round(tc * 1e3, 4), "complex_params": best["complex"][1],
+                       "speedup_vs_complex_plan": round(tc / t, 3), "explicit_rfft_ms": round(te * 1e3, 4),
+                       "speedup_vs_explicit_rfft": round(te / t, 3), "rel_err_vs_explicit": err}
+            log(f"[bench] real {key}: {t * 1e3:.3f} ms (complex plan {tc * 1e3:.3f}, rfft {te * 1e3:.3f}), rel {err:.1e}")
+            del ft, gt, fc, gc, best, h, ref
+            torch.cuda.empty_cache()
+        out["real"] = rl
 
-    # unequal extents in 2D/3D: a small filter against a large image or volume,
-    # separable per-axis search over (m, Lambda), against explicit padding and the
-    # equal-extent plan with the filter zero-padded to the image
-    und = {}
-    for sf, sg, dt in (((12, 12), (4096, 4096), "c64"), ((12, 12), (4096, 4096), "c128"),
-                       ((5, 5), (1024, 1024), "c64"), ((64, 64), (2048, 2048), "c64"),
-                       ((3, 3, 3), (256, 256, 256), "c64")):
-        M = [a + b - 1 for a, b in zip(sf, sg)]
-        np_dt = np.complex128 if dt == "c128" else np.complex64
-        td = torch.complex128 if dt == "c128" else torch.complex64
-        ft = torch.from_numpy(synth.uniform_complex(sf, 6, sum(sg), 0, np_dt)).to(dev)
-        gt = torch.from_numpy(synth.uniform_complex(sg, 6, sum(sg), 1, np_dt)).to(dev)
-        h = torch.empty(M, dtype=td, device=dev)
-        mm, ll, ntim = tune.uneq_nd_separable(sf, sg, M, dt)
-        plan = hdc.UneqPlan.nd(sf, sg, M, m=mm, lam=ll, dtype=dt)
-        ws = plan.workspace(dev)
-        reps = 10 if int(np.prod(sg)) <= (1 << 22) else 5
-        t = timed(lambda: plan.convolve(ft, gt, h, ws=ws), reps, warm=1)
-        n2 = [tune.pow2_ceil(x) for x in M]
-        sl = tuple(slice(0, x) for x in M)
+    if want("batch"):
+        # uneven batch: 4096 complex64 problems, L = round(2^U[6,16])
+        Ls = synth.batch_lengths(4096, 6, 16, cfg=3)
+        B = hdc.Batch(Ls, dtype="c64")
+        fb = torch.from_numpy(np.concatenate([synth.uniform_complex(int(L), 3, i, 0, np.complex64)
+                                              for i, L in enumerate(Ls)])).to(dev)
+        gb = torch.from_numpy(np.concatenate([synth.uniform_complex(int(L), 3, i, 1, np.complex64)
+                                              for i, L in enumerate(Ls)])).to(dev)
+        hb = torch.empty(B.total_M, dtype=torch.complex64, device=dev)
+        tb = timed(lambda: B.convolve(fb, gb, hb), 10)
+        comp = (2 * B.total_L + B.total_M) * 8
+        out["batch_4096_c64"] = {"convs_per_s": round(4096 / tb, 1), "ms": round(tb * 1e3, 4), "buckets": B.n_buckets,
+                                 "compulsory_GBps": round(comp / tb / 1e9, 1)}
+        del fb, gb, hb, B
 
-        def explicit():
-            return torch.fft.ifftn(torch.fft.fftn(ft, s=n2) * torch.fft.fftn(gt, s=n2))[sl]
-        ref = explicit()
-        err = float(torch.linalg.vector_norm(h - ref) / torch.linalg.vector_norm(ref))
-        del ref
-        te = timed(explicit, reps, warm=1)
-        fp = torch.zeros(sg, dtype=td, device=dev)
-        fp[tuple(slice(0, x) for x in sf)] = ft
-        Me = [2 * x - 1 for x in sg]
-        eq = hdc.Plan.nd(list(sg), Me, [tune.pow2_ceil(x) for x in sg], dtype=dt)
-        he = torch.empty(Me, dtype=td, device=dev)
-        wse = eq.workspace(dev)
-        tq = timed(lambda: eq.convolve(fp, gt, he, ws=wse), reps, warm=1)
-        comp = (int(np.prod(sf)) + int(np.prod(sg)) + int(np.prod(M))) * (16 if dt == "c128" else 8)
-        key = "x".join(map(str, sf)) + "_" + "x".join(map(str, sg)) + "_" + dt
-        und[key] = {"params": {"m": mm, "lam": ll}, "timings": ntim, "ms": round(t * 1e3, 4),
-                    "compulsory_GBps": round(comp / t / 1e9, 1), "explicit_ms": round(te * 1e3, 4),
-                    "speedup_vs_explicit": round(te / t, 3), "equal_padded_ms": round(tq * 1e3, 4),
-                    "speedup_vs_equal_padded": round(tq / t, 3), "rel_err_vs_explicit": err}
-        log(f"[bench] {key}: {t * 1e3:.3f} ms (explicit {te * 1e3:.3f}, equal-padded {tq * 1e3:.3f}), rel {err:.1e}")
-        del ft, gt, h, plan, ws, fp, eq, he, wse
-        torch.cuda.empty_cache()
-    out["uneq_nd"] = und
+    if want("nd"):
+        # 2D squares and rectangles, and the 2D/3D evaluation sizes (parameters from the per-axis tuner)
+        shapes = [((256, 256), "c64"), ((512, 512), "c64"), ((1024, 1024), "c64"), ((2048, 512), "c64"),
+                  ((1024, 4096), "c64"), ((1024, 1024), "c128"), ((1024, 4096), "c128"), ((4096, 4096), "c64"),
+                  ((8192, 8192), "c64"), ((256, 256, 256), "c64")]
+        from paper_2306_10016_amd import predict
+        timer = predict.NDTimer(reps=3, warmup=1)
+        nd = {}
+        for Ls, dt in shapes:
+            Ms = tuple(2 * x - 1 for x in Ls)
+            best, _, _ = predict.tune_separable(list(Ls), list(Ms), dt, timer)  # A0 per axis
+            ms = tuple(b[0] for b in best)
+            Ds = tuple(b[1] for b in best)
+            np_dt = np.complex128 if dt == "c128" else np.complex64
+            td = torch.complex128 if dt == "c128" else torch.complex64
+            f, g = synth.pair(Ls, 4, sum(Ls), np_dt)
+            ft, gt = torch.from_numpy(f).to(dev), torch.from_numpy(g).to(dev)
+            plan = hdc.Plan.nd(Ls, Ms, ms, D=Ds, dtype=dt)
+            h = torch.empty(Ms, dtype=td, device=dev)
+            ws = plan.workspace(dev)
+            reps = 10 if np.prod(Ls) <= (1 << 22) else 3
+            t = timed(lambda: plan.convolve(ft, gt, h, ws=ws), reps, warm=1)
+            s2 = tuple(2 * x for x in Ls)
+            sl = tuple(slice(0, m) for m in Ms)
+
+            def explicit():
+                return torch.fft.ifftn(torch.fft.fftn(ft, s=s2) * torch.fft.fftn(gt, s=s2))[sl]
+            err = float(torch.linalg.vector_norm(h - explicit()) / torch.linalg.vector_norm(explicit()))
+            te = timed(explicit, reps, warm=1)
+            comp = (2 * int(np.prod(Ls)) + int(np.prod(Ms))) * (16 if dt == "c128" else 8)
+            key = "x".join(str(x) for x in Ls) + "_" + dt
+            nd[key] = {"params": {"m": list(ms), "D": list(Ds)}, "ms": round(t * 1e3, 4), "compulsory_GBps": round(comp / t / 1e9, 1),
+                       "explicit_ms": round(te * 1e3, 4), "speedup_vs_explicit": round(te / t, 3),
+                       "rel_err_vs_explicit": err}
+            log(f"[bench] {key}: {t * 1e3:.3f} ms (explicit {te * 1e3:.3f} ms), rel {err:.1e}")
+            del ft, gt, h, plan, ws
+            torch.cuda.empty_cache()
+        out["nd"] = nd
+
+    if want("uneq"):
+        # unequal lengths (section 3.5): a short filter against a long signal, tuned over
+        # (m, Lambda, D), against explicit padding and against the equal-length plan with
+        # the filter zero-padded to the signal's length
+        from paper_2306_10016_amd import tune
+        db = tune.TuneDB(None if args.no_tune else args.tune_db, device=tune.device_name(), build=tune.build_hash())
+        tu = tune.TunerUneq(db, reps=3, warmup=1)
+        un = {}
+        for Lf, Lg, dt in ((2, 1 << 22, "c128"), (12, 1 << 22, "c128"), (12, 3 ** 13, "c128"), (1000, 1 << 20, "c128"),
+                           (12, 1 << 22, "c64"), (12, 1 << 16, "c128")):
+            M = Lf + Lg - 1
+            np_dt = np.complex128 if dt == "c128" else np.complex64
+            td = torch.complex128 if dt == "c128" else torch.complex64
+            ft = torch.from_numpy(synth.uniform_complex(Lf, 5, Lg, 0, np_dt)).to(dev)
+            gt = torch.from_numpy(synth.uniform_complex(Lg, 5, Lg, 1, np_dt)).to(dev)
+            h = torch.empty(M, dtype=td, device=dev)
+            r = tu.a1(Lf, Lg, M, dt)
+            plan = hdc.UneqPlan(Lf, Lg, M, m=r.params["m"], lam=r.params["lam"], D=r.params["D"], dtype=dt)
+            ws = plan.workspace(dev)
+            t = timed(lambda: plan.convolve(ft, gt, h, ws=ws), 20)
+            n2 = tune.pow2_ceil(M)
+
+            def explicit():
+                return torch.fft.ifft(torch.fft.fft(ft, n2) * torch.fft.fft(gt, n2))[:M]
+            ref = explicit()
+            err = float(torch.linalg.vector_norm(h - ref) / torch.linalg.vector_norm(ref))
+            te = timed(explicit, 20)
+            fp = torch.zeros(Lg, dtype=td, device=dev)
+            fp[:Lf] = ft
+            eq = hdc.Plan(Lg, 2 * Lg - 1, tune.pow2_ceil(Lg), dtype=dt)
+            he = torch.empty(2 * Lg - 1, dtype=td, device=dev)
+            wse = eq.workspace(dev)
+            tq = timed(lambda: eq.convolve(fp, gt, he, ws=wse), 20)
+            comp = (Lf + Lg + M) * (16 if dt == "c128" else 8)
+            key = f"Lf{Lf}_Lg{Lg}_{dt}"
+            un[key] = {"params": r.params, "tuned_by": r.source, "ms": round(t * 1e3, 4),
+                       "compulsory_GBps": round(comp / t / 1e9, 1), "explicit_ms": round(te * 1e3, 4),
+                       "speedup_vs_explicit": round(te / t, 3), "equal_padded_ms": round(tq * 1e3, 4),
+                       "speedup_vs_equal_padded": round(tq / t, 3), "rel_err_vs_explicit": err}
+            log(f"[bench] {key}: {t * 1e3:.3f} ms (explicit {te * 1e3:.3f}, equal-padded {tq * 1e3:.3f}), rel {err:.1e}")
+            del ft, gt, h, plan, ws, fp, eq, he, wse
+            torch.cuda.empty_cache()
+        out["uneq"] = un
+
+    if want("uneq_nd"):
+        from paper_2306_10016_amd import tune
+        # unequal extents in 2D/3D: a small filter against a large image or volume,
+        # separable per-axis search over (m, Lambda), against explicit padding and the
+        # equal-extent plan with the filter zero-padded to the image
+        und = {}
+        for sf, sg, dt in (((12, 12), (4096, 4096), "c64"), ((12, 12), (4096, 4096), "c128"),
+                           ((5, 5), (1024, 1024), "c64"), ((64, 64), (2048, 2048), "c64"),
+                           ((3, 3, 3), (256, 256, 256), "c64")):
+            M = [a + b - 1 for a, b in zip(sf, sg)]
+            np_dt = np.complex128 if dt == "c128" else np.complex64
+            td = torch.complex128 if dt == "c128" else torch.complex64
+            ft = torch.from_numpy(synth.uniform_complex(sf, 6, sum(sg), 0, np_dt)).to(dev)
+            gt = torch.from_numpy(synth.uniform_complex(sg, 6, sum(sg), 1, np_dt)).to(dev)
+            h = torch.empty(M, dtype=td, device=dev)
+            mm, ll, ntim = tune.uneq_nd_separable(sf, sg, M, dt)
+            plan = hdc.UneqPlan.nd(sf, sg, M, m=mm, lam=ll, dtype=dt)
+            ws = plan.workspace(dev)
+            reps = 10 if int(np.prod(sg)) <= (1 << 22) else 5
+            t = timed(lambda: plan.convolve(ft, gt, h, ws=ws), reps, warm=1)
+            n2 = [tune.pow2_ceil(x) for x in M]
+            sl = tuple(slice(0, x) for x in M)
+
+            def explicit():
+                return torch.fft.ifftn(torch.fft.fftn(ft, s=n2) * torch.fft.fftn(gt, s=n2))[sl]
+            ref = explicit()
+            err = float(torch.linalg.vector_norm(h - ref) / torch.linalg.vector_norm(ref))
+            del ref
+            te = timed(explicit, reps, warm=1)
+            fp = torch.zeros(sg, dtype=td, device=dev)
+            fp[tuple(slice(0, x) for x in sf)] = ft
+            Me = [2 * x - 1 for x in sg]
+            eq = hdc.Plan.nd(list(sg), Me, [tune.pow2_ceil(x) for x in sg], dtype=dt)
+            he = torch.empty(Me, dtype=td, device=dev)
+            wse = eq.workspace(dev)
+            tq = timed(lambda: eq.convolve(fp, gt, he, ws=wse), reps, warm=1)
+            comp = (int(np.prod(sf)) + int(np.prod(sg)) + int(np.prod(M))) * (16 if dt == "c128" else 8)
+            key = "x".join(map(str, sf)) + "_" + "x".join(map(str, sg)) + "_" + dt
+            und[key] = {"params": {"m": mm, "lam": ll}, "timings": ntim, "ms": round(t * 1e3, 4),
+                        "compulsory_GBps": round(comp / t / 1e9, 1), "explicit_ms": round(te * 1e3, 4),
+                        "speedup_vs_explicit": round(te / t, 3), "equal_padded_ms": round(tq * 1e3, 4),
+                        "speedup_vs_equal_padded": round(tq / t, 3), "rel_err_vs_explicit": err}
+            log(f"[bench] {key}: {t * 1e3:.3f} ms (explicit {te * 1e3:.3f}, equal-padded {tq * 1e3:.3f}), rel {err:.1e}")
+            del ft, gt, h, plan, ws, fp, eq, he, wse
+            torch.cuda.empty_cache()
+        out["uneq_nd"] = und
+
     return out
 
 
@@ -325,6 +391,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--extras", default="", help="comma list of secondary workloads to run (default: all of "
+                    "small,first_L,real,batch,nd,uneq,uneq_nd)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 512 MiB first (counter calibration)")
     args = ap.parse_args()

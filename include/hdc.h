@@ -45,7 +45,9 @@
 extern "C" {
 #endif
 
-typedef enum { HDC_C64 = 0, HDC_C128 = 1 } hdc_dtype;
+/* Data types: complex64 / complex128 (interleaved re, im), and real float32 /
+ * float64 (the real case of section 7, 1D plans only; see hdc_plan). */
+typedef enum { HDC_C64 = 0, HDC_C128 = 1, HDC_R32 = 2, HDC_R64 = 3 } hdc_dtype;
 
 typedef enum {
     HDC_OK = 0,
@@ -86,7 +88,23 @@ hdc_status hdc_derive(int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, int
                       hdc_dtype dtype, hdc_axis_desc* out);
 
 /* 1D plan (eqs. (3)-(4)).  Allocates the device twiddle tables on the current device
- * (the only allocation a plan makes).  Errors as hdc_derive, plus HDC_ERR_HIP. */
+ * (the only allocation a plan makes).  Errors as hdc_derive, plus HDC_ERR_HIP.
+ *
+ * Real data (dtype HDC_R32 or HDC_R64; the real case that section 7 names as
+ * future work): f, g and h are real arrays of float or double, L x C and M x C
+ * values with element j of copy c at j*C + c, and the plan computes in
+ * complex64 / complex128.  The two inputs are transformed together as
+ * z = f + i g (one forward transform instead of two): with k = q l + r,
+ *     F_k = (Z_k + conj Z_{N-k}) / 2,  G_k = (Z_k - conj Z_{N-k}) / (2i),
+ * and N - k lies in residue q - r.  The product H is Hermitian, so only the
+ * residues r <= q/2 are multiplied and inverted, D of them per pass (D is
+ * clamped to q/2 + 1), and h is the real part of their sum weighted 2 (1 for
+ * r = 0 and r = q/2).  Such a plan supports hdc_convolve, hdc_time_convolve
+ * and hdc_convolve_profiled; the residue-level calls (hdc_forward,
+ * hdc_multiply, hdc_backward, hdc_residues_natural, hdc_residue_buffer_size)
+ * return HDC_ERR_UNSUPPORTED for it, as do hdc_plan_nd, hdc_plan_uneq* and
+ * hdc_batch_plan given a real dtype.  Pointers need 4-byte (HDC_R32) or
+ * 8-byte (HDC_R64) alignment. */
 hdc_status hdc_plan(hdc_plan_t* out, int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, int64_t C,
                     int64_t D, hdc_dtype dtype);
 

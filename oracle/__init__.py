@@ -9,7 +9,8 @@ The convolution oracle is ``oracle.c`` (plain C, FP64, OpenMP), built into
 convolution of eq. (5) (section 2.3) two independent ways:
 
 * :func:`direct_1d`, :func:`direct_1d_sampled`, :func:`direct_nd_sampled` --
-  the defining sum;
+  the defining sum; :func:`direct_1d_real` the same sum in real arithmetic for
+  real operands (the real case section 7 leaves to future work);
 * :func:`padded_1d`, :func:`padded_nd` -- explicit dealiasing (section 3.1):
   zero padding to the smallest 2^a 3^b 5^c 7^d size >= 2L-1, DFT with
   zeta = e^{+2 pi i/n}, product, inverse DFT with 1/n, crop to M.

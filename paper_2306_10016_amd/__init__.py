@@ -26,20 +26,25 @@ from typing import Optional, Sequence
 from . import _lib
 from ._lib import AxisDesc, HdcError, lib, check  # noqa: F401
 
-C64, C128 = 0, 1
-_DT = {"c64": C64, "complex64": C64, "c128": C128, "complex128": C128, C64: C64, C128: C128}
+C64, C128, R32, R64 = 0, 1, 2, 3
+_DT = {"c64": C64, "complex64": C64, "c128": C128, "complex128": C128, "r32": R32, "float32": R32,
+       "r64": R64, "float64": R64, C64: C64, C128: C128, R32: R32, R64: R64}
 
 
 def dtype_code(dtype) -> int:
     if hasattr(dtype, "is_complex"):  # torch dtype
         import torch
-        return C128 if dtype == torch.complex128 else C64
+        return {torch.complex128: C128, torch.complex64: C64, torch.float64: R64, torch.float32: R32}[dtype]
     return _DT[dtype]
 
 
 def torch_dtype(code: int):
     import torch
-    return torch.complex128 if code == C128 else torch.complex64
+    return {C128: torch.complex128, C64: torch.complex64, R64: torch.float64, R32: torch.float32}[code]
+
+
+def is_real(code: int) -> bool:
+    return code in (R32, R64)
 
 
 def derive(L: int, M: int, m: int, p: int = 0, q: int = 0, C: int = 1, D: int = 0, dtype="c128") -> dict:

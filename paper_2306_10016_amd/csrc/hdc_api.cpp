@@ -50,7 +50,10 @@ int ilog2i(int64_t x) {
     return l;
 }
 
-size_t elem_bytes(hdc_dtype t) { return t == HDC_C128 ? 16 : 8; }
+size_t elem_bytes(hdc_dtype t) { return (t == HDC_C128 || t == HDC_R64) ? 16 : 8; }
+bool is_real(hdc_dtype t) { return t == HDC_R32 || t == HDC_R64; }
+// the complex type a real plan computes in (z = f + i g)
+hdc_dtype complex_of(hdc_dtype t) { return t == HDC_R64 ? HDC_C128 : (t == HDC_R32 ? HDC_C64 : t); }
 
 // exp(+2 pi i e / n) from an exactly reduced exponent, evaluated in long double.
 void root(int64_t e, int64_t n, double* re, double* im) {
@@ -155,6 +158,8 @@ struct hdc_plan_s {
     // operand's geometry (Lambda m-point residues) and fx[a] the shorter one's
     // (m-point residues); swap[a]: the caller's f is the longer one on axis a
     bool uneq = false;
+    // real f, g and h (HDC_R32 / HDC_R64, 1D); dtype is then the complex type computed in
+    bool real = false;
     bool swap[3] = {false, false, false};
     int64_t lam[3] = {1, 1, 1};
     int64_t Lf[3] = {1, 1, 1}, Lg[3] = {1, 1, 1};
@@ -172,7 +177,9 @@ namespace {
 // t < p of section 2.2 gives the first L).
 hdc_status derive_axis(int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, int64_t C, int64_t D, hdc_dtype dtype,
                        hdc_axis_desc* o, int64_t K = -1) {
-    if (dtype != HDC_C64 && dtype != HDC_C128) return fail(HDC_ERR_INVALID_ARG, "dtype must be HDC_C64 or HDC_C128");
+    if (is_real(dtype))
+        return fail(HDC_ERR_UNSUPPORTED, "real data (HDC_R32 / HDC_R64) are implemented for 1D plans (hdc_plan) only");
+    if (dtype != HDC_C64 && dtype != HDC_C128) return fail(HDC_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
     if (L < 1) return fail(HDC_ERR_INVALID_ARG, "L = %lld must be >= 1", (long long)L);
     if (K < 0) K = 2 * L - 1;
     if (M < 1) return fail(HDC_ERR_INVALID_ARG, "M = %lld must be >= 1", (long long)M);
@@ -529,10 +536,14 @@ hdc_status run_fused(const AxisPlan& A, const void* f, const void* g, void* h, i
 // that slot (d, l1, li) lands on row (d m1 + l1) lam + li.
 hdc_status run_col_fwd(const AxisPlan& A, const void* x, void* X, int64_t B, int64_t in_bs, int64_t out_bs,
                        int64_t C1, int64_t r0, int64_t Dg, hipStream_t s, const int64_t* desc = nullptr,
-                       int64_t lam = 1, int64_t rstride = 0) {
+                       int64_t lam = 1, int64_t rstride = 0, const void* x2 = nullptr, int64_t nsec = 0,
+                       int64_t r2 = 0) {
     ColFwdArgs a{};
     a.desc = desc;
     a.x = x;
+    a.x2 = x2;
+    a.nsec = (int32_t)nsec;
+    a.r2 = (int32_t)r2;
     a.X = X;
     a.B = B;
     a.in_bs = in_bs;
@@ -549,23 +560,28 @@ hdc_status run_col_fwd(const AxisPlan& A, const void* x, void* X, int64_t B, int
     a.Dg = (int32_t)(Dg * lam);
     a.lam = (int32_t)lam;
     a.rstride = (int32_t)rstride;
-    a.tile = A.cf_tile;
-    a.ntiles = (int32_t)ceil_div(a.Ccols, A.cf_tile);
+    const bool real = x2 != nullptr;
+    // the real-input kernel runs at most 512 threads: half the tile when wider
+    const int tdiv = (real && A.cf_threads > 512) ? 2 : 1;
+    a.tile = std::max(1, A.cf_tile / tdiv);
+    a.ntiles = (int32_t)ceil_div(a.Ccols, a.tile);
     a.hiprec = A.hiprec ? 1 : 0;
     a.tw = A.tw;
     a.tw1 = A.tw_m1;
     const int64_t gx = round8((int64_t)a.ntiles * a.Dg);
     if (gx > 0x7fffffff) return fail(HDC_ERR_UNSUPPORTED, "column grid too large");
-    const double eb = A.dbl ? 16.0 : 8.0;
-    const size_t esz = A.dbl ? 16 : 8;
+    const double eb = A.dbl ? 16.0 : 8.0;  // real: two inputs of L reals = L complex values
+    const size_t esz = (A.dbl ? 16 : 8) / (real ? 2 : 1);
     LaunchScope ls(s, 1, eb * (double)B * (double)C1 * ((double)A.d.L + (double)(a.Dg * A.d.m)));
     for (int64_t b0 = 0; b0 < B; b0 += kMaxGridY) {  // the grid's y extent is limited
         ColFwdArgs c = a;
         c.B = std::min<int64_t>(kMaxGridY, B - b0);
         if (desc) c.desc = desc + 2 * b0;
         else c.x = (const char*)x + (size_t)(b0 * in_bs) * esz;
-        c.X = (char*)X + (size_t)(b0 * out_bs) * esz;
-        hipError_t e = launch_col_fwd(A.dbl, (int)A.d.m1, c, A.cf_threads, gx, c.B, A.cf_lds, s);
+        if (real) c.x2 = (const char*)x2 + (size_t)(b0 * in_bs) * esz;
+        c.X = (char*)X + (size_t)(b0 * out_bs) * (A.dbl ? 16 : 8);
+        hipError_t e = launch_col_fwd(A.dbl, (int)A.d.m1, c, a.tile * (A.cf_threads / A.cf_tile), gx, c.B,
+                                      A.cf_lds / A.cf_tile * a.tile, s, real);
         if (e != hipSuccess) return hip_fail(e, "column forward launch");
     }
     return HDC_OK;
@@ -573,7 +589,7 @@ hdc_status run_col_fwd(const AxisPlan& A, const void* x, void* X, int64_t B, int
 
 hdc_status run_col_bwd(const AxisPlan& A, const void* Y, void* h, int64_t B, int64_t in_bs, int64_t out_bs,
                        int64_t C1, int64_t r0, int64_t Dg, bool accumulate, hipStream_t s,
-                       const int64_t* desc = nullptr) {
+                       const int64_t* desc = nullptr, bool real = false) {
     ColBwdArgs a{};
     a.desc = desc;
     a.Y = Y;
@@ -600,14 +616,17 @@ hdc_status run_col_bwd(const AxisPlan& A, const void* Y, void* h, int64_t B, int
     a.invN = 1.0 / (double)A.d.N;
     const double eb = A.dbl ? 16.0 : 8.0;
     const size_t esz = A.dbl ? 16 : 8;
-    LaunchScope ls(s, 3, eb * (double)B * (double)C1 * ((double)(Dg * A.d.m) + (accumulate ? 2.0 : 1.0) * (double)A.d.M));
+    const size_t hsz = real ? esz / 2 : esz;  // real output: M reals per copy
+    LaunchScope ls(s, 3, eb * (double)B * (double)C1 *
+                             ((double)(Dg * A.d.m) + (accumulate ? 2.0 : 1.0) * (double)A.d.M * (real ? 0.5 : 1.0)));
     for (int64_t b0 = 0; b0 < B; b0 += kMaxGridY) {  // the grid's y extent is limited
         ColBwdArgs c = a;
         c.B = std::min<int64_t>(kMaxGridY, B - b0);
         c.Y = (const char*)Y + (size_t)(b0 * in_bs) * esz;
         if (desc) c.desc = desc + 2 * b0;
-        else c.h = (char*)h + (size_t)(b0 * out_bs) * esz;
-        hipError_t e = launch_col_bwd(A.dbl, (int)A.d.m1, c, A.cb_threads, round8(a.ntiles), c.B, A.cb_lds, s);
+        else c.h = (char*)h + (size_t)(b0 * out_bs) * hsz;
+        hipError_t e =
+            launch_col_bwd(A.dbl, (int)A.d.m1, c, A.cb_threads, round8(a.ntiles), c.B, A.cb_lds, s, real);
         if (e != hipSuccess) return hip_fail(e, "column backward launch");
     }
     return HDC_OK;
@@ -789,6 +808,136 @@ hdc_status conv1d(const AxisPlan& A, const void* xf, const void* xg, void* out, 
         st = run_rows(A, Xf, Xg, Xf, B * Dg * A.d.m1 * C1, C1, MODE_CONV, s);
         if (st != HDC_OK) return st;
         st = run_col_bwd(A, Xf, out, B, xbs, out_bs, C1, r0, Dg, r0 > 0, s);
+        if (st != HDC_OK) return st;
+    }
+    return HDC_OK;
+}
+
+// ---------------------------------------------------------------- real data --
+//
+// Real f and g (the real case section 7 leaves to future work): the complex
+// sequence z = f + i g is transformed once.  Because f and g are real,
+// F_k = (Z_k + conj Z_{N-k}) / 2 and G_k = (Z_k - conj Z_{N-k}) / (2i), and with
+// k = q l + r the index N - k lies in residue q - r (residue 0 for r = 0).  The
+// product H is Hermitian, so only residues r <= q/2 are formed and inverted; the
+// backward sums them with weight 2 (1 for r = 0 and r = q/2) and keeps the real
+// part.  A pass over the group [r0, r0 + Dg) of those residues transforms Z for
+// the group and for the partners q - r it needs.
+
+struct RealGroup {
+    int64_t Dg, pfirst, npart;  // residues r0 .. r0+Dg-1; partners q - pfirst, q - pfirst - 1, ...
+};
+
+RealGroup real_group(const hdc_axis_desc& d, int64_t r0) {
+    const int64_t qh = d.q / 2 + 1;
+    const int64_t D = std::min(d.D, qh);
+    RealGroup g{};
+    g.Dg = std::min(D, qh - r0);
+    g.pfirst = std::max<int64_t>(r0, 1);
+    const int64_t plast = std::min(r0 + g.Dg - 1, (d.q - 1) / 2);
+    g.npart = std::max<int64_t>(0, plast - g.pfirst + 1);
+    return g;
+}
+
+// Workspace (complex elements) of the column/row/column real convolution:
+// Z (Dg + npart slots) and the product rows (Dg slots) of the largest group.
+int64_t ws_real(const AxisPlan& A, int64_t B, int64_t C1) {
+    if (A.d.variant == 0) return 0;
+    const int64_t qh = A.d.q / 2 + 1;
+    const int64_t D = std::min(A.d.D, qh);
+    int64_t slots = 0;
+    for (int64_t r0 = 0; r0 < qh; r0 += D) {
+        const RealGroup g = real_group(A.d, r0);
+        slots = std::max(slots, 2 * g.Dg + g.npart);
+    }
+    return B * slots * A.d.m * C1;
+}
+
+hdc_status run_fused_real(const AxisPlan& A, const void* f, const void* g, void* h, int64_t nrows, RowAddr in,
+                          RowAddr out, hipStream_t s) {
+    if (nrows <= 0) return HDC_OK;
+    FusedArgs a{};
+    a.f = f;
+    a.g = g;
+    a.h = h;
+    a.nrows = nrows;
+    a.in = in;
+    a.out = out;
+    a.L = (int32_t)A.d.L;
+    a.M = (int32_t)A.d.M;
+    a.p = (int32_t)A.d.p;
+    a.q = (int32_t)A.d.q;
+    a.qout = (int32_t)A.d.q_out;
+    a.N = (int32_t)A.d.N;
+    a.Dc = A.Dc;
+    a.rpw = A.f_rpw;
+    a.hiprec = A.hiprec ? 1 : 0;
+    a.tw = A.tw;
+    a.twm = A.tw_m;
+    a.invN = 1.0 / (double)A.d.N;
+    const int64_t blocks = ceil_div(nrows, A.f_rpw);
+    if (blocks > 0x7fffffff) return fail(HDC_ERR_UNSUPPORTED, "too many rows");
+    const double rb = A.dbl ? 8.0 : 4.0;  // bytes per real value
+    LaunchScope ls(s, 0, rb * (double)nrows * (2.0 * (double)A.d.L + (double)A.d.M));
+    hipError_t e = launch_fused_real(A.dbl, (int)A.d.m, a, A.f_threads, blocks, A.f_lds, s);
+    if (e != hipSuccess) return hip_fail(e, "fused real convolution launch");
+    return HDC_OK;
+}
+
+// Product rows of the group at r0: Z has S = Dg + npart slots per batch, the
+// output Dg slots; row ((b Dg + d) m1 + l1) C1 + c1.
+hdc_status run_rows_real(const AxisPlan& A, const void* Z, void* O, int64_t B, int64_t C1, int64_t r0,
+                         const RealGroup& g, hipStream_t s) {
+    const int64_t nrows = B * g.Dg * A.d.m1 * C1;
+    if (nrows <= 0) return HDC_OK;
+    RowArgs a{};
+    a.a = Z;
+    a.out = O;
+    a.nrows = nrows;
+    a.addr.inner_cnt = C1;
+    a.addr.outer_stride = A.d.m2 * C1;
+    a.addr.inner_stride = 1;
+    a.addr.es = C1;
+    a.mode = MODE_CONV;
+    a.rpw = A.r_rpw;
+    a.tw = A.tw_m2;
+    a.r0 = (int32_t)r0;
+    a.qg = (int32_t)A.d.q;
+    a.m1g = (int32_t)A.d.m1;
+    a.Dg = (int32_t)g.Dg;
+    a.S = (int32_t)(g.Dg + g.npart);
+    a.pfirst = (int32_t)g.pfirst;
+    const int64_t blocks = ceil_div(nrows, A.r_rpw);
+    if (blocks > 0x7fffffff) return fail(HDC_ERR_UNSUPPORTED, "too many rows");
+    const double eb = A.dbl ? 16.0 : 8.0;
+    LaunchScope ls(s, 2, eb * 3.0 * (double)nrows * (double)A.d.m2);
+    hipError_t e = launch_row_real(A.dbl, (int)A.d.m2, a, A.r_threads, blocks, A.r_lds, s);
+    if (e != hipSuccess) return hip_fail(e, "real row launch");
+    return HDC_OK;
+}
+
+// Real 1D convolution along axis A: B batches (strides in_bs / out_bs, in real
+// elements) of C1 interleaved copies.
+hdc_status conv1d_real(const AxisPlan& A, const void* xf, const void* xg, void* out, int64_t B, int64_t in_bs,
+                       int64_t out_bs, int64_t C1, char* ws, size_t eb, hipStream_t s) {
+    if (A.d.variant == 0) {
+        RowAddr in{C1, in_bs, 1, C1};
+        RowAddr ou{C1, out_bs, 1, C1};
+        return run_fused_real(A, xf, xg, out, B * C1, in, ou, s);
+    }
+    const int64_t qh = A.d.q / 2 + 1;
+    const int64_t D = std::min(A.d.D, qh);
+    for (int64_t r0 = 0; r0 < qh; r0 += D) {
+        const RealGroup g = real_group(A.d, r0);
+        const int64_t S = g.Dg + g.npart;
+        char* Z = ws;
+        char* O = ws + (size_t)(B * S * A.d.m * C1) * eb;
+        hdc_status st = run_col_fwd(A, xf, Z, B, in_bs, S * A.d.m * C1, C1, r0, S, s, nullptr, 1, 0, xg, g.npart,
+                                    A.d.q - g.pfirst);
+        if (st != HDC_OK) return st;
+        st = run_rows_real(A, Z, O, B, C1, r0, g, s);
+        if (st != HDC_OK) return st;
+        st = run_col_bwd(A, O, out, B, g.Dg * A.d.m * C1, out_bs, C1, r0, g.Dg, r0 > 0, s, nullptr, true);
         if (st != HDC_OK) return st;
     }
     return HDC_OK;
@@ -1010,6 +1159,8 @@ hdc_status finish_plan(hdc_plan_s* P) {
     if (P->uneq) {
         P->ws_bytes = (size_t)(P->ndim == 1 ? ws_uneq(P->ax[0], P->fx[0], 1, P->ax[0].d.C) : wsnd_uneq(P, 0, 1)) *
                       elem(P);
+    } else if (P->real) {
+        P->ws_bytes = (size_t)ws_real(P->ax[0], 1, P->ax[0].d.C) * elem(P);
     } else if (P->ndim == 1) {
         P->ws_bytes = (size_t)ws1d(P->ax[0], 1, P->ax[0].d.C) * elem(P);
     } else {
@@ -1033,7 +1184,7 @@ hdc_status hdc_derive(int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, int
                       hdc_axis_desc* out) {
     if (!out) return fail(HDC_ERR_INVALID_ARG, "out is NULL");
     hdc_axis_desc d{};
-    hdc_status st = derive_axis(L, M, m, p, q, C, D, dtype, &d);
+    hdc_status st = derive_axis(L, M, m, p, q, C, D, complex_of(dtype), &d);
     if (st != HDC_OK) return st;
     *out = d;
     return HDC_OK;
@@ -1045,11 +1196,12 @@ hdc_status hdc_plan(hdc_plan_t* out, int64_t L, int64_t M, int64_t m, int64_t p,
     *out = nullptr;
     hdc_plan_s* P = new hdc_plan_s();
     P->ndim = 1;
-    P->dtype = dtype;
+    P->real = is_real(dtype);
+    P->dtype = complex_of(dtype);
     AxisPlan& A = P->ax[0];
-    hdc_status st = derive_axis(L, M, m, p, q, C, D, dtype, &A.d);
+    hdc_status st = derive_axis(L, M, m, p, q, C, D, P->dtype, &A.d);
     if (st == HDC_OK) {
-        A.dbl = dtype == HDC_C128;
+        A.dbl = P->dtype == HDC_C128;
         st = geometry(A, false);
     }
     if (st == HDC_OK) st = finish_plan(P);
@@ -1210,14 +1362,15 @@ hdc_status hdc_workspace_size(hdc_plan_t P, size_t* bytes) {
 
 hdc_status hdc_residue_buffer_size(hdc_plan_t P, size_t* bytes) {
     if (!P || !bytes) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
-    if (P->ndim != 1) return fail(HDC_ERR_UNSUPPORTED, "residue buffers are defined for 1D plans");
+    if (P->ndim != 1 || P->real)
+        return fail(HDC_ERR_UNSUPPORTED, "residue buffers are defined for complex 1D plans");
     const hdc_axis_desc& d = P->ax[0].d;
     *bytes = (size_t)(std::min(d.D, d.q) * d.m * d.C) * elem(P);
     return HDC_OK;
 }
 
 static hdc_status check_ptrs(hdc_plan_t P, const void* a, const void* b, const void* c) {
-    const size_t al = elem(P) == 16 ? 16 : 8;
+    const size_t al = (elem(P) == 16 ? 16 : 8) / (P->real ? 2 : 1);
     if ((a && !aligned(a, al)) || (b && !aligned(b, al)) || (c && !aligned(c, al)))
         return fail(HDC_ERR_INVALID_ARG, "data pointers must be %zu-byte aligned", al);
     return HDC_OK;
@@ -1240,6 +1393,10 @@ hdc_status hdc_convolve(hdc_plan_t P, const void* f, const void* g, void* h, voi
         return P->swap[0] ? conv_uneq(G, P->fx[0], P->lam[0], g, f, h, 1, 0, 0, 0, C, (char*)ws, elem(P), s)
                           : conv_uneq(G, P->fx[0], P->lam[0], f, g, h, 1, 0, 0, 0, C, (char*)ws, elem(P), s);
     }
+    if (P->real) {
+        const AxisPlan& A = P->ax[0];
+        return conv1d_real(A, f, g, h, 1, 0, 0, A.d.C, (char*)ws, elem(P), s);
+    }
     if (P->ndim == 1) {
         const AxisPlan& A = P->ax[0];
         return conv1d(A, f, g, h, 1, 0, 0, A.d.C, (char*)ws, elem(P), s);
@@ -1248,6 +1405,7 @@ hdc_status hdc_convolve(hdc_plan_t P, const void* f, const void* g, void* h, voi
 }
 
 static hdc_status group_check(hdc_plan_t P, int64_t r0, int64_t* Dg) {
+    if (P->real) return fail(HDC_ERR_UNSUPPORTED, "a real-data plan exposes hdc_convolve only");
     if (P->ndim != 1) return fail(HDC_ERR_UNSUPPORTED, "forward/multiply/backward are defined for 1D plans");
     const hdc_axis_desc& d = P->ax[0].d;
     const int64_t D = std::min(d.D, d.q);
@@ -1488,6 +1646,7 @@ hdc_status hdc_batch_plan(hdc_batch_t* out, int64_t n, const int64_t* L, const i
                           hdc_dtype dtype) {
     if (!out || !L || n < 1) return fail(HDC_ERR_INVALID_ARG, "bad batch arguments");
     *out = nullptr;
+    if (is_real(dtype)) return fail(HDC_ERR_UNSUPPORTED, "real data are implemented for 1D plans (hdc_plan) only");
     if (dtype != HDC_C64 && dtype != HDC_C128) return fail(HDC_ERR_INVALID_ARG, "bad dtype");
     hdc_batch_s* Bt = new hdc_batch_s();
     Bt->dtype = dtype;

@@ -53,11 +53,13 @@ struct FusedArgs {
 
 struct ColFwdArgs {
     const void* x;
+    const void* x2;            // real case: g (x is f), both real
     void* X;
     int64_t B, in_bs, out_bs;  // batch count and strides (elements)
     int32_t L, Ccols, C1, m2, m, q, p, N;
     int32_t r0, Dg;            // Dg residue slots; slot d lam + li is residue r0 + d + li rstride
     int32_t lam, rstride;      // lam = 1 (rstride unused): residues [r0, r0 + Dg)
+    int32_t nsec, r2;          // the last nsec slots hold residues r2, r2 - 1, ... (real case)
     int32_t tile, ntiles;
     int32_t hiprec;
     TwN tw;
@@ -98,6 +100,9 @@ struct RowArgs {
     TwN twN;
     int64_t fbs;
     int32_t Lf, pf, qf, N, r0, qg, m1g, Dg, hiprec;
+    // real case (k_row_real): product rows of residues r0 + d (d < Dg, each
+    // q = qg), Z with S slots per batch, partner slots from residue pfirst on
+    int32_t S, pfirst;
 };
 
 enum { MODE_FWD = 0, MODE_INV = 1, MODE_CONV = 2 };
@@ -106,9 +111,13 @@ enum { MODE_FWD = 0, MODE_INV = 1, MODE_CONV = 2 };
 hipError_t launch_fused(bool dbl, int m, const FusedArgs& a, int threads, int64_t blocks, size_t lds,
                         hipStream_t s);
 hipError_t launch_col_fwd(bool dbl, int m1, const ColFwdArgs& a, int threads, int64_t gx, int64_t gy,
-                          size_t lds, hipStream_t s);
+                          size_t lds, hipStream_t s, bool real = false);
 hipError_t launch_col_bwd(bool dbl, int m1, const ColBwdArgs& a, int threads, int64_t gx, int64_t gy,
-                          size_t lds, hipStream_t s);
+                          size_t lds, hipStream_t s, bool real = false);
+hipError_t launch_row_real(bool dbl, int m2, const RowArgs& a, int threads, int64_t blocks, size_t lds,
+                           hipStream_t s);
+hipError_t launch_fused_real(bool dbl, int m, const FusedArgs& a, int threads, int64_t blocks, size_t lds,
+                             hipStream_t s);
 hipError_t launch_row(bool dbl, int m2, const RowArgs& a, int threads, int64_t blocks, size_t lds,
                       hipStream_t s);
 hipError_t launch_mul(bool dbl, void* F, const void* G, int64_t n, hipStream_t s);

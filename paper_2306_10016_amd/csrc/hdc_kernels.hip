@@ -420,8 +420,12 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
 // Column c' = s2*C1 + c1 (s2 < m2 the four-step column, c1 < C1 the copy);
 // axis index j = t*m + s1*m2 + s2 lives at element (t*m1 + s1)*Ccols + c'.
 
-template <typename T, int M1>
-__global__ void __launch_bounds__(1024) k_col_fwd(ColFwdArgs a) {
+// REAL: the input is two real arrays x (f) and x2 (g), transformed together as
+// z = f + i g (the real case, whose product stage pairs residue r with q - r).
+// (the real variant holds two input pointers and runs at most 512 threads, so
+// that its registers fit without spilling)
+template <typename T, int M1, bool REAL = false>
+__global__ void __launch_bounds__(REAL ? 512 : 1024) k_col_fwd(ColFwdArgs a) {
     using P = FP<M1>;
     constexpr int PPT = P::PPT;
     constexpr int TPF = P::TPF;
@@ -448,6 +452,9 @@ __global__ void __launch_bounds__(1024) k_col_fwd(ColFwdArgs a) {
     // block (d m1 + l1) lam + li (section 3.5's matching when lam > 1)
     const int d = dd / a.lam;
     const int li = dd - d * a.lam;
+    // the last nsec slots hold the descending residues r2, r2 - 1, ...
+    const int dg1 = a.Dg - a.nsec;
+    const bool second = dd >= dg1;
     const int tile = a.tile;
     const int tid = threadIdx.x;
     const int cc = tid % tile;
@@ -463,16 +470,19 @@ __global__ void __launch_bounds__(1024) k_col_fwd(ColFwdArgs a) {
         L = a.desc[2 * b + 1];
     }
     const cplx<T>* x = reinterpret_cast<const cplx<T>*>(a.x) + xoff;
+    const T* xr = reinterpret_cast<const T*>(a.x) + xoff;
+    const T* xi = reinterpret_cast<const T*>(a.x2) + xoff;
     cplx<T>* X = reinterpret_cast<cplx<T>*>(a.X) + b * a.out_bs;
 
     // block t, point v of this thread: x[(t*m1 + s1)*Ccols + cp], zero beyond L
+#define HDC_IDX(t, v) (((int64_t)(t) * M1 + lane + (v) * TPF) * a.Ccols + cp)
 #define HDC_LOAD(t, v)                                                                        \
     ((ok && (((int64_t)(t) * M1 + lane + (v) * TPF) * a.m2 + s2) < L)                         \
-         ? x[((int64_t)(t) * M1 + lane + (v) * TPF) * a.Ccols + cp]                           \
+         ? (REAL ? mk<T>(xr[HDC_IDX(t, v)], xi[HDC_IDX(t, v)]) : x[HDC_IDX(t, v)])            \
          : mk<T>(0, 0))
 
     {
-        const int r = a.r0 + d + li * a.rstride;
+        const int r = second ? a.r2 - (dd - dg1) : a.r0 + d + li * a.rstride;
         cplx<T> w[PPT];
 #pragma unroll
         for (int v = 0; v < PPT; ++v) w[v] = HDC_LOAD(0, v);
@@ -516,9 +526,13 @@ __global__ void __launch_bounds__(1024) k_col_fwd(ColFwdArgs a) {
         }
     }
 #undef HDC_LOAD
+#undef HDC_IDX
 }
 
-template <typename T, int M1, int DMAX>
+// REAL: the residues are those of a Hermitian product (real output, the real
+// case of section 7): only r <= q/2 are given, each counted twice except r = 0
+// and r = q/2, and the real part is written to a real h.
+template <typename T, int M1, int DMAX, bool REAL = false>
 __global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
     using P = FP<M1>;
     using S = TwSplit<M1>;
@@ -554,6 +568,7 @@ __global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
     }
     const cplx<T>* Y = reinterpret_cast<const cplx<T>*>(a.Y) + b * a.in_bs;
     cplx<T>* h = reinterpret_cast<cplx<T>*>(a.h) + hoff;
+    T* hr = reinterpret_cast<T*>(a.h) + hoff;
     const T invN = (T)a.invN;
     // four-step twiddle conj(zeta_m^{l1 s2}), l1 = lane + v TPF, as z0 zs^v
     const bool fs = a.m2 > 1 && s2 != 0;
@@ -610,13 +625,27 @@ __global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
                 const int s1 = lane + v * TPF;
                 const int64_t k = (int64_t)t * a.m + (int64_t)s1 * a.m2 + s2;
                 if (!ok || k >= M) continue;
-                cplx<T> acc = mk<T>(0, 0);
-#pragma unroll
-                for (int dd = 0; dd < DMAX; ++dd)
-                    if (dd < nd) acc = acc + mul_tw<true>(V[dd][v], z[dd], false);
                 const int64_t idx = ((int64_t)t * M1 + s1) * a.Ccols + cp;
-                if (add) acc = acc + h[idx];
-                h[idx] = acc;
+                if constexpr (REAL) {
+                    T acc = 0;
+#pragma unroll
+                    for (int dd = 0; dd < DMAX; ++dd) {
+                        if (dd < nd) {
+                            const int r = a.r0 + db + dd;
+                            const T wgt = (r == 0 || 2 * r == a.q) ? (T)1 : (T)2;
+                            acc += wgt * mul_tw<true>(V[dd][v], z[dd], false).x;
+                        }
+                    }
+                    if (add) acc += hr[idx];
+                    hr[idx] = acc;
+                } else {
+                    cplx<T> acc = mk<T>(0, 0);
+#pragma unroll
+                    for (int dd = 0; dd < DMAX; ++dd)
+                        if (dd < nd) acc = acc + mul_tw<true>(V[dd][v], z[dd], false);
+                    if (add) acc = acc + h[idx];
+                    h[idx] = acc;
+                }
             }
         }
     }
@@ -763,6 +792,229 @@ __global__ void __launch_bounds__(512) k_row(RowArgs a) {
     }
 }
 
+// --------------------------------------------------------------- real case --
+//
+// Real f and g are transformed together as z = f + i g, so Z_k = F_k + i G_k
+// with F, G Hermitian: F_k = (Z_k + conj Z_{N-k}) / 2, G_k = (Z_k - conj Z_{N-k}) / (2i)
+// and H_k = F_k G_k = (Z_k^2 - (conj Z_{N-k})^2) / (4i).  With k = q l + r,
+// N - k lies in residue q - r at l' = m - 1 - l (residue 0: l' = -l mod m); in
+// the four-step order l = l1 + m1 l2 that is row m1 - 1 - l1, point m2 - 1 - l2
+// (residue 0, l1 > 0: row m1 - l1, point m2 - 1 - l2; residue 0, l1 = 0: row 0,
+// point -l2 mod m2).  A row DFT turns a conjugated row pre-multiplied by
+// zeta_m2^{s} into conj X_{m2-1-l2} (unmultiplied: conj X_{-l2}), so the partner
+// arrives in the right registers without a permutation.  H is Hermitian too,
+// so only residues r <= q/2 are formed and inverted.
+
+// Rows of one product: the Z row, the partner Z row, whether the partner's
+// points run m2 - 1 - l2 (else -l2), and the output row.  Z holds S slots per
+// batch (slot d < Dg: residue r0 + d; slot Dg + i: residue q - (pfirst + i)).
+__device__ __forceinline__ void real_rows(const RowArgs& a, int64_t row, int64_t& ab, int64_t& pb, bool& rev,
+                                          int64_t& ob) {
+    const int64_t C1 = a.addr.inner_cnt;
+    const int64_t m1 = a.m1g;
+    const int64_t c1 = row % C1;
+    const int64_t t1 = row / C1;
+    const int64_t l1 = t1 % m1;
+    const int64_t t2 = t1 / m1;
+    const int64_t d = t2 % a.Dg;
+    const int64_t b = t2 / a.Dg;
+    const int64_t j = a.r0 + d;
+    int64_t ps, pl;
+    if (j == 0) {
+        ps = d;
+        pl = l1 == 0 ? 0 : m1 - l1;
+        rev = l1 != 0;
+    } else {
+        ps = (2 * j == a.qg) ? d : a.Dg + (j - a.pfirst);
+        pl = m1 - 1 - l1;
+        rev = true;
+    }
+    const int64_t os = a.addr.outer_stride;  // m2 C1
+    ab = ((b * a.S + d) * m1 + l1) * os + c1;
+    pb = ((b * a.S + ps) * m1 + pl) * os + c1;
+    ob = ((b * a.Dg + d) * m1 + l1) * os + c1;
+}
+
+template <typename T, int MSZ>
+__global__ void __launch_bounds__(512) k_row_real(RowArgs a) {
+    using P = FP<MSZ>;
+    using S = TwSplit<MSZ>;
+    constexpr int PPT = P::PPT;
+    constexpr int TPF = P::TPF;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T>* smem = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* tlo = smem + (size_t)a.rpw * padded(MSZ);
+    cplx<T>* thi = tlo + S::LO;
+    const int tid = threadIdx.x;
+    const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.tw);
+    for (int e = tid; e < S::LO; e += blockDim.x) tlo[e] = twg[e];
+    for (int e = tid; e < S::HI; e += blockDim.x) thi[e] = twg[e * S::LO];
+    __syncthreads();
+    const TwLds<T> tw{tlo, thi, S::LO - 1, S::LG};
+    const int rloc = tid / TPF;
+    const int lane = tid - rloc * TPF;
+    cplx<T>* buf = smem + (size_t)rloc * padded(MSZ);
+    const int64_t es = a.addr.es;
+    const int64_t stride = (int64_t)gridDim.x * a.rpw;
+    const cplx<T>* Z = reinterpret_cast<const cplx<T>*>(a.a);
+    cplx<T>* Og = reinterpret_cast<cplx<T>*>(a.out);
+    for (int64_t base = (int64_t)blockIdx.x * a.rpw; base < a.nrows; base += stride) {
+        const int64_t row = base + rloc;
+        const bool ok = row < a.nrows;
+        int64_t ab, pb, ob;
+        bool rev;
+        real_rows(a, ok ? row : 0, ab, pb, rev, ob);
+        cplx<T> v[PPT], u[PPT];
+#pragma unroll
+        for (int w = 0; w < PPT; ++w) {
+            const int s = lane + w * TPF;
+            v[w] = ok ? Z[ab + (int64_t)s * es] : mk<T>(0, 0);
+            cplx<T> x = ok ? Z[pb + (int64_t)s * es] : mk<T>(0, 0);
+            x.y = -x.y;
+            u[w] = rev ? x * tw[s] : x;
+        }
+        fft_regs<T, MSZ, +1, true>(v, buf, 1, lane, tw, ok);
+        fft_regs<T, MSZ, +1, true>(u, buf, 1, lane, tw, ok);
+        // H = (Z^2 - W^2) / (4i), W = conj Z_{N-k}
+#pragma unroll
+        for (int w = 0; w < PPT; ++w) v[w] = scale(mul_i<-1>(v[w] * v[w] - u[w] * u[w]), (T)0.25);
+        fft_regs<T, MSZ, -1, true>(v, buf, 1, lane, tw, ok);
+        if (ok) {
+#pragma unroll
+            for (int w = 0; w < PPT; ++w) Og[ob + (int64_t)(lane + w * TPF) * es] = v[w];
+        }
+    }
+}
+
+// Fused real case: every residue of one row in LDS.  Pass 1 forms Z for all q
+// residues; pass 2 forms H for r <= q/2 from Z_r and the mirrored Z_{q-r},
+// inverts it and stores u^(r)_s zeta_N^{-r s} / N; the output is the real part
+// of the weighted residue sum.  f, g and h are real.
+template <typename T, int MSZ>
+__global__ void __launch_bounds__(512) k_fused_real(FusedArgs a) {
+    using P = FP<MSZ>;
+    constexpr int PPT = P::PPT;
+    constexpr int TPF = P::TPF;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T>* smem = reinterpret_cast<cplx<T>*>(smem_raw);
+    using S = TwSplit<MSZ>;
+    double2* twq =
+        reinterpret_cast<double2*>(smem_raw + ((size_t)a.rpw * a.q * padded(MSZ) * sizeof(cplx<T>) + 15) / 16 * 16);
+    cplx<T>* tlo = reinterpret_cast<cplx<T>*>(twq + a.q);
+    cplx<T>* thi = tlo + S::LO;
+    constexpr int RS = padded(MSZ);
+    const int rowthreads = TPF * a.Dc;
+    const int tid = threadIdx.x;
+    const int rloc = tid / rowthreads;
+    const int lt = tid - rloc * rowthreads;
+    const int grp = lt / TPF;
+    const int lane = lt - grp * TPF;
+    const int64_t row = (int64_t)blockIdx.x * a.rpw + rloc;
+    const bool rowok = row < a.nrows;
+    for (int e = tid; e < a.q; e += blockDim.x) twq[e] = tw_n(a.tw, (uint32_t)e * (uint32_t)MSZ);
+    {
+        const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.twm);
+        for (int e = tid; e < S::LO; e += blockDim.x) tlo[e] = twg[e];
+        for (int e = tid; e < S::HI; e += blockDim.x) thi[e] = twg[e * S::LO];
+    }
+    __syncthreads();
+    const TwLds<T> twm{tlo, thi, S::LO - 1, S::LG};
+    const int L = a.L, M = a.M, q = a.q;
+    const int qh = q / 2 + 1;
+    const int64_t fbase = row_base(a.in, rowok ? row : 0);
+    const int64_t hbase = row_base(a.out, rowok ? row : 0);
+    const int64_t ies = a.in.es, oes = a.out.es;
+    const T* f = reinterpret_cast<const T*>(a.f) + fbase;
+    const T* g = reinterpret_cast<const T*>(a.g) + fbase;
+    T* h = reinterpret_cast<T*>(a.h) + hbase;
+    cplx<T>* U = smem + (size_t)rloc * q * RS;
+    const T invN = (T)a.invN;
+
+    // pass 1: Z_r for every residue
+    for (int rb = 0; rb < q; rb += a.Dc) {
+        const int r = rb + grp;
+        const bool act = rowok && r < q;
+        cplx<T>* buf = U + (size_t)(act ? r : 0) * RS;
+        cplx<T> Zr[PPT];
+#pragma unroll
+        for (int v = 0; v < PPT; ++v) Zr[v] = mk<T>(0, 0);
+        if (act) {
+            int e = 0;
+            for (int t = 0; t < a.p; ++t) {
+                const double2 z = twq[e];
+                e += r;
+                if (e >= q) e -= q;
+#pragma unroll
+                for (int v = 0; v < PPT; ++v) {
+                    const int j = t * MSZ + lane + v * TPF;
+                    if (j < L) Zr[v] = Zr[v] + mul_tw<false>(mk<T>(f[(int64_t)j * ies], g[(int64_t)j * ies]), z, false);
+                }
+            }
+        }
+        const uint32_t ru = (uint32_t)(act ? r : 0);
+        {
+            double2 z = tw_n(a.tw, ru * (uint32_t)lane);
+            const double2 zs = tw_n(a.tw, ru * (uint32_t)TPF);
+#pragma unroll
+            for (int v = 0; v < PPT; ++v) {
+                Zr[v] = mul_tw<false>(Zr[v], z, a.hiprec);
+                z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
+            }
+        }
+        fft_regs<T, MSZ, +1, true>(Zr, buf, 1, lane, twm, act);
+        if (act) {
+#pragma unroll
+            for (int v = 0; v < PPT; ++v) buf[lds_at<true>(lane + v * TPF, 1)] = Zr[v];
+        }
+        __syncthreads();
+    }
+    // pass 2: H_r, r <= q/2, inverted in place
+    for (int rb = 0; rb < qh; rb += a.Dc) {
+        const int r = rb + grp;
+        const bool act = rowok && r < qh;
+        const int ru = act ? r : 0;
+        cplx<T>* buf = U + (size_t)ru * RS;
+        const cplx<T>* pbuf = U + (size_t)(ru == 0 ? 0 : q - ru) * RS;
+        cplx<T> Hr[PPT];
+#pragma unroll
+        for (int v = 0; v < PPT; ++v) {
+            const int l = lane + v * TPF;
+            const int lp = ru == 0 ? (l == 0 ? 0 : MSZ - l) : MSZ - 1 - l;
+            const cplx<T> z = act ? buf[lds_at<true>(l, 1)] : mk<T>(0, 0);
+            cplx<T> w = act ? pbuf[lds_at<true>(lp, 1)] : mk<T>(0, 0);
+            w.y = -w.y;
+            Hr[v] = scale(mul_i<-1>(z * z - w * w), (T)0.25);
+        }
+        __syncthreads();  // every partner read before the transforms reuse the buffers
+        fft_regs<T, MSZ, -1, true>(Hr, buf, 1, lane, twm, act);
+        if (act) {
+            double2 z = tw_n(a.tw, (uint32_t)ru * (uint32_t)lane);
+            const double2 zs = tw_n(a.tw, (uint32_t)ru * (uint32_t)TPF);
+#pragma unroll
+            for (int v = 0; v < PPT; ++v) {
+                buf[lds_at<true>(lane + v * TPF, 1)] = scale(mul_tw<true>(Hr[v], z, a.hiprec), invN);
+                z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
+            }
+        }
+        __syncthreads();
+    }
+    if (!rowok) return;
+    // h_{t m + s} = Re sum_{r <= q/2} w_r zeta_q^{-t r} U[r][s]
+    for (int k = lt; k < M; k += rowthreads) {
+        const int t = k / MSZ;
+        const int s2 = k - t * MSZ;
+        T acc = 0;
+        int e = 0;
+        for (int r = 0; r < qh; ++r) {
+            const T wgt = (r == 0 || 2 * r == q) ? (T)1 : (T)2;
+            acc += wgt * mul_tw<true>(U[(size_t)r * RS + lds_at<true>(s2, 1)], twq[e], false).x;
+            e += t;
+            if (e >= q) e -= q;
+        }
+        h[(int64_t)k * oes] = acc;
+    }
+}
+
 // ------------------------------------------------------------ elementwise --
 
 template <typename T>
@@ -790,6 +1042,19 @@ __global__ void k_natural(const cplx<T>* F, cplx<T>* out, int64_t Dg, int64_t m1
 
 namespace {
 
+int cu_count() {
+    static int n = 0;
+    if (n == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            n = v;
+        else
+            n = 256;
+    }
+    return n;
+}
+
 template <typename K>
 hipError_t allow_lds(K kernel, size_t lds) {
     if (lds <= 65536) return hipSuccess;
@@ -806,37 +1071,58 @@ hipError_t fused_t(const FusedArgs& a, int threads, int64_t blocks, size_t lds, 
     return hipGetLastError();
 }
 
-template <typename T, int M1>
-hipError_t colf_t(const ColFwdArgs& a, int threads, int64_t gx, int64_t gy, size_t lds, hipStream_t s) {
+template <typename T, int M1, bool REAL>
+hipError_t colf_r(const ColFwdArgs& a, int threads, int64_t gx, int64_t gy, size_t lds, hipStream_t s) {
     lds += (size_t)(TwSplit<M1>::LO + TwSplit<M1>::HI) * sizeof(cplx<T>);
-    hipError_t e = allow_lds(k_col_fwd<T, M1>, lds);
+    hipError_t e = allow_lds(k_col_fwd<T, M1, REAL>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_col_fwd<T, M1>), dim3((unsigned)gx, (unsigned)gy), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL((k_col_fwd<T, M1, REAL>), dim3((unsigned)gx, (unsigned)gy), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
 template <typename T, int M1>
-hipError_t colb_t(const ColBwdArgs& a, int threads, int64_t gx, int64_t gy, size_t lds, hipStream_t s) {
+hipError_t colf_t(const ColFwdArgs& a, int threads, int64_t gx, int64_t gy, size_t lds, hipStream_t s, bool real) {
+    return real ? colf_r<T, M1, true>(a, threads, gx, gy, lds, s) : colf_r<T, M1, false>(a, threads, gx, gy, lds, s);
+}
+
+template <typename T, int M1, bool REAL>
+hipError_t colb_r(const ColBwdArgs& a, int threads, int64_t gx, int64_t gy, size_t lds, hipStream_t s) {
     constexpr int DMAX = sizeof(T) == 8 ? 2 : 4;
     lds += (size_t)(TwSplit<M1>::LO + TwSplit<M1>::HI) * sizeof(cplx<T>);
-    hipError_t e = allow_lds(k_col_bwd<T, M1, DMAX>, lds);
+    hipError_t e = allow_lds(k_col_bwd<T, M1, DMAX, REAL>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_col_bwd<T, M1, DMAX>), dim3((unsigned)gx, (unsigned)gy), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL((k_col_bwd<T, M1, DMAX, REAL>), dim3((unsigned)gx, (unsigned)gy), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
-int cu_count() {
-    static int n = 0;
-    if (n == 0) {
-        int dev = 0, v = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-            n = v;
-        else
-            n = 256;
-    }
-    return n;
+template <typename T, int M1>
+hipError_t colb_t(const ColBwdArgs& a, int threads, int64_t gx, int64_t gy, size_t lds, hipStream_t s, bool real) {
+    return real ? colb_r<T, M1, true>(a, threads, gx, gy, lds, s) : colb_r<T, M1, false>(a, threads, gx, gy, lds, s);
 }
+
+template <typename T, int MSZ>
+hipError_t row_real_t(const RowArgs& a, int threads, int64_t blocks, size_t lds, hipStream_t s) {
+    lds += (size_t)(TwSplit<MSZ>::LO + TwSplit<MSZ>::HI) * sizeof(cplx<T>);
+    auto kern = k_row_real<T, MSZ>;
+    hipError_t e = allow_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, threads, lds) != hipSuccess || occ < 1) occ = 1;
+    const int64_t resident = (int64_t)occ * cu_count();
+    const int64_t grid = blocks < resident ? blocks : resident;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int MSZ>
+hipError_t fused_real_t(const FusedArgs& a, int threads, int64_t blocks, size_t lds, hipStream_t s) {
+    lds += (size_t)(TwSplit<MSZ>::LO + TwSplit<MSZ>::HI) * sizeof(cplx<T>);
+    hipError_t e = allow_lds(k_fused_real<T, MSZ>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_fused_real<T, MSZ>), dim3((unsigned)blocks), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
 
 template <typename T, int MSZ, int MODE, bool TWO, bool FRAW = false>
 hipError_t row_mode(const RowArgs& a, int threads, int64_t blocks, size_t lds, hipStream_t s) {
@@ -901,17 +1187,39 @@ static hipError_t row_disp(int m, const RowArgs& a, int th, int64_t bl, size_t l
 }
 
 template <typename T>
-static hipError_t colf_disp(int m1, const ColFwdArgs& a, int th, int64_t gx, int64_t gy, size_t lds, hipStream_t s) {
+static hipError_t colf_disp(int m1, const ColFwdArgs& a, int th, int64_t gx, int64_t gy, size_t lds, hipStream_t s,
+                            bool real) {
     switch (m1) {
-        HDC_POW2_CASES(colf_t, a, th, gx, gy, lds, s)
+        HDC_POW2_CASES(colf_t, a, th, gx, gy, lds, s, real)
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T>
-static hipError_t colb_disp(int m1, const ColBwdArgs& a, int th, int64_t gx, int64_t gy, size_t lds, hipStream_t s) {
+static hipError_t colb_disp(int m1, const ColBwdArgs& a, int th, int64_t gx, int64_t gy, size_t lds, hipStream_t s,
+                            bool real) {
     switch (m1) {
-        HDC_POW2_CASES(colb_t, a, th, gx, gy, lds, s)
+        HDC_POW2_CASES(colb_t, a, th, gx, gy, lds, s, real)
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+static hipError_t row_real_disp(int m, const RowArgs& a, int th, int64_t bl, size_t lds, hipStream_t s) {
+    switch (m) {
+        HDC_POW2_CASES(row_real_t, a, th, bl, lds, s)
+        case 2048: return row_real_t<T, 2048>(a, th, bl, lds, s);
+        case 4096: return row_real_t<T, 4096>(a, th, bl, lds, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+static hipError_t fused_real_disp(int m, const FusedArgs& a, int th, int64_t bl, size_t lds, hipStream_t s) {
+    switch (m) {
+        HDC_POW2_CASES(fused_real_t, a, th, bl, lds, s)
+        case 2048: return fused_real_t<T, 2048>(a, th, bl, lds, s);
+        case 4096: return fused_real_t<T, 4096>(a, th, bl, lds, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -926,15 +1234,27 @@ hipError_t launch_row(bool dbl, int m2, const RowArgs& a, int threads, int64_t b
 }
 
 hipError_t launch_col_fwd(bool dbl, int m1, const ColFwdArgs& a, int threads, int64_t gx, int64_t gy, size_t lds,
-                          hipStream_t s) {
-    return dbl ? colf_disp<double>(m1, a, threads, gx, gy, lds, s)
-               : colf_disp<float>(m1, a, threads, gx, gy, lds, s);
+                          hipStream_t s, bool real) {
+    return dbl ? colf_disp<double>(m1, a, threads, gx, gy, lds, s, real)
+               : colf_disp<float>(m1, a, threads, gx, gy, lds, s, real);
 }
 
 hipError_t launch_col_bwd(bool dbl, int m1, const ColBwdArgs& a, int threads, int64_t gx, int64_t gy, size_t lds,
-                          hipStream_t s) {
-    return dbl ? colb_disp<double>(m1, a, threads, gx, gy, lds, s)
-               : colb_disp<float>(m1, a, threads, gx, gy, lds, s);
+                          hipStream_t s, bool real) {
+    return dbl ? colb_disp<double>(m1, a, threads, gx, gy, lds, s, real)
+               : colb_disp<float>(m1, a, threads, gx, gy, lds, s, real);
+}
+
+hipError_t launch_row_real(bool dbl, int m2, const RowArgs& a, int threads, int64_t blocks, size_t lds,
+                           hipStream_t s) {
+    return dbl ? row_real_disp<double>(m2, a, threads, blocks, lds, s)
+               : row_real_disp<float>(m2, a, threads, blocks, lds, s);
+}
+
+hipError_t launch_fused_real(bool dbl, int m, const FusedArgs& a, int threads, int64_t blocks, size_t lds,
+                             hipStream_t s) {
+    return dbl ? fused_real_disp<double>(m, a, threads, blocks, lds, s)
+               : fused_real_disp<float>(m, a, threads, blocks, lds, s);
 }
 
 hipError_t launch_mul(bool dbl, void* F, const void* G, int64_t n, hipStream_t s) {

@@ -55,3 +55,18 @@ def pair(shape, cfg: int, size_idx: int, dtype=np.complex128):
     """The (f, g) operand pair for one workload entry."""
     return (uniform_complex(shape, cfg, size_idx, 0, dtype),
             uniform_complex(shape, cfg, size_idx, 1, dtype))
+
+
+def uniform_real(shape, cfg: int, size_idx: int, which: int, dtype=np.float64) -> np.ndarray:
+    """Real array ~ U[-1, 1] i.i.d., drawn in float64 and rounded to ``dtype``."""
+    shape = tuple(int(s) for s in np.atleast_1d(shape))
+    r = rng(cfg, size_idx, which)
+    n = int(np.prod(shape)) if shape else 1
+    return r.uniform(-1.0, 1.0, n).reshape(shape).astype(np.dtype(dtype))
+
+
+def integers_real(shape, bound: int, cfg: int, size_idx: int, which: int) -> np.ndarray:
+    """float64 array of integers uniform on [-bound, bound]."""
+    shape = tuple(int(s) for s in np.atleast_1d(shape))
+    r = rng(cfg, size_idx, which)
+    return r.integers(-bound, bound + 1, int(np.prod(shape))).astype(np.float64).reshape(shape)
