@@ -289,7 +289,8 @@ hdc_status geometry(AxisPlan& A, bool outer, bool many_rows = false, bool keep_s
         while (A.cb_tile > 1 && (size_t)d.m1 * A.cb_tile * b > 65536) A.cb_tile /= 2;
         A.cb_threads = A.cb_tile * tpf;
         A.cb_lds = (size_t)d.m1 * A.cb_tile * b;
-        if (A.cf_lds > device_lds_max() || A.cb_lds > device_lds_max())
+        const size_t tab = (size_t)pass_tab_len(d.m1) * b;
+        if (A.cf_lds + tab > device_lds_max() || A.cb_lds + tab > device_lds_max())
             return fail(HDC_ERR_UNSUPPORTED, "column stage m1 = %lld needs %zu bytes of LDS", (long long)d.m1,
                         A.cf_lds);
     }
@@ -300,8 +301,9 @@ hdc_status geometry(AxisPlan& A, bool outer, bool many_rows = false, bool keep_s
         int rpw = std::max(1, 256 / tpf);
         A.r_rpw = rpw;
         A.r_threads = rpw * tpf;
-        A.r_lds = (size_t)rpw * padded_len(d.m2) * b;
-        if (A.r_lds > device_lds_max())
+        A.r_lds = (size_t)rpw * 2 * d.m2 * b;  // two exchange buffers per row
+        // plus the pass table and (real-data rows) the two-level zeta_m2 table
+        if (A.r_lds + (size_t)(pass_tab_len(d.m2) + 128) * b > device_lds_max())
             return fail(HDC_ERR_UNSUPPORTED, "row stage m2 = %lld needs %zu bytes of LDS", (long long)d.m2, A.r_lds);
     }
     // with many independent rows (the innermost axis of an N-D problem) one

@@ -127,6 +127,17 @@ hipError_t launch_natural(bool dbl, const void* F, void* out, int64_t Dg, int64_
 // Slots of a contiguous n-point LDS buffer (one pad slot per 8 values).
 inline int64_t padded_len(int64_t n) { return n + (n >> 3); }
 
+// Entries of the per-pass twiddle table of an n-point row transform (radix R0
+// first, then radix 8 at Ns = R0, 8 R0, ...: three arrays of Ns values each).
+inline int64_t pass_tab_len(int64_t n) {
+    int lg = 0;
+    while ((int64_t(1) << lg) < n) ++lg;
+    if (n < 8) return 0;
+    const int r0 = lg % 3 == 0 ? 8 : (1 << (lg % 3));
+    const int np = lg % 3 == 0 ? lg / 3 : lg / 3 + 1;
+    return np > 1 ? 3 * (int64_t)r0 * ((int64_t(1) << (3 * (np - 1))) - 1) / 7 : 0;
+}
+
 // Points per thread of the Stockham transforms for size n.
 inline int ppt_for(int n) { return n >= 8 ? 8 : n; }
 

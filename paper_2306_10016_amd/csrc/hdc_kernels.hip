@@ -138,13 +138,32 @@ __device__ __forceinline__ void dft_r(cplx<T>* x) {
     }
 }
 
-// LDS address of transform position `pos`.  Contiguous layouts (PAD) insert
-// one slot after every 8 values, which keeps the stride-R writes of the first
-// pass and the stride-Ns writes of later passes on distinct banks; column
-// layouts (tile columns side by side) are already conflict-free.
-template <bool PAD>
+// LDS layouts of a transform's exchange buffer.  LAY_COL: tile columns side
+// by side (position pos of column cc at pos * tile + cc), conflict-free as it
+// is.  LAY_PAD: contiguous with one pad slot after every 8 values (the fused
+// kernels, whose address arithmetic then folds into instruction offsets).
+// LAY_XOR: contiguous, positions permuted inside aligned blocks of 16
+// (complex128) or 32 (complex64) values by an XOR of the low bits with
+// higher bits, chosen so that the stride-8 writes of the first pass, the
+// blocked writes of the later passes and the unit-stride reloads each put the
+// lanes that the LDS serves together on distinct banks, whether it serves 128
+// or 256 bytes per clock (the row kernels).
+enum { LAY_COL = 0, LAY_PAD = 1, LAY_XOR = 2 };
+
+template <int LAY, typename T, int NSZ>
 __device__ __forceinline__ int lds_at(int pos, int bstride) {
-    return PAD ? pos + (pos >> 3) : pos * bstride;
+    constexpr int c = ilog2c(NSZ) % 3;  // the first pass is radix 8, 2 or 4 for c = 0, 1, 2
+    if constexpr (LAY == LAY_COL) {
+        return pos * bstride;
+    } else if constexpr (LAY == LAY_PAD) {
+        return pos + (pos >> 3);
+    } else if constexpr (sizeof(T) == 8) {  // 16-byte values
+        return pos ^ (((pos >> 3) ^ (pos >> (c == 1 ? 4 : 5))) & 15);
+    } else if constexpr (c == 1) {  // 8-byte values
+        return pos ^ (((pos >> 3) ^ (pos >> 4) ^ (pos >> 5)) & 31);
+    } else {
+        return pos ^ (((pos >> 3) ^ (pos >> (c == 0 ? 7 : 4))) & 31);
+    }
 }
 
 // Padded length of a contiguous n-point LDS buffer.
@@ -161,7 +180,58 @@ struct TwLds {
     int mask;
     int lg;
     __device__ __forceinline__ cplx<T> operator[](int e) const { return lo[e & mask] * hi[e >> lg]; }
+    // the twiddles zeta^{e1}, zeta^{2 e1}, zeta^{4 e1} of a radix-8 pass
+    __device__ __forceinline__ void get3(int, int, int e1, cplx<T>& w1, cplx<T>& w2, cplx<T>& w4) const {
+        w1 = (*this)[e1];
+        w2 = (*this)[2 * e1];
+        w4 = (*this)[4 * e1];
+    }
 };
+
+// Per-pass twiddle tables in LDS for transforms whose lanes run along the
+// transform (rows): the radix-8 pass over sub-transforms of length Ns needs
+// zeta_{8 Ns}^{i k}, i = 1, 2, 4, at k = position mod Ns.  Stored as three
+// arrays of Ns values per pass, lanes with consecutive k read consecutive
+// 16-byte slots, so the reads are free of bank conflicts (the two-level table
+// is read at strides of up to 8 slots there) and need no product.  Passes
+// follow the first one (radix R0, Ns = 1, no twiddles): Ns = R0 8^j.
+template <int NSZ>
+struct PassTab {
+    static constexpr int R0 = FP<NSZ>::R0;
+    static constexpr int NP = FP<NSZ>::NPASS;
+    // entries: 3 * (R0 + 8 R0 + ... + 8^(NP-2) R0)
+    static constexpr int LEN = NP > 1 ? 3 * R0 * ((1 << (3 * (NP - 1))) - 1) / 7 : 0;
+};
+
+template <typename T>
+struct TwPass {
+    const cplx<T>* t;
+    int r0;
+    __device__ __forceinline__ void get3(int Ns, int k, int, cplx<T>& w1, cplx<T>& w2, cplx<T>& w4) const {
+        const cplx<T>* p = t + 3 * (Ns - r0) / 7;
+        w1 = p[k];
+        w2 = p[Ns + k];
+        w4 = p[2 * Ns + k];
+    }
+};
+
+// Fill a PassTab<NSZ> table from the global zeta_NSZ^e table twg (e < NSZ).
+template <typename T, int NSZ>
+__device__ __forceinline__ void fill_pass_tab(cplx<T>* t, const cplx<T>* twg, int tid, int nth) {
+    using PT = PassTab<NSZ>;
+    for (int e = tid; e < PT::LEN; e += nth) {
+        // locate (pass, i, k) of entry e
+        int Ns = PT::R0, off = 0;
+        while (e >= off + 3 * Ns) {
+            off += 3 * Ns;
+            Ns *= 8;
+        }
+        const int r = e - off;
+        const int i = r / Ns;
+        const int k = r - i * Ns;
+        t[e] = twg[(k << i) * (NSZ / (8 * Ns))];
+    }
+}
 
 template <int NSZ>
 struct TwSplit {
@@ -172,9 +242,9 @@ struct TwSplit {
 
 // One radix-R pass over sub-transforms of length Ns -> Ns*R.  Register v[w]
 // holds position lane + w*TPF.  Non-final passes write to LDS; the final
-// pass leaves its outputs in v.  Twiddles zeta^{i k} come from three table
-// loads (i = 1, 2, 4) and four products.
-template <typename T, int NSZ, int R, int SIGN, bool LAST, bool PAD, int PPTW = (NSZ >= 8 ? 8 : NSZ), class TW>
+// pass leaves its outputs in v.  Twiddles zeta^{i k}: i = 1, 2, 4 from the
+// table `tw`, the other four as products.
+template <typename T, int NSZ, int R, int SIGN, bool LAST, int PAD, int PPTW = (NSZ >= 8 ? 8 : NSZ), class TW>
 __device__ __forceinline__ void stock_pass(cplx<T> (&v)[PPTW], int Ns, cplx<T>* buf, int bstride, int lane,
                                            const TW& tw, bool act) {
     constexpr int PPT = PPTW;
@@ -187,23 +257,20 @@ __device__ __forceinline__ void stock_pass(cplx<T> (&v)[PPTW], int Ns, cplx<T>* 
         cplx<T> x[R];
 #pragma unroll
         for (int i = 0; i < R; ++i) x[i] = v[u + i * NB];
-        if (Ns > 1) {
+        // only the radix-8 passes after the first (Ns > 1) carry twiddles
+        if (R == 8 && Ns > 1) {
             const int e1 = k * (NSZ / (Ns * R));
             cplx<T> w[8];
-            w[1] = tw[e1];
-            if (SIGN < 0) w[1].y = -w[1].y;
-            if constexpr (R >= 4) {
-                w[2] = tw[2 * e1];
-                if (SIGN < 0) w[2].y = -w[2].y;
-                w[3] = w[1] * w[2];
+            tw.get3(Ns, k, e1, w[1], w[2], w[4]);
+            if (SIGN < 0) {
+                w[1].y = -w[1].y;
+                w[2].y = -w[2].y;
+                w[4].y = -w[4].y;
             }
-            if constexpr (R == 8) {
-                w[4] = tw[4 * e1];
-                if (SIGN < 0) w[4].y = -w[4].y;
-                w[5] = w[1] * w[4];
-                w[6] = w[2] * w[4];
-                w[7] = w[3] * w[4];
-            }
+            w[3] = w[1] * w[2];
+            w[5] = w[1] * w[4];
+            w[6] = w[2] * w[4];
+            w[7] = w[3] * w[4];
 #pragma unroll
             for (int i = 1; i < R; ++i) x[i] = x[i] * w[i];
         }
@@ -215,13 +282,13 @@ __device__ __forceinline__ void stock_pass(cplx<T> (&v)[PPTW], int Ns, cplx<T>* 
             if (act) {
                 const int base = (j - k) * R + k;
 #pragma unroll
-                for (int a = 0; a < R; ++a) buf[lds_at<PAD>(base + a * Ns, bstride)] = x[a];
+                for (int a = 0; a < R; ++a) buf[lds_at<PAD, T, NSZ>(base + a * Ns, bstride)] = x[a];
             }
         }
     }
 }
 
-template <typename T, int NSZ, bool PAD, int PPTW = (NSZ >= 8 ? 8 : NSZ)>
+template <typename T, int NSZ, int PAD, int PPTW = (NSZ >= 8 ? 8 : NSZ)>
 __device__ __forceinline__ void lds_reload(cplx<T> (&v)[PPTW], const cplx<T>* buf, int bstride, int lane,
                                            bool act) {
     constexpr int PPT = PPTW;
@@ -229,14 +296,14 @@ __device__ __forceinline__ void lds_reload(cplx<T> (&v)[PPTW], const cplx<T>* bu
     __syncthreads();
     if (act) {
 #pragma unroll
-        for (int w = 0; w < PPT; ++w) v[w] = buf[lds_at<PAD>(lane + w * Q, bstride)];
+        for (int w = 0; w < PPT; ++w) v[w] = buf[lds_at<PAD, T, NSZ>(lane + w * Q, bstride)];
     }
     __syncthreads();
 }
 
 // NSZ-point DFT with zeta_NSZ^{SIGN}, registers in and out (positions lane + w*TPF).
 // Every thread of the workgroup must call it (it contains barriers).
-template <typename T, int NSZ, int SIGN, bool PAD, int PPTW = (NSZ >= 8 ? 8 : NSZ), class TW>
+template <typename T, int NSZ, int SIGN, int PAD, int PPTW = (NSZ >= 8 ? 8 : NSZ), class TW>
 __device__ __forceinline__ void fft_regs(cplx<T> (&v)[PPTW], cplx<T>* buf, int bstride, int lane, const TW& tw,
                                          bool act) {
     using P = FP<NSZ, PPTW>;
@@ -253,6 +320,41 @@ __device__ __forceinline__ void fft_regs(cplx<T> (&v)[PPTW], cplx<T>* buf, int b
         }
         lds_reload<T, NSZ, PAD, PPTW>(v, buf, bstride, lane, act);
         stock_pass<T, NSZ, 8, SIGN, true, PAD, PPTW>(v, Ns, buf, bstride, lane, tw, act);
+    }
+}
+
+// The same transform for contiguous rows with two exchange buffers used in
+// turn (ping-pong): exchange n writes buf[ph], waits at one barrier and reads
+// it back, and the next exchange writes the other buffer, so no second
+// barrier is needed before the writes (the one barrier in between orders every
+// read of a buffer before its next write).  `ph` carries the turn across
+// consecutive transforms that share the buffers.
+template <typename T, int NSZ, int SIGN, class TW>
+__device__ __forceinline__ void fft_rows_pp(cplx<T> (&v)[FP<NSZ>::PPT], cplx<T>* buf0, cplx<T>* buf1, int& ph,
+                                            int lane, const TW& tw, bool act) {
+    using P = FP<NSZ>;
+    constexpr int PPT = P::PPT;
+    constexpr int Q = NSZ / PPT;
+    if constexpr (P::NPASS == 1) {
+        stock_pass<T, NSZ, P::R0, SIGN, true, LAY_XOR>(v, 1, buf0, 1, lane, tw, act);
+    } else if constexpr (P::NPASS > 1) {
+        int Ns = 1;
+#pragma unroll
+        for (int ps = 0; ps < P::NPASS - 1; ++ps) {
+            cplx<T>* buf = ph ? buf1 : buf0;
+            if (ps == 0)
+                stock_pass<T, NSZ, P::R0, SIGN, false, LAY_XOR>(v, 1, buf, 1, lane, tw, act);
+            else
+                stock_pass<T, NSZ, 8, SIGN, false, LAY_XOR>(v, Ns, buf, 1, lane, tw, act);
+            Ns = ps == 0 ? P::R0 : Ns * 8;
+            __syncthreads();
+            if (act) {
+#pragma unroll
+                for (int w = 0; w < PPT; ++w) v[w] = buf[lds_at<LAY_XOR, T, NSZ>(lane + w * Q, 1)];
+            }
+            ph ^= 1;
+        }
+        stock_pass<T, NSZ, 8, SIGN, true, LAY_XOR>(v, Ns, buf0, 1, lane, tw, act);
     }
 }
 
@@ -374,22 +476,22 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
                 z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
             }
         }
-        fft_regs<T, MSZ, +1, true>(F, buf, 1, lane, twm, act);
+        fft_regs<T, MSZ, +1, LAY_PAD>(F, buf, 1, lane, twm, act);
         if (!a.same) {
-            fft_regs<T, MSZ, +1, true>(G, buf, 1, lane, twm, act);
+            fft_regs<T, MSZ, +1, LAY_PAD>(G, buf, 1, lane, twm, act);
 #pragma unroll
             for (int v = 0; v < PPT; ++v) F[v] = F[v] * G[v];
         } else {
 #pragma unroll
             for (int v = 0; v < PPT; ++v) F[v] = F[v] * F[v];
         }
-        fft_regs<T, MSZ, -1, true>(F, buf, 1, lane, twm, act);
+        fft_regs<T, MSZ, -1, LAY_PAD>(F, buf, 1, lane, twm, act);
         if (act) {
             double2 z = z0;
 #pragma unroll
             for (int v = 0; v < PPT; ++v) {
                 const int s = lane + v * TPF;
-                buf[lds_at<true>(s, 1)] = scale(mul_tw<true>(F[v], z, a.hiprec), invN);
+                buf[lds_at<LAY_PAD, T, MSZ>(s, 1)] = scale(mul_tw<true>(F[v], z, a.hiprec), invN);
                 z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
             }
         }
@@ -403,7 +505,7 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
         cplx<T> acc = mk<T>(0, 0);
         int e = 0;  // (t r) mod q
         for (int r = 0; r < a.q; ++r) {
-            acc = acc + mul_tw<true>(U[(size_t)r * RS + lds_at<true>(s, 1)], twq[e], false);
+            acc = acc + mul_tw<true>(U[(size_t)r * RS + lds_at<LAY_PAD, T, MSZ>(s, 1)], twq[e], false);
             e += t;
             if (e >= a.q) e -= a.q;
         }
@@ -429,18 +531,12 @@ __global__ void __launch_bounds__(REAL ? 512 : 1024) k_col_fwd(ColFwdArgs a) {
     using P = FP<M1>;
     constexpr int PPT = P::PPT;
     constexpr int TPF = P::TPF;
-    using S = TwSplit<M1>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-    cplx<T>* tlo = lds + (size_t)M1 * a.tile;
-    cplx<T>* thi = tlo + S::LO;
-    {
-        const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.tw1);
-        for (int e = threadIdx.x; e < S::LO; e += blockDim.x) tlo[e] = twg[e];
-        for (int e = threadIdx.x; e < S::HI; e += blockDim.x) thi[e] = twg[e * S::LO];
-        __syncthreads();
-    }
-    const TwLds<T> tw1{tlo, thi, S::LO - 1, S::LG};
+    cplx<T>* tpt = lds + (size_t)M1 * a.tile;
+    fill_pass_tab<T, M1>(tpt, reinterpret_cast<const cplx<T>*>(a.tw1), threadIdx.x, blockDim.x);
+    __syncthreads();
+    const TwPass<T> tw1{tpt, PassTab<M1>::R0};
 
     // task = (tile, residue) with the residue fastest: the Dg residues of a
     // tile run back to back on one XCD and re-read its input from that L2
@@ -508,7 +604,7 @@ __global__ void __launch_bounds__(REAL ? 512 : 1024) k_col_fwd(ColFwdArgs a) {
                 z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
             }
         }
-        fft_regs<T, M1, +1, false>(w, lds + cc, tile, lane, tw1, true);
+        fft_regs<T, M1, +1, LAY_COL>(w, lds + cc, tile, lane, tw1, true);
         if (a.m2 > 1 && s2 != 0) {
             // four-step twiddle zeta_m^{l1 s2}, l1 = lane + v TPF: z0 zs^v
             double2 z = tw_n(a.tw, (uint32_t)lane * (uint32_t)s2 * (uint32_t)a.q);
@@ -535,20 +631,14 @@ __global__ void __launch_bounds__(REAL ? 512 : 1024) k_col_fwd(ColFwdArgs a) {
 template <typename T, int M1, int DMAX, bool REAL = false>
 __global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
     using P = FP<M1>;
-    using S = TwSplit<M1>;
     constexpr int PPT = P::PPT;
     constexpr int TPF = P::TPF;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-    cplx<T>* tlo = lds + (size_t)M1 * a.tile;
-    cplx<T>* thi = tlo + S::LO;
-    {
-        const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.tw1);
-        for (int e = threadIdx.x; e < S::LO; e += blockDim.x) tlo[e] = twg[e];
-        for (int e = threadIdx.x; e < S::HI; e += blockDim.x) thi[e] = twg[e * S::LO];
-        __syncthreads();
-    }
-    const TwLds<T> tw1{tlo, thi, S::LO - 1, S::LG};
+    cplx<T>* tpt = lds + (size_t)M1 * a.tile;
+    fill_pass_tab<T, M1>(tpt, reinterpret_cast<const cplx<T>*>(a.tw1), threadIdx.x, blockDim.x);
+    __syncthreads();
+    const TwPass<T> tw1{tpt, PassTab<M1>::R0};
 
     const int tl = xcd_task(blockIdx.x, gridDim.x);
     if (tl >= a.ntiles) return;
@@ -596,7 +686,7 @@ __global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
                         z = make_double2(z.x * fzs.x - z.y * fzs.y, z.x * fzs.y + z.y * fzs.x);
                     }
                 }
-                fft_regs<T, M1, -1, false>(w, lds + cc, tile, lane, tw1, true);
+                fft_regs<T, M1, -1, LAY_COL>(w, lds + cc, tile, lane, tw1, true);
                 const int r = a.r0 + d;
                 // conj(zeta_N^{r s}), s = (lane + v TPF) m2 + s2, as z0 zs^v
                 const uint32_t N = (uint32_t)a.N;
@@ -710,23 +800,22 @@ __device__ __forceinline__ void raw_row(const RowArgs& a, int64_t row, bool ok, 
 template <typename T, int MSZ, int MODE, bool TWO, bool FRAW>
 __global__ void __launch_bounds__(512) k_row(RowArgs a) {
     using P = FP<MSZ>;
-    using S = TwSplit<MSZ>;
     constexpr int PPT = P::PPT;
     constexpr int TPF = P::TPF;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* smem = reinterpret_cast<cplx<T>*>(smem_raw);
-    cplx<T>* tlo = smem + (size_t)a.rpw * padded(MSZ);
-    cplx<T>* thi = tlo + S::LO;
+    cplx<T>* tpt = smem + (size_t)a.rpw * 2 * MSZ;
     const int tid = threadIdx.x;
-    const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.tw);
-    for (int e = tid; e < S::LO; e += blockDim.x) tlo[e] = twg[e];
-    for (int e = tid; e < S::HI; e += blockDim.x) thi[e] = twg[e * S::LO];
+    fill_pass_tab<T, MSZ>(tpt, reinterpret_cast<const cplx<T>*>(a.tw), tid, blockDim.x);
     __syncthreads();
-    const TwLds<T> tw{tlo, thi, S::LO - 1, S::LG};
+    const TwPass<T> tw{tpt, PassTab<MSZ>::R0};
 
     const int rloc = tid / TPF;
     const int lane = tid - rloc * TPF;
-    cplx<T>* buf = smem + (size_t)rloc * padded(MSZ);
+    // two exchange buffers per row, used in turn
+    cplx<T>* buf0 = smem + (size_t)rloc * 2 * MSZ;
+    cplx<T>* buf1 = buf0 + MSZ;
+    int ph = 0;
     const int64_t es = a.addr.es;
     const int64_t stride = (int64_t)gridDim.x * a.rpw;
     constexpr bool conv = MODE == MODE_CONV;
@@ -762,23 +851,23 @@ __global__ void __launch_bounds__(512) k_row(RowArgs a) {
         if constexpr (MODE == MODE_INV) {
 #pragma unroll
             for (int w = 0; w < PPT; ++w) pv[w] = nok ? Ag[nrb + (int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
-            fft_regs<T, MSZ, -1, true>(v, buf, 1, lane, tw, ok);
+            fft_rows_pp<T, MSZ, -1>(v, buf0, buf1, ph, lane, tw, ok);
         } else {
-            fft_regs<T, MSZ, +1, true>(v, buf, 1, lane, tw, ok);
+            fft_rows_pp<T, MSZ, +1>(v, buf0, buf1, ph, lane, tw, ok);
             if constexpr (!FRAW) {
 #pragma unroll
                 for (int w = 0; w < PPT; ++w) pv[w] = nok ? Ag[nrb + (int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
             }
             if constexpr (conv) {
                 if constexpr (two) {
-                    fft_regs<T, MSZ, +1, true>(u, buf, 1, lane, tw, ok);
+                    fft_rows_pp<T, MSZ, +1>(u, buf0, buf1, ph, lane, tw, ok);
 #pragma unroll
                     for (int w = 0; w < PPT; ++w) v[w] = v[w] * u[w];
                 } else {
 #pragma unroll
                     for (int w = 0; w < PPT; ++w) v[w] = v[w] * v[w];
                 }
-                fft_regs<T, MSZ, -1, true>(v, buf, 1, lane, tw, ok);
+                fft_rows_pp<T, MSZ, -1>(v, buf0, buf1, ph, lane, tw, ok);
             }
         }
         if (ok) {
@@ -843,17 +932,22 @@ __global__ void __launch_bounds__(512) k_row_real(RowArgs a) {
     constexpr int TPF = P::TPF;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* smem = reinterpret_cast<cplx<T>*>(smem_raw);
-    cplx<T>* tlo = smem + (size_t)a.rpw * padded(MSZ);
+    cplx<T>* tlo = smem + (size_t)a.rpw * 2 * MSZ;
     cplx<T>* thi = tlo + S::LO;
+    cplx<T>* tpt = thi + S::HI;
     const int tid = threadIdx.x;
     const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.tw);
     for (int e = tid; e < S::LO; e += blockDim.x) tlo[e] = twg[e];
     for (int e = tid; e < S::HI; e += blockDim.x) thi[e] = twg[e * S::LO];
+    fill_pass_tab<T, MSZ>(tpt, twg, tid, blockDim.x);
     __syncthreads();
-    const TwLds<T> tw{tlo, thi, S::LO - 1, S::LG};
+    const TwLds<T> twl{tlo, thi, S::LO - 1, S::LG};  // zeta_m2^s for the partner rows
+    const TwPass<T> tw{tpt, PassTab<MSZ>::R0};
     const int rloc = tid / TPF;
     const int lane = tid - rloc * TPF;
-    cplx<T>* buf = smem + (size_t)rloc * padded(MSZ);
+    cplx<T>* buf0 = smem + (size_t)rloc * 2 * MSZ;  // two exchange buffers, used in turn
+    cplx<T>* buf1 = buf0 + MSZ;
+    int ph = 0;
     const int64_t es = a.addr.es;
     const int64_t stride = (int64_t)gridDim.x * a.rpw;
     const cplx<T>* Z = reinterpret_cast<const cplx<T>*>(a.a);
@@ -871,14 +965,14 @@ __global__ void __launch_bounds__(512) k_row_real(RowArgs a) {
             v[w] = ok ? Z[ab + (int64_t)s * es] : mk<T>(0, 0);
             cplx<T> x = ok ? Z[pb + (int64_t)s * es] : mk<T>(0, 0);
             x.y = -x.y;
-            u[w] = rev ? x * tw[s] : x;
+            u[w] = rev ? x * twl[s] : x;
         }
-        fft_regs<T, MSZ, +1, true>(v, buf, 1, lane, tw, ok);
-        fft_regs<T, MSZ, +1, true>(u, buf, 1, lane, tw, ok);
+        fft_rows_pp<T, MSZ, +1>(v, buf0, buf1, ph, lane, tw, ok);
+        fft_rows_pp<T, MSZ, +1>(u, buf0, buf1, ph, lane, tw, ok);
         // H = (Z^2 - W^2) / (4i), W = conj Z_{N-k}
 #pragma unroll
         for (int w = 0; w < PPT; ++w) v[w] = scale(mul_i<-1>(v[w] * v[w] - u[w] * u[w]), (T)0.25);
-        fft_regs<T, MSZ, -1, true>(v, buf, 1, lane, tw, ok);
+        fft_rows_pp<T, MSZ, -1>(v, buf0, buf1, ph, lane, tw, ok);
         if (ok) {
 #pragma unroll
             for (int w = 0; w < PPT; ++w) Og[ob + (int64_t)(lane + w * TPF) * es] = v[w];
@@ -961,10 +1055,10 @@ __global__ void __launch_bounds__(512) k_fused_real(FusedArgs a) {
                 z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
             }
         }
-        fft_regs<T, MSZ, +1, true>(Zr, buf, 1, lane, twm, act);
+        fft_regs<T, MSZ, +1, LAY_PAD>(Zr, buf, 1, lane, twm, act);
         if (act) {
 #pragma unroll
-            for (int v = 0; v < PPT; ++v) buf[lds_at<true>(lane + v * TPF, 1)] = Zr[v];
+            for (int v = 0; v < PPT; ++v) buf[lds_at<LAY_PAD, T, MSZ>(lane + v * TPF, 1)] = Zr[v];
         }
         __syncthreads();
     }
@@ -980,19 +1074,19 @@ __global__ void __launch_bounds__(512) k_fused_real(FusedArgs a) {
         for (int v = 0; v < PPT; ++v) {
             const int l = lane + v * TPF;
             const int lp = ru == 0 ? (l == 0 ? 0 : MSZ - l) : MSZ - 1 - l;
-            const cplx<T> z = act ? buf[lds_at<true>(l, 1)] : mk<T>(0, 0);
-            cplx<T> w = act ? pbuf[lds_at<true>(lp, 1)] : mk<T>(0, 0);
+            const cplx<T> z = act ? buf[lds_at<LAY_PAD, T, MSZ>(l, 1)] : mk<T>(0, 0);
+            cplx<T> w = act ? pbuf[lds_at<LAY_PAD, T, MSZ>(lp, 1)] : mk<T>(0, 0);
             w.y = -w.y;
             Hr[v] = scale(mul_i<-1>(z * z - w * w), (T)0.25);
         }
         __syncthreads();  // every partner read before the transforms reuse the buffers
-        fft_regs<T, MSZ, -1, true>(Hr, buf, 1, lane, twm, act);
+        fft_regs<T, MSZ, -1, LAY_PAD>(Hr, buf, 1, lane, twm, act);
         if (act) {
             double2 z = tw_n(a.tw, (uint32_t)ru * (uint32_t)lane);
             const double2 zs = tw_n(a.tw, (uint32_t)ru * (uint32_t)TPF);
 #pragma unroll
             for (int v = 0; v < PPT; ++v) {
-                buf[lds_at<true>(lane + v * TPF, 1)] = scale(mul_tw<true>(Hr[v], z, a.hiprec), invN);
+                buf[lds_at<LAY_PAD, T, MSZ>(lane + v * TPF, 1)] = scale(mul_tw<true>(Hr[v], z, a.hiprec), invN);
                 z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
             }
         }
@@ -1007,7 +1101,7 @@ __global__ void __launch_bounds__(512) k_fused_real(FusedArgs a) {
         int e = 0;
         for (int r = 0; r < qh; ++r) {
             const T wgt = (r == 0 || 2 * r == q) ? (T)1 : (T)2;
-            acc += wgt * mul_tw<true>(U[(size_t)r * RS + lds_at<true>(s2, 1)], twq[e], false).x;
+            acc += wgt * mul_tw<true>(U[(size_t)r * RS + lds_at<LAY_PAD, T, MSZ>(s2, 1)], twq[e], false).x;
             e += t;
             if (e >= q) e -= q;
         }
@@ -1073,7 +1167,7 @@ hipError_t fused_t(const FusedArgs& a, int threads, int64_t blocks, size_t lds, 
 
 template <typename T, int M1, bool REAL>
 hipError_t colf_r(const ColFwdArgs& a, int threads, int64_t gx, int64_t gy, size_t lds, hipStream_t s) {
-    lds += (size_t)(TwSplit<M1>::LO + TwSplit<M1>::HI) * sizeof(cplx<T>);
+    lds += (size_t)PassTab<M1>::LEN * sizeof(cplx<T>);
     hipError_t e = allow_lds(k_col_fwd<T, M1, REAL>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_col_fwd<T, M1, REAL>), dim3((unsigned)gx, (unsigned)gy), dim3(threads), lds, s, a);
@@ -1088,7 +1182,7 @@ hipError_t colf_t(const ColFwdArgs& a, int threads, int64_t gx, int64_t gy, size
 template <typename T, int M1, bool REAL>
 hipError_t colb_r(const ColBwdArgs& a, int threads, int64_t gx, int64_t gy, size_t lds, hipStream_t s) {
     constexpr int DMAX = sizeof(T) == 8 ? 2 : 4;
-    lds += (size_t)(TwSplit<M1>::LO + TwSplit<M1>::HI) * sizeof(cplx<T>);
+    lds += (size_t)PassTab<M1>::LEN * sizeof(cplx<T>);
     hipError_t e = allow_lds(k_col_bwd<T, M1, DMAX, REAL>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_col_bwd<T, M1, DMAX, REAL>), dim3((unsigned)gx, (unsigned)gy), dim3(threads), lds, s, a);
@@ -1102,7 +1196,7 @@ hipError_t colb_t(const ColBwdArgs& a, int threads, int64_t gx, int64_t gy, size
 
 template <typename T, int MSZ>
 hipError_t row_real_t(const RowArgs& a, int threads, int64_t blocks, size_t lds, hipStream_t s) {
-    lds += (size_t)(TwSplit<MSZ>::LO + TwSplit<MSZ>::HI) * sizeof(cplx<T>);
+    lds += (size_t)(TwSplit<MSZ>::LO + TwSplit<MSZ>::HI + PassTab<MSZ>::LEN) * sizeof(cplx<T>);
     auto kern = k_row_real<T, MSZ>;
     hipError_t e = allow_lds(kern, lds);
     if (e != hipSuccess) return e;
@@ -1139,8 +1233,7 @@ hipError_t row_mode(const RowArgs& a, int threads, int64_t blocks, size_t lds, h
 
 template <typename T, int MSZ>
 hipError_t row_t(const RowArgs& a, int threads, int64_t blocks, size_t lds, hipStream_t s) {
-    using S = TwSplit<MSZ>;
-    lds += (size_t)(S::LO + S::HI) * sizeof(cplx<T>);
+    lds += (size_t)PassTab<MSZ>::LEN * sizeof(cplx<T>);
     switch (a.mode) {
         case MODE_FWD: return row_mode<T, MSZ, MODE_FWD, false>(a, threads, blocks, lds, s);
         case MODE_INV: return row_mode<T, MSZ, MODE_INV, false>(a, threads, blocks, lds, s);

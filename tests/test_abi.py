@@ -187,3 +187,15 @@ def test_real_dtype_rules():
     with pytest.raises(hdc.HdcError) as e:
         hdc.uneq_derive(12, 1000, 1011, dtype="r32")
     assert e.value.status == 2
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_largest_1d_geometry_fits_lds(dtype):
+    """Every kernel geometry of the largest 1D plans (column stage 1024, row stage
+    4096, their twiddle tables) fits the LDS of a gfx950 workgroup."""
+    for L in (1 << 22, 1 << 21, 3 ** 13):
+        for m in (1 << 22, 1 << 21, 1 << 20, 4096):
+            if m * 2 < L:
+                continue
+            ax = hdc.check_nd([L], [2 * L - 1], [m], dtype=dtype)[0]
+            assert ax["m1"] * ax["m2"] == m
