@@ -563,9 +563,12 @@ hdc_status run_col_fwd(const AxisPlan& A, const void* x, void* X, int64_t B, int
     a.lam = (int32_t)lam;
     a.rstride = (int32_t)rstride;
     const bool real = x2 != nullptr;
-    // the real-input kernel runs at most 512 threads: half the tile when wider
-    const int tdiv = (real && A.cf_threads > 512) ? 2 : 1;
-    a.tile = std::max(1, A.cf_tile / tdiv);
+    // the real-input kernel gives each thread 16 points (m1 >= 16) and runs at
+    // most 512 threads: at most 8 columns per tile for m1 = 1024
+    const int64_t tpf = real && A.d.m1 >= 16 ? A.d.m1 / 16 : A.d.m1 / ppt_for((int)A.d.m1);
+    int rtile = A.cf_tile;
+    while (real && rtile > 1 && rtile * tpf > 512) rtile /= 2;
+    a.tile = rtile;
     a.ntiles = (int32_t)ceil_div(a.Ccols, a.tile);
     a.hiprec = A.hiprec ? 1 : 0;
     a.tw = A.tw;
@@ -582,7 +585,7 @@ hdc_status run_col_fwd(const AxisPlan& A, const void* x, void* X, int64_t B, int
         else c.x = (const char*)x + (size_t)(b0 * in_bs) * esz;
         if (real) c.x2 = (const char*)x2 + (size_t)(b0 * in_bs) * esz;
         c.X = (char*)X + (size_t)(b0 * out_bs) * (A.dbl ? 16 : 8);
-        hipError_t e = launch_col_fwd(A.dbl, (int)A.d.m1, c, a.tile * (A.cf_threads / A.cf_tile), gx, c.B,
+        hipError_t e = launch_col_fwd(A.dbl, (int)A.d.m1, c, (int)(a.tile * tpf), gx, c.B,
                                       A.cf_lds / A.cf_tile * a.tile, s, real);
         if (e != hipSuccess) return hip_fail(e, "column forward launch");
     }
@@ -887,10 +890,18 @@ hdc_status run_fused_real(const AxisPlan& A, const void* f, const void* g, void*
 }
 
 // Product rows of the group at r0: Z has S = Dg + npart slots per batch, the
-// output Dg slots; row ((b Dg + d) m1 + l1) C1 + c1.
+// output Dg slots; row ((b Dg + d) m1 + l1) C1 + c1.  The residues 0 and q/2
+// pair rows of their own (one work item gives rows l1 and its mirror), so the
+// launch covers m1/2 + 1 (residue 0) and m1/2 (q/2) items for them, m1 for the
+// others (one item each when m1 = 1).
 hdc_status run_rows_real(const AxisPlan& A, const void* Z, void* O, int64_t B, int64_t C1, int64_t r0,
                          const RealGroup& g, hipStream_t s) {
-    const int64_t nrows = B * g.Dg * A.d.m1 * C1;
+    const int64_t m1 = A.d.m1, q = A.d.q;
+    const int64_t n0 = m1 == 1 ? 1 : m1 / 2 + 1, nh = m1 == 1 ? 1 : m1 / 2;
+    const bool has0 = r0 == 0;
+    const bool hash = q % 2 == 0 && r0 + g.Dg - 1 == q / 2 && q / 2 != 0;
+    const int64_t W = g.Dg * m1 - (has0 ? m1 - n0 : 0) - (hash ? m1 - nh : 0);
+    const int64_t nrows = B * W * C1;
     if (nrows <= 0) return HDC_OK;
     RowArgs a{};
     a.a = Z;
@@ -911,8 +922,12 @@ hdc_status run_rows_real(const AxisPlan& A, const void* Z, void* O, int64_t B, i
     a.pfirst = (int32_t)g.pfirst;
     const int64_t blocks = ceil_div(nrows, A.r_rpw);
     if (blocks > 0x7fffffff) return fail(HDC_ERR_UNSUPPORTED, "too many rows");
+    // algorithmic bytes: a self-paired residue reads and writes each of its m1
+    // rows once, any other reads its rows and its partner's and writes its own
     const double eb = A.dbl ? 16.0 : 8.0;
-    LaunchScope ls(s, 2, eb * 3.0 * (double)nrows * (double)A.d.m2);
+    const int64_t nself = (has0 ? 1 : 0) + (hash ? 1 : 0);
+    const double rows_rw = (double)(2 * nself + 3 * (g.Dg - nself)) * (double)(m1 * C1 * B);
+    LaunchScope ls(s, 2, eb * rows_rw * (double)A.d.m2);
     hipError_t e = launch_row_real(A.dbl, (int)A.d.m2, a, A.r_threads, blocks, A.r_lds, s);
     if (e != hipSuccess) return hip_fail(e, "real row launch");
     return HDC_OK;

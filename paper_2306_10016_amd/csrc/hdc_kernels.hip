@@ -524,11 +524,17 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
 
 // REAL: the input is two real arrays x (f) and x2 (g), transformed together as
 // z = f + i g (the real case, whose product stage pairs residue r with q - r).
-// (the real variant holds two input pointers and runs at most 512 threads, so
-// that its registers fit without spilling)
+// (the real variant reads two arrays of half-size values: its threads own 16
+// points each, so that 8 columns, 64-byte segments of each array, take at most
+// 512 threads and the registers fit without spilling)
+template <int M1, bool REAL>
+constexpr int colf_ppt() {
+    return (REAL && M1 >= 16) ? 16 : (M1 >= 8 ? 8 : M1);
+}
+
 template <typename T, int M1, bool REAL = false>
 __global__ void __launch_bounds__(REAL ? 512 : 1024) k_col_fwd(ColFwdArgs a) {
-    using P = FP<M1>;
+    using P = FP<M1, colf_ppt<M1, REAL>()>;
     constexpr int PPT = P::PPT;
     constexpr int TPF = P::TPF;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -604,7 +610,7 @@ __global__ void __launch_bounds__(REAL ? 512 : 1024) k_col_fwd(ColFwdArgs a) {
                 z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
             }
         }
-        fft_regs<T, M1, +1, LAY_COL>(w, lds + cc, tile, lane, tw1, true);
+        fft_regs<T, M1, +1, LAY_COL, PPT>(w, lds + cc, tile, lane, tw1, true);
         if (a.m2 > 1 && s2 != 0) {
             // four-step twiddle zeta_m^{l1 s2}, l1 = lane + v TPF: z0 zs^v
             double2 z = tw_n(a.tw, (uint32_t)lane * (uint32_t)s2 * (uint32_t)a.q);
@@ -894,34 +900,64 @@ __global__ void __launch_bounds__(512) k_row(RowArgs a) {
 // arrives in the right registers without a permutation.  H is Hermitian too,
 // so only residues r <= q/2 are formed and inverted.
 
-// Rows of one product: the Z row, the partner Z row, whether the partner's
-// points run m2 - 1 - l2 (else -l2), and the output row.  Z holds S slots per
-// batch (slot d < Dg: residue r0 + d; slot Dg + i: residue q - (pfirst + i)).
-__device__ __forceinline__ void real_rows(const RowArgs& a, int64_t row, int64_t& ab, int64_t& pb, bool& rev,
-                                          int64_t& ob) {
+// Work items of a group's product rows.  A residue j other than 0 and q/2
+// pairs with residue q - j (stored in slot Dg + j - pfirst): each of its m1
+// rows is one item, its row l1 against the partner's row m1 - 1 - l1.  The
+// residues 0 and q/2 pair with themselves, row l1 with row l1' (m1 - l1 mod m1
+// for 0, m1 - 1 - l1 for q/2): H is Hermitian, so the inverse of row l1' is
+// zeta_m2^s conj(inverse of row l1) and one item (l1 < l1') gives both rows;
+// a row that is its own partner is an item of its own.  Per batch and copy
+// the items run residue 0 (m1/2 + 1 of them, or 1 when m1 = 1), the other
+// residues (m1 each), residue q/2 (m1/2, or 1), which is always last in its
+// group.  Z holds S slots per batch (slot d < Dg: residue r0 + d).
+struct RealItem {
+    int64_t ab, pb, ob, ob2;  // Z row, partner Z row, output row, mirrored output row (-1: none)
+    bool rev;                 // partner points run m2 - 1 - l2 (else -l2)
+};
+
+__device__ __forceinline__ RealItem real_item(const RowArgs& a, int64_t item) {
     const int64_t C1 = a.addr.inner_cnt;
     const int64_t m1 = a.m1g;
-    const int64_t c1 = row % C1;
-    const int64_t t1 = row / C1;
-    const int64_t l1 = t1 % m1;
-    const int64_t t2 = t1 / m1;
-    const int64_t d = t2 % a.Dg;
-    const int64_t b = t2 / a.Dg;
+    const int64_t n0 = m1 == 1 ? 1 : m1 / 2 + 1;
+    const int64_t nh = m1 == 1 ? 1 : m1 / 2;
+    const bool has0 = a.r0 == 0;
+    const bool hash = (a.qg % 2 == 0) && (a.r0 + a.Dg - 1 == a.qg / 2) && a.qg / 2 != 0;
+    const int64_t W = a.Dg * m1 - (has0 ? m1 - n0 : 0) - (hash ? m1 - nh : 0);
+    const int64_t c1 = item % C1;
+    const int64_t t1 = item / C1;
+    const int64_t b = t1 / W;
+    int64_t t = t1 - b * W;
+    int64_t d, l1;
+    if (has0 && t < n0) {
+        d = 0;
+        l1 = t;
+    } else {
+        if (has0) t -= n0;
+        const int64_t d0 = has0 ? 1 : 0;
+        d = d0 + t / m1;
+        l1 = t - (d - d0) * m1;
+    }
     const int64_t j = a.r0 + d;
     int64_t ps, pl;
+    RealItem it;
+    bool self = false;
     if (j == 0) {
         ps = d;
         pl = l1 == 0 ? 0 : m1 - l1;
-        rev = l1 != 0;
+        it.rev = l1 != 0;
+        self = true;
     } else {
-        ps = (2 * j == a.qg) ? d : a.Dg + (j - a.pfirst);
+        self = 2 * j == a.qg;
+        ps = self ? d : a.Dg + (j - a.pfirst);
         pl = m1 - 1 - l1;
-        rev = true;
+        it.rev = true;
     }
     const int64_t os = a.addr.outer_stride;  // m2 C1
-    ab = ((b * a.S + d) * m1 + l1) * os + c1;
-    pb = ((b * a.S + ps) * m1 + pl) * os + c1;
-    ob = ((b * a.Dg + d) * m1 + l1) * os + c1;
+    it.ab = ((b * a.S + d) * m1 + l1) * os + c1;
+    it.pb = ((b * a.S + ps) * m1 + pl) * os + c1;
+    it.ob = ((b * a.Dg + d) * m1 + l1) * os + c1;
+    it.ob2 = (self && pl != l1) ? ((b * a.Dg + d) * m1 + pl) * os + c1 : -1;
+    return it;
 }
 
 template <typename T, int MSZ>
@@ -955,17 +991,15 @@ __global__ void __launch_bounds__(512) k_row_real(RowArgs a) {
     for (int64_t base = (int64_t)blockIdx.x * a.rpw; base < a.nrows; base += stride) {
         const int64_t row = base + rloc;
         const bool ok = row < a.nrows;
-        int64_t ab, pb, ob;
-        bool rev;
-        real_rows(a, ok ? row : 0, ab, pb, rev, ob);
+        const RealItem it = real_item(a, ok ? row : 0);
         cplx<T> v[PPT], u[PPT];
 #pragma unroll
         for (int w = 0; w < PPT; ++w) {
             const int s = lane + w * TPF;
-            v[w] = ok ? Z[ab + (int64_t)s * es] : mk<T>(0, 0);
-            cplx<T> x = ok ? Z[pb + (int64_t)s * es] : mk<T>(0, 0);
+            v[w] = ok ? Z[it.ab + (int64_t)s * es] : mk<T>(0, 0);
+            cplx<T> x = ok ? Z[it.pb + (int64_t)s * es] : mk<T>(0, 0);
             x.y = -x.y;
-            u[w] = rev ? x * twl[s] : x;
+            u[w] = it.rev ? x * twl[s] : x;
         }
         fft_rows_pp<T, MSZ, +1>(v, buf0, buf1, ph, lane, tw, ok);
         fft_rows_pp<T, MSZ, +1>(u, buf0, buf1, ph, lane, tw, ok);
@@ -975,7 +1009,17 @@ __global__ void __launch_bounds__(512) k_row_real(RowArgs a) {
         fft_rows_pp<T, MSZ, -1>(v, buf0, buf1, ph, lane, tw, ok);
         if (ok) {
 #pragma unroll
-            for (int w = 0; w < PPT; ++w) Og[ob + (int64_t)(lane + w * TPF) * es] = v[w];
+            for (int w = 0; w < PPT; ++w) Og[it.ob + (int64_t)(lane + w * TPF) * es] = v[w];
+            if (it.ob2 >= 0) {
+                // the mirrored row of a self-paired residue: zeta_m2^s conj(v_s)
+#pragma unroll
+                for (int w = 0; w < PPT; ++w) {
+                    const int s = lane + w * TPF;
+                    cplx<T> x = v[w];
+                    x.y = -x.y;
+                    Og[it.ob2 + (int64_t)s * es] = x * twl[s];
+                }
+            }
         }
     }
 }
