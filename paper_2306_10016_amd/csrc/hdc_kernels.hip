@@ -1225,7 +1225,8 @@ hipError_t colf_t(const ColFwdArgs& a, int threads, int64_t gx, int64_t gy, size
 
 template <typename T, int M1, bool REAL>
 hipError_t colb_r(const ColBwdArgs& a, int threads, int64_t gx, int64_t gy, size_t lds, hipStream_t s) {
-    constexpr int DMAX = sizeof(T) == 8 ? 2 : 4;
+    // residues held in registers per pass over h (more passes read-modify-write h)
+    constexpr int DMAX = sizeof(T) == 8 ? (M1 >= 1024 ? 2 : 3) : 4;
     lds += (size_t)PassTab<M1>::LEN * sizeof(cplx<T>);
     hipError_t e = allow_lds(k_col_bwd<T, M1, DMAX, REAL>, lds);
     if (e != hipSuccess) return e;
