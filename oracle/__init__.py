@@ -11,6 +11,9 @@ convolution of eq. (5) (section 2.3) two independent ways:
 * :func:`direct_1d`, :func:`direct_1d_sampled`, :func:`direct_nd_sampled` --
   the defining sum; :func:`direct_1d_real` the same sum in real arithmetic for
   real operands (the real case section 7 leaves to future work);
+  :func:`direct_multi` and :func:`padded_multi` the convolution of A >= 2
+  sequences (section 6.1's multi-convolution), by the defining sum applied
+  operand by operand and by explicit padding;
 * :func:`padded_1d`, :func:`padded_nd` -- explicit dealiasing (section 3.1):
   zero padding to the smallest 2^a 3^b 5^c 7^d size >= 2L-1, DFT with
   zeta = e^{+2 pi i/n}, product, inverse DFT with 1/n, crop to M.
@@ -211,6 +214,57 @@ def padded_dft(x, N: int) -> np.ndarray:
     X = np.empty(int(N), np.complex128)
     _check(_load().oracle_padded_dft(x.size, int(N), x.ctypes.data, X.ctypes.data), "padded_dft")
     return X
+
+
+def direct_multi(xs, M: int) -> np.ndarray:
+    """The convolution of A >= 2 sequences (section 6.1's multi-convolution of N arrays):
+    h_k = sum over j_0 + ... + j_{A-1} = k of prod_a x_a[j_a], k < M; x_a of shape (L_a,)
+    or (L_a, C).  Evaluated as the defining sum of eq. (5) applied operand by operand
+    (the nested sums regroup the A-fold sum exactly)."""
+    flat = np.asarray(xs[0]).ndim == 1
+    xs = [_as_2d(x)[0] for x in xs]
+    if len(xs) < 2:
+        raise ValueError("need at least two sequences")
+    h = xs[0]
+    for x in xs[1:]:
+        h = direct_1d(h, x, h.shape[0] + x.shape[0] - 1)
+        h = h.reshape(-1, x.shape[1])
+    out = np.zeros((int(M), h.shape[1]), np.complex128)
+    n = min(int(M), h.shape[0])
+    out[:n] = h[:n]
+    return out.reshape(-1) if flat else out
+
+
+def padded_multi(xs, M: int) -> np.ndarray:
+    """Explicit dealiasing for A sequences (section 3.1 applied to section 6.1's N arrays):
+    zero-pad every x_a to the smallest friendly size Ne >= sum_a L_a - (A - 1), take their
+    DFTs, multiply them pointwise, inverse DFT with 1/Ne, crop to M (zeros beyond)."""
+    flat = np.asarray(xs[0]).ndim == 1
+    xs = [_as_2d(x)[0] for x in xs]
+    C = xs[0].shape[1]
+    K = sum(x.shape[0] for x in xs) - (len(xs) - 1)
+    Ne = friendly_size(K)
+    out = np.zeros((int(M), C), np.complex128)
+    for c in range(C):
+        H = np.ones(Ne, np.complex128)
+        for x in xs:
+            z = np.zeros(Ne, np.complex128)
+            z[:x.shape[0]] = x[:, c]
+            H *= dft(z, +1)
+        h = dft(H, -1) / Ne
+        n = min(int(M), K)
+        out[:n, c] = h[:n]
+    return out.reshape(-1) if flat else out
+
+
+def multi_sampled(xs, ks) -> np.ndarray:
+    """Outputs ks of the A-fold convolution: the first A - 1 operands by padded_multi (or
+    the single first operand), the last one by the defining sum at each k."""
+    flat = np.asarray(xs[0]).ndim == 1
+    xs = [_as_2d(x)[0] for x in xs]
+    pre = xs[0] if len(xs) == 2 else padded_multi(xs[:-1], sum(x.shape[0] for x in xs[:-1]) - (len(xs) - 2))
+    out = direct_1d_sampled(pre, xs[-1], ks)
+    return out.reshape(-1) if flat else out
 
 
 def rel_l2(a, b) -> float:

@@ -323,3 +323,69 @@ def test_real_integer_exact():
     f, g = r.integers(-50, 51, 300).astype(float), r.integers(-50, 51, 300).astype(float)
     exact = [sum(int(f[j]) * int(g[k - j]) for j in range(max(0, k - 299), min(k, 299) + 1)) for k in range(599)]
     assert np.array_equal(oracle.direct_1d_real(f, g, 599), np.array(exact, dtype=float))
+
+
+# --- multi-convolution of A sequences (section 6.1) -------------------------------------
+
+def _brute_multi(xs, M):
+    """The A-fold defining sum by enumerating every index tuple (tiny inputs only)."""
+    import itertools
+    h = [0j] * M
+    for js in itertools.product(*[range(len(x)) for x in xs]):
+        k = sum(js)
+        if k < M:
+            p = 1 + 0j
+            for x, j in zip(xs, js):
+                p *= x[j]
+            h[k] += p
+    return np.array(h)
+
+
+@pytest.mark.parametrize("A,L", [(3, 1), (3, 5), (4, 4), (5, 3), (2, 6)])
+def test_multi_matches_tuple_enumeration(A, L):
+    r = synth.rng(120, A, L)
+    xs = [r.uniform(-1, 1, L) + 1j * r.uniform(-1, 1, L) for _ in range(A)]
+    M = A * (L - 1) + 3
+    want = _brute_multi(xs, M)
+    assert np.max(np.abs(oracle.direct_multi(xs, M) - want)) < 1e-13
+    assert np.max(np.abs(oracle.padded_multi(xs, M) - want)) < 1e-13
+
+
+@pytest.mark.parametrize("A", [2, 3, 4, 6])
+def test_multi_matches_numpy_chain_and_copies(A):
+    r = synth.rng(121, A, 0)
+    L, C = 57, 3
+    xs = [r.uniform(-1, 1, (L, C)) + 1j * r.uniform(-1, 1, (L, C)) for _ in range(A)]
+    K = A * (L - 1) + 1
+    h = oracle.direct_multi(xs, K + 4)
+    hp = oracle.padded_multi(xs, K + 4)
+    for c in range(C):
+        ref = xs[0][:, c]
+        for x in xs[1:]:
+            ref = np.convolve(ref, x[:, c])
+        assert np.max(np.abs(h[:K, c] - ref)) < 1e-12 * np.max(np.abs(ref))
+        assert np.all(h[K:, c] == 0)
+        assert np.max(np.abs(hp[:K, c] - ref)) < 1e-12 * np.max(np.abs(ref))
+    ks = np.array([0, 1, K // 2, K - 1], np.int64)
+    assert np.max(np.abs(oracle.multi_sampled(xs, ks) - h[ks])) < 1e-12 * np.max(np.abs(h))
+
+
+def test_multi_deltas_and_exact_integers():
+    """delta_a * delta_b * delta_c = delta_(a+b+c); Gaussian-integer inputs give the exact
+    integer result (Python integers) and the A = 2 case is the two-operand oracle."""
+    L = 9
+    for a, b, c in ((0, 0, 0), (8, 8, 8), (1, 5, 7), (3, 0, 2)):
+        xs = [np.eye(L)[i].astype(complex) for i in (a, b, c)]
+        h = oracle.direct_multi(xs, 3 * L - 2)
+        want = np.zeros(3 * L - 2, complex)
+        want[a + b + c] = 1
+        assert np.array_equal(h, want)
+    xs = [synth.gaussian_integers(40, 6, 122, 0, w) for w in range(4)]
+    ex = [complex(int(v.real), int(v.imag)) for v in xs[0]]
+    for x in xs[1:]:
+        xi = [complex(int(v.real), int(v.imag)) for v in x]
+        ex = [sum(ex[j] * xi[k - j] for j in range(max(0, k - len(xi) + 1), min(k, len(ex) - 1) + 1))
+              for k in range(len(ex) + len(xi) - 1)]
+    assert np.array_equal(oracle.direct_multi(xs, len(ex)), np.array(ex))
+    assert np.array_equal(np.round(oracle.padded_multi(xs, len(ex))), np.array(ex))
+    assert np.array_equal(oracle.direct_multi(xs[:2], 79), oracle.direct_1d(xs[0], xs[1], 79))
