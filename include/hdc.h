@@ -183,6 +183,27 @@ hdc_status hdc_uneq_nd_check(int ndim, const int64_t* Lf, const int64_t* Lg, con
 hdc_status hdc_plan_uneq_nd(hdc_plan_t* out, int ndim, const int64_t* Lf, const int64_t* Lg, const int64_t* M,
                             const int64_t* m, const int64_t* Lambda, const int64_t* D, hdc_dtype dtype);
 
+/*
+ * Multi-convolution (section 6.1, the convolution applied to N arrays rather
+ * than two): h = x_0 * x_1 * ... * x_{A-1} for A = 2 .. 8 sequences of length L,
+ *     h_k = sum over j_0 + ... + j_{A-1} = k of prod_a x_a[j_a],  k = 0 .. M-1,
+ * C copies (element j of copy c at j*C + c).  The linear result has A(L-1)+1
+ * terms, so the transform length N = q m must reach max(M, A(L-1)+1) (q = 0
+ * derives it; M below A(L-1)+1 writes the first M terms).  Every residue of
+ * every operand is formed as in eq. (3), the A residues multiply pointwise and
+ * one backward, eq. (4), accumulates h.  Other arguments and errors as
+ * hdc_plan; complex types only (HDC_ERR_UNSUPPORTED for real ones).
+ * hdc_convolve_multi(plan, x, h, ws, stream): x is a HOST array of plan's A
+ * DEVICE pointers (A = 2 for a plan of hdc_plan), each of L x C values; h must
+ * not alias any operand; ws as hdc_workspace_size.  hdc_convolve refuses a
+ * plan of more than two operands.  The residue-level calls work on such a plan
+ * operand by operand: hdc_forward of each, hdc_multiply of the first buffer by
+ * every other, hdc_backward of the product.
+ */
+hdc_status hdc_plan_multi(hdc_plan_t* out, int A, int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, int64_t C,
+                          int64_t D, hdc_dtype dtype);
+hdc_status hdc_convolve_multi(hdc_plan_t plan, const void* const* x, void* h, void* ws, hipStream_t stream);
+
 hdc_status hdc_plan_destroy(hdc_plan_t plan);
 
 /* Number of axes and the description of axis `axis`. */

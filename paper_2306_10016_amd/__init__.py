@@ -14,6 +14,8 @@ Names follow ``include/hdc.h``:
   from a captured HIP graph);
 * :class:`UneqPlan` wraps ``hdc_plan_uneq`` (operands of different lengths,
   section 3.5) and adds ``forward_operand`` (``hdc_forward_operand``);
+* :class:`MultiPlan` wraps ``hdc_plan_multi`` / ``hdc_convolve_multi`` (the
+  convolution of A sequences, section 6.1);
 * :func:`derive` / :func:`uneq_derive` are the host-only admissibility checks
   (``hdc_derive`` / ``hdc_uneq_derive``).
 """
@@ -345,6 +347,38 @@ class UneqPlan(Plan):
 
     def forward(self, f, F, r0: int, stream=None):
         raise HdcError(1, "unequal-length plan: use forward_operand")
+
+
+class MultiPlan(Plan):
+    """Multi-convolution (hdc_plan_multi, section 6.1): h = x_0 * ... * x_{A-1} for
+    A = 2 .. 8 sequences of length L (C copies), output length M (default the
+    A(L-1)+1 terms of the linear result)."""
+
+    def __init__(self, A: int, L: int, M: Optional[int] = None, m: int = 0, p: int = 0, q: int = 0, C: int = 1,
+                 D: int = 0, dtype="c128"):
+        M = int(A) * (int(L) - 1) + 1 if M is None else int(M)
+        h = ctypes.c_void_p()
+        check(lib().hdc_plan_multi(ctypes.byref(h), int(A), int(L), M, int(m), int(p), int(q), int(C), int(D),
+                                   dtype_code(dtype)))
+        super().__init__(0, 0, 0, dtype=dtype, _handle=h)
+        self.A = int(A)
+
+    def convolve(self, xs, out=None, ws=None, stream=None):
+        """h = x_0 * ... * x_{A-1} (hdc_convolve_multi); ``xs`` holds the A device tensors."""
+        import torch
+        if len(xs) != self.A:
+            raise ValueError(f"plan has {self.A} operands, got {len(xs)}")
+        for i, x in enumerate(xs):
+            _check_tensor(x, self.dtype, self.in_numel(), f"x[{i}]")
+        if out is None:
+            out = torch.empty(self.out_shape(), dtype=torch_dtype(self.dtype), device=xs[0].device)
+        _check_tensor(out, self.dtype, self.out_numel(), "out")
+        if ws is None:
+            ws = self.workspace(xs[0].device)
+        arr = (ctypes.c_void_p * self.A)(*[x.data_ptr() for x in xs])
+        check(self._lib.hdc_convolve_multi(self._h, arr, _ptr(out), _ptr(ws) if ws is not None else None,
+                                           _stream(stream)))
+        return out
 
 
 class Profile:

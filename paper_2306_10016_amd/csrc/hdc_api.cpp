@@ -160,6 +160,8 @@ struct hdc_plan_s {
     bool uneq = false;
     // real f, g and h (HDC_R32 / HDC_R64, 1D); dtype is then the complex type computed in
     bool real = false;
+    // operands of a multi-convolution (section 6.1), 2 for every other plan
+    int nops = 2;
     bool swap[3] = {false, false, false};
     int64_t lam[3] = {1, 1, 1};
     int64_t Lf[3] = {1, 1, 1}, Lg[3] = {1, 1, 1};
@@ -495,7 +497,8 @@ void bind_tables(AxisPlan& A, unsigned char* base) {
 // Lf >= 0: f has length Lf and g the axis length, g's rows addressed by ing
 // (section 3.5 with Lambda = 1).
 hdc_status run_fused(const AxisPlan& A, const void* f, const void* g, void* h, int64_t nrows, RowAddr in, RowAddr out,
-                     const int64_t* desc, hipStream_t s, int64_t Lf = -1, RowAddr ing = RowAddr{}) {
+                     const int64_t* desc, hipStream_t s, int64_t Lf = -1, RowAddr ing = RowAddr{},
+                     const void* const* xs = nullptr, int nops = 2) {
     if (nrows <= 0) return HDC_OK;
     FusedArgs a{};
     a.f = f;
@@ -523,10 +526,13 @@ hdc_status run_fused(const AxisPlan& A, const void* f, const void* g, void* h, i
     a.tw = A.tw;
     a.twm = A.tw_m;
     a.invN = 1.0 / (double)A.d.N;
+    a.nops = nops;
+    for (int o = 2; o < nops; ++o) a.xm[o - 2] = xs[o];
     const int64_t blocks = ceil_div(nrows, A.f_rpw);
     if (blocks > 0x7fffffff) return fail(HDC_ERR_UNSUPPORTED, "too many rows");
     const double eb = A.dbl ? 16.0 : 8.0;
-    const double lin = Lf >= 0 ? (double)(Lf + A.d.L) : (a.same ? 1.0 : 2.0) * (double)A.d.L;
+    const double lin = Lf >= 0 ? (double)(Lf + A.d.L)
+                               : (a.same ? (double)(nops - 1) : (double)nops) * (double)A.d.L;
     LaunchScope ls(s, 0, eb * (double)nrows * (lin + (double)A.d.M));
     hipError_t e = launch_fused(A.dbl, (int)A.d.m, a, A.f_threads, blocks, A.f_lds, s);
     if (e != hipSuccess) return hip_fail(e, "fused convolution launch");
@@ -960,6 +966,68 @@ hdc_status conv1d_real(const AxisPlan& A, const void* xf, const void* xg, void* 
     return HDC_OK;
 }
 
+// ------------------------------------------------------- multi-convolution --
+//
+// The convolution of A >= 2 sequences (section 6.1): every residue of every
+// operand is formed as in eq. (3), the A residues multiply pointwise, and one
+// backward, eq. (4), gives h.  The transform must cover the A(L - 1) + 1 terms.
+
+// Rows of the A residue buffers of a group: operand o's at X + o ostride; the
+// product overwrites operand 0's.
+hdc_status run_rows_multi(const AxisPlan& A, void* X, int64_t ostride, int64_t nrows, int64_t C1, int nops,
+                          hipStream_t s) {
+    if (nrows <= 0) return HDC_OK;
+    RowArgs a{};
+    a.a = X;
+    a.out = X;
+    a.nrows = nrows;
+    a.addr.inner_cnt = C1;
+    a.addr.outer_stride = A.d.m2 * C1;
+    a.addr.inner_stride = 1;
+    a.addr.es = C1;
+    a.mode = MODE_CONV;
+    a.rpw = A.r_rpw;
+    a.tw = A.tw_m2;
+    a.nops = nops;
+    a.ostride = ostride;
+    const int64_t blocks = ceil_div(nrows, A.r_rpw);
+    if (blocks > 0x7fffffff) return fail(HDC_ERR_UNSUPPORTED, "too many rows");
+    const double eb = A.dbl ? 16.0 : 8.0;
+    LaunchScope ls(s, 2, eb * (double)(nops + 1) * (double)nrows * (double)A.d.m2);
+    hipError_t e = launch_row_multi(A.dbl, (int)A.d.m2, a, A.r_threads, blocks, A.r_lds, s);
+    if (e != hipSuccess) return hip_fail(e, "multi row launch");
+    return HDC_OK;
+}
+
+int64_t ws_multi(const AxisPlan& A, int nops, int64_t B, int64_t C1) {
+    if (A.d.variant == 0) return 0;
+    return (int64_t)nops * B * std::min(A.d.D, A.d.q) * A.d.m * C1;
+}
+
+hdc_status conv1d_multi(const AxisPlan& A, const void* const* xs, int nops, void* out, int64_t B, int64_t in_bs,
+                        int64_t out_bs, int64_t C1, char* ws, size_t eb, hipStream_t s) {
+    if (A.d.variant == 0) {
+        RowAddr in{C1, in_bs, 1, C1};
+        RowAddr ou{C1, out_bs, 1, C1};
+        return run_fused(A, xs[0], xs[1], out, B * C1, in, ou, nullptr, s, -1, RowAddr{}, xs, nops);
+    }
+    const int64_t D = std::min(A.d.D, A.d.q);
+    const int64_t ostride = B * D * A.d.m * C1;
+    for (int64_t r0 = 0; r0 < A.d.q; r0 += D) {
+        const int64_t Dg = std::min(D, A.d.q - r0);
+        const int64_t xbs = Dg * A.d.m * C1;
+        for (int o = 0; o < nops; ++o) {
+            hdc_status st = run_col_fwd(A, xs[o], ws + (size_t)(o * ostride) * eb, B, in_bs, xbs, C1, r0, Dg, s);
+            if (st != HDC_OK) return st;
+        }
+        hdc_status st = run_rows_multi(A, ws, ostride, B * Dg * A.d.m1 * C1, C1, nops, s);
+        if (st != HDC_OK) return st;
+        st = run_col_bwd(A, ws, out, B, xbs, out_bs, C1, r0, Dg, r0 > 0, s);
+        if (st != HDC_OK) return st;
+    }
+    return HDC_OK;
+}
+
 int64_t prod_L(const hdc_plan_s* P, int from) {
     int64_t v = 1;
     for (int a = from; a < P->ndim; ++a) v *= P->ax[a].d.L;
@@ -1178,6 +1246,8 @@ hdc_status finish_plan(hdc_plan_s* P) {
                       elem(P);
     } else if (P->real) {
         P->ws_bytes = (size_t)ws_real(P->ax[0], 1, P->ax[0].d.C) * elem(P);
+    } else if (P->nops > 2) {
+        P->ws_bytes = (size_t)ws_multi(P->ax[0], P->nops, 1, P->ax[0].d.C) * elem(P);
     } else if (P->ndim == 1) {
         P->ws_bytes = (size_t)ws1d(P->ax[0], 1, P->ax[0].d.C) * elem(P);
     } else {
@@ -1228,6 +1298,56 @@ hdc_status hdc_plan(hdc_plan_t* out, int64_t L, int64_t M, int64_t m, int64_t p,
     }
     *out = P;
     return HDC_OK;
+}
+
+static hdc_status check_ptrs(hdc_plan_t P, const void* a, const void* b, const void* c);
+
+hdc_status hdc_plan_multi(hdc_plan_t* out, int A, int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, int64_t C,
+                          int64_t D, hdc_dtype dtype) {
+    if (!out) return fail(HDC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (A < 2 || A > kMaxOps) return fail(HDC_ERR_INVALID_ARG, "A = %d operands: must be 2 .. %d", A, kMaxOps);
+    if (L < 1) return fail(HDC_ERR_INVALID_ARG, "L = %lld must be >= 1", (long long)L);
+    hdc_plan_s* P = new hdc_plan_s();
+    P->ndim = 1;
+    P->dtype = dtype;
+    P->nops = A;
+    AxisPlan& Ax = P->ax[0];
+    // the A-fold linear convolution has A (L - 1) + 1 terms: the transform must cover them
+    hdc_status st = derive_axis(L, M, m, p, q, C, D, dtype, &Ax.d, (int64_t)A * (L - 1) + 1);
+    if (st == HDC_OK) {
+        Ax.dbl = dtype == HDC_C128;
+        st = geometry(Ax, false);
+    }
+    if (st == HDC_OK) st = finish_plan(P);
+    if (st != HDC_OK) {
+        delete P;
+        return st;
+    }
+    *out = P;
+    return HDC_OK;
+}
+
+hdc_status hdc_convolve_multi(hdc_plan_t P, const void* const* x, void* h, void* ws, hipStream_t s) {
+    if (!P || !x || !h) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+    if (P->uneq || P->real || P->ndim != 1)
+        return fail(HDC_ERR_INVALID_ARG, "hdc_convolve_multi takes a plan of hdc_plan_multi or hdc_plan");
+    for (int o = 0; o < P->nops; ++o) {
+        if (!x[o]) return fail(HDC_ERR_INVALID_ARG, "operand %d is NULL", o);
+        if (x[o] == h) return fail(HDC_ERR_INVALID_ARG, "h must not alias an operand");
+        hdc_status st = check_ptrs(P, x[o], nullptr, nullptr);
+        if (st != HDC_OK) return st;
+    }
+    hdc_status st = check_ptrs(P, h, nullptr, nullptr);
+    if (st != HDC_OK) return st;
+    if (P->ws_bytes > 0 && !ws) return fail(HDC_ERR_WORKSPACE, "workspace of %zu bytes required", P->ws_bytes);
+    struct CurPlan {
+        explicit CurPlan(const void* p) { g_cur_plan = p; }
+        ~CurPlan() { g_cur_plan = nullptr; }
+    } cur(P);
+    const AxisPlan& Ax = P->ax[0];
+    if (P->nops == 2) return conv1d(Ax, x[0], x[1], h, 1, 0, 0, Ax.d.C, (char*)ws, elem(P), s);
+    return conv1d_multi(Ax, x, P->nops, h, 1, 0, 0, Ax.d.C, (char*)ws, elem(P), s);
 }
 
 hdc_status hdc_uneq_derive(int64_t Lf, int64_t Lg, int64_t M, int64_t m, int64_t Lambda, int64_t C, int64_t D,
@@ -1399,6 +1519,8 @@ hdc_status hdc_convolve(hdc_plan_t P, const void* f, const void* g, void* h, voi
     hdc_status st = check_ptrs(P, f, g, h);
     if (st != HDC_OK) return st;
     if (P->ws_bytes > 0 && !ws) return fail(HDC_ERR_WORKSPACE, "workspace of %zu bytes required", P->ws_bytes);
+    if (P->nops > 2)
+        return fail(HDC_ERR_INVALID_ARG, "a plan of %d operands takes hdc_convolve_multi", P->nops);
     struct CurPlan {
         explicit CurPlan(const void* p) { g_cur_plan = p; }
         ~CurPlan() { g_cur_plan = nullptr; }

@@ -49,6 +49,10 @@ struct FusedArgs {
     TwN tw;
     const void* twm;      // zeta_m^e, e < m, in the data type
     double invN;
+    // multi-convolution (section 6.1): nops > 2 operands, f and g the first two,
+    // xm[o - 2] the others (same lengths and layout as f)
+    int32_t nops;
+    const void* xm[6];
 };
 
 struct ColFwdArgs {
@@ -103,6 +107,9 @@ struct RowArgs {
     // real case (k_row_real): product rows of residues r0 + d (d < Dg, each
     // q = qg), Z with S slots per batch, partner slots from residue pfirst on
     int32_t S, pfirst;
+    // multi-convolution (k_row_multi): nops operands' rows at a + o * ostride
+    int32_t nops;
+    int64_t ostride;
 };
 
 enum { MODE_FWD = 0, MODE_INV = 1, MODE_CONV = 2 };
@@ -120,6 +127,8 @@ hipError_t launch_fused_real(bool dbl, int m, const FusedArgs& a, int threads, i
                              hipStream_t s);
 hipError_t launch_row(bool dbl, int m2, const RowArgs& a, int threads, int64_t blocks, size_t lds,
                       hipStream_t s);
+hipError_t launch_row_multi(bool dbl, int m2, const RowArgs& a, int threads, int64_t blocks, size_t lds,
+                            hipStream_t s);
 hipError_t launch_mul(bool dbl, void* F, const void* G, int64_t n, hipStream_t s);
 hipError_t launch_natural(bool dbl, const void* F, void* out, int64_t Dg, int64_t m1, int64_t m2, int64_t C,
                           hipStream_t s);
@@ -145,5 +154,7 @@ inline int ppt_for(int n) { return n >= 8 ? 8 : n; }
 constexpr int kMaxM1 = 1024;
 constexpr int kMaxRow = 4096;
 constexpr int kMaxFused = 4096;
+// Largest number of operands of a multi-convolution.
+constexpr int kMaxOps = 8;
 
 }  // namespace hdc

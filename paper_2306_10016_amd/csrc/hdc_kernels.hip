@@ -373,6 +373,19 @@ __device__ __forceinline__ int64_t row_base(const RowAddr& a, int64_t row) {
 }
 
 // ------------------------------------------------------------- fused kernel --
+
+// Operand o >= 2 of a multi-convolution (constant indices into the kernel
+// argument, so the array is never copied to private memory).
+__device__ __forceinline__ const void* multi_ptr(const FusedArgs& a, int o) {
+    switch (o) {
+        case 2: return a.xm[0];
+        case 3: return a.xm[1];
+        case 4: return a.xm[2];
+        case 5: return a.xm[3];
+        case 6: return a.xm[4];
+        default: return a.xm[5];
+    }
+}
 //
 // One row (an independent 1D convolution) per group of TPF*Dc threads; its
 // q residues are processed Dc at a time.  Residue r uses LDS region U[r]
@@ -484,6 +497,35 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
         } else {
 #pragma unroll
             for (int v = 0; v < PPT; ++v) F[v] = F[v] * F[v];
+        }
+        // further operands of a multi-convolution (section 6.1): the residue of
+        // each is formed like f's and multiplies into the product
+        for (int o = 2; o < a.nops; ++o) {
+            const cplx<T>* x = reinterpret_cast<const cplx<T>*>(multi_ptr(a, o)) + fbase;
+#pragma unroll
+            for (int v = 0; v < PPT; ++v) G[v] = mk<T>(0, 0);
+            if (act) {
+                int e = 0;
+                for (int t = 0; t < a.p; ++t) {
+                    const double2 z = twq[e];
+                    e += r;
+                    if (e >= a.q) e -= a.q;
+#pragma unroll
+                    for (int v = 0; v < PPT; ++v) {
+                        const int j = t * MSZ + lane + v * TPF;
+                        if (j < L) G[v] = G[v] + mul_tw<false>(x[(int64_t)j * ies], z, false);
+                    }
+                }
+            }
+            double2 z = z0;
+#pragma unroll
+            for (int v = 0; v < PPT; ++v) {
+                G[v] = mul_tw<false>(G[v], z, a.hiprec);
+                z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
+            }
+            fft_regs<T, MSZ, +1, LAY_PAD>(G, buf, 1, lane, twm, act);
+#pragma unroll
+            for (int v = 0; v < PPT; ++v) F[v] = F[v] * G[v];
         }
         fft_regs<T, MSZ, -1, LAY_PAD>(F, buf, 1, lane, twm, act);
         if (act) {
@@ -887,6 +929,54 @@ __global__ void __launch_bounds__(512) k_row(RowArgs a) {
     }
 }
 
+// Multi-convolution rows (section 6.1): operand o's row of the group sits at
+// a + o ostride; the row DFTs of all nops operands multiply into one product,
+// whose inverse overwrites operand 0's row.
+template <typename T, int MSZ>
+__global__ void __launch_bounds__(512) k_row_multi(RowArgs a) {
+    using P = FP<MSZ>;
+    constexpr int PPT = P::PPT;
+    constexpr int TPF = P::TPF;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T>* smem = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* tpt = smem + (size_t)a.rpw * 2 * MSZ;
+    const int tid = threadIdx.x;
+    fill_pass_tab<T, MSZ>(tpt, reinterpret_cast<const cplx<T>*>(a.tw), tid, blockDim.x);
+    __syncthreads();
+    const TwPass<T> tw{tpt, PassTab<MSZ>::R0};
+    const int rloc = tid / TPF;
+    const int lane = tid - rloc * TPF;
+    cplx<T>* buf0 = smem + (size_t)rloc * 2 * MSZ;
+    cplx<T>* buf1 = buf0 + MSZ;
+    int ph = 0;
+    const int64_t es = a.addr.es;
+    const int64_t stride = (int64_t)gridDim.x * a.rpw;
+    const cplx<T>* X = reinterpret_cast<const cplx<T>*>(a.a);
+    cplx<T>* Og = reinterpret_cast<cplx<T>*>(a.out);
+    for (int64_t base = (int64_t)blockIdx.x * a.rpw; base < a.nrows; base += stride) {
+        const int64_t row = base + rloc;
+        const bool ok = row < a.nrows;
+        const int64_t rb = row_base(a.addr, ok ? row : 0);
+        cplx<T> v[PPT], u[PPT];
+#pragma unroll
+        for (int w = 0; w < PPT; ++w) v[w] = ok ? X[rb + (int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
+        fft_rows_pp<T, MSZ, +1>(v, buf0, buf1, ph, lane, tw, ok);
+        for (int o = 1; o < a.nops; ++o) {
+            const cplx<T>* Xo = X + o * a.ostride;
+#pragma unroll
+            for (int w = 0; w < PPT; ++w) u[w] = ok ? Xo[rb + (int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
+            fft_rows_pp<T, MSZ, +1>(u, buf0, buf1, ph, lane, tw, ok);
+#pragma unroll
+            for (int w = 0; w < PPT; ++w) v[w] = v[w] * u[w];
+        }
+        fft_rows_pp<T, MSZ, -1>(v, buf0, buf1, ph, lane, tw, ok);
+        if (ok) {
+#pragma unroll
+            for (int w = 0; w < PPT; ++w) Og[rb + (int64_t)(lane + w * TPF) * es] = v[w];
+        }
+    }
+}
+
 // --------------------------------------------------------------- real case --
 //
 // Real f and g are transformed together as z = f + i g, so Z_k = F_k + i G_k
@@ -1254,6 +1344,20 @@ hipError_t row_real_t(const RowArgs& a, int threads, int64_t blocks, size_t lds,
 }
 
 template <typename T, int MSZ>
+hipError_t row_multi_t(const RowArgs& a, int threads, int64_t blocks, size_t lds, hipStream_t s) {
+    lds += (size_t)PassTab<MSZ>::LEN * sizeof(cplx<T>);
+    auto kern = k_row_multi<T, MSZ>;
+    hipError_t e = allow_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, threads, lds) != hipSuccess || occ < 1) occ = 1;
+    const int64_t resident = (int64_t)occ * cu_count();
+    const int64_t grid = blocks < resident ? blocks : resident;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int MSZ>
 hipError_t fused_real_t(const FusedArgs& a, int threads, int64_t blocks, size_t lds, hipStream_t s) {
     lds += (size_t)(TwSplit<MSZ>::LO + TwSplit<MSZ>::HI) * sizeof(cplx<T>);
     hipError_t e = allow_lds(k_fused_real<T, MSZ>, lds);
@@ -1353,6 +1457,16 @@ static hipError_t row_real_disp(int m, const RowArgs& a, int th, int64_t bl, siz
 }
 
 template <typename T>
+static hipError_t row_multi_disp(int m, const RowArgs& a, int th, int64_t bl, size_t lds, hipStream_t s) {
+    switch (m) {
+        HDC_POW2_CASES(row_multi_t, a, th, bl, lds, s)
+        case 2048: return row_multi_t<T, 2048>(a, th, bl, lds, s);
+        case 4096: return row_multi_t<T, 4096>(a, th, bl, lds, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
 static hipError_t fused_real_disp(int m, const FusedArgs& a, int th, int64_t bl, size_t lds, hipStream_t s) {
     switch (m) {
         HDC_POW2_CASES(fused_real_t, a, th, bl, lds, s)
@@ -1387,6 +1501,12 @@ hipError_t launch_row_real(bool dbl, int m2, const RowArgs& a, int threads, int6
                            hipStream_t s) {
     return dbl ? row_real_disp<double>(m2, a, threads, blocks, lds, s)
                : row_real_disp<float>(m2, a, threads, blocks, lds, s);
+}
+
+hipError_t launch_row_multi(bool dbl, int m2, const RowArgs& a, int threads, int64_t blocks, size_t lds,
+                            hipStream_t s) {
+    return dbl ? row_multi_disp<double>(m2, a, threads, blocks, lds, s)
+               : row_multi_disp<float>(m2, a, threads, blocks, lds, s);
 }
 
 hipError_t launch_fused_real(bool dbl, int m, const FusedArgs& a, int threads, int64_t blocks, size_t lds,
