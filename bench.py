@@ -224,6 +224,74 @@ def secondary(args, dev, hdc, synth, log):
             torch.cuda.empty_cache()
         out["real"] = rl
 
+    if want("multi"):
+        # multi-convolution (section 6.1): A sequences of L points, h = x_0 * ... * x_{A-1};
+        # the hybrid plan (best of a few m) against explicit padding with torch.fft and
+        # against convolving pairwise (the equal-length plan, then unequal-length plans)
+        mu = {}
+        for A, L, dt in ((3, 1 << 20, "c128"), (4, 1 << 20, "c128"), (3, 1 << 20, "c64"), (3, 3 ** 11, "c128")):
+            K = A * (L - 1) + 1
+            np_dt = np.complex128 if dt == "c128" else np.complex64
+            td = torch.complex128 if dt == "c128" else torch.complex64
+            xs = [torch.from_numpy(synth.uniform_complex(L, 9, L, w, np_dt)).to(dev) for w in range(A)]
+            n2 = 1
+            while n2 < K:
+                n2 *= 2
+            best = None
+            for m in (n2, n2 // 2, n2 // 4):
+                try:
+                    plan = hdc.MultiPlan(A, L, K, m=m, dtype=dt)
+                except hdc.HdcError:
+                    continue
+                h = torch.empty(K, dtype=td, device=dev)
+                ws = plan.workspace(dev)
+                t = timed(lambda: plan.convolve(xs, h, ws=ws), 10)
+                if best is None or t < best[0]:
+                    best = (t, {"m": m, "q": plan.axes[0]["q"]}, h)
+                del plan, ws
+
+            def explicit():
+                H = torch.fft.fft(xs[0], n2)
+                for x in xs[1:]:
+                    H = H * torch.fft.fft(x, n2)
+                return torch.fft.ifft(H)[:K]
+            ref = explicit()
+            t, params, h = best
+            err = float(torch.linalg.vector_norm(h - ref) / torch.linalg.vector_norm(ref))
+            te = timed(explicit, 10)
+            # pairwise: the two-operand equal-length plan applied A - 1 times, each later
+            # operand zero-padded to the running result's length (first outputs only)
+            chain, bufs, pads = [], [], []
+            La = L
+            for a_ in range(1, A):
+                Lo = (a_ + 1) * (L - 1) + 1
+                mm = 1
+                while mm < La:
+                    mm *= 2
+                chain.append(hdc.Plan(La, Lo, mm, dtype=dt))
+                bufs.append(torch.empty(Lo, dtype=td, device=dev))
+                pz = torch.zeros(La, dtype=td, device=dev)
+                pz[:L] = xs[a_]
+                pads.append(pz)
+                La = Lo
+
+            def pairwise():
+                cur = xs[0]
+                for i, pl in enumerate(chain):
+                    pl.convolve(cur if i == 0 else cur, pads[i], bufs[i])
+                    cur = bufs[i]
+            tp = timed(pairwise, 10)
+            key = f"A{A}_L{L}_{dt}"
+            eb = 16 if dt == "c128" else 8
+            mu[key] = {"params": params, "ms": round(t * 1e3, 4), "compulsory_GBps": round((A * L + K) * eb / t / 1e9, 1),
+                       "explicit_ms": round(te * 1e3, 4), "speedup_vs_explicit": round(te / t, 3),
+                       "pairwise_ms": round(tp * 1e3, 4), "speedup_vs_pairwise": round(tp / t, 3),
+                       "rel_err_vs_explicit": err}
+            log(f"[bench] multi {key}: {t * 1e3:.3f} ms (explicit {te * 1e3:.3f}, pairwise {tp * 1e3:.3f}), rel {err:.1e}")
+            del xs, best, h, ref, chain, bufs, pads
+            torch.cuda.empty_cache()
+        out["multi"] = mu
+
     if want("batch"):
         # uneven batch: 4096 complex64 problems, L = round(2^U[6,16])
         Ls = synth.batch_lengths(4096, 6, 16, cfg=3)
@@ -511,7 +579,7 @@ def main():
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--extras", default="", help="comma list of secondary workloads to run (default: all of "
-                    "small,first_L,real,batch,nd,uneq,uneq_nd)")
+                    "small,first_L,real,multi,batch,nd,uneq,uneq_nd)")
     ap.add_argument("--streams", type=int, default=8,
                     help="streams of the captured step graph (0: time the eager launch loop only)")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -145,8 +145,13 @@ struct AxisPlan {
     const void* tw_m = nullptr;
     const void* tw_m1 = nullptr;
     const void* tw_m2 = nullptr;
+    // per-pass twiddle tables of the m1- and m2-point transforms (the layout the
+    // kernels keep in LDS: for each radix-8 pass of length Ns, three arrays of
+    // Ns values zeta_{8 Ns}^{i k}, i = 1, 2, 4)
+    const void* tw_p1 = nullptr;
+    const void* tw_p2 = nullptr;
     // table layout offsets (bytes) inside the plan's table block
-    size_t off_lo = 0, off_hi = 0, off_m = 0, off_m1 = 0, off_m2 = 0;
+    size_t off_lo = 0, off_hi = 0, off_m = 0, off_m1 = 0, off_m2 = 0, off_p1 = 0, off_p2 = 0;
     int64_t nlo = 0, nhi = 0;
 };
 
@@ -477,9 +482,37 @@ void stage_tables(AxisPlan& A, std::vector<unsigned char>& blob) {
         }
         return off;
     };
+    // the radix-8 passes after the first (radix R0 at Ns = 1): Ns = R0, 8 R0, ...
+    auto pass_table = [&](int64_t n) {
+        align(256);
+        size_t off = blob.size();
+        if (n < 8) return off;
+        const int lg = ilog2i(n);
+        const int64_t r0 = lg % 3 == 0 ? 8 : (int64_t(1) << (lg % 3));
+        const int np = lg % 3 == 0 ? lg / 3 : lg / 3 + 1;
+        int64_t Ns = r0;
+        for (int ps = 1; ps < np; ++ps, Ns *= 8) {
+            for (int i = 0; i < 3; ++i) {
+                for (int64_t k = 0; k < Ns; ++k) {
+                    double re, im;
+                    root((k << i) * (n / (8 * Ns)), n, &re, &im);
+                    if (A.dbl) {
+                        double v[2] = {re, im};
+                        blob.insert(blob.end(), (unsigned char*)v, (unsigned char*)v + 16);
+                    } else {
+                        float v[2] = {(float)re, (float)im};
+                        blob.insert(blob.end(), (unsigned char*)v, (unsigned char*)v + 8);
+                    }
+                }
+            }
+        }
+        return off;
+    };
     A.off_m = small_table(A.d.m <= kMaxFused ? A.d.m : 1);
     A.off_m1 = small_table(A.d.m1);
     A.off_m2 = small_table(A.d.m2);
+    A.off_p1 = pass_table(A.d.m1);
+    A.off_p2 = pass_table(A.d.m2);
     A.tw.lgB = lgB;
     A.tw.mask = (int32_t)(B - 1);
 }
@@ -490,6 +523,8 @@ void bind_tables(AxisPlan& A, unsigned char* base) {
     A.tw_m = base + A.off_m;
     A.tw_m1 = base + A.off_m1;
     A.tw_m2 = base + A.off_m2;
+    A.tw_p1 = base + A.off_p1;
+    A.tw_p2 = base + A.off_p2;
 }
 
 // ---------------------------------------------------------------- launches --
@@ -578,7 +613,7 @@ hdc_status run_col_fwd(const AxisPlan& A, const void* x, void* X, int64_t B, int
     a.ntiles = (int32_t)ceil_div(a.Ccols, a.tile);
     a.hiprec = A.hiprec ? 1 : 0;
     a.tw = A.tw;
-    a.tw1 = A.tw_m1;
+    a.tw1 = A.tw_p1;
     const int64_t gx = round8((int64_t)a.ntiles * a.Dg);
     if (gx > 0x7fffffff) return fail(HDC_ERR_UNSUPPORTED, "column grid too large");
     const double eb = A.dbl ? 16.0 : 8.0;  // real: two inputs of L reals = L complex values
@@ -623,7 +658,7 @@ hdc_status run_col_bwd(const AxisPlan& A, const void* Y, void* h, int64_t B, int
     a.ntiles = (int32_t)ceil_div(a.Ccols, A.cb_tile);
     a.hiprec = A.hiprec ? 1 : 0;
     a.tw = A.tw;
-    a.tw1 = A.tw_m1;
+    a.tw1 = A.tw_p1;
     a.invN = 1.0 / (double)A.d.N;
     const double eb = A.dbl ? 16.0 : 8.0;
     const size_t esz = A.dbl ? 16 : 8;
@@ -682,7 +717,7 @@ hdc_status run_col_plain(const AxisPlan& A, void* x, int64_t B, int64_t cols, in
         a.ntiles = (int32_t)ceil_div(cols, A.mf_tile);
         a.hiprec = 0;
         a.tw = A.tw;
-        a.tw1 = A.tw_m2;
+        a.tw1 = A.tw_p2;
         LaunchScope ls(s, 1, eb * 2.0 * (double)B * (double)bs);
         hipError_t e = launch_col_fwd(A.dbl, m2, a, A.mf_threads, round8(a.ntiles), B, A.mf_lds, s);
         if (e != hipSuccess) return hip_fail(e, "strided DFT launch");
@@ -709,7 +744,7 @@ hdc_status run_col_plain(const AxisPlan& A, void* x, int64_t B, int64_t cols, in
     a.ntiles = (int32_t)ceil_div(cols, A.mb_tile);
     a.hiprec = 0;
     a.tw = A.tw;
-    a.tw1 = A.tw_m2;
+    a.tw1 = A.tw_p2;
     a.invN = 1.0;
     LaunchScope ls(s, 3, eb * 2.0 * (double)B * (double)bs);
     hipError_t e = launch_col_bwd(A.dbl, m2, a, A.mb_threads, round8(a.ntiles), B, A.mb_lds, s);
@@ -734,6 +769,7 @@ hdc_status run_rows(const AxisPlan& A, const void* a_, const void* b_, void* out
     a.same = (a_ == b_) ? 1 : 0;
     a.rpw = A.r_rpw;
     a.tw = A.tw_m2;
+    a.twp = A.tw_p2;
     const int64_t blocks = ceil_div(nrows, A.r_rpw);
     if (blocks > 0x7fffffff) return fail(HDC_ERR_UNSUPPORTED, "too many rows");
     const double eb = A.dbl ? 16.0 : 8.0;
@@ -764,6 +800,7 @@ hdc_status run_rows_raw(const AxisPlan& G, const AxisPlan& F, const void* xs, co
     a.same = 0;
     a.rpw = G.r_rpw;
     a.tw = G.tw_m2;
+    a.twp = G.tw_p2;
     a.fraw = xs;
     a.twN = F.tw;
     a.Lf = (int32_t)F.d.L;
@@ -920,6 +957,7 @@ hdc_status run_rows_real(const AxisPlan& A, const void* Z, void* O, int64_t B, i
     a.mode = MODE_CONV;
     a.rpw = A.r_rpw;
     a.tw = A.tw_m2;
+    a.twp = A.tw_p2;
     a.r0 = (int32_t)r0;
     a.qg = (int32_t)A.d.q;
     a.m1g = (int32_t)A.d.m1;
@@ -988,6 +1026,7 @@ hdc_status run_rows_multi(const AxisPlan& A, void* X, int64_t ostride, int64_t n
     a.mode = MODE_CONV;
     a.rpw = A.r_rpw;
     a.tw = A.tw_m2;
+    a.twp = A.tw_p2;
     a.nops = nops;
     a.ostride = ostride;
     const int64_t blocks = ceil_div(nrows, A.r_rpw);

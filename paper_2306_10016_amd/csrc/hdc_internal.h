@@ -67,7 +67,7 @@ struct ColFwdArgs {
     int32_t tile, ntiles;
     int32_t hiprec;
     TwN tw;
-    const void* tw1;           // zeta_{m1}^e, e < m1, data type
+    const void* tw1;           // per-pass twiddle table of the m1-point transform, data type
     const int64_t* desc;       // optional per-batch {input offset, L}; replaces b*in_bs and L
 };
 
@@ -94,7 +94,8 @@ struct RowArgs {
     int32_t mode;  // 0 forward DFT, 1 inverse DFT, 2 forward a and b, product, inverse
     int32_t same;
     int32_t rpw;
-    const void* tw;  // zeta_{m2}^e, e < m2
+    const void* tw;   // zeta_{m2}^e, e < m2
+    const void* twp;  // per-pass twiddle table of the m2-point transform
     // MODE_CONV with fraw != nullptr (section 3.5, shorter operand with a
     // trivial column stage): operand a is formed from the raw input fraw
     // (batches fbs apart, Lf x C1 values each, pf blocks of m2) instead of being

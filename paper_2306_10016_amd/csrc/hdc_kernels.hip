@@ -215,22 +215,11 @@ struct TwPass {
     }
 };
 
-// Fill a PassTab<NSZ> table from the global zeta_NSZ^e table twg (e < NSZ).
+// Copy a PassTab<NSZ> table (built by the plan in the same layout) into LDS.
 template <typename T, int NSZ>
-__device__ __forceinline__ void fill_pass_tab(cplx<T>* t, const cplx<T>* twg, int tid, int nth) {
-    using PT = PassTab<NSZ>;
-    for (int e = tid; e < PT::LEN; e += nth) {
-        // locate (pass, i, k) of entry e
-        int Ns = PT::R0, off = 0;
-        while (e >= off + 3 * Ns) {
-            off += 3 * Ns;
-            Ns *= 8;
-        }
-        const int r = e - off;
-        const int i = r / Ns;
-        const int k = r - i * Ns;
-        t[e] = twg[(k << i) * (NSZ / (8 * Ns))];
-    }
+__device__ __forceinline__ void fill_pass_tab(cplx<T>* t, const void* twp, int tid, int nth) {
+    const cplx<T>* src = reinterpret_cast<const cplx<T>*>(twp);
+    for (int e = tid; e < PassTab<NSZ>::LEN; e += nth) t[e] = src[e];
 }
 
 template <int NSZ>
@@ -394,7 +383,9 @@ __device__ __forceinline__ const void* multi_ptr(const FusedArgs& a, int o) {
 // there.  After all residues, the output blocks t < ceil(M/m) are the
 // q-point sums over r with zeta_q^{-t r}.  LDS: rows * N values + q twiddles.
 
-template <typename T, int MSZ>
+// MULTI: more than two operands (section 6.1), a separate instantiation so that
+// the two-operand kernel keeps its registers.
+template <typename T, int MSZ, bool MULTI = false>
 __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
     using P = FP<MSZ>;
     constexpr int PPT = P::PPT;
@@ -500,7 +491,7 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
         }
         // further operands of a multi-convolution (section 6.1): the residue of
         // each is formed like f's and multiplies into the product
-        for (int o = 2; o < a.nops; ++o) {
+        for (int o = 2; MULTI && o < a.nops; ++o) {
             const cplx<T>* x = reinterpret_cast<const cplx<T>*>(multi_ptr(a, o)) + fbase;
 #pragma unroll
             for (int v = 0; v < PPT; ++v) G[v] = mk<T>(0, 0);
@@ -582,7 +573,7 @@ __global__ void __launch_bounds__(REAL ? 512 : 1024) k_col_fwd(ColFwdArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* tpt = lds + (size_t)M1 * a.tile;
-    fill_pass_tab<T, M1>(tpt, reinterpret_cast<const cplx<T>*>(a.tw1), threadIdx.x, blockDim.x);
+    fill_pass_tab<T, M1>(tpt, a.tw1, threadIdx.x, blockDim.x);
     __syncthreads();
     const TwPass<T> tw1{tpt, PassTab<M1>::R0};
 
@@ -684,7 +675,7 @@ __global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* tpt = lds + (size_t)M1 * a.tile;
-    fill_pass_tab<T, M1>(tpt, reinterpret_cast<const cplx<T>*>(a.tw1), threadIdx.x, blockDim.x);
+    fill_pass_tab<T, M1>(tpt, a.tw1, threadIdx.x, blockDim.x);
     __syncthreads();
     const TwPass<T> tw1{tpt, PassTab<M1>::R0};
 
@@ -854,7 +845,7 @@ __global__ void __launch_bounds__(512) k_row(RowArgs a) {
     cplx<T>* smem = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* tpt = smem + (size_t)a.rpw * 2 * MSZ;
     const int tid = threadIdx.x;
-    fill_pass_tab<T, MSZ>(tpt, reinterpret_cast<const cplx<T>*>(a.tw), tid, blockDim.x);
+    fill_pass_tab<T, MSZ>(tpt, a.twp, tid, blockDim.x);
     __syncthreads();
     const TwPass<T> tw{tpt, PassTab<MSZ>::R0};
 
@@ -941,7 +932,7 @@ __global__ void __launch_bounds__(512) k_row_multi(RowArgs a) {
     cplx<T>* smem = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* tpt = smem + (size_t)a.rpw * 2 * MSZ;
     const int tid = threadIdx.x;
-    fill_pass_tab<T, MSZ>(tpt, reinterpret_cast<const cplx<T>*>(a.tw), tid, blockDim.x);
+    fill_pass_tab<T, MSZ>(tpt, a.twp, tid, blockDim.x);
     __syncthreads();
     const TwPass<T> tw{tpt, PassTab<MSZ>::R0};
     const int rloc = tid / TPF;
@@ -1065,7 +1056,7 @@ __global__ void __launch_bounds__(512) k_row_real(RowArgs a) {
     const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.tw);
     for (int e = tid; e < S::LO; e += blockDim.x) tlo[e] = twg[e];
     for (int e = tid; e < S::HI; e += blockDim.x) thi[e] = twg[e * S::LO];
-    fill_pass_tab<T, MSZ>(tpt, twg, tid, blockDim.x);
+    fill_pass_tab<T, MSZ>(tpt, a.twp, tid, blockDim.x);
     __syncthreads();
     const TwLds<T> twl{tlo, thi, S::LO - 1, S::LG};  // zeta_m2^s for the partner rows
     const TwPass<T> tw{tpt, PassTab<MSZ>::R0};
@@ -1290,13 +1281,19 @@ hipError_t allow_lds(K kernel, size_t lds) {
                                (int)lds);
 }
 
+template <typename T, int MSZ, bool MULTI>
+hipError_t fused_m(const FusedArgs& a, int threads, int64_t blocks, size_t lds, hipStream_t s) {
+    lds += (size_t)(TwSplit<MSZ>::LO + TwSplit<MSZ>::HI) * sizeof(cplx<T>);
+    hipError_t e = allow_lds(k_fused<T, MSZ, MULTI>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_fused<T, MSZ, MULTI>), dim3((unsigned)blocks), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
 template <typename T, int MSZ>
 hipError_t fused_t(const FusedArgs& a, int threads, int64_t blocks, size_t lds, hipStream_t s) {
-    lds += (size_t)(TwSplit<MSZ>::LO + TwSplit<MSZ>::HI) * sizeof(cplx<T>);
-    hipError_t e = allow_lds(k_fused<T, MSZ>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_fused<T, MSZ>), dim3((unsigned)blocks), dim3(threads), lds, s, a);
-    return hipGetLastError();
+    return a.nops > 2 ? fused_m<T, MSZ, true>(a, threads, blocks, lds, s)
+                      : fused_m<T, MSZ, false>(a, threads, blocks, lds, s);
 }
 
 template <typename T, int M1, bool REAL>
