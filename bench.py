@@ -580,7 +580,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--extras", default="", help="comma list of secondary workloads to run (default: all of "
                     "small,first_L,real,multi,batch,nd,uneq,uneq_nd)")
-    ap.add_argument("--streams", type=int, default=8,
+    ap.add_argument("--streams", type=int, default=16,
                     help="streams of the captured step graph (0: time the eager launch loop only)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 512 MiB first (counter calibration)")
