@@ -573,7 +573,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
     ap.add_argument("--max-sizes", type=int, default=0, help="use only the largest N sizes (profiling runs)")
-    ap.add_argument("--tune-db", default=os.path.join(HERE, "gpurun_out", "tune_db.jsonl"))
+    ap.add_argument("--tune-db", default=os.path.join(HERE, "results", "tune_db.jsonl"))
     ap.add_argument("--no-tune", action="store_true", help="default parameters m = 2^ceil(log2 L), p = 1, q = 2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")

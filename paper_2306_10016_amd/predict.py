@@ -186,7 +186,7 @@ def tune_separable(Ls, Ms, dtype, timer, batch=1, db: Optional[tune.TuneDB] = No
 
 
 def tune_joint(Ls, Ms, dtype, timer, batch=1):
-    """Exhaustive search over the product of the per-axis candidate sets (the regret judge).
+    """Exhaustive search over the product of the per-axis candidate sets (the reference point of the regret).
     For 3D problems the product is limited to the all-residues mode (D = q) on every
     axis, which keeps it at (#m)^3 combinations."""
     from . import HdcError
@@ -312,8 +312,8 @@ EVAL_PROBLEMS = [([4096, 4096], "c64"), ([8192, 8192], "c64"), ([256, 256, 256],
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--db", default="gpurun_out/predictor_db.jsonl")
-    ap.add_argument("--out", default="gpurun_out/predictor.json")
+    ap.add_argument("--db", default="results/predictor_db.jsonl")
+    ap.add_argument("--out", default="results/predictor.json")
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--max-problems", type=int, default=0)
     args = ap.parse_args(argv)

@@ -92,7 +92,7 @@ def run(squares: Sequence[int], max_height: int = 256, dtype: str = "c64", reps:
 
 def main(argv: Optional[List[str]] = None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default=os.path.join("gpurun_out", "epsilon_study.json"))
+    ap.add_argument("--out", default=os.path.join("results", "epsilon_study.json"))
     ap.add_argument("--dtype", default="c64")
     ap.add_argument("--squares", default="243,256,343,512,625,1024,1125,2048")
     ap.add_argument("--max-height", type=int, default=256)
