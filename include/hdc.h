@@ -268,7 +268,13 @@ hdc_status hdc_residues_natural(hdc_plan_t plan, const void* F, int64_t r0, void
  * The first hdc_batch_convolve captures the launches in a HIP graph on a private
  * stream of the batch; later calls with the same buffers replay it.  Every
  * call is ordered after the work already on `stream`, and work enqueued on
- * `stream` afterwards runs after it.
+ * `stream` afterwards runs after it.  Inside the graph the buckets run on up to
+ * four concurrent lanes (dealt longest first onto the least-loaded lane; the
+ * buckets of one lane run in turn), each lane with its own region of `ws`, so
+ * the workspace is the sum over lanes of the largest bucket need of each.
+ * Results do not depend on the lanes: every problem is computed by the same
+ * launches as in hdc_batch_convolve_eager, which runs the buckets in turn on
+ * `stream`.  Calls on one batch must not overlap (they share its graph).
  */
 hdc_status hdc_batch_plan(hdc_batch_t* out, int64_t n, const int64_t* L, const int64_t* M, const int64_t* bucket_m,
                           hdc_dtype dtype);

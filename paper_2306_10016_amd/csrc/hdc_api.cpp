@@ -1744,6 +1744,10 @@ namespace {
 struct Bucket {
     AxisPlan A;
     int64_t count = 0;
+    // concurrency lane of the captured graph and the element offset of the
+    // lane's workspace region (buckets of one lane run in turn and share it)
+    int lane = 0;
+    size_t ws_off = 0;
     // host descriptors, uploaded into the batch's device block
     std::vector<int64_t> fused_desc;  // {f_off, h_off, L, M} per problem
     std::vector<int64_t> fwd_desc;    // {f_off, L} per problem
@@ -1762,6 +1766,7 @@ struct hdc_batch_s {
     std::vector<Bucket> buckets;
     void* block = nullptr;
     size_t ws_bytes = 0;
+    int nlanes = 1;
     // captured graph and the arguments it was captured with
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
@@ -1771,23 +1776,34 @@ struct hdc_batch_s {
     // priority), ordered after and before the caller's stream with events
     hipStream_t side = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // lanes 1.. of the graph: streams forked from `side` inside the capture
+    // (default priority) and the events that join them back
+    std::vector<hipStream_t> lane_streams;
+    std::vector<hipEvent_t> ev_join;
+    hipEvent_t ev_fork = nullptr;
 };
 
 namespace {
 
 // Default FFT size for a problem of length L: the smallest power of two >= L
 // (p = 1, q = 2 for M = 2L-1), i.e. explicit padding to m, implicit to 2m.
+constexpr int kBatchLanes = 4;  // concurrent lanes of a batch's captured graph
+
 int64_t default_m(int64_t L) {
     int64_t m = 1;
     while (m < L) m <<= 1;
     return m;
 }
 
-hdc_status batch_launch(hdc_batch_s* Bt, const void* f, const void* g, void* h, void* ws, hipStream_t s) {
+// Every bucket's launches, on stream lanes[bk.lane] (or all on s when lanes is
+// NULL); each bucket uses its lane's workspace region.
+hdc_status batch_launch(hdc_batch_s* Bt, const void* f, const void* g, void* h, void* ws, hipStream_t s,
+                        const hipStream_t* lanes = nullptr) {
     const size_t eb = elem_bytes(Bt->dtype);
     const bool same = f == g;
     for (const Bucket& bk : Bt->buckets) {
         const AxisPlan& A = bk.A;
+        if (lanes) s = lanes[bk.lane];
         if (A.d.variant == 0) {
             RowAddr in{1, 0, 0, 1}, out{1, 0, 0, 1};
             hdc_status st = run_fused(A, f, g, h, bk.count, in, out, bk.d_fused, s);
@@ -1795,7 +1811,7 @@ hdc_status batch_launch(hdc_batch_s* Bt, const void* f, const void* g, void* h, 
             continue;
         }
         const int64_t D = std::min(A.d.D, A.d.q);
-        char* Xf = (char*)ws;
+        char* Xf = (char*)ws + bk.ws_off * eb;
         char* Xg = same ? Xf : Xf + (size_t)(bk.count * D * A.d.m) * eb;
         for (int64_t r0 = 0; r0 < A.d.q; r0 += D) {
             const int64_t Dg = std::min(D, A.d.q - r0);
@@ -1863,7 +1879,8 @@ hdc_status hdc_batch_plan(hdc_batch_t* out, int64_t n, const int64_t* L, const i
     Bt->total_L = fo;
     Bt->total_M = ho;
     std::vector<unsigned char> blob;
-    size_t ws_elems = 0;
+    std::vector<double> cost;       // estimated HBM bytes of each bucket
+    std::vector<size_t> bucket_ws;  // workspace elements of each bucket
     for (size_t b = 0; b < keys.size(); ++b) {
         Bucket bk;
         int64_t Lmax = 0, Mmax = 0;
@@ -1881,8 +1898,10 @@ hdc_status hdc_batch_plan(hdc_batch_t* out, int64_t n, const int64_t* L, const i
             return st;
         }
         bk.count = (int64_t)members[b].size();
+        double bytes = 0;
         for (int64_t i : members[b]) {
             const int64_t Mi = M ? M[i] : 2 * L[i] - 1;
+            bytes += (double)(2 * L[i] + Mi) * (double)elem_bytes(dtype);
             bk.fused_desc.insert(bk.fused_desc.end(), {foff[i], hoff[i], L[i], Mi});
             bk.fwd_desc.insert(bk.fwd_desc.end(), {foff[i], L[i]});
             bk.bwd_desc.insert(bk.bwd_desc.end(), {hoff[i], Mi});
@@ -1897,9 +1916,35 @@ hdc_status hdc_batch_plan(hdc_batch_t* out, int64_t n, const int64_t* L, const i
         bk.off_fused = put(bk.fused_desc);
         bk.off_fwd = put(bk.fwd_desc);
         bk.off_bwd = put(bk.bwd_desc);
-        if (bk.A.d.variant != 0) ws_elems = std::max<size_t>(ws_elems, (size_t)ws1d(bk.A, bk.count, 1));
+        // the column/row/column path moves about four times the problem bytes;
+        // every launch costs about as much as 64 MB of traffic
+        const bool fused = bk.A.d.variant == 0;
+        cost.push_back(bytes * (fused ? 1.0 : 4.0) + (fused ? 1.0 : 4.0) * 6.4e7);
+        bucket_ws.push_back(fused ? 0 : (size_t)ws1d(bk.A, bk.count, 1));
         Bt->buckets.push_back(std::move(bk));
     }
+    // lanes of the captured graph: buckets dealt longest first onto the
+    // least-loaded lane; each lane owns a workspace region as large as its
+    // largest bucket needs
+    const int nl = (int)std::min<size_t>(kBatchLanes, Bt->buckets.size());
+    std::vector<size_t> order(Bt->buckets.size());
+    for (size_t b = 0; b < order.size(); ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+    std::vector<double> load(nl, 0.0);
+    std::vector<size_t> lane_ws(nl, 0), lane_off(nl, 0);
+    for (size_t b : order) {
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        Bt->buckets[b].lane = k;
+        load[k] += cost[b];
+        lane_ws[k] = std::max(lane_ws[k], bucket_ws[b]);
+    }
+    size_t ws_elems = 0;
+    for (int k = 0; k < nl; ++k) {
+        lane_off[k] = ws_elems;
+        ws_elems += lane_ws[k];
+    }
+    for (Bucket& bk : Bt->buckets) bk.ws_off = lane_off[bk.lane];
+    Bt->nlanes = nl;
     void* dev = nullptr;
     hipError_t e = hipMalloc(&dev, std::max<size_t>(blob.size(), 256));
     if (e == hipSuccess) e = hipMemcpy(dev, blob.data(), blob.size(), hipMemcpyHostToDevice);
@@ -1954,6 +1999,19 @@ hdc_status hdc_batch_convolve(hdc_batch_t Bt, const void* f, const void* g, void
         HIP_TRY(hipStreamCreateWithFlags(&Bt->side, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&Bt->ev_in, hipEventDisableTiming));
         HIP_TRY(hipEventCreateWithFlags(&Bt->ev_out, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&Bt->ev_fork, hipEventDisableTiming));
+    }
+    while ((int)Bt->lane_streams.size() + 1 < Bt->nlanes) {
+        hipStream_t ls = nullptr;
+        hipEvent_t ev = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&ls, hipStreamNonBlocking));
+        hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            (void)hipStreamDestroy(ls);
+            return hip_fail(e, "hipEventCreateWithFlags");
+        }
+        Bt->lane_streams.push_back(ls);
+        Bt->ev_join.push_back(ev);
     }
     const bool hit = Bt->exec && Bt->g_f == f && Bt->g_g == g && Bt->g_h == h && Bt->g_ws == ws;
     if (!hit) {
@@ -1966,9 +2024,22 @@ hdc_status hdc_batch_convolve(hdc_batch_t Bt, const void* f, const void* g, void
             Bt->graph = nullptr;
         }
         HIP_TRY(hipStreamBeginCapture(Bt->side, hipStreamCaptureModeThreadLocal));
-        st = batch_launch(Bt, f, g, h, ws, Bt->side);
+        // fork: lanes 1.. join the capture by waiting on an event of the
+        // capturing stream, and are joined back before the capture ends
+        std::vector<hipStream_t> lanes{Bt->side};
+        hipError_t e = hipEventRecord(Bt->ev_fork, Bt->side);
+        for (size_t k = 0; e == hipSuccess && k < Bt->lane_streams.size(); ++k) {
+            e = hipStreamWaitEvent(Bt->lane_streams[k], Bt->ev_fork, 0);
+            lanes.push_back(Bt->lane_streams[k]);
+        }
+        st = e == hipSuccess ? batch_launch(Bt, f, g, h, ws, Bt->side, lanes.data()) : hip_fail(e, "graph fork");
+        for (size_t k = 0; k + 1 < lanes.size(); ++k) {
+            hipError_t ej = hipEventRecord(Bt->ev_join[k], Bt->lane_streams[k]);
+            if (ej == hipSuccess) ej = hipStreamWaitEvent(Bt->side, Bt->ev_join[k], 0);
+            if (ej != hipSuccess && st == HDC_OK) st = hip_fail(ej, "graph join");
+        }
         hipGraph_t graph = nullptr;
-        hipError_t e = hipStreamEndCapture(Bt->side, &graph);
+        e = hipStreamEndCapture(Bt->side, &graph);
         if (st != HDC_OK) {
             if (graph) (void)hipGraphDestroy(graph);
             return st;
@@ -2001,6 +2072,12 @@ hdc_status hdc_batch_destroy(hdc_batch_t Bt) {
         (void)hipStreamSynchronize(Bt->side);
         (void)hipStreamDestroy(Bt->side);
     }
+    for (hipStream_t ls : Bt->lane_streams) {
+        (void)hipStreamSynchronize(ls);
+        (void)hipStreamDestroy(ls);
+    }
+    for (hipEvent_t ev : Bt->ev_join) (void)hipEventDestroy(ev);
+    if (Bt->ev_fork) (void)hipEventDestroy(Bt->ev_fork);
     if (Bt->ev_in) (void)hipEventDestroy(Bt->ev_in);
     if (Bt->ev_out) (void)hipEventDestroy(Bt->ev_out);
     if (Bt->block) (void)hipFree(Bt->block);

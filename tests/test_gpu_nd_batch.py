@@ -125,6 +125,38 @@ def test_batch_edge_lengths():
     _batch([1, 2, 3, 1, 64, 65, 4096, 4097, 9000], "c128", graph=True, replays=2)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_lanes_bitwise_equal_eager(dtype):
+    """The graph runs the buckets on concurrent lanes, each with its own workspace
+    region; every replay equals the eager launches (buckets in turn on one stream)
+    bit for bit, and both match the oracle on sampled problems."""
+    import torch
+    Ls = [int(x) for x in synth.batch_lengths(240, 6, 15, cfg=313)]
+    Ms = [2 * x - 1 for x in Ls]
+    fp = to_dev(np.concatenate([synth.uniform_complex(L, 313, i, 0, NP_DT[dtype]) for i, L in enumerate(Ls)]))
+    gp = to_dev(np.concatenate([synth.uniform_complex(L, 313, i, 1, NP_DT[dtype]) for i, L in enumerate(Ls)]))
+    B = hdc.Batch(Ls, dtype=dtype)
+    say(f"batch lanes n={len(Ls)} buckets={B.n_buckets} {dtype}")
+    assert B.n_buckets >= 8
+    eager = torch.empty(B.total_M, dtype=fp.dtype, device="cuda")
+    B.convolve(fp, gp, eager, graph=False)
+    out = torch.empty_like(eager)
+    for rep in range(3):
+        out.fill_(float("nan"))
+        B.convolve(fp, gp, out, graph=True)
+        tmp = torch.ones(1000, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert float(tmp) == 1000.0
+        assert torch.equal(out.view(torch.float64 if dtype == "c128" else torch.float32),
+                           eager.view(torch.float64 if dtype == "c128" else torch.float32)), rep
+    h = to_host(eager)
+    offs = np.concatenate([[0], np.cumsum(Ms)])
+    for i in sorted({int(np.argmax(Ls)), int(np.argmin(Ls)), 7, 100, 200}):
+        ref = oracle.padded_1d(synth.uniform_complex(Ls[i], 313, i, 0, NP_DT[dtype]).astype(np.complex128),
+                               synth.uniform_complex(Ls[i], 313, i, 1, NP_DT[dtype]).astype(np.complex128), Ms[i])
+        assert rel(h[offs[i]:offs[i + 1]], ref) <= TOL[dtype], (i, Ls[i])
+
+
 def test_batch_full_workload_sampled():
     """4096 complex64 problems, L log-uniform in [64, 65536]; 40 problems checked in full."""
     Ls = synth.batch_lengths(4096, 6, 16, cfg=3)
