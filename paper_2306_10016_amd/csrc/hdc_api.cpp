@@ -188,6 +188,12 @@ hdc_status derive_axis(int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, in
         return fail(HDC_ERR_UNSUPPORTED, "real data (HDC_R32 / HDC_R64) are implemented for 1D plans (hdc_plan) only");
     if (dtype != HDC_C64 && dtype != HDC_C128) return fail(HDC_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
     if (L < 1) return fail(HDC_ERR_INVALID_ARG, "L = %lld must be >= 1", (long long)L);
+    // no admissible size comes near 2^40; bounding every argument first keeps
+    // the products below (2L, p m, q m) inside 64 bits
+    constexpr int64_t kHuge = int64_t(1) << 40;
+    if (L >= kHuge || M >= kHuge || m >= kHuge || p >= kHuge || q >= kHuge || C >= kHuge || D >= kHuge ||
+        K >= kHuge)
+        return fail(HDC_ERR_UNSUPPORTED, "sizes of 2^40 and beyond are not supported");
     if (K < 0) K = 2 * L - 1;
     if (M < 1) return fail(HDC_ERR_INVALID_ARG, "M = %lld must be >= 1", (long long)M);
     const int64_t Mt = std::max(M, K);
@@ -205,8 +211,10 @@ hdc_status derive_axis(int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, in
     if (D == 0 || D > q) D = q;
     if (!is_pow2(m)) return fail(HDC_ERR_UNSUPPORTED, "m = %lld: only powers of two are implemented", (long long)m);
     const int64_t N = q * m;
-    if (N >= (int64_t(1) << 31) || M * C >= (int64_t(1) << 40))
+    if (N >= (int64_t(1) << 31))
         return fail(HDC_ERR_UNSUPPORTED, "N = %lld exceeds the 32-bit twiddle index range", (long long)N);
+    if (C > (int64_t(1) << 40) / M)
+        return fail(HDC_ERR_UNSUPPORTED, "M C = %lld x %lld outputs exceed 2^40", (long long)M, (long long)C);
     o->L = L;
     o->M = M;
     o->m = m;
@@ -342,6 +350,9 @@ hdc_status derive_uneq(int64_t Lf, int64_t Lg, int64_t M, int64_t m, int64_t lam
                        bool inner_nd = false) {
     if (Lf < 1 || Lg < 1) return fail(HDC_ERR_INVALID_ARG, "Lf = %lld and Lg = %lld must be >= 1", (long long)Lf,
                                       (long long)Lg);
+    constexpr int64_t kHuge = int64_t(1) << 40;  // as in derive_axis: keeps Lf + Lg and Lambda m in range
+    if (Lf >= kHuge || Lg >= kHuge || M >= kHuge || m >= kHuge || lam >= kHuge)
+        return fail(HDC_ERR_UNSUPPORTED, "sizes of 2^40 and beyond are not supported");
     const bool sw = Lf > Lg;
     const int64_t Ls = sw ? Lg : Lf, Ll = sw ? Lf : Lg;
     if (M < 1) return fail(HDC_ERR_INVALID_ARG, "M = %lld must be >= 1", (long long)M);
@@ -1347,6 +1358,7 @@ hdc_status hdc_plan_multi(hdc_plan_t* out, int A, int64_t L, int64_t M, int64_t 
     *out = nullptr;
     if (A < 2 || A > kMaxOps) return fail(HDC_ERR_INVALID_ARG, "A = %d operands: must be 2 .. %d", A, kMaxOps);
     if (L < 1) return fail(HDC_ERR_INVALID_ARG, "L = %lld must be >= 1", (long long)L);
+    if (L >= (int64_t(1) << 40)) return fail(HDC_ERR_UNSUPPORTED, "sizes of 2^40 and beyond are not supported");
     hdc_plan_s* P = new hdc_plan_s();
     P->ndim = 1;
     P->dtype = dtype;
@@ -1421,6 +1433,24 @@ hdc_status hdc_plan_uneq(hdc_plan_t* out, int64_t Lf, int64_t Lg, int64_t M, int
     return HDC_OK;
 }
 
+// Extents of an N-D problem.  No buffer is longer along an axis than that
+// axis' transform length N; the column kernels index m2 x (inner extents)
+// columns in 32 bits, and the element count must stay far inside 64 bits.
+static hdc_status nd_extents_ok(int ndim, const AxisPlan* ax) {
+    int64_t total = 1;
+    for (int a = 0; a < ndim; ++a) {
+        int64_t inner = 1;
+        for (int b = a + 1; b < ndim; ++b) inner *= ax[b].d.N;  // at most two factors below 2^31
+        if (inner > ((int64_t(1) << 31) - 1) / std::max<int64_t>(1, ax[a].d.m2))
+            return fail(HDC_ERR_UNSUPPORTED, "axis %d: %lld x %lld columns exceed the 32-bit range", a,
+                        (long long)ax[a].d.m2, (long long)inner);
+        if (total > (int64_t(1) << 40) / ax[a].d.N)
+            return fail(HDC_ERR_UNSUPPORTED, "the N-D transform holds more than 2^40 values");
+        total *= ax[a].d.N;
+    }
+    return HDC_OK;
+}
+
 static hdc_status uneq_nd_fill(hdc_plan_s* P, int ndim, const int64_t* Lf, const int64_t* Lg, const int64_t* M,
                                const int64_t* m, const int64_t* Lambda, const int64_t* D) {
     if (!Lf || !Lg || !M) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
@@ -1434,7 +1464,8 @@ static hdc_status uneq_nd_fill(hdc_plan_s* P, int ndim, const int64_t* Lf, const
                                   a < ndim - 1, ndim > 1 && a == ndim - 1);
         if (st != HDC_OK) return st;
     }
-    return HDC_OK;
+    hdc_status st = nd_extents_ok(ndim, P->ax);
+    return st == HDC_OK ? nd_extents_ok(ndim, P->fx) : st;
 }
 
 hdc_status hdc_uneq_nd_check(int ndim, const int64_t* Lf, const int64_t* Lg, const int64_t* M, const int64_t* m,
@@ -1508,7 +1539,7 @@ hdc_status hdc_plan_nd_check(int ndim, const int64_t* L, const int64_t* M, const
         if (st != HDC_OK) return st;
         if (out) out[a] = ax[a].d;
     }
-    return HDC_OK;
+    return nd_extents_ok(ndim, ax);
 }
 
 hdc_status hdc_plan_destroy(hdc_plan_t P) {

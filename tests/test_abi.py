@@ -50,6 +50,10 @@ def test_derive_fig2_shape():
     ((10, 19, 6), 2),            # m not a power of two: unsupported by the kernels
     ((10, 19, 4, 0, 0, 0), 1),   # C < 1
     ((1 << 23, (1 << 24) - 1, 1 << 24), 2),  # m beyond the column x row limit
+    ((1 << 62, 1 << 40, 1 << 20), 2),           # L far beyond any supported size (2L - 1 would overflow)
+    ((100, 199, 16, 1 << 62, 0), 2),            # p m would overflow
+    ((100, 199, 16, 0, 1 << 61), 2),            # q m would overflow
+    ((1000, 1999, 1024, 0, 0, 1 << 39), 2),     # M C beyond 2^40 (the product stays in range)
 ])
 def test_derive_rejects(args, status):
     with pytest.raises(hdc.HdcError) as e:
@@ -86,6 +90,15 @@ def test_nd_check_is_host_only_and_reports_axes():
     assert d[1]["p"] == 1 and d[1]["q"] == 2
     with pytest.raises(hdc.HdcError):
         hdc.check_nd([1024, 4096], [2047, 8191], [1 << 21, 4096], dtype="c64")  # outer m > 2^20
+    # extents whose column count (m2 x inner transform lengths) or element count
+    # would leave the kernels' index ranges
+    for L, m in (([1 << 20] * 3, [1 << 20, 1 << 20, 4096]), ([1 << 20, 1 << 21], [1 << 20, 1 << 22])):
+        with pytest.raises(hdc.HdcError) as e:
+            hdc.check_nd(L, [2 * x - 1 for x in L], m, dtype="c64")
+        assert e.value.status == 2
+    with pytest.raises(hdc.HdcError) as e:
+        hdc.uneq_nd_check([1 << 20] * 3, [1 << 20] * 3)
+    assert e.value.status == 2
 
 
 @pytest.mark.parametrize("Lf,Lg,m,lam", [(12, 1000, 16, 4), (37, 38, 8, 2), (5, 20000, 4, 1024), (1000, 100000, 32768, 4),
@@ -130,6 +143,9 @@ def test_uneq_derive_errors():
         assert e.value.status == 2
     with pytest.raises(hdc.HdcError):
         hdc.uneq_derive(0, 1000, 1011)
+    with pytest.raises(hdc.HdcError) as e:  # Lf + Lg - 1 would overflow
+        hdc.uneq_derive(1 << 62, 1 << 62, 1 << 62)
+    assert e.value.status == 2
 
 
 @pytest.mark.parametrize("sf,sg,m,lam", [((12, 12), (4096, 4096), None, None), ((5, 8), (3000, 20), (8, 8), (512, 4)),
@@ -199,3 +215,13 @@ def test_largest_1d_geometry_fits_lds(dtype):
                 continue
             ax = hdc.check_nd([L], [2 * L - 1], [m], dtype=dtype)[0]
             assert ax["m1"] * ax["m2"] == m
+
+
+def test_multi_plan_rejects_before_touching_the_device():
+    """hdc_plan_multi validates on the host: operand count, lengths, and sizes whose
+    term count A (L - 1) + 1 would overflow."""
+    for args, kw, status in [((1, 100), {}, 1), ((9, 100), {}, 1), ((3, 0), {}, 1),
+                             ((3, 1 << 62), {"M": 100}, 2), ((3, 100), {"m": 64, "q": 2}, 1)]:
+        with pytest.raises(hdc.HdcError) as e:
+            hdc.MultiPlan(*args, **kw)
+        assert e.value.status == status, (args, kw)
