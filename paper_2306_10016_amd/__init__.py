@@ -159,7 +159,9 @@ class Plan:
         return tuple(ax["M"] for ax in self.axes)
 
     def workspace(self, device=None):
-        """A cached device workspace of ``workspace_bytes`` (allocated by torch)."""
+        """A cached device workspace of ``workspace_bytes`` (allocated by torch).  Calls
+        that use it must not overlap: concurrent calls on different streams each
+        pass a workspace of their own (``ws=``)."""
         import torch
         if self.workspace_bytes == 0:
             return None
