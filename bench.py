@@ -145,8 +145,49 @@ def secondary(args, dev, hdc, synth, log):
         t = timed(lambda: plan.convolve(ft, gt, h), 200)
         plan8 = hdc.Plan(1024, 2047, 256, 4, 8, 1, 8, "c128")
         t8 = timed(lambda: plan8.convolve(ft, gt, h), 200)
+        with hdc.Profile(plan) as prof:
+            for _ in range(20):
+                plan.convolve(ft, gt, h)
+        kern_us = prof.summary()["fused"]["mean_ms"] * 1e3
+        # graph-replayed: n convolutions of the workload (own output each) captured in one
+        # HIP graph over 8 streams and replayed; every replay is checked against the eager result
+        n, K = 1024, 8
+        ref = plan.convolve(ft, gt).clone()
+        hs = torch.empty((n, 2047), dtype=torch.complex128, device=dev)
+        s0 = torch.cuda.Stream()
+        streams = [torch.cuda.Stream() for _ in range(K)]
+
+        def body():
+            for st in streams:
+                st.wait_stream(s0)
+            for i in range(n):
+                plan.convolve(ft, gt, hs[i], stream=streams[i % K])
+            for st in streams:
+                s0.wait_stream(st)
+        torch.cuda.synchronize()
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr, stream=s0, capture_error_mode="thread_local"):
+            body()
+        reps = []
+        for rep in range(7):
+            hs.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gr.replay()
+            torch.cuda.synchronize()
+            reps.append(time.perf_counter() - t0)
+            if not bool((hs == ref).all()):
+                raise RuntimeError("small-workload graph replay differs from the eager result")
+        tg = sorted(reps[2:])[len(reps[2:]) // 2]
         out["small_L1024_c128"] = {"us_per_conv_D1": round(t * 1e6, 2), "us_per_conv_D8": round(t8 * 1e6, 2),
-                                   "note": "one convolution per launch; launch latency dominates"}
+                                   "kernel_us": round(kern_us, 2),
+                                   "graph_convs_per_s": round(n / tg, 1), "graph_us_per_conv": round(tg / n * 1e6, 3),
+                                   "note": "eager: one launch per call, host launch latency dominates; kernel_us: "
+                                           "HIP-event duration of the one launch; graph: 1024 convolutions "
+                                           "captured over 8 streams and replayed"}
+        log(f"[bench] small L=1024: eager {t * 1e6:.1f} us/conv, kernel {kern_us:.1f} us, graph "
+            f"{n / tg:.0f} convs/s ({tg / n * 1e6:.2f} us/conv)")
+        del gr, hs
 
     if want("first_L"):
         # first-outputs mode: M = L (the backward range t < p of section 2.2) against
