@@ -1,0 +1,54 @@
+"""Host-side logic of bench.py: the sweep's size set, the refusal of multi-GPU runs,
+and the CPU baseline's record (run on a tiny sample, no GPU)."""
+import json
+import math
+import os
+import subprocess
+import sys
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def _smooth357(n):
+    for p in (3, 5, 7):
+        while n % p == 0:
+            n //= p
+    return n == 1
+
+
+def test_sweep_sizes_are_the_powers_of_two_and_the_3_5_7_smooth_sizes():
+    s = bench.sweep_sizes()
+    assert s == sorted(set(s))
+    pow2 = [L for L in s if L & (L - 1) == 0]
+    odd = [L for L in s if L & (L - 1)]
+    assert pow2 == [1 << k for k in range(6, 23)]
+    assert all(_smooth357(L) and 64 <= L <= 4e6 for L in odd)
+    # every 3^a 5^b 7^c in [64, 4e6] is there (brute force over the exponents)
+    want = {3 ** a * 5 ** b * 7 ** c for a in range(15) for b in range(10) for c in range(9)
+            if 64 <= 3 ** a * 5 ** b * 7 ** c <= 4e6}
+    assert set(odd) == want
+    assert len(s) == 263 and len(pow2) == 17 and len(odd) == 246
+
+
+def test_more_than_one_gpu_is_refused_before_touching_a_device():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"] and line["n_gpus"] == 2
+
+
+def test_cpu_baseline_record_on_a_tiny_sample(monkeypatch):
+    # cpu_baseline pins OMP_NUM_THREADS for its workers: restored after the test
+    monkeypatch.setenv("OMP_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", "0"))
+    out = bench.cpu_baseline([64, 81, 125, 128, 243, 256], "c128", budget_s=5.0)
+    assert out["kind"] == "oracle" and out["unit"] == "convs/s"
+    assert out["value"] > 0 and 1 <= out["cores"] <= 16
+    assert "sample" in out and "3 of 6" in out["sample"]
+    assert math.isfinite(out["value"])
