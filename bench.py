@@ -113,6 +113,45 @@ def load_traffic(kernel: str, workload: str):
     return None
 
 
+def tuner_regret(sizes, params, dtype, log, n=6, timer=None):
+    """Regret of the experience tuner (A1) against the exhaustive search (A0) on a sample
+    of the sweep (n sizes spread over L >= 4096): the A0 table and the A1 choice are timed
+    in the same session, R = T(A1 choice) / T(A0 best) - 1."""
+    from paper_2306_10016_amd import tune
+    big = [i for i, L in enumerate(sizes) if L >= 4096]
+    pick = sorted({big[round(k * (len(big) - 1) / max(1, n - 1))] for k in range(n)})
+    exhaustive = tune.Tuner1D(tune.TuneDB(None), reps=5, warmup=2, timer=timer)
+    rows = []
+    for i in pick:
+        L, M = sizes[i], 2 * sizes[i] - 1
+        r = exhaustive.a0(L, M, dtype)
+        tab = {(p["m"], p["D"]): ms for p, ms in r.table}
+        c = (int(params[i]["m"]), int(params[i]["D"]))
+        t1 = tab[c] if c in tab else exhaustive.measure(L, M, c[0], c[1], dtype)
+        rows.append({"L": L, "A1": {"m": c[0], "D": c[1]}, "A0": r.params, "A1_ms": round(t1, 4),
+                     "A0_ms": round(r.ms, 4), "A0_timings": len(r.table), "regret": round(t1 / r.ms - 1, 4)})
+    worst = max(x["regret"] for x in rows)
+    log(f"[bench] tuner regret A1 vs A0 on {len(rows)} sizes: worst {worst:+.3f}")
+    return {"kind": "A1 experience tuner vs A0 exhaustive search, 1D sweep sample", "sizes": rows,
+            "worst_regret": round(worst, 4), "mean_regret": round(sum(x["regret"] for x in rows) / len(rows), 4)}
+
+
+def predictor_summary():
+    """The learned predictor's regret on the 2D/3D evaluation problems, from the committed
+    evaluation run (training takes minutes, so it is not repeated here)."""
+    path = os.path.join(HERE, "profiles", "predictor_eval.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    ev = [{"L": e["L"], "dtype": e["dtype"], "predicted": round(e["predicted"]["regret"], 4),
+           "predicted_top2_verified": round(e["predicted_top2_verified"]["regret"], 4),
+           "separable_A0": round(e["separable_A0"]["regret"], 4), "default": round(e["default"]["regret"], 4)}
+          for e in d.get("eval", [])]
+    return {"source": "profiles/predictor_eval.json (stored run of python -m paper_2306_10016_amd.predict)",
+            "regret_vs": "joint exhaustive search", "eval": ev}
+
+
 def secondary(args, dev, hdc, synth, log):
     """Measured secondary workloads: the single small convolution, the uneven batch,
     the 2D squares/rectangles and the 2D/3D evaluation sizes, each against
@@ -787,6 +826,9 @@ def main():
     if not args.no_extras:
         del F, G, H, plans, ws
         torch.cuda.empty_cache()
+        if not args.no_tune:
+            out["tuner"] = tuner_regret(sizes, params, dt, log)
+        out["predictor"] = predictor_summary()
         out["secondary"] = secondary(args, dev, hdc, synth, log)
 
     if not args.no_cpu_baseline:

@@ -52,3 +52,37 @@ def test_cpu_baseline_record_on_a_tiny_sample(monkeypatch):
     assert out["value"] > 0 and 1 <= out["cores"] <= 16
     assert "sample" in out and "3 of 6" in out["sample"]
     assert math.isfinite(out["value"])
+
+
+def test_tuner_regret_against_the_exhaustive_table():
+    """With a synthetic cost model, A1 choices equal to the exhaustive argmin have regret
+    0 and a worse choice has exactly T(choice) / T(best) - 1."""
+    def cost(L, M, m, D, dtype):  # known argmin: the m nearest 2L, all residues
+        q = -(-M // m)
+        return 1.0 + abs(math.log2(m) - math.log2(2 * L)) + (0.5 if D < q else 0.0)
+    sizes = bench.sweep_sizes()
+    from paper_2306_10016_amd import tune
+    best = {}
+    for L in sizes:
+        t = tune.Tuner1D(tune.TuneDB(None), timer=cost).a0(L, 2 * L - 1, "c128")
+        best[L] = t.params
+    params = [dict(best[L]) for L in sizes]
+    out = bench.tuner_regret(sizes, params, "c128", lambda *a: None, timer=cost)
+    assert len(out["sizes"]) == 6 and out["worst_regret"] == 0.0
+    i = sizes.index(out["sizes"][-1]["L"])
+    params[i] = {"m": params[i]["m"] // 4, "D": 1}
+    out = bench.tuner_regret(sizes, params, "c128", lambda *a: None, timer=cost)
+    L = sizes[i]
+    M = 2 * L - 1
+    want = cost(L, M, params[i]["m"], 1, "c128") / min(
+        cost(L, M, m, D, "c128") for m, D in tune.candidates_1d(L, M, d_choices="all")) - 1
+    assert out["sizes"][-1]["regret"] == pytest.approx(want, abs=1e-4)
+    assert out["worst_regret"] > 0
+
+
+def test_predictor_summary_reads_the_committed_evaluation():
+    out = bench.predictor_summary()
+    assert out is not None and "predictor_eval.json" in out["source"]
+    assert [e["L"] for e in out["eval"]] == [[4096, 4096], [8192, 8192], [256, 256, 256]]
+    for e in out["eval"]:
+        assert set(e) >= {"predicted", "predicted_top2_verified", "separable_A0", "default"}
