@@ -381,10 +381,12 @@ def secondary(args, dev, hdc, synth, log):
         gb = torch.from_numpy(np.concatenate([synth.uniform_complex(int(L), 3, i, 1, np.complex64)
                                               for i, L in enumerate(Ls)])).to(dev)
         hb = torch.empty(B.total_M, dtype=torch.complex64, device=dev)
-        tb = timed(lambda: B.convolve(fb, gb, hb), 10)
+        graph = not args.batch_eager
+        tb = timed(lambda: B.convolve(fb, gb, hb, graph=graph), 10)
         comp = (2 * B.total_L + B.total_M) * 8
         out["batch_4096_c64"] = {"convs_per_s": round(4096 / tb, 1), "ms": round(tb * 1e3, 4), "buckets": B.n_buckets,
-                                 "compulsory_GBps": round(comp / tb / 1e9, 1)}
+                                 "compulsory_GBps": round(comp / tb / 1e9, 1),
+                                 "mode": "graph (4 lanes)" if graph else "eager (buckets in turn)"}
         del fb, gb, hb, B
 
     if want("nd"):
@@ -657,6 +659,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="default parameters m = 2^ceil(log2 L), p = 1, q = 2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
+    ap.add_argument("--batch-eager", action="store_true",
+                    help="launch the uneven batch eagerly, buckets in turn (per-kernel profiling)")
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--extras", default="", help="comma list of secondary workloads to run (default: all of "
                     "small,first_L,real,multi,batch,nd,uneq,uneq_nd)")
