@@ -204,6 +204,8 @@ hdc_status hdc_plan_multi(hdc_plan_t* out, int A, int64_t L, int64_t M, int64_t 
                           int64_t D, hdc_dtype dtype);
 hdc_status hdc_convolve_multi(hdc_plan_t plan, const void* const* x, void* h, void* ws, hipStream_t stream);
 
+/* Frees the plan and its device twiddle tables (hipFree: synchronises with the
+ * device).  No call that uses the plan may still be in flight.  NULL is a no-op. */
 hdc_status hdc_plan_destroy(hdc_plan_t plan);
 
 /* Number of axes and the description of axis `axis`. */
