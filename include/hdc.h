@@ -258,7 +258,8 @@ hdc_status hdc_backward(hdc_plan_t plan, void* F, void* h, int64_t r0, void* ws,
 
 /* Debug view: copy residues [r0, r0 + D') of F into `out` in the natural order,
  * out[(d*m + l)*C + c] = F_{q l + r0 + d} of copy c (= the length-N zero-extended
- * DFT of f at index k = q l + r). */
+ * DFT of f at index k = q l + r).  `out` (D' m C values) must not alias F;
+ * HDC_ERR_INVALID_ARG for r0 outside the plan's groups or misaligned pointers. */
 hdc_status hdc_residues_natural(hdc_plan_t plan, const void* F, int64_t r0, void* out, hipStream_t stream);
 
 /*

@@ -1686,8 +1686,10 @@ hdc_status hdc_backward(hdc_plan_t P, void* F, void* h, int64_t r0, void* ws, hi
 
 hdc_status hdc_residues_natural(hdc_plan_t P, const void* F, int64_t r0, void* out, hipStream_t s) {
     if (!P || !F || !out) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+    if (F == out) return fail(HDC_ERR_INVALID_ARG, "out must not alias F");
     int64_t Dg = 0;
     hdc_status st = group_check(P, r0, &Dg);
+    if (st == HDC_OK) st = check_ptrs(P, F, out, nullptr);
     if (st != HDC_OK) return st;
     const hdc_axis_desc& d = P->ax[0].d;
     hipError_t e = launch_natural(P->dtype == HDC_C128, F, out, Dg, d.m1, d.m2, d.C, s);
