@@ -609,10 +609,16 @@ __global__ void __launch_bounds__(REAL ? 512 : 1024) k_col_fwd(ColFwdArgs a) {
     const T* xi = reinterpret_cast<const T*>(a.x2) + xoff;
     cplx<T>* X = reinterpret_cast<cplx<T>*>(a.X) + b * a.out_bs;
 
-    // block t, point v of this thread: x[(t*m1 + s1)*Ccols + cp], zero beyond L
-#define HDC_IDX(t, v) (((int64_t)(t) * M1 + lane + (v) * TPF) * a.Ccols + cp)
+    // block t, point v of this thread: x[(t*m1 + s1)*Ccols + cp] with s1 = lane + v TPF,
+    // axis index j = t m + s1 m2 + s2, zero for j >= L.  Per-thread bases plus uniform
+    // strides, so the per-point offsets are scalar products.
+    const int64_t ibase = (int64_t)lane * a.Ccols + cp, istep_v = (int64_t)TPF * a.Ccols,
+                  istep_t = (int64_t)M1 * a.Ccols;
+    const int64_t jbase = (int64_t)lane * a.m2 + s2, jstep_v = (int64_t)TPF * a.m2,
+                  jstep_t = (int64_t)M1 * a.m2;
+#define HDC_IDX(t, v) ((t) * istep_t + ibase + (v) * istep_v)
 #define HDC_LOAD(t, v)                                                                        \
-    ((ok && (((int64_t)(t) * M1 + lane + (v) * TPF) * a.m2 + s2) < L)                         \
+    ((ok && (t) * jstep_t + jbase + (v) * jstep_v < L)                                        \
          ? (REAL ? mk<T>(xr[HDC_IDX(t, v)], xi[HDC_IDX(t, v)]) : x[HDC_IDX(t, v)])            \
          : mk<T>(0, 0))
 
@@ -633,10 +639,10 @@ __global__ void __launch_bounds__(REAL ? 512 : 1024) k_col_fwd(ColFwdArgs a) {
             }
         }
         if (r != 0) {
-            // zeta_N^{r s}, s = (lane + v TPF) m2 + s2: z0 zs^v
-            const uint32_t N = (uint32_t)a.N;
-            double2 z = tw_n(a.tw, (uint32_t)(((uint64_t)r * ((uint64_t)lane * a.m2 + s2)) % N));
-            const double2 zs = tw_n(a.tw, (uint32_t)(((uint64_t)r * a.m2 * TPF) % N));
+            // zeta_N^{r s}, s = (lane + v TPF) m2 + s2: z0 zs^v (r < q and s < m, so
+            // r s < q m = N needs no reduction)
+            double2 z = tw_n(a.tw, (uint32_t)r * (uint32_t)jbase);
+            const double2 zs = tw_n(a.tw, (uint32_t)r * (uint32_t)jstep_v);
 #pragma unroll
             for (int v = 0; v < PPT; ++v) {
                 w[v] = mul_tw<false>(w[v], z, a.hiprec);
@@ -654,10 +660,12 @@ __global__ void __launch_bounds__(REAL ? 512 : 1024) k_col_fwd(ColFwdArgs a) {
                 z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
             }
         }
+        // X[((d m1 + l1) lam + li) Ccols + cp], l1 = lane + v TPF
+        const int64_t obase = (((int64_t)d * M1 + lane) * a.lam + li) * a.Ccols + cp;
+        const int64_t ostep = (int64_t)TPF * a.lam * a.Ccols;
 #pragma unroll
         for (int v = 0; v < PPT; ++v) {
-            const int l1 = lane + v * TPF;
-            if (ok) X[(((int64_t)d * M1 + l1) * a.lam + li) * a.Ccols + cp] = w[v];
+            if (ok) X[obase + v * ostep] = w[v];
         }
     }
 #undef HDC_LOAD
@@ -704,6 +712,13 @@ __global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
     const double2 fz0 = fs ? tw_n(a.tw, (uint32_t)lane * (uint32_t)s2 * (uint32_t)a.q) : make_double2(1.0, 0.0);
     const double2 fzs = fs ? tw_n(a.tw, (uint32_t)TPF * (uint32_t)s2 * (uint32_t)a.q) : make_double2(1.0, 0.0);
 
+    // per-thread bases and uniform strides of the residue reads Y[(d m1 + l1) Ccols + cp],
+    // l1 = lane + v TPF, and of the output h[(t m1 + s1) Ccols + cp] at axis index
+    // k = t m + s1 m2 + s2, s1 = lane + v TPF
+    const int64_t ibase = (int64_t)lane * a.Ccols + cp, istep_v = (int64_t)TPF * a.Ccols,
+                  istep_t = (int64_t)M1 * a.Ccols;
+    const int64_t kbase = (int64_t)lane * a.m2 + s2, kstep_v = (int64_t)TPF * a.m2, kstep_t = (int64_t)M1 * a.m2;
+
     for (int db = 0; db < a.Dg; db += DMAX) {
         const int nd = min(DMAX, a.Dg - db);
         cplx<T> V[DMAX][PPT];
@@ -713,10 +728,7 @@ __global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
             if (dd < nd) {
                 cplx<T> w[PPT];
 #pragma unroll
-                for (int v = 0; v < PPT; ++v) {
-                    const int l1 = lane + v * TPF;
-                    w[v] = ok ? Y[((int64_t)d * M1 + l1) * a.Ccols + cp] : mk<T>(0, 0);
-                }
+                for (int v = 0; v < PPT; ++v) w[v] = ok ? Y[d * istep_t + ibase + v * istep_v] : mk<T>(0, 0);
                 if (fs) {
                     double2 z = fz0;
 #pragma unroll
@@ -727,10 +739,10 @@ __global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
                 }
                 fft_regs<T, M1, -1, LAY_COL>(w, lds + cc, tile, lane, tw1, true);
                 const int r = a.r0 + d;
-                // conj(zeta_N^{r s}), s = (lane + v TPF) m2 + s2, as z0 zs^v
-                const uint32_t N = (uint32_t)a.N;
-                double2 z = tw_n(a.tw, (uint32_t)(((uint64_t)r * ((uint64_t)lane * a.m2 + s2)) % N));
-                const double2 zs = tw_n(a.tw, (uint32_t)(((uint64_t)r * a.m2 * TPF) % N));
+                // conj(zeta_N^{r s}), s = (lane + v TPF) m2 + s2, as z0 zs^v (r < q and
+                // s < m, so r s < q m = N needs no reduction)
+                double2 z = tw_n(a.tw, (uint32_t)r * (uint32_t)kbase);
+                const double2 zs = tw_n(a.tw, (uint32_t)r * (uint32_t)kstep_v);
 #pragma unroll
                 for (int v = 0; v < PPT; ++v) {
                     V[dd][v] = scale(mul_tw<true>(w[v], z, a.hiprec), invN);
@@ -742,19 +754,27 @@ __global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
             }
         }
         const bool add = a.accumulate || db > 0;
+        // (t r) mod q for residue r = r0 + db + dd, advanced by r per block t (r < q, so
+        // one subtraction keeps it below q; unused slots dd >= nd stay at 0)
+        int e[DMAX], rs[DMAX];
+#pragma unroll
+        for (int dd = 0; dd < DMAX; ++dd) {
+            e[dd] = 0;
+            rs[dd] = dd < nd ? a.r0 + db + dd : 0;
+        }
         for (int t = 0; t < a.qout; ++t) {
             double2 z[DMAX];
 #pragma unroll
             for (int dd = 0; dd < DMAX; ++dd) {
-                const int64_t r = a.r0 + db + dd;
-                z[dd] = tw_n(a.tw, (uint32_t)(((int64_t)t * r) % a.q) * (uint32_t)a.m);
+                z[dd] = tw_n(a.tw, (uint32_t)e[dd] * (uint32_t)a.m);
+                e[dd] += rs[dd];
+                if (e[dd] >= a.q) e[dd] -= a.q;
             }
 #pragma unroll
             for (int v = 0; v < PPT; ++v) {
-                const int s1 = lane + v * TPF;
-                const int64_t k = (int64_t)t * a.m + (int64_t)s1 * a.m2 + s2;
+                const int64_t k = t * kstep_t + kbase + v * kstep_v;
                 if (!ok || k >= M) continue;
-                const int64_t idx = ((int64_t)t * M1 + s1) * a.Ccols + cp;
+                const int64_t idx = t * istep_t + ibase + v * istep_v;
                 if constexpr (REAL) {
                     T acc = 0;
 #pragma unroll
