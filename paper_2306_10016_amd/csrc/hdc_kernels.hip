@@ -357,6 +357,7 @@ __device__ __forceinline__ int xcd_task(int bid, int nblk) {
 }
 
 __device__ __forceinline__ int64_t row_base(const RowAddr& a, int64_t row) {
+    if (a.inner_cnt == 1) return row * a.outer_stride;  // uniform: plain rows need no division
     const int64_t o = row / a.inner_cnt;
     return o * a.outer_stride + (row - o * a.inner_cnt) * a.inner_stride;
 }
@@ -876,6 +877,8 @@ __global__ void __launch_bounds__(512) k_row(RowArgs a) {
     cplx<T>* buf1 = buf0 + MSZ;
     int ph = 0;
     const int64_t es = a.addr.es;
+    // point w of this thread sits at row base + lane es + w (TPF es)
+    const int64_t lbase = (int64_t)lane * es, wstep = (int64_t)TPF * es;
     const int64_t stride = (int64_t)gridDim.x * a.rpw;
     constexpr bool conv = MODE == MODE_CONV;
     constexpr bool two = conv && TWO;
@@ -890,7 +893,7 @@ __global__ void __launch_bounds__(512) k_row(RowArgs a) {
         const bool ok = row < a.nrows;
         const int64_t rb = row_base(a.addr, ok ? row : 0);
 #pragma unroll
-        for (int w = 0; w < PPT; ++w) v[w] = ok ? Ag[rb + (int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
+        for (int w = 0; w < PPT; ++w) v[w] = ok ? Ag[rb + lbase + w * wstep] : mk<T>(0, 0);
     }
     for (; base < a.nrows; base += stride) {
         const int64_t row = base + rloc;
@@ -902,20 +905,20 @@ __global__ void __launch_bounds__(512) k_row(RowArgs a) {
         cplx<T> u[PPT], pv[PPT];
         if constexpr (two) {
 #pragma unroll
-            for (int w = 0; w < PPT; ++w) u[w] = ok ? Bg[rb + (int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
+            for (int w = 0; w < PPT; ++w) u[w] = ok ? Bg[rb + lbase + w * wstep] : mk<T>(0, 0);
         }
         // a raw operand row is formed from L2-resident input while the b row
         // is in flight, so it needs no prefetch
         if constexpr (FRAW) raw_row<T, MSZ>(a, row, ok, lane, v);
         if constexpr (MODE == MODE_INV) {
 #pragma unroll
-            for (int w = 0; w < PPT; ++w) pv[w] = nok ? Ag[nrb + (int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
+            for (int w = 0; w < PPT; ++w) pv[w] = nok ? Ag[nrb + lbase + w * wstep] : mk<T>(0, 0);
             fft_rows_pp<T, MSZ, -1>(v, buf0, buf1, ph, lane, tw, ok);
         } else {
             fft_rows_pp<T, MSZ, +1>(v, buf0, buf1, ph, lane, tw, ok);
             if constexpr (!FRAW) {
 #pragma unroll
-                for (int w = 0; w < PPT; ++w) pv[w] = nok ? Ag[nrb + (int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
+                for (int w = 0; w < PPT; ++w) pv[w] = nok ? Ag[nrb + lbase + w * wstep] : mk<T>(0, 0);
             }
             if constexpr (conv) {
                 if constexpr (two) {
@@ -931,7 +934,7 @@ __global__ void __launch_bounds__(512) k_row(RowArgs a) {
         }
         if (ok) {
 #pragma unroll
-            for (int w = 0; w < PPT; ++w) Og[rb + (int64_t)(lane + w * TPF) * es] = v[w];
+            for (int w = 0; w < PPT; ++w) Og[rb + lbase + w * wstep] = v[w];
         }
         if constexpr (!FRAW) {
 #pragma unroll
