@@ -964,6 +964,7 @@ __global__ void __launch_bounds__(512) k_row_multi(RowArgs a) {
     cplx<T>* buf1 = buf0 + MSZ;
     int ph = 0;
     const int64_t es = a.addr.es;
+    const int64_t lbase = (int64_t)lane * es, wstep = (int64_t)TPF * es;  // point w at lbase + w wstep
     const int64_t stride = (int64_t)gridDim.x * a.rpw;
     const cplx<T>* X = reinterpret_cast<const cplx<T>*>(a.a);
     cplx<T>* Og = reinterpret_cast<cplx<T>*>(a.out);
@@ -973,12 +974,12 @@ __global__ void __launch_bounds__(512) k_row_multi(RowArgs a) {
         const int64_t rb = row_base(a.addr, ok ? row : 0);
         cplx<T> v[PPT], u[PPT];
 #pragma unroll
-        for (int w = 0; w < PPT; ++w) v[w] = ok ? X[rb + (int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
+        for (int w = 0; w < PPT; ++w) v[w] = ok ? X[rb + lbase + w * wstep] : mk<T>(0, 0);
         fft_rows_pp<T, MSZ, +1>(v, buf0, buf1, ph, lane, tw, ok);
         for (int o = 1; o < a.nops; ++o) {
             const cplx<T>* Xo = X + o * a.ostride;
 #pragma unroll
-            for (int w = 0; w < PPT; ++w) u[w] = ok ? Xo[rb + (int64_t)(lane + w * TPF) * es] : mk<T>(0, 0);
+            for (int w = 0; w < PPT; ++w) u[w] = ok ? Xo[rb + lbase + w * wstep] : mk<T>(0, 0);
             fft_rows_pp<T, MSZ, +1>(u, buf0, buf1, ph, lane, tw, ok);
 #pragma unroll
             for (int w = 0; w < PPT; ++w) v[w] = v[w] * u[w];
@@ -986,7 +987,7 @@ __global__ void __launch_bounds__(512) k_row_multi(RowArgs a) {
         fft_rows_pp<T, MSZ, -1>(v, buf0, buf1, ph, lane, tw, ok);
         if (ok) {
 #pragma unroll
-            for (int w = 0; w < PPT; ++w) Og[rb + (int64_t)(lane + w * TPF) * es] = v[w];
+            for (int w = 0; w < PPT; ++w) Og[rb + lbase + w * wstep] = v[w];
         }
     }
 }
