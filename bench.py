@@ -97,6 +97,26 @@ def cpu_baseline(sizes, dtype, budget_s: float = 25.0):
                       f"extrapolated to the full sweep by N log2 N weights (x{scale:.1f})"}
 
 
+def copy_bandwidth(dev, nbytes: int = 1 << 29, reps: int = 5) -> float:
+    """GB/s of a plain device-to-device copy of nbytes (read + write), median of reps,
+    timed with HIP events on the current stream."""
+    import torch
+    x = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        y.copy_(x)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    del x, y
+    t = sorted(ts)[reps // 2]
+    return 2 * nbytes / (t * 1e-3) / 1e9
+
+
 def load_traffic(kernel: str, workload: str):
     """HBM traffic per launch from the committed counter summary, if it matches the current kernels."""
     import hashlib
@@ -778,6 +798,10 @@ def main():
     comp = (2 * sizes[big] + (2 * sizes[big] - 1)) * eb
     roof["conv_ms"] = round(conv_ms, 4)
     roof["conv_compulsory_GBps"] = round(comp / (conv_ms * 1e-3) / 1e9, 1)
+    # the same kernel against the bandwidth a plain device copy reaches on this GPU
+    copy_gbps = copy_bandwidth(dev)
+    roof["copy_GBps"] = round(copy_gbps, 1)
+    roof["frac_of_copy"] = round(achieved / copy_gbps, 4)
     log(f"[bench] {value:.1f} convs/s, {ms_per_step:.3f} ms/step; dominant {dom} {achieved:.0f} GB/s")
 
     out = {"metric": METRIC, "value": round(value, 2), "unit": "convs/s", "n_gpus": 1, "steps": args.steps,
