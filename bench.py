@@ -404,9 +404,27 @@ def secondary(args, dev, hdc, synth, log):
         graph = not args.batch_eager
         tb = timed(lambda: B.convolve(fb, gb, hb, graph=graph), 10)
         comp = (2 * B.total_L + B.total_M) * 8
-        out["batch_4096_c64"] = {"convs_per_s": round(4096 / tb, 1), "ms": round(tb * 1e3, 4), "buckets": B.n_buckets,
-                                 "compulsory_GBps": round(comp / tb / 1e9, 1),
-                                 "mode": "graph (4 lanes)" if graph else "eager (buckets in turn)"}
+        res = {"convs_per_s": round(4096 / tb, 1), "ms": round(tb * 1e3, 4), "buckets": B.n_buckets,
+               "compulsory_GBps": round(comp / tb / 1e9, 1),
+               "mode": "graph (4 lanes)" if graph else "eager (buckets in turn)", "params": "default (p = 1)"}
+        if not args.no_tune:
+            # per-bucket A0: every default bucket tries m, m/2, m/4, m/8 on its own problems
+            from paper_2306_10016_amd import tune
+            t0 = time.time()
+            choice, tables = tune.tune_batch(Ls, "c64")
+            Bt = hdc.Batch(Ls, bucket_m=choice, dtype="c64")
+            tt = timed(lambda: Bt.convolve(fb, gb, hb, graph=graph), 10)
+            ref = B.convolve(fb, gb, graph=graph).clone()
+            err = float(torch.linalg.vector_norm(Bt.convolve(fb, gb, graph=graph) - ref) / torch.linalg.vector_norm(ref))
+            res["tuned"] = {"convs_per_s": round(4096 / tt, 1), "ms": round(tt * 1e3, 4), "buckets": Bt.n_buckets,
+                            "compulsory_GBps": round(comp / tt / 1e9, 1), "tuning_s": round(time.time() - t0, 1),
+                            "m_per_default_bucket": {str(k): (min(v, key=lambda r: (r[1], -r[0]))[0] if v else None)
+                                                     for k, v in tables.items()},
+                            "rel_diff_vs_default": err}
+            log(f"[bench] batch 4096 c64: default {tb * 1e3:.3f} ms, bucket-tuned {tt * 1e3:.3f} ms "
+                f"({res['tuned']['tuning_s']} s of tuning), rel diff {err:.1e}")
+            del Bt
+        out["batch_4096_c64"] = res
         del fb, gb, hb, B
 
     if want("nd"):

@@ -537,3 +537,63 @@ def uneq_nd_separable(sf, sg, M, dtype: str = "c64", timer=None, reps: int = 3, 
                 best = (t, m, lam)
         best_m[axis], best_l[axis] = best[1], best[2]
     return best_m, best_l, count
+
+
+# --------------------------------------------------------------- batches --
+
+def _batch_gpu_time(Ls: Sequence[int], ms: Sequence[int], dtype: str, reps: int = 3, warmup: int = 1) -> float:
+    """Median ms of one captured batch over problems Ls with FFT sizes ms (random inputs)."""
+    import torch
+    from . import Batch, torch_dtype, dtype_code
+    B = Batch(Ls, bucket_m=ms, dtype=dtype)
+    td = torch_dtype(dtype_code(dtype))
+    f = torch.randn(B.total_L, dtype=td, device="cuda")
+    g = torch.randn(B.total_L, dtype=td, device="cuda")
+    h = torch.empty(B.total_M, dtype=td, device="cuda")
+    ws = B.workspace()
+    for _ in range(warmup + 1):
+        B.convolve(f, g, h, ws=ws)
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        B.convolve(f, g, h, ws=ws)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    B.close()
+    return sorted(ts)[reps // 2]
+
+
+def tune_batch(Ls: Sequence[int], dtype: str = "c64", timer: Optional[Callable] = None, max_shift: int = 3,
+               reps: int = 3) -> Tuple[List[int], Dict[int, List[Tuple[int, float]]]]:
+    """Per-bucket exhaustive search (A0 of section 4.2 applied bucket by bucket) for an
+    uneven batch with M = 2L - 1.  Problems are grouped by their default FFT size (the
+    next power of two of L, p = 1); for each group every m = size / 2^j, j = 0 .. max_shift
+    (p = 1, 2, 4, 8), is timed on the group's problems alone and the fastest kept (ties:
+    the larger m).  ``timer(Ls, ms, dtype) -> ms`` defaults to the captured batch on the
+    GPU.  Returns the FFT size of every problem and each group's table [(m, ms)]."""
+    from . import HdcError
+    timer = timer or (lambda ls, ms, dt: _batch_gpu_time(ls, ms, dt, reps=reps))
+    groups: Dict[int, List[int]] = {}
+    for i, L in enumerate(Ls):
+        groups.setdefault(pow2_ceil(int(L)), []).append(i)
+    choice = [pow2_ceil(int(L)) for L in Ls]
+    tables: Dict[int, List[Tuple[int, float]]] = {}
+    for size, idx in sorted(groups.items()):
+        gl = [int(Ls[i]) for i in idx]
+        rows = []
+        for j in range(max_shift + 1):
+            m = size >> j
+            if m < 1:
+                break
+            try:
+                rows.append((m, float(timer(gl, [m] * len(gl), dtype))))
+            except HdcError:
+                continue
+        tables[size] = rows
+        if rows:
+            best = min(rows, key=lambda r: (r[1], -r[0]))[0]
+            for i in idx:
+                choice[i] = best
+    return choice, tables

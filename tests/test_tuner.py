@@ -181,3 +181,32 @@ def test_uneq_nd_separable_finds_per_axis_argmin():
         assert want[ax] in tune.uneq_nd_candidates(sf, sg, M, ax)
     m, lam, n = tune.uneq_nd_separable(sf, sg, M, timer=cost)
     assert list(zip(m, lam)) == want and n > 4
+
+
+def test_batch_tuner_picks_each_buckets_argmin():
+    """Per-bucket A0 for an uneven batch: with a synthetic cost whose best FFT size is the
+    next power of two up to L = 4096 and half of it beyond (p = 2), every group gets its
+    argmin; ties go to the larger m."""
+    Ls = [70, 100, 300, 1000, 3000, 5000, 7000, 9000, 20000, 40000, 64, 65536]
+    calls = []
+
+    def cost(ls, ms, dtype):
+        calls.append((tuple(ls), ms[0]))
+        tot = 0.0
+        for L, m in zip(ls, ms):
+            p = -(-L // m)
+            want = 1 if L <= 4096 else 2
+            tot += 1.0 + abs(p - want) + (0.0 if m >= 2 else 5.0)
+        return tot
+    choice, tables = tune.tune_batch(Ls, "c64", timer=cost)
+    for L, m in zip(Ls, choice):
+        p = -(-L // m)
+        assert p == (1 if L <= 4096 else 2), (L, m)
+        assert m == tune.pow2_ceil(L) >> (p - 1)
+    # every group timed its 4 candidates once, on its own problems only
+    groups = {tune.pow2_ceil(L) for L in Ls}
+    assert set(tables) == groups and all(len(t) == 4 for t in tables.values())
+    assert len(calls) == 4 * len(groups)
+    # a flat cost: the larger m wins the tie
+    choice, _ = tune.tune_batch([300, 5000], "c64", timer=lambda ls, ms, dt: 1.0)
+    assert choice == [512, 8192]
