@@ -284,7 +284,9 @@ hdc_status hdc_batch_plan(hdc_batch_t* out, int64_t n, const int64_t* L, const i
 hdc_status hdc_batch_workspace_size(hdc_batch_t batch, size_t* bytes);
 hdc_status hdc_batch_convolve(hdc_batch_t batch, const void* f, const void* g, void* h, void* ws,
                               hipStream_t stream);
-/* Same work as hdc_batch_convolve, launched directly without a graph. */
+/* Same work as hdc_batch_convolve, launched directly without a graph: the call to
+ * use inside a caller's stream capture (hdc_batch_convolve returns
+ * HDC_ERR_INVALID_ARG on a capturing stream, since it captures a graph of its own). */
 hdc_status hdc_batch_convolve_eager(hdc_batch_t batch, const void* f, const void* g, void* h, void* ws,
                                    hipStream_t stream);
 hdc_status hdc_batch_info(hdc_batch_t batch, int64_t* n_buckets, int64_t* total_L, int64_t* total_M);

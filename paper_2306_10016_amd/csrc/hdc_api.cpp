@@ -2028,6 +2028,11 @@ hdc_status hdc_batch_convolve_eager(hdc_batch_t Bt, const void* f, const void* g
 hdc_status hdc_batch_convolve(hdc_batch_t Bt, const void* f, const void* g, void* h, void* ws, hipStream_t s) {
     hdc_status st = batch_args(Bt, f, g, h, ws);
     if (st != HDC_OK) return st;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+        return fail(HDC_ERR_INVALID_ARG,
+                    "the stream is being captured: hdc_batch_convolve replays a graph of its own, "
+                    "call hdc_batch_convolve_eager inside a capture");
     if (!Bt->side) {
         HIP_TRY(hipStreamCreateWithFlags(&Bt->side, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&Bt->ev_in, hipEventDisableTiming));

@@ -186,3 +186,33 @@ def test_column_batches_beyond_grid_limit():
     """(16, 4096, 16): the middle axis's strided pass runs 65536 column batches (> 65535 per launch)."""
     L = (16, 4096, 16)
     _nd(L, tuple(2 * a - 1 for a in L), (16, 4096, 16), "c64", idx=99, full=False, nsample=40)
+
+
+def test_batch_inside_a_caller_capture():
+    """hdc_batch_convolve refuses a capturing stream (it replays a graph of its own);
+    hdc_batch_convolve_eager can be captured: every replay of the caller's graph, with
+    eager work between replays, equals the eager result bit for bit."""
+    import torch
+    Ls = [int(x) for x in synth.batch_lengths(48, 6, 13, cfg=314)]
+    fp = to_dev(np.concatenate([synth.uniform_complex(L, 314, i, 0, np.complex64) for i, L in enumerate(Ls)]))
+    gp = to_dev(np.concatenate([synth.uniform_complex(L, 314, i, 1, np.complex64) for i, L in enumerate(Ls)]))
+    B = hdc.Batch(Ls, dtype="c64")
+    say(f"batch in capture n={len(Ls)} buckets={B.n_buckets}")
+    ws = B.workspace()
+    eager = B.convolve(fp, gp, ws=ws, graph=False).clone()
+    out = torch.empty_like(eager)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr, stream=s, capture_error_mode="thread_local"):
+        with pytest.raises(hdc.HdcError) as e:
+            B.convolve(fp, gp, out, ws=ws, stream=s, graph=True)
+        B.convolve(fp, gp, out, ws=ws, stream=s, graph=False)
+    assert e.value.status == 1 and "captured" in str(e.value)
+    for rep in range(3):
+        out.fill_(float("nan"))
+        gr.replay()
+        tmp = torch.ones(1000, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert float(tmp) == 1000.0
+        assert torch.equal(out.view(torch.float32), eager.view(torch.float32)), rep
