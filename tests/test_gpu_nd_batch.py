@@ -35,7 +35,9 @@ def _nd(L, M, m, dtype, D=None, cfg=300, idx=0, full=True, nsample=48):
 @pytest.mark.parametrize("L,extra,m,D", [((6, 9), (0, 0), (4, 8), None), ((16, 24), (0, 3), (8, 16), None),
                                          ((16, 24), (0, 0), (8, 16), (1, 2)), ((37, 50), (5, 0), (16, 32), (3, 0)),
                                          ((1, 50), (0, 0), (1, 64), None), ((50, 1), (0, 0), (64, 1), None),
-                                         ((33, 700), (0, 0), (64, 1024), (1, 1))])
+                                         ((33, 700), (0, 0), (64, 1024), (1, 1)),
+                                         # outer axes with several input blocks (p = 3), one split 1024 x 2
+                                         ((3000, 50), (0, 0), (1024, 64), None), ((5000, 20), (0, 0), (2048, 32), None)])
 def test_2d(L, extra, m, D, dtype):
     M = tuple(2 * a - 1 + e for a, e in zip(L, extra))
     _nd(L, M, m, dtype, D=D, idx=L[0])
@@ -43,7 +45,7 @@ def test_2d(L, extra, m, D, dtype):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("L,m,D", [((8, 12, 10), (4, 8, 8), None), ((5, 6, 7), (2, 4, 8), (1, 2, 0)),
-                                   ((9, 4, 33), (16, 2, 64), None)])
+                                   ((9, 4, 33), (16, 2, 64), None), ((2500, 7, 30), (1024, 8, 32), None)])
 def test_3d(L, m, D, dtype):
     M = tuple(2 * a - 1 for a in L)
     _nd(L, M, m, dtype, D=D, idx=L[2])

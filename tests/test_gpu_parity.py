@@ -92,7 +92,8 @@ def test_column_row_passes(L, m, D, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("L,C,m", [(100, 4, 64), (37, 3, 8), (3000, 3, 8192), (2000, 5, 512)])
+@pytest.mark.parametrize("L,C,m", [(100, 4, 64), (37, 3, 8), (3000, 3, 8192), (2000, 5, 512),
+                                   (20000, 3, 8192)])  # copies through the column/row path with p = 3
 def test_copies(L, C, m, dtype):
     _check(L, 2 * L - 1, m, 0, 0, C, 0, dtype, cfg=204, idx=L)
 
