@@ -52,10 +52,39 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(sizes, dtype, budget_s: float = 25.0):
-    """The oracle (explicit zero-padded FFT, FP64 C) on a stratified sample of the sweep,
-    run by a thread pool over the host cores; extrapolated to the whole sweep by
-    N log2 N work weights."""
+def host_cpu():
+    """The host's CPU as this process sees it: nproc, the CPUs it may run on, the
+    cgroup's CPU quota (if any), the lscpu model name, and the threads that fit."""
+    import subprocess
+    nproc = os.cpu_count() or 1
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = nproc
+    quota = None
+    try:
+        q, per = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if q != "max":
+            quota = float(q) / float(per)
+    except (OSError, ValueError):
+        pass
+    model = ""
+    try:
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    threads = affinity if quota is None else max(1, min(affinity, int(quota)))
+    return {"nproc": nproc, "affinity": affinity, "cgroup_cpus": quota, "model": model, "threads": threads}
+
+
+def cpu_baseline(sizes, dtype, budget_s: float = 40.0):
+    """The oracle (explicit zero-padded FFT, FP64 C) over the whole sweep, one size per
+    task of a thread pool over every CPU this process may use.  If the estimated
+    work exceeds the budget, the largest sizes are dropped and the rate is stated
+    for the sizes actually run (no extrapolation)."""
     from concurrent.futures import ThreadPoolExecutor
 
     import numpy as np
@@ -64,37 +93,37 @@ def cpu_baseline(sizes, dtype, budget_s: float = 25.0):
     import synth
     oracle.build(force=False)
     np_dt = np.complex128 if dtype == "c128" else np.complex64
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
-    cores = max(1, min(cores, os.cpu_count() or 1, 16))
+    cpu = host_cpu()
+    cores = cpu["threads"]
     os.environ["OMP_NUM_THREADS"] = "1"
 
     def w(L):
         N = 2 * L
         return N * math.log2(N)
-    sample = list(sizes[::2])
-    # keep the sample within the budget: ~66 ns per N log2 N unit per core (measured)
+    sample = list(sizes)
+    # keep the run within the budget: ~66 ns per N log2 N unit per core (measured)
     while sample and max(sum(w(L) for L in sample) / cores, w(sample[-1])) * 66e-9 > budget_s:
         sample = sample[:-1]
 
-    def one(i_L):
-        i, L = i_L
+    data = {}
+    for i, L in enumerate(sample):
         f, g = synth.pair(L, 2, i, np_dt)
-        f = f.astype(np.complex128)
-        g = g.astype(np.complex128)
-        t = time.perf_counter()
-        oracle.padded_1d(f, g, 2 * L - 1)
-        return time.perf_counter() - t
+        data[i] = (f.astype(np.complex128), g.astype(np.complex128))
+
+    def one(i):
+        f, g = data[i]
+        oracle.padded_1d(f, g, 2 * f.shape[0] - 1)
 
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=cores) as ex:
-        list(ex.map(one, enumerate(sample)))
+        list(ex.map(one, sorted(range(len(sample)), key=lambda i: -sample[i])))
     wall = time.perf_counter() - t0
-    scale = sum(w(L) for L in sizes) / sum(w(L) for L in sample)
-    est_sweep_s = wall * scale
-    return {"value": len(sizes) / est_sweep_s, "unit": "convs/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(sample)} of {len(sizes)} sweep sizes (every 2nd, L = {sample[0]}.."
-                      f"{sample[-1]}), FP64 explicit-padded FFT oracle, {cores} threads, wall {wall:.2f} s, "
-                      f"extrapolated to the full sweep by N log2 N weights (x{scale:.1f})"}
+    del data
+    return {"value": len(sample) / wall, "unit": "convs/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(sample)} of {len(sizes)} sweep sizes (L = {sample[0]}..{sample[-1]}), one convolution "
+                      f"each, FP64 explicit-padded FFT oracle, {cores} threads (one size per thread, largest "
+                      f"first), wall {wall:.2f} s, inputs generated outside the timing",
+            "host": cpu}
 
 
 def copy_bandwidth(dev, nbytes: int = 1 << 29, reps: int = 5) -> float:
@@ -131,6 +160,42 @@ def load_traffic(kernel: str, workload: str):
     except (OSError, ValueError, KeyError):
         pass
     return None
+
+
+def roofline(summ, steps, L, eb, workload_tag, dom):
+    """The roofline object of the dominant plan (the largest transform of the step).
+
+    Unit of work: one whole convolution of that plan, i.e. all of its launches.
+    Algorithmic bytes: the compulsory (2L + M) b (read f and g, write h), the
+    per-convolution figure of the method; its time: the sum of the HIP-event
+    durations of its launches over the timed steps, divided by the steps.
+    `traffic` is the counter-measured HBM bytes of the same launches (committed
+    FETCH_SIZE / WRITE_SIZE summary, only while the kernel source is unchanged),
+    and `traffic_ratio` = traffic / algorithmic bytes.  The largest kernel is
+    reported beside it with its own read + write bytes (workspace included)."""
+    comp = (2 * L + (2 * L - 1)) * eb
+    conv_ms = sum(v["ms"] for v in summ.values()) / steps
+    achieved = comp / (conv_ms * 1e-3) / 1e9
+    traffic = 0.0
+    for k, v in summ.items():
+        t = load_traffic(k, workload_tag)
+        if t is None:
+            traffic = None
+            break
+        traffic += t * v["launches"] / steps
+    d = summ[dom]
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None if traffic is None else int(traffic),
+            "unit_of_work": f"one convolution of the dominant plan ({workload_tag}, all of its launches)",
+            "algorithmic_bytes": comp, "conv_ms": round(conv_ms, 5), "workload": workload_tag,
+            "traffic_ratio": None if traffic is None else round(traffic / comp, 3),
+            "counter_GBps": None if traffic is None else round(traffic / (conv_ms * 1e-3) / 1e9, 1),
+            "largest_kernel": {"kernel": dom, "mean_launch_ms": round(d["mean_ms"], 5),
+                               "own_bytes_per_launch": d["mean_bytes"], "own_GBps": round(d["GBps"], 1),
+                               "own_frac": round(d["GBps"] / HBM_PEAK_GBPS, 4)},
+            "all_kernels": {k: {"mean_ms": round(v["mean_ms"], 5), "own_GBps": round(v["GBps"], 1),
+                                "launches_per_conv": v["launches"] // steps} for k, v in summ.items()}}
+    return roof
 
 
 def tuner_regret(sizes, params, dtype, log, n=6, timer=None):
@@ -803,24 +868,14 @@ def main():
     d = summ[dom]
     ax = plans[big].axes[0]
     workload_tag = f"1D {dt} L={sizes[big]} m={ax['m']} p={ax['p']} q={ax['q']} D={ax['D']}"
-    achieved = d["GBps"]
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBPS, 4),
-            "traffic": load_traffic(dom, workload_tag),
-            "kernel": dom, "workload": workload_tag,
-            "mean_launch_ms": round(d["mean_ms"], 5), "algorithmic_bytes_per_launch": d["mean_bytes"],
-            "all_kernels": {k: {"mean_ms": round(v["mean_ms"], 5), "GBps": round(v["GBps"], 1),
-                                "launches_per_conv": v["launches"] // args.steps} for k, v in summ.items()}}
-    # whole-convolution bandwidth of the dominant plan against its compulsory bytes (2L + M) b
-    conv_ms = sum(v["ms"] for v in summ.values()) / args.steps
-    comp = (2 * sizes[big] + (2 * sizes[big] - 1)) * eb
-    roof["conv_ms"] = round(conv_ms, 4)
-    roof["conv_compulsory_GBps"] = round(comp / (conv_ms * 1e-3) / 1e9, 1)
-    # the same kernel against the bandwidth a plain device copy reaches on this GPU
+    roof = roofline(summ, args.steps, sizes[big], eb, workload_tag, dom)
+    # the same convolution against the bandwidth a plain device copy reaches on this GPU
     copy_gbps = copy_bandwidth(dev)
     roof["copy_GBps"] = round(copy_gbps, 1)
-    roof["frac_of_copy"] = round(achieved / copy_gbps, 4)
-    log(f"[bench] {value:.1f} convs/s, {ms_per_step:.3f} ms/step; dominant {dom} {achieved:.0f} GB/s")
+    roof["frac_of_copy"] = round(roof["achieved"] / copy_gbps, 4)
+    achieved = roof["achieved"]
+    log(f"[bench] {value:.1f} convs/s, {ms_per_step:.3f} ms/step; dominant plan {achieved:.0f} GB/s compulsory "
+        f"(frac {roof['frac']:.3f}), its largest kernel {dom}")
 
     out = {"metric": METRIC, "value": round(value, 2), "unit": "convs/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,

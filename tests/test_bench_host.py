@@ -49,9 +49,35 @@ def test_cpu_baseline_record_on_a_tiny_sample(monkeypatch):
     monkeypatch.setenv("OMP_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", "0"))
     out = bench.cpu_baseline([64, 81, 125, 128, 243, 256], "c128", budget_s=5.0)
     assert out["kind"] == "oracle" and out["unit"] == "convs/s"
-    assert out["value"] > 0 and 1 <= out["cores"] <= 16
-    assert "sample" in out and "3 of 6" in out["sample"]
-    assert math.isfinite(out["value"])
+    host = out["host"]
+    assert out["cores"] == host["threads"] >= 1 and host["nproc"] >= 1 and host["affinity"] >= 1
+    assert out["cores"] <= host["affinity"]
+    assert "sample" in out and "6 of 6" in out["sample"]
+    assert math.isfinite(out["value"]) and out["value"] > 0
+
+
+def test_roofline_is_the_compulsory_bytes_over_the_convolution_time(monkeypatch):
+    """frac = (2L + M) b / (sum of the plan's launch durations per step) / 8 TB/s;
+    traffic sums the counter bytes of every launch; the ratio is traffic / compulsory."""
+    L, eb, steps = 1 << 22, 16, 4
+    summ = {"col_fwd": {"launches": 8, "ms": 8 * 0.064, "mean_ms": 0.064, "mean_bytes": 2.0e8, "GBps": 3125.0},
+            "row": {"launches": 4, "ms": 4 * 0.111, "mean_ms": 0.111, "mean_bytes": 4.0e8, "GBps": 3600.0},
+            "col_bwd": {"launches": 4, "ms": 4 * 0.0756, "mean_ms": 0.0756, "mean_bytes": 2.7e8, "GBps": 3571.0}}
+    counters = {"col_fwd": 2.0e8, "row": 4.0e8, "col_bwd": 2.7e8}
+    monkeypatch.setattr(bench, "load_traffic", lambda k, w: counters[k])
+    r = bench.roofline(summ, steps, L, eb, "tag", "col_fwd")
+    conv_ms = 2 * 0.064 + 0.111 + 0.0756
+    comp = (4 * L - 1) * eb
+    assert r["algorithmic_bytes"] == comp
+    assert abs(r["conv_ms"] - conv_ms) < 1e-9
+    assert abs(r["achieved"] - comp / (conv_ms * 1e-3) / 1e9) < 0.1
+    assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-4
+    assert r["traffic"] == int(2 * 2.0e8 + 4.0e8 + 2.7e8)
+    assert abs(r["traffic_ratio"] - r["traffic"] / comp) < 1e-3
+    assert r["largest_kernel"]["kernel"] == "col_fwd" and r["all_kernels"]["col_fwd"]["launches_per_conv"] == 2
+    monkeypatch.setattr(bench, "load_traffic", lambda k, w: None if k == "row" else 1.0)
+    r = bench.roofline(summ, steps, L, eb, "tag", "col_fwd")
+    assert r["traffic"] is None and r["traffic_ratio"] is None
 
 
 def test_tuner_regret_against_the_exhaustive_table():

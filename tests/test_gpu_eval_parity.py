@@ -1,0 +1,129 @@
+"""GPU parity at the full evaluation sizes, checked densely.
+
+* L = 2^22, M = 2^23 - 1 (the largest sweep size) at EVERY output against the
+  oracle's explicitly padded FFT (section 3.1), one reference per dtype reused
+  for m = 2^22, 2^21, 2^20 (q = 2, 4, 8 residues).
+* The 2D/3D evaluation problems of the learned-parameter run -- 4096^2 and
+  8192^2 complex64, 256^3 complex64 -- at the parameters the per-axis tuner
+  picks for them (and at an alternative inner-axis split), on at least 256
+  outputs computed one by one by the oracle's direct sum (eq. (5)).  The
+  sample holds every output-block boundary t m - 1, t m, t m + 1 of each axis
+  (and of the outer axes' column stage m1), crossed with the boundaries and
+  random coordinates of the other axes, plus random points.
+
+Bars: relative L2 1e-12 (complex128) and 2e-6 (complex64) over the outputs
+compared; the oracle receives the complex64-rounded inputs widened to FP64.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import TOL, inputs, rel, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+hdc = pytest.importorskip("paper_2306_10016_amd")
+
+_REF = {}
+
+
+def _ref_L22(dtype):
+    """(f, g, h_ref) for L = 2^22: one padded-FFT oracle run per dtype."""
+    if dtype not in _REF:
+        L = 1 << 22
+        f, g, f64, g64 = inputs(L, 209, 0, dtype)
+        say(f"oracle padded_1d L=2^22 {dtype} ...")
+        _REF[dtype] = (f, g, oracle.padded_1d(f64, g64, 2 * L - 1))
+    return _REF[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("m", [1 << 22, 1 << 21, 1 << 20])
+def test_L22_every_output(m, dtype):
+    L = 1 << 22
+    M = 2 * L - 1
+    f, g, ref = _ref_L22(dtype)
+    say(f"L=2^22 every output m={m} {dtype}")
+    plan = hdc.Plan(L, M, m, dtype=dtype)
+    h = to_host(plan.convolve(to_dev(f), to_dev(g)))
+    err = rel(h, ref)
+    # the worst 4096-output window: an error confined to one tile or residue group shows here
+    w = 4096
+    d = np.abs(h - ref) ** 2
+    win = np.sqrt(np.add.reduceat(d, np.arange(0, M, w)) / np.add.reduceat(np.abs(ref) ** 2, np.arange(0, M, w)))
+    say(f"   q={plan.axes[0]['q']} rel={err:.3e} worst window rel={win.max():.3e}")
+    assert err <= TOL[dtype], err
+    assert win.max() <= 4 * TOL[dtype], win.max()
+
+
+def _axis_coords(Mx, marks, rng, nrand):
+    """Coordinates along one output axis: 0, 1, M-1, M-2, every mark t -/+ 1, and random ones."""
+    c = {0, 1, Mx - 2, Mx - 1}
+    for t in marks:
+        for d in (-1, 0, 1):
+            if 0 <= t + d < Mx:
+                c.add(t + d)
+    c.update(int(x) for x in rng.integers(0, Mx, nrand))
+    return sorted(c)
+
+
+def _sample(M, marks_per_axis, cfg, idx, nmin=256):
+    """Linear output indices: boundary coordinates of every axis crossed with random
+    coordinates of the others, boundary x boundary corners, and random points."""
+    rng = synth.rng(cfg, idx, 9)
+    nd = len(M)
+    bnd = [_axis_coords(M[a], marks_per_axis[a], rng, 0) for a in range(nd)]
+    pts = set()
+    for a in range(nd):
+        for x in bnd[a]:
+            for _ in range(3):
+                p = [int(rng.integers(0, M[b])) for b in range(nd)]
+                p[a] = x
+                pts.add(tuple(p))
+    # corners of boundary coordinates (a bounded random subset)
+    for _ in range(96):
+        pts.add(tuple(int(bnd[a][rng.integers(0, len(bnd[a]))]) for a in range(nd)))
+    while len(pts) < nmin + 64:
+        pts.add(tuple(int(rng.integers(0, M[a])) for a in range(nd)))
+    arr = np.array(sorted(pts), dtype=np.int64)
+    lin = np.unique(np.ravel_multi_index(tuple(arr.T), M)).astype(np.int64)
+    return lin
+
+
+EVAL = [  # (L, m, D) per axis: the tuner's choice, then an alternative split
+    ((4096, 4096), (4096, 4096), None),
+    ((4096, 4096), (4096, 2048), None),
+    ((8192, 8192), (8192, 8192), None),
+    ((8192, 8192), (8192, 4096), (0, 1)),
+    ((256, 256, 256), (128, 256, 256), None),
+    ((256, 256, 256), (256, 256, 256), (1, 0, 0)),
+]
+
+
+@pytest.mark.parametrize("L,m,D", EVAL, ids=["x".join(map(str, c[0])) + "_m" + "x".join(map(str, c[1])) for c in EVAL])
+def test_eval_problem_sampled(L, m, D):
+    import torch
+    dtype = "c64"
+    M = tuple(2 * a - 1 for a in L)
+    say(f"eval {L} m={m} D={D} {dtype}")
+    f, g, f64, g64 = inputs(tuple(L), 500, sum(L), dtype)
+    plan = hdc.Plan.nd(L, M, m, D=D, dtype=dtype)
+    marks = []
+    for ax in plan.axes:
+        # output blocks t m, the four-step split s = s1 m2 + s2 (a few multiples of m2), L - 1, L
+        mk = [t * ax["m"] for t in range(1, ax["q_out"] + 1)] + [ax["L"] - 1, ax["L"]]
+        if ax["m1"] > 1 and ax["m2"] > 1:
+            mk += [j * ax["m2"] for j in (1, 2, ax["m1"] // 2, ax["m1"] - 1)]
+        marks.append(sorted(set(mk)))
+    ks = _sample(M, marks, 500, sum(L))
+    assert ks.size >= 256
+    ws = plan.workspace("cuda")
+    h = plan.convolve(to_dev(f), to_dev(g), ws=ws)
+    hk = to_host(h.reshape(-1)[torch.from_numpy(ks).cuda()])
+    del h, ws
+    torch.cuda.empty_cache()
+    ref = oracle.direct_nd_sampled(f64, g64, M, ks)
+    err = rel(hk, ref)
+    say(f"   {ks.size} outputs, rel={err:.3e}")
+    assert err <= TOL[dtype], err

@@ -3,10 +3,15 @@ the linear convolution (M = L is the backward range t < p of section 2.2).  The
 transform still covers all 2L - 1 (or Lf + Lg - 1) terms; only the first M
 outputs are written.  Reference: the oracle's direct sum over k < M.
 
-The bar: the transform's rounding error is bounded normwise over all of its
-outputs, so a prefix inherits the absolute error of the whole; errors are
-measured as ||h - ref||_2 over the prefix divided by the norm of the full
-convolution (for a full-length output this is the usual relative L2)."""
+The bar: relative L2 over the prefix itself, ||h - ref|| / ||ref|| over the M
+outputs written, at the usual 1e-12 / 2e-6.  It is loosened only for short
+prefixes, by the factor kappa = sqrt(M/K) ||full|| / ||prefix|| (K outputs in
+the full linear convolution): the transform's rounding error is spread evenly
+over its outputs, so a prefix of M of them carries about sqrt(M/K) of the
+whole error, while its own norm is ||prefix|| / ||full|| of the whole; kappa
+is the ratio of those shares (about 1 for M = L, about 20 for M = 1 of
+L = 1000).  The bar is TOL max(1, kappa).
+"""
 import numpy as np
 import pytest
 
@@ -16,8 +21,12 @@ from tests.gpu_util import TOL, NP_DT, inputs, say, to_dev, to_host
 
 
 def rel(h, ref, full):
-    """||h - ref|| over the prefix, relative to the full convolution's norm."""
-    return float(np.linalg.norm(np.ravel(h) - np.ravel(ref)) / np.linalg.norm(np.ravel(full)))
+    """||h - ref|| / ||ref|| over the prefix, divided by max(1, kappa) (module docstring),
+    so that it is compared with the plain bar TOL."""
+    h, ref, full = np.ravel(h), np.ravel(ref), np.ravel(full)
+    nref = np.linalg.norm(ref)
+    kappa = np.sqrt(ref.size / full.size) * np.linalg.norm(full) / nref
+    return float(np.linalg.norm(h - ref) / nref / max(1.0, kappa))
 
 pytestmark = pytest.mark.gpu
 

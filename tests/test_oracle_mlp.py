@@ -81,6 +81,35 @@ def test_adam_first_step_closed_form():
     assert np.allclose(m1[0][0], 0.1 * g[0][0]) and np.allclose(v1[0][0], 0.001 * g[0][0] ** 2)
 
 
+def test_adam_second_step_closed_form():
+    """t = 2, from the definition of Adam's bias-corrected moments (Kingma & Ba):
+    m_2 = b1 (1 - b1) g_1 + (1 - b1) g_2, v_2 = b2 (1 - b2) g_1^2 + (1 - b2) g_2^2,
+    step = lr (m_2 / (1 - b1^2)) / (sqrt(v_2 / (1 - b2^2)) + eps).
+
+    Two entries pin it: a constant gradient, whose corrected moments are exactly g
+    and g^2 at every t (the purpose of the correction), so the step equals the
+    first one; and g_1 = 1, g_2 = -1, worked by hand with b1 = 0.9, b2 = 0.999:
+    m_2 = 0.09 - 0.1 = -0.01, corrected -0.01 / 0.19 = -1/19; v_2 = 0.000999 + 0.001
+    = 0.001999, corrected 0.001999 / 0.001999 = 1; step = lr (-1/19) / (1 + eps).
+    A correction that used t = 1 at t = 2 would give steps of 1.9/sqrt(1.999) and
+    -0.1/sqrt(1.999) instead."""
+    lr, eps = 0.01, 1e-8
+    params = [(np.array([[0.0, 0.0]]), np.array([0.0]))]
+    g1 = [(np.array([[0.5, 1.0]]), np.array([-3.0]))]
+    g2 = [(np.array([[0.5, -1.0]]), np.array([-3.0]))]
+    m0, v0 = mlp.zeros_like(params), mlp.zeros_like(params)
+    p1, m1, v1 = mlp.adam_step(params, g1, m0, v0, 1, lr=lr, eps=eps)
+    p2, m2, v2 = mlp.adam_step(p1, g2, m1, v1, 2, lr=lr, eps=eps)
+    step = p1[0][0] - p2[0][0]
+    # constant gradient 0.5: the same step as t = 1, lr g / (|g| + eps)
+    assert abs(step[0, 0] - lr * 0.5 / (0.5 + eps)) < 1e-15
+    assert abs((p1[0][1] - p2[0][1])[0] - lr * (-3.0) / (3.0 + eps)) < 1e-15
+    # g_1 = 1, g_2 = -1
+    assert abs(m2[0][0][0, 1] - (-0.01)) < 1e-15
+    assert abs(v2[0][0][0, 1] - 0.001999) < 1e-15
+    assert abs(step[0, 1] - lr * (-1.0 / 19.0) / (1.0 + eps)) < 1e-15
+
+
 def test_training_decreases_loss():
     X, y = _data(64, 6, 4, seed=9)
     params = _net([6, 16, 16, 16, 4], seed=9)
