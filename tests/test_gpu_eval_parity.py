@@ -2,7 +2,9 @@
 
 * L = 2^22, M = 2^23 - 1 (the largest sweep size) at EVERY output against the
   oracle's explicitly padded FFT (section 3.1), one reference per dtype reused
-  for m = 2^22, 2^21, 2^20 (q = 2, 4, 8 residues).
+  for m = 2^22, 2^21, 2^20 (q = 2, 4, 8 residues); besides the relative L2 over
+  all outputs, every 4096-output window's RMS error must stay within 4x the bar
+  times the reference's RMS.
 * The 2D/3D evaluation problems of the learned-parameter run -- 4096^2 and
   8192^2 complex64, 256^3 complex64 -- at the parameters the per-axis tuner
   picks for them (and at an alternative inner-axis split), on at least 256
@@ -48,11 +50,17 @@ def test_L22_every_output(m, dtype):
     plan = hdc.Plan(L, M, m, dtype=dtype)
     h = to_host(plan.convolve(to_dev(f), to_dev(g)))
     err = rel(h, ref)
-    # the worst 4096-output window: an error confined to one tile or residue group shows here
+    # the worst 4096-output window: an error confined to one tile or residue group
+    # shows here.  The transform's rounding error is spread evenly over the outputs
+    # (its bound is normwise over all N of them), while |h_k| falls towards both ends
+    # of the convolution, so each window's RMS error is measured against the RMS of
+    # the whole reference, not against the window's own (smaller) values.
     w = 4096
     d = np.abs(h - ref) ** 2
-    win = np.sqrt(np.add.reduceat(d, np.arange(0, M, w)) / np.add.reduceat(np.abs(ref) ** 2, np.arange(0, M, w)))
-    say(f"   q={plan.axes[0]['q']} rel={err:.3e} worst window rel={win.max():.3e}")
+    starts = np.arange(0, M, w)
+    cnt = np.diff(np.append(starts, M))
+    win = np.sqrt(np.add.reduceat(d, starts) / cnt) / np.sqrt(np.mean(np.abs(ref) ** 2))
+    say(f"   q={plan.axes[0]['q']} rel={err:.3e} worst window RMS error / reference RMS={win.max():.3e}")
     assert err <= TOL[dtype], err
     assert win.max() <= 4 * TOL[dtype], win.max()
 
