@@ -226,6 +226,24 @@ hdc_status hdc_residue_buffer_size(hdc_plan_t plan, size_t* bytes);
 hdc_status hdc_convolve(hdc_plan_t plan, const void* f, const void* g, void* h, void* ws, hipStream_t stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * work as hdc_convolve(plan, f, g, h, ws, stream), with the workspace taken
+ * from a library-owned device array of HDC_SCRATCH_BYTES bytes per GPU instead
+ * of a caller buffer.  The array is set up on a device by the first call made
+ * with that device current (one symbol-address lookup, no allocation) and
+ * stays until the process ends.  The call itself allocates nothing: no
+ * hipMalloc, hipFree or allocating library routine.  Every call on a GPU
+ * shares that GPU's array, which keeps the last call's contents; calls that
+ * overlap on one GPU (different streams, threads, or a captured graph replayed
+ * while another call runs) race on it and must be serialised by the caller.
+ * HDC_ERR_WORKSPACE when hdc_workspace_size(plan) exceeds HDC_SCRATCH_BYTES;
+ * other errors as hdc_convolve.  Multi-operand plans take hdc_convolve_multi.
+ */
+#define HDC_SCRATCH_BYTES ((size_t)64 << 20)
+hdc_status hdc_convolve_noalloc(hdc_plan_t plan, const void* f, const void* g, void* h, hipStream_t stream);
+
+/*
  * Forward residues [r0, r0 + D') of a 1D plan, D' = min(D, q - r0): the m-point
  * DFTs of eq. (3).  F holds D' x m x C values; within a residue the order is
  * implementation-defined (hdc_residues_natural gives the natural order).

@@ -29,6 +29,8 @@ from . import _lib
 from ._lib import AxisDesc, HdcError, lib, check  # noqa: F401
 
 C64, C128, R32, R64 = 0, 1, 2, 3
+# bytes of the per-GPU device array that hdc_convolve_noalloc uses as its workspace
+SCRATCH_BYTES = 64 << 20
 _DT = {"c64": C64, "complex64": C64, "c128": C128, "complex128": C128, "r32": R32, "float32": R32,
        "r64": R64, "float64": R64, C64: C64, C128: C128, R32: R32, R64: R64}
 
@@ -191,6 +193,15 @@ class Plan:
                                      _ptr(ws) if ws is not None else None, _stream(stream)))
         return out
 
+    def convolve_noalloc(self, f, g, out, stream=None):
+        """h = f * g through hdc_convolve_noalloc: the library's per-GPU scratch array
+        serves as the workspace, so the call allocates nothing (``out`` is required)."""
+        _check_tensor(f, self.dtype, self.in_numel(), "f")
+        _check_tensor(g, self.dtype, self.in_numel(), "g")
+        _check_tensor(out, self.dtype, self.out_numel(), "out")
+        check(self._lib.hdc_convolve_noalloc(self._h, _ptr(f), _ptr(g), _ptr(out), _stream(stream)))
+        return out
+
     def forward(self, f, F, r0: int, stream=None):
         _check_tensor(f, self.dtype, self.in_numel(), "f")
         check(self._lib.hdc_forward(self._h, _ptr(f), _ptr(F), int(r0), None, _stream(stream)))
@@ -338,6 +349,14 @@ class UneqPlan(Plan):
             ws = self.workspace(f.device)
         check(self._lib.hdc_convolve(self._h, _ptr(f), _ptr(g), _ptr(out),
                                      _ptr(ws) if ws is not None else None, _stream(stream)))
+        return out
+
+    def convolve_noalloc(self, f, g, out, stream=None):
+        """hdc_convolve_noalloc of the unequal-length plan (library scratch as workspace)."""
+        _check_tensor(f, self.dtype, self._numel(self.f_shape), "f")
+        _check_tensor(g, self.dtype, self._numel(self.g_shape), "g")
+        _check_tensor(out, self.dtype, self.out_numel(), "out")
+        check(self._lib.hdc_convolve_noalloc(self._h, _ptr(f), _ptr(g), _ptr(out), _stream(stream)))
         return out
 
     def forward_operand(self, operand: int, x, F, r0: int, stream=None):

@@ -53,6 +53,7 @@ SIGNATURES = {
     "hdc_workspace_size": [_P, ctypes.POINTER(ctypes.c_size_t)],
     "hdc_residue_buffer_size": [_P, ctypes.POINTER(ctypes.c_size_t)],
     "hdc_convolve": [_P, _P, _P, _P, _P, _P],
+    "hdc_convolve_noalloc": [_P, _P, _P, _P, _P],
     "hdc_forward": [_P, _P, _P, _I64, _P, _P],
     "hdc_multiply": [_P, _P, _P, _I64, _P],
     "hdc_backward": [_P, _P, _P, _I64, _P, _P],

@@ -1613,6 +1613,48 @@ hdc_status hdc_convolve(hdc_plan_t P, const void* f, const void* g, void* h, voi
     return convnd(P, 0, f, g, h, 1, (char*)ws, s);
 }
 
+// Workspace of hdc_convolve_noalloc: a device array of HDC_SCRATCH_BYTES per
+// GPU, alive until the process ends.  In host code `scratch` names a host-side
+// stand-in, never the device memory: the device address is looked up once per
+// device (hipGetSymbolAddress with that device current) and only that address
+// is handed to the kernels.
+static __device__ __align__(256) unsigned char scratch[HDC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (set up on first use).
+hdc_status scratch_address(void** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(HDC_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(HDC_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL on device %d", dev);
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return HDC_OK;
+}
+}  // namespace
+
+hdc_status hdc_convolve_noalloc(hdc_plan_t P, const void* f, const void* g, void* h, hipStream_t s) {
+    if (!P) return fail(HDC_ERR_INVALID_ARG, "NULL plan");
+    if (P->ws_bytes > HDC_SCRATCH_BYTES)
+        return fail(HDC_ERR_WORKSPACE, "the plan needs %zu bytes of workspace; hdc_convolve_noalloc holds %zu",
+                    P->ws_bytes, (size_t)HDC_SCRATCH_BYTES);
+    void* ws = nullptr;
+    if (P->ws_bytes > 0) {
+        hdc_status st = scratch_address(&ws);
+        if (st != HDC_OK) return st;
+    }
+    return hdc_convolve(P, f, g, h, ws, s);
+}
+
 static hdc_status group_check(hdc_plan_t P, int64_t r0, int64_t* Dg) {
     if (P->real) return fail(HDC_ERR_UNSUPPORTED, "a real-data plan exposes hdc_convolve only");
     if (P->ndim != 1) return fail(HDC_ERR_UNSUPPORTED, "forward/multiply/backward are defined for 1D plans");

@@ -225,3 +225,11 @@ def test_multi_plan_rejects_before_touching_the_device():
         with pytest.raises(hdc.HdcError) as e:
             hdc.MultiPlan(*args, **kw)
         assert e.value.status == status, (args, kw)
+
+
+def test_scratch_size_matches_header():
+    """The binding's SCRATCH_BYTES is the header's HDC_SCRATCH_BYTES (the no-allocation workspace)."""
+    import re
+    src = open(os.path.join(ROOT, "include", "hdc.h")).read()
+    a, b = re.search(r"#define HDC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", src).groups()
+    assert hdc.SCRATCH_BYTES == int(a) << int(b)
