@@ -210,7 +210,7 @@ def tuner_regret(sizes, params, dtype, log, n=6, timer=None):
     for i in pick:
         L, M = sizes[i], 2 * sizes[i] - 1
         r = exhaustive.a0(L, M, dtype)
-        tab = {(p["m"], p["D"]): ms for p, ms in r.table}
+        tab = {(p["m"], p["D"]): ms for p, ms in r.table if "tile" not in p}
         c = (int(params[i]["m"]), int(params[i]["D"]))
         t1 = tab[c] if c in tab else exhaustive.measure(L, M, c[0], c[1], dtype)
         rows.append({"L": L, "A1": {"m": c[0], "D": c[1]}, "A0": r.params, "A1_ms": round(t1, 4),
@@ -830,7 +830,7 @@ def main():
             params.append(tuner.a1(L, M, dt).params)
     log(f"[bench] parameters chosen ({time.time() - t0:.1f} s)")
 
-    plans = [hdc.Plan(L, 2 * L - 1, p["m"], 0, 0, 1, p["D"], dt) for L, p in zip(sizes, params)]
+    plans = [hdc.Plan.from_params(L, 2 * L - 1, dt, p) for L, p in zip(sizes, params)]
     ws_bytes = max(pl.workspace_bytes for pl in plans)
     ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()

@@ -130,6 +130,27 @@ class Plan:
         check(lib().hdc_plan_nd(ctypes.byref(h), n, a(L), a(M), a(m), a(p), a(q), a(D), dtype_code(dtype)))
         return cls(0, 0, 0, dtype=dtype, _handle=h)
 
+    @classmethod
+    def from_params(cls, L, M, dtype, params: dict, batch: int = 1):
+        """Plan from a tuner's parameter set (hdc_plan_params): ``params`` holds "m" and
+        "D" (and optionally "tile", 0 = default), scalars for 1D (int L) or per-axis
+        lists for N-D; p and q are derived."""
+        from ._lib import Params
+        from .tune import problem
+        pr = problem(L, M, dtype, batch)
+        nd = pr.ndim
+        pm = Params()
+
+        def axis(v, a):
+            return int(v[a]) if isinstance(v, (list, tuple)) else int(v)
+        for a in range(nd):
+            pm.m[a] = axis(params["m"], a)
+            pm.D[a] = axis(params.get("D", 0), a)
+            pm.tile[a] = axis(params.get("tile", 0), a)
+        h = ctypes.c_void_p()
+        check(lib().hdc_plan_params(ctypes.byref(h), ctypes.byref(pr), ctypes.byref(pm)))
+        return cls(0, 0, 0, dtype=dtype, _handle=h)
+
     # -- properties
     @property
     def L(self):

@@ -33,6 +33,20 @@ class AxisDesc(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class Problem(ctypes.Structure):
+    """hdc_problem (include/hdc_tune.h)."""
+    _fields_ = [("ndim", ctypes.c_int32), ("L", _I64 * 3), ("M", _I64 * 3), ("dtype", ctypes.c_int),
+                ("batch", _I64)]
+
+
+class Params(ctypes.Structure):
+    """hdc_params (include/hdc_tune.h): per-axis m, p, q, D, C and column tile."""
+    _fields_ = [("m", _I64 * 3), ("p", _I64 * 3), ("q", _I64 * 3), ("D", _I64 * 3), ("C", _I64 * 3),
+                ("tile", ctypes.c_int32 * 3)]
+
+
+COST_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.POINTER(Problem), ctypes.POINTER(Params), ctypes.c_void_p)
+
 SIGNATURES = {
     "hdc_derive": [_I64, _I64, _I64, _I64, _I64, _I64, _I64, ctypes.c_int, ctypes.POINTER(AxisDesc)],
     "hdc_plan": [_PP, _I64, _I64, _I64, _I64, _I64, _I64, _I64, ctypes.c_int],
@@ -71,6 +85,16 @@ SIGNATURES = {
     "hdc_profile_begin": [_P],
     "hdc_profile_end": [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int32),
                         ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double)],
+    "hdc_plan_params": [_PP, ctypes.POINTER(Problem), ctypes.POINTER(Params)],
+    "hdc_params_check": [ctypes.POINTER(Problem), ctypes.POINTER(Params), ctypes.POINTER(Params)],
+    "hdc_tune": [ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_char_p, ctypes.POINTER(Params),
+                 ctypes.POINTER(ctypes.c_double)],
+    "hdc_tune_host": [ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p,
+                      COST_FN, ctypes.c_void_p, ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_double)],
+    "hdc_build_id": [],
+    "hdc_predictor_load": [_PP, ctypes.c_char_p],
+    "hdc_predict": [_P, ctypes.POINTER(Problem), ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_float)],
+    "hdc_predictor_destroy": [_P],
     "hdc_last_error": [],
     "hdc_version": [],
 }
@@ -87,7 +111,7 @@ def lib():
         for name, args in SIGNATURES.items():
             fn = getattr(L, name)
             fn.argtypes = args
-            fn.restype = ctypes.c_char_p if name in ("hdc_last_error", "hdc_version") else _ST
+            fn.restype = ctypes.c_char_p if name in ("hdc_last_error", "hdc_version", "hdc_build_id") else _ST
         try:
             from . import mlp as _mlp
             _mlp.bind(L)

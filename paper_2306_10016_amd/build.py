@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhdc.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["hdc_kernels.hip", "hdc_api.cpp", "hdc_mlp.hip"]
+SOURCES = ["hdc_kernels.hip", "hdc_api.cpp", "hdc_mlp.hip", "hdc_tune.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = [

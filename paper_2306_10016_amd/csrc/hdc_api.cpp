@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/hdc.h"
+#include "../../include/hdc_tune.h"
 #include "hdc_internal.h"
 
 using namespace hdc;
@@ -137,6 +138,8 @@ struct AxisPlan {
     // column/row geometry
     int cf_tile = 1, cf_threads = 1, cb_tile = 1, cb_threads = 1, r_rpw = 1, r_threads = 1;
     size_t cf_lds = 0, cb_lds = 0, r_lds = 0;
+    // requested columns per workgroup of the column passes (0: the default below)
+    int tile_req = 0;
     // outer N-D axes with m2 > 1: plain strided m2-point DFT passes (column kernels)
     int mf_tile = 1, mf_threads = 1, mb_tile = 1, mb_threads = 1;
     size_t mf_lds = 0, mb_lds = 0;
@@ -302,6 +305,18 @@ hdc_status geometry(AxisPlan& A, bool outer, bool many_rows = false, bool keep_s
         A.cf_lds = (size_t)d.m1 * A.cf_tile * b;
         A.cb_tile = tile_for(tpf, tmin, 512);
         while (A.cb_tile > 1 && (size_t)d.m1 * A.cb_tile * b > 65536) A.cb_tile /= 2;
+        if (A.tile_req > 0) {
+            // a tuner's choice: the forward tile as requested, the backward one the
+            // same within its 512 threads and 64 KiB of LDS
+            if (!is_pow2(A.tile_req) || A.tile_req * tpf > 1024)
+                return fail(HDC_ERR_UNSUPPORTED, "column tile %d: a power of two with %d threads per column and "
+                            "at most 1024 threads", A.tile_req, tpf);
+            A.cf_tile = A.tile_req;
+            A.cf_threads = A.cf_tile * tpf;
+            A.cf_lds = (size_t)d.m1 * A.cf_tile * b;
+            A.cb_tile = A.tile_req;
+            while (A.cb_tile > 1 && (A.cb_tile * tpf > 512 || (size_t)d.m1 * A.cb_tile * b > 65536)) A.cb_tile /= 2;
+        }
         A.cb_threads = A.cb_tile * tpf;
         A.cb_lds = (size_t)d.m1 * A.cb_tile * b;
         const size_t tab = (size_t)pass_tab_len(d.m1) * b;
@@ -1540,6 +1555,68 @@ hdc_status hdc_plan_nd_check(int ndim, const int64_t* L, const int64_t* M, const
         if (out) out[a] = ax[a].d;
     }
     return nd_extents_ok(ndim, ax);
+}
+
+// Axes of a tuner parameter set (hdc_tune.h): derivation and geometry of every
+// axis with its column tile, the checks of hdc_plan (1D, C = batch copies) or
+// hdc_plan_nd (N-D, no copies).
+static hdc_status params_axes(const hdc_problem* pr, const hdc_params* pm, AxisPlan* ax) {
+    if (!pr || !pm) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+    const int nd = pr->ndim;
+    if (nd < 1 || nd > 3) return fail(HDC_ERR_INVALID_ARG, "ndim = %d must be 1..3", nd);
+    if (pr->dtype != HDC_C64 && pr->dtype != HDC_C128)
+        return fail(HDC_ERR_UNSUPPORTED, "tuner problems are complex (HDC_C64 / HDC_C128)");
+    if (pr->batch < 1) return fail(HDC_ERR_INVALID_ARG, "batch = %lld must be >= 1", (long long)pr->batch);
+    if (nd > 1 && pr->batch != 1) return fail(HDC_ERR_UNSUPPORTED, "batched N-D problems are not implemented");
+    for (int a = 0; a < nd; ++a) {
+        hdc_status st = derive_axis(pr->L[a], pr->M[a], pm->m[a], pm->p[a], pm->q[a], nd == 1 ? pr->batch : 1,
+                                    pm->D[a], pr->dtype, &ax[a].d);
+        if (st != HDC_OK) return st;
+        ax[a].dbl = pr->dtype == HDC_C128;
+        if (pm->tile[a] < 0) return fail(HDC_ERR_INVALID_ARG, "tile %d must be >= 0", (int)pm->tile[a]);
+        ax[a].tile_req = pm->tile[a];
+        st = geometry(ax[a], a < nd - 1, nd > 1 && a == nd - 1);
+        if (st != HDC_OK) return st;
+    }
+    return nd > 1 ? nd_extents_ok(nd, ax) : HDC_OK;
+}
+
+hdc_status hdc_params_check(const hdc_problem* pr, const hdc_params* pm, hdc_params* out) {
+    AxisPlan ax[3];
+    hdc_status st = params_axes(pr, pm, ax);
+    if (st != HDC_OK || !out) return st;
+    hdc_params o{};
+    int64_t inner = 1;
+    for (int a = pr->ndim - 1; a >= 0; --a) {
+        const hdc_axis_desc& d = ax[a].d;
+        o.m[a] = d.m;
+        o.p[a] = d.p;
+        o.q[a] = d.q;
+        o.D[a] = d.D;
+        o.C[a] = pr->ndim == 1 ? pr->batch : inner;
+        o.tile[a] = d.variant == 1 ? ax[a].cf_tile : 0;
+        inner *= d.M;
+    }
+    *out = o;
+    return HDC_OK;
+}
+
+hdc_status hdc_plan_params(hdc_plan_t* out, const hdc_problem* pr, const hdc_params* pm) {
+    if (!out) return fail(HDC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    hdc_plan_s* P = new hdc_plan_s();
+    hdc_status st = params_axes(pr, pm, P->ax);
+    if (st == HDC_OK) {
+        P->ndim = pr->ndim;
+        P->dtype = pr->dtype;
+        st = finish_plan(P);
+    }
+    if (st != HDC_OK) {
+        delete P;
+        return st;
+    }
+    *out = P;
+    return HDC_OK;
 }
 
 hdc_status hdc_plan_destroy(hdc_plan_t P) {

@@ -1,36 +1,40 @@
 """Experience-based autotuner for the hybrid-dealiasing parameters (section 4).
 
-Two searches, both scoring a parameter set by the measured time of the whole
-convolution (hdc_time_convolve: HIP events, median of the repetitions):
+The searches run in the library (hdc_tune / hdc_tune_host of
+include/hdc_tune.h); this module marshals arguments and reads the timing
+database back:
 
 * **A0** (section 4.2): exhaustive grid over the candidate FFT sizes m (each
-  fixing p = ceil(L/m), q = ceil(M/m)) and residues-per-pass D.  For N-D
-  problems each axis is searched on its own with the other axes held at
-  their defaults (the per-dimension separability argument of section 4.2).
+  fixing p = ceil(L/m), q = ceil(M/m)), residues per pass D and, for the best,
+  the column tile.  N-D problems are searched one axis at a time with the
+  other axes at their defaults (the per-dimension separability of section 4.2).
 * **A1** (section 4.3, "experience"): (1) reuse the best entry of the timing
-  database for the same problem; (2) seed with the scale-free class (p, D)
-  that won on the nearest already-tuned problem, including the rectangle ->
-  square reuse of section 4.3's third heuristic; (3) a random subset of the
-  remaining candidates (random search); (4) local refinement around the best
-  so far (the neighbouring m and D), which biases sampling toward the region
-  that scored well (the Bayesian-search idea, without a surrogate model).
+  database for the same problem; (2) seed with the scale-free classes (p, D)
+  that won on the nearest already-tuned problems; (3) random candidates; (4)
+  local refinement around the best so far (the neighbouring m and D).
 
-All timings are appended to a JSON-lines database (section 5.1 keeps every
-measured result), keyed by problem, parameters, device and library build, so a
-killed run resumes where it stopped.
+Every candidate is scored by the measured time of the whole convolution (HIP
+events, median of 5 after 2 warm-ups), or by a caller's cost function
+(``timer=``, host only: the searches' CPU tests).  All timings are appended to
+a JSON-lines database (section 5.1 keeps every measured result), keyed by
+problem, parameters, device and library build, so a killed run resumes where
+it stopped.  The unequal-length tuner and the per-bucket batch tuner below
+remain Python searches over the timing entry point.
 """
 from __future__ import annotations
 
-import hashlib
+import ctypes
 import json
 import math
 import os
 import random
+import tempfile
 import time
 from dataclasses import dataclass, field
 from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 P_CLASSES = (1, 2, 3, 4, 6, 8, 12, 16)
+A0, A1 = 0, 1
 
 
 def pow2_ceil(x: int) -> int:
@@ -38,29 +42,6 @@ def pow2_ceil(x: int) -> int:
     while m < x:
         m <<= 1
     return m
-
-
-def candidates_1d(L: int, M: int, max_m: int = 1 << 22, p_classes: Sequence[int] = P_CLASSES,
-                  d_choices: str = "q") -> List[Tuple[int, int]]:
-    """(m, D) candidates: power-of-two m whose p = ceil(L/m) is in ``p_classes``,
-    plus the explicit-padding case q = 1 when m >= M fits.  ``d_choices`` = "q"
-    (all residues in one pass) or "all" (also D = 1, 2, 4, ...)."""
-    out = []
-    m = 1
-    while m <= max_m:
-        p = -(-L // m)
-        q = -(-M // m)
-        if p in p_classes or q == 1:
-            Ds = [q]
-            if d_choices == "all":
-                d = 1
-                while d < q:
-                    Ds.append(d)
-                    d *= 2
-            for D in sorted(set(Ds)):
-                out.append((m, D))
-        m <<= 1
-    return out
 
 
 def scale_class(L: int, M: int, m: int, D: int) -> Tuple[int, int]:
@@ -76,12 +57,9 @@ def m_for_class(L: int, p: int) -> int:
 
 
 def build_hash() -> str:
-    from ._lib import LIB_PATH
-    try:
-        st = os.stat(LIB_PATH)
-        return hashlib.sha1(f"{st.st_size}:{int(st.st_mtime)}".encode()).hexdigest()[:12]
-    except OSError:
-        return "none"
+    """This library build's identity (hdc_build_id), as the tuner records it in the database."""
+    from ._lib import lib
+    return lib().hdc_build_id().decode()
 
 
 def device_name() -> str:
@@ -99,15 +77,35 @@ def problem_key(L, M, dtype: str, batch: int = 1) -> str:
 
 
 class TuneDB:
-    """Append-only JSON-lines timing database."""
+    """Append-only JSON-lines timing database shared with the library's tuner.
+
+    ``path=None`` keeps the database in a temporary file for the life of this
+    object (the library reads and appends it on every search).  ``device`` /
+    ``build`` select the rows that count ("any" accepts every value)."""
 
     def __init__(self, path: Optional[str] = None, device: Optional[str] = None, build: Optional[str] = None):
+        self._tmp = None
+        if path is None:
+            fd, path = tempfile.mkstemp(prefix="hdc_tune_", suffix=".jsonl")
+            os.close(fd)
+            self._tmp = path
         self.path = path
         self.device = device or "any"
         self.build = build or "any"
         self.rows: List[dict] = []
-        if path and os.path.exists(path):
-            with open(path) as fh:
+        self.reload()
+
+    def __del__(self):
+        if getattr(self, "_tmp", None):
+            try:
+                os.unlink(self._tmp)
+            except OSError:
+                pass
+
+    def reload(self):
+        self.rows = []
+        if os.path.exists(self.path):
+            with open(self.path) as fh:
                 for line in fh:
                     line = line.strip()
                     if not line:
@@ -123,15 +121,15 @@ class TuneDB:
         if extra:
             row.update(extra)
         self.rows.append(row)
-        if self.path:
-            d = os.path.dirname(self.path)
-            if d:
-                os.makedirs(d, exist_ok=True)
-            with open(self.path, "a") as fh:
-                fh.write(json.dumps(row) + "\n")
+        d = os.path.dirname(self.path)
+        if d:
+            os.makedirs(d, exist_ok=True)
+        with open(self.path, "a") as fh:
+            fh.write(json.dumps(row) + "\n")
 
     def _mine(self, r):
-        return r.get("device") == self.device and r.get("build") == self.build
+        return (self.device == "any" or r.get("device") == self.device) and \
+            (self.build == "any" or r.get("build") == self.build)
 
     def timings(self, key: str) -> Dict[str, float]:
         out = {}
@@ -160,139 +158,122 @@ class TuneResult:
     source: str = "search"
 
 
-def _pick(table: List[Tuple[dict, float]]) -> Tuple[dict, float]:
-    """argmin with the tie rule: within 1 %, prefer the smaller m, then the smaller D."""
-    best_ms = min(ms for _, ms in table)
-    near = [(p, ms) for p, ms in table if ms <= best_ms * 1.01]
-    near.sort(key=lambda x: (x[0]["m"], x[0]["D"], x[1]))
-    return near[0]
+def problem(L, M, dtype: str, batch: int = 1):
+    """hdc_problem of a 1D (int L) or N-D (sequence L) problem."""
+    from . import dtype_code
+    from ._lib import Problem
+    Ls = list(L) if isinstance(L, (list, tuple)) else [int(L)]
+    Ms = list(M) if isinstance(M, (list, tuple)) else [int(M)]
+    pr = Problem()
+    pr.ndim = len(Ls)
+    for a in range(len(Ls)):
+        pr.L[a], pr.M[a] = int(Ls[a]), int(Ms[a])
+    pr.dtype = dtype_code(dtype)
+    pr.batch = int(batch)
+    return pr
+
+
+def params_dict(prm, ndim: int) -> dict:
+    """hdc_params as the database writes it: {"m", "D"} (+ "tile" when not the default),
+    scalars for 1D and per-axis lists for N-D."""
+    if ndim == 1:
+        d = {"m": int(prm.m[0]), "D": int(prm.D[0])}
+        if prm.tile[0]:
+            d["tile"] = int(prm.tile[0])
+        return d
+    d = {"m": [int(prm.m[a]) for a in range(ndim)], "D": [int(prm.D[a]) for a in range(ndim)]}
+    if any(prm.tile[a] for a in range(ndim)):
+        d["tile"] = [int(prm.tile[a]) for a in range(ndim)]
+    return d
+
+
+def run_search(db: TuneDB, L, M, dtype: str, mode: int, timer: Optional[Callable] = None, batch: int = 1):
+    """One search of the library's tuner (mode A0 or A1) on problem (L, M, dtype, batch).
+    ``timer(prob, params) -> ms`` (ctypes records) replaces the GPU timing: hdc_tune_host.
+    Returns (TuneResult, the hdc_params chosen)."""
+    from ._lib import COST_FN, Params, check, lib
+    pr = problem(L, M, dtype, batch)
+    key = problem_key(L, M, dtype, batch)
+    db.reload()
+    before = len(db.timings(key))
+    best, ms = Params(), ctypes.c_double()
+    if timer is None:
+        check(lib().hdc_tune(ctypes.byref(pr), mode, db.path.encode(), ctypes.byref(best), ctypes.byref(ms)))
+    else:
+        def cost(pp, pm, _ctx):
+            try:
+                return float(timer(pp.contents, pm.contents))
+            except Exception:  # an exception cannot cross the C boundary: report the set as unusable
+                return -1.0
+        cb = COST_FN(cost)
+        check(lib().hdc_tune_host(ctypes.byref(pr), mode, db.path.encode(), db.device.encode(), db.build.encode(),
+                                  cb, None, ctypes.byref(best), ctypes.byref(ms)))
+    db.reload()
+    table = [(json.loads(pk), t) for pk, t in db.timings(key).items()]
+    source = ("db" if (mode == A1 and before > 0 and len(table) == before) else ("A0" if mode == A0 else "A1"))
+    return TuneResult(params_dict(best, pr.ndim), float(ms.value), table, source), best
 
 
 class Tuner1D:
-    """Tunes a 1D problem (L, M, dtype) on the GPU through the C-ABI."""
+    """Tunes a 1D problem (L, M, dtype) with the library's searches.
 
-    def __init__(self, db: Optional[TuneDB] = None, reps: int = 5, warmup: int = 2, max_m: int = 1 << 22,
-                 timer: Optional[Callable[[int, int, int, int, str], float]] = None, seed: int = 0):
+    ``timer(L, M, m, D, dtype) -> ms`` replaces the GPU timing (host-only
+    searches through hdc_tune_host); by default every candidate is timed on the
+    GPU by hdc_tune."""
+
+    def __init__(self, db: Optional[TuneDB] = None, reps: int = 5, warmup: int = 2,
+                 timer: Optional[Callable[[int, int, int, int, str], float]] = None):
         self.db = db or TuneDB(None)
-        self.reps = reps
+        self.reps = reps      # for measure(): the searches time with 2 warm-ups and 5 runs
         self.warmup = warmup
-        self.max_m = max_m
-        self.timer = timer  # (L, M, m, D, dtype) -> ms ; defaults to the GPU timer
-        self.rng = random.Random(seed)
+        self.timer = timer
         self._bufs = {}
 
-    # -- timing backends
-    def _gpu_time(self, L, M, m, D, dtype):
+    def _search(self, mode, L, M, dtype, batch=1):
+        t = None
+        if self.timer is not None:
+            def t(pr, pm):
+                return self.timer(int(pr.L[0]), int(pr.M[0]), int(pm.m[0]), int(pm.D[0]), dtype)
+        return run_search(self.db, L, M, dtype, mode, t, batch)[0]
+
+    def a0(self, L: int, M: int, dtype: str = "c128", batch: int = 1) -> TuneResult:
+        """Exhaustive search (section 4.2)."""
+        return self._search(A0, L, M, dtype, batch)
+
+    def a1(self, L: int, M: int, dtype: str = "c128", batch: int = 1) -> TuneResult:
+        """Experience search (section 4.3)."""
+        return self._search(A1, L, M, dtype, batch)
+
+    def measure(self, L, M, m, D, dtype, tile: int = 0) -> float:
+        """Median time of one parameter set (the caller's timer, or hdc_time_convolve)."""
+        if self.timer is not None:
+            return float(self.timer(L, M, m, D, dtype))
         import torch
         from . import Plan, torch_dtype, dtype_code
         key = (L, M, dtype)
         if key not in self._bufs:
             self._bufs.clear()
             td = torch_dtype(dtype_code(dtype))
-            f = torch.randn(L, dtype=td, device="cuda")
-            g = torch.randn(L, dtype=td, device="cuda")
-            h = torch.empty(M, dtype=td, device="cuda")
-            self._bufs[key] = (f, g, h)
+            self._bufs[key] = (torch.randn(L, dtype=td, device="cuda"), torch.randn(L, dtype=td, device="cuda"),
+                               torch.empty(M, dtype=td, device="cuda"))
         f, g, h = self._bufs[key]
-        plan = Plan(L, M, m, 0, 0, 1, D, dtype)
-        ws = _shared_ws(plan.workspace_bytes)
-        ms = plan.time_convolve(f, g, h, ws=ws, warmup=self.warmup, reps=self.reps)
+        plan = Plan.from_params(L, M, dtype, {"m": m, "D": D, "tile": tile})
+        ms = plan.time_convolve(f, g, h, ws=_shared_ws(plan.workspace_bytes), warmup=self.warmup, reps=self.reps)
         plan.close()
         ms.sort()
         return ms[len(ms) // 2]
 
-    def measure(self, L, M, m, D, dtype) -> float:
-        if self.timer is not None:
-            return float(self.timer(L, M, m, D, dtype))
-        return self._gpu_time(L, M, m, D, dtype)
 
-    def _run(self, key, L, M, dtype, cands, table, seen):
-        for (m, D) in cands:
-            params = {"m": int(m), "D": int(D)}
-            pk = json.dumps(params, sort_keys=True)
-            if pk in seen:
-                continue
-            ms = self.measure(L, M, m, D, dtype)
-            seen[pk] = ms
-            table.append((params, ms))
-            self.db.add(key, params, ms)
+def a0_candidates(L, M, dtype: str = "c128", batch: int = 1) -> List[dict]:
+    """The parameter sets the library's A0 times for a problem, in its order (a
+    host-only search with a constant cost)."""
+    seen: List[dict] = []
 
-    # -- A0: exhaustive grid
-    def a0(self, L: int, M: int, dtype: str = "c128", d_choices: str = "all") -> TuneResult:
-        key = problem_key(L, M, dtype)
-        table: List[Tuple[dict, float]] = []
-        seen = dict(self.db.timings(key))
-        for pk, ms in seen.items():
-            table.append((json.loads(pk), ms))
-        self._run(key, L, M, dtype, candidates_1d(L, M, self.max_m, d_choices=d_choices), table, seen)
-        p, ms = _pick(table)
-        return TuneResult(p, ms, table, "A0")
-
-    # -- A1: experience
-    def a1(self, L: int, M: int, dtype: str = "c128", n_random: int = 2, reuse: bool = True) -> TuneResult:
-        key = problem_key(L, M, dtype)
-        if reuse:
-            hit = self.db.best(key)
-            if hit is not None:
-                return TuneResult(hit[0], hit[1], [hit], "db")
-        cands = candidates_1d(L, M, self.max_m, d_choices="q")
-        table: List[Tuple[dict, float]] = []
-        seen: Dict[str, float] = {}
-        # (2) experience: the winning (p, D) class of the nearest tuned problems of this dtype
-        seeds = []
-        for cls in self.experience_classes(L, dtype):
-            m = m_for_class(L, cls[0])
-            if m <= self.max_m:
-                q = -(-M // m)
-                seeds.append((m, q if cls[1] == 0 else min(cls[1], q)))
-        if not seeds:
-            seeds = [(pow2_ceil(L), 2)]
-        self._run(key, L, M, dtype, seeds, table, seen)
-        # (3) random search over the rest
-        rest = [c for c in cands if json.dumps({"m": c[0], "D": c[1]}, sort_keys=True) not in seen]
-        self.rng.shuffle(rest)
-        self._run(key, L, M, dtype, rest[:n_random], table, seen)
-        # (4) local refinement around the incumbent
-        for _ in range(3):
-            best, _ms = _pick(table)
-            m0, D0 = best["m"], best["D"]
-            neigh = []
-            for m in (m0 // 2, m0 * 2):
-                if 1 <= m <= self.max_m:
-                    q = -(-M // m)
-                    p = -(-L // m)
-                    if q >= p:
-                        neigh.append((m, q))
-            q0 = -(-M // m0)
-            if D0 < q0:
-                neigh.append((m0, q0))
-            before = len(table)
-            self._run(key, L, M, dtype, neigh, table, seen)
-            if len(table) == before:
-                break
-        p, ms = _pick(table)
-        return TuneResult(p, ms, table, "A1")
-
-    def experience_classes(self, L: int, dtype: str, k: int = 2):
-        """Winning (p, D) classes of the k tuned 1D problems of this dtype nearest in log2 L."""
-        scored = []
-        for key in self.db.keys():
-            d = json.loads(key)
-            if d["dtype"] != dtype or len(d["L"]) != 1 or d["batch"] != 1:
-                continue
-            b = self.db.best(key)
-            if b is None:
-                continue
-            Lk, Mk = d["L"][0], d["M"][0]
-            scored.append((abs(math.log2(Lk) - math.log2(L)), scale_class(Lk, Mk, b[0]["m"], b[0]["D"])))
-        scored.sort()
-        out = []
-        for _, c in scored:
-            if c not in out:
-                out.append(c)
-            if len(out) >= k:
-                break
-        return out
+    def t(pr, pm):
+        seen.append(params_dict(pm, int(pr.ndim)))
+        return 1.0
+    run_search(TuneDB(None), L, M, dtype, A0, t, batch)
+    return seen
 
 
 _WS = {"buf": None}

@@ -101,7 +101,7 @@ def test_tuner_regret_against_the_exhaustive_table():
     L = sizes[i]
     M = 2 * L - 1
     want = cost(L, M, params[i]["m"], 1, "c128") / min(
-        cost(L, M, m, D, "c128") for m, D in tune.candidates_1d(L, M, d_choices="all")) - 1
+        cost(L, M, c["m"], c["D"], "c128") for c in tune.a0_candidates(L, M, "c128")) - 1
     assert out["sizes"][-1]["regret"] == pytest.approx(want, abs=1e-4)
     assert out["worst_regret"] > 0
 

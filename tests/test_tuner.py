@@ -22,19 +22,26 @@ def cost_model(L, M, m, D, dtype):
 
 @pytest.mark.parametrize("L", [37, 1000, 4096, 100000, 3 ** 13])
 def test_candidates_are_admissible(L):
+    """Every parameter set the library's A0 times is admissible (section 2.5) and in the
+    class grid: p = ceil(L/m) in the classes or q = 1."""
     M = 2 * L - 1
-    cands = tune.candidates_1d(L, M, d_choices="all")
+    cands = tune.a0_candidates(L, M, "c64")
     assert cands
-    for m, D in cands:
+    for c in cands:
+        m, D = c["m"], c["D"]
         d = hdc.derive(L, M, m, D=D)
         assert d["p"] * m >= L and d["q"] * m >= M and d["q"] >= d["p"]
         assert d["p"] in tune.P_CLASSES or d["q"] == 1
+        assert D == d["q"] or (D & (D - 1)) == 0  # all residues, or a power of two per pass
+    grid = {(c["m"], c["D"]) for c in cands if "tile" not in c}
+    assert len(grid) == len([c for c in cands if "tile" not in c])  # each timed once
 
 
 def test_a0_finds_the_model_argmin():
     t = tune.Tuner1D(tune.TuneDB(None), timer=cost_model)
     r = t.a0(5000, 9999, "c64")
     assert r.params["m"] == tune.pow2_ceil(5000) // 4 and r.params["D"] == -(-9999 // r.params["m"])
+    assert "tile" not in r.params  # the tiles cost the same: the default wins the tie
     assert r.source == "A0"
 
 
@@ -45,14 +52,15 @@ def test_a1_uses_experience_and_matches_a0_with_fewer_timings():
         calls.append((L, m, D))
         return cost_model(L, M, m, D, dt)
     db = tune.TuneDB(None)
-    t = tune.Tuner1D(db, timer=counting, seed=1)
+    t = tune.Tuner1D(db, timer=counting)
     for L in (2000, 4000, 8000):  # experience accumulates
         t.a1(L, 2 * L - 1, "c64")
     calls.clear()
     r = t.a1(16000, 31999, "c64")
     a0 = tune.Tuner1D(tune.TuneDB(None), timer=cost_model).a0(16000, 31999, "c64")
     assert r.params == a0.params
-    assert len(calls) < len(tune.candidates_1d(16000, 31999, d_choices="all"))
+    assert r.source == "A1"
+    assert len(calls) < len(tune.a0_candidates(16000, 31999, "c64"))
 
 
 def test_db_reuse_and_resume(tmp_path):
@@ -68,13 +76,35 @@ def test_db_reuse_and_resume(tmp_path):
     # another build does not reuse the timings
     db3 = tune.TuneDB(path, device="dev", build="b2")
     assert db3.best(tune.problem_key(3000, 5999, "c128")) is None
+    # a search after the cut line appends whole records that read back
+    tune.Tuner1D(db3, timer=cost_model).a0(700, 1399, "c128")
+    db4 = tune.TuneDB(path, device="dev", build="b2")
+    assert db4.best(tune.problem_key(700, 1399, "c128")) is not None
 
 
 def test_tie_rule_prefers_smaller_m_then_D():
-    table = [({"m": 64, "D": 2}, 1.000), ({"m": 32, "D": 4}, 1.005), ({"m": 32, "D": 1}, 1.009),
-             ({"m": 16, "D": 8}, 1.5)]
-    p, ms = tune._pick(table)
-    assert p == {"m": 32, "D": 1}
+    """Within 1 % of the fastest: the smaller m, then the smaller D."""
+    table = {(64, 2): 1.000, (32, 4): 1.005, (32, 1): 1.009}
+
+    def cost(L, M, m, D, dt):
+        return table.get((m, D), 2.0)
+    r = tune.Tuner1D(tune.TuneDB(None), timer=cost).a0(100, 199, "c128")
+    assert r.params == {"m": 32, "D": 1}
+
+
+def test_nd_a0_is_separable_per_axis():
+    """N-D A0 searches each axis with the others at their defaults and returns the
+    per-axis argmins combined (section 4.2)."""
+    want = {0: 64, 1: 256}
+
+    def cost(pr, pm):
+        t = 1.0
+        for a in range(2):
+            t += abs(math.log2(pm.m[a]) - math.log2(want[a])) + (0.3 if pm.D[a] < pm.q[a] else 0.0)
+        return t
+    r, best = tune.run_search(tune.TuneDB(None), [200, 300], [399, 599], "c64", tune.A0, cost)
+    assert r.params["m"] == [64, 256] and list(best.D[:2]) == list(best.q[:2])
+    assert best.p[0] == 4 and best.p[1] == 2 and best.C[0] == 599 and best.C[1] == 1
 
 
 def test_regret():
