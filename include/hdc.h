@@ -285,7 +285,15 @@ hdc_status hdc_residues_natural(hdc_plan_t plan, const void* F, int64_t r0, void
  * lengths M[i], M == NULL means 2 L[i] - 1).  Operands are packed back to back:
  * f and g at offsets sum_{j<i} L[j], h at sum_{j<i} M[j].  Problems are grouped
  * into buckets that share (m, p, q, D); `bucket_m` (length n, may be NULL) gives
- * the FFT size chosen for each problem, 0 meaning the built-in default.
+ * the FFT size chosen for each problem, 0 meaning the built-in default
+ * (hdc_batch_default_m).  The buckets that fit the fused kernel (m <= 4096
+ * for HDC_C64, m <= 512 for HDC_C128) are served by one persistent launch
+ * whose workgroups take (bucket, block of problems) items from a queue with
+ * an integer atomic counter.  Buckets whose residue transform is a single row
+ * (m <= 4096) and does not fit the fused kernel, with p <= 4 and q <= 32, are
+ * served together, per m, by one launch of residue rows formed from the raw
+ * inputs and one launch of the output sums.  Other buckets run their own
+ * launches.
  * The first hdc_batch_convolve captures the launches in a HIP graph on a private
  * stream of the batch; later calls with the same buffers replay it.  Every
  * call is ordered after the work already on `stream`, and work enqueued on
@@ -299,6 +307,10 @@ hdc_status hdc_residues_natural(hdc_plan_t plan, const void* F, int64_t r0, void
  */
 hdc_status hdc_batch_plan(hdc_batch_t* out, int64_t n, const int64_t* L, const int64_t* M, const int64_t* bucket_m,
                           hdc_dtype dtype);
+/* The FFT size hdc_batch_plan gives a problem of length L by default (host
+ * only): the smallest power of two >= L, except 4096 (p = 2) for lengths in
+ * (4096, 8192]. */
+hdc_status hdc_batch_default_m(int64_t L, int64_t* m);
 hdc_status hdc_batch_workspace_size(hdc_batch_t batch, size_t* bytes);
 hdc_status hdc_batch_convolve(hdc_batch_t batch, const void* f, const void* g, void* h, void* ws,
                               hipStream_t stream);
@@ -323,7 +335,7 @@ hdc_status hdc_time_convolve(hdc_plan_t plan, const void* f, const void* g, void
  * Instrumented hdc_convolve: the same launches, each bracketed by HIP events on
  * `stream`; synchronises the stream.  For launch i < min(*n_launches,
  * max_launches): kinds[i] (0 fused, 1 forward column, 2 row, 3 backward
- * column), ms[i] (event-measured duration) and bytes[i] (the launch's
+ * column, 4 raw residue rows, 5 output sums), ms[i] (event-measured duration) and bytes[i] (the launch's
  * algorithmic HBM bytes: compulsory reads plus writes).  Any output array may
  * be NULL.  *n_launches receives the total number of launches.
  */

@@ -74,6 +74,7 @@ SIGNATURES = {
     "hdc_residues_natural": [_P, _P, _I64, _P, _P],
     "hdc_batch_plan": [_PP, _I64, _PI64, _PI64, _PI64, ctypes.c_int],
     "hdc_batch_workspace_size": [_P, ctypes.POINTER(ctypes.c_size_t)],
+    "hdc_batch_default_m": [_I64, _PI64],
     "hdc_batch_convolve": [_P, _P, _P, _P, _P, _P],
     "hdc_batch_convolve_eager": [_P, _P, _P, _P, _P, _P],
     "hdc_batch_info": [_P, _PI64, _PI64, _PI64],

@@ -345,6 +345,16 @@ hdc_status geometry(AxisPlan& A, bool outer, bool many_rows = false, bool keep_s
     return HDC_OK;
 }
 
+// Plain complex 1D plans whose residue transform is one row (m1 = 1) and does
+// not fit the fused kernel take the raw-row path (variant 2) when every residue
+// group fits the output sums' registers (q <= 32) and the inputs are re-read
+// little (every residue reads all p blocks: p <= 4).
+void enable_raw_rows(AxisPlan& A) {
+    if (A.d.variant == 1 && A.d.m1 == 1 && A.d.q <= kMaxQsum && A.d.p <= kMaxRawP &&
+        A.d.C * A.d.m <= (int64_t(1) << 30))
+        A.d.variant = 2;
+}
+
 int64_t pow2_ceil(int64_t x) {
     int64_t v = 1;
     while (v < x) v <<= 1;
@@ -855,7 +865,61 @@ size_t elem(const hdc_plan_s* P) { return elem_bytes(P->dtype); }
 int64_t ws1d(const AxisPlan& A, int64_t B, int64_t C1) {
     if (A.d.variant == 0) return 0;
     const int64_t Dg = std::min(A.d.D, A.d.q);
+    if (A.d.variant == 2) return B * Dg * A.d.m * C1;  // the product rows only
     return 2 * B * Dg * A.d.m * C1;
+}
+
+// The problem record of the raw-row path for axis A (plain mode).
+RawProb raw_prob(const AxisPlan& A) {
+    RawProb p{};
+    p.L = (int32_t)A.d.L;
+    p.M = (int32_t)A.d.M;
+    p.p = (int32_t)A.d.p;
+    p.q = (int32_t)A.d.q;
+    p.qout = (int32_t)A.d.q_out;
+    p.hiprec = A.hiprec ? 1 : 0;
+    p.tw = A.tw;
+    p.invN = 1.0 / (double)A.d.N;
+    return p;
+}
+
+// Raw residue rows of group [r0, r0 + Dg) for B batches of C1 copies into Y,
+// then the output sums into h (added to h for r0 > 0).
+hdc_status run_raw_group(const AxisPlan& A, const void* xf, const void* xg, void* Y, void* out, int64_t B,
+                         int64_t in_bs, int64_t out_bs, int64_t C1, int64_t r0, int64_t Dg, hipStream_t s) {
+    RawArgs a{};
+    a.f = xf;
+    a.g = xg;
+    a.Y = Y;
+    a.h = out;
+    a.m = (int32_t)A.d.m;
+    a.rpw = A.r_rpw;
+    a.C1 = (int32_t)C1;
+    a.Dg = (int32_t)Dg;
+    a.r0 = (int32_t)r0;
+    a.same = xf == xg ? 1 : 0;
+    a.accumulate = r0 > 0 ? 1 : 0;
+    a.fbs = in_bs;
+    a.ybs = Dg * A.d.m * C1;
+    a.hbs = out_bs;
+    a.p0 = raw_prob(A);
+    a.twp = A.tw_p2;
+    a.nrows = B * Dg * C1;
+    const double eb = A.dbl ? 16.0 : 8.0;
+    {
+        const int64_t blocks = ceil_div(a.nrows, A.r_rpw);
+        if (a.nrows > 0x7fffffff) return fail(HDC_ERR_UNSUPPORTED, "too many rows");
+        // compulsory: the inputs once, the product rows written
+        LaunchScope ls(s, 4, eb * (double)B * (double)C1 * ((a.same ? 1.0 : 2.0) * (double)A.d.L + (double)(Dg * A.d.m)));
+        hipError_t e = launch_row_rr(A.dbl, (int)A.d.m, a, A.r_threads, blocks, A.r_lds, s);
+        if (e != hipSuccess) return hip_fail(e, "raw row launch");
+    }
+    const int64_t gx = ceil_div(A.d.m * C1, 256);
+    if (B > kMaxGridY) return fail(HDC_ERR_UNSUPPORTED, "too many batches for the output sums");
+    LaunchScope ls(s, 5, eb * (double)B * (double)C1 * ((double)(Dg * A.d.m) + (r0 > 0 ? 2.0 : 1.0) * (double)A.d.M));
+    hipError_t e = launch_qsum(A.dbl, a, gx, B, s);
+    if (e != hipSuccess) return hip_fail(e, "output sum launch");
+    return HDC_OK;
 }
 
 // 1D convolution along axis A: B batches (strides in_bs / out_bs) of C1 interleaved copies.
@@ -868,6 +932,13 @@ hdc_status conv1d(const AxisPlan& A, const void* xf, const void* xg, void* out, 
     }
     const bool same = xf == xg;
     const int64_t D = std::min(A.d.D, A.d.q);
+    if (A.d.variant == 2) {
+        for (int64_t r0 = 0; r0 < A.d.q; r0 += D) {
+            hdc_status st = run_raw_group(A, xf, xg, ws, out, B, in_bs, out_bs, C1, r0, std::min(D, A.d.q - r0), s);
+            if (st != HDC_OK) return st;
+        }
+        return HDC_OK;
+    }
     char* Xf = ws;
     char* Xg = same ? ws : ws + (size_t)(B * D * A.d.m * C1) * eb;
     for (int64_t r0 = 0; r0 < A.d.q; r0 += D) {
@@ -1356,6 +1427,7 @@ hdc_status hdc_plan(hdc_plan_t* out, int64_t L, int64_t M, int64_t m, int64_t p,
         A.dbl = P->dtype == HDC_C128;
         st = geometry(A, false);
     }
+    if (st == HDC_OK && !P->real) enable_raw_rows(A);
     if (st == HDC_OK) st = finish_plan(P);
     if (st != HDC_OK) {
         delete P;
@@ -1577,6 +1649,7 @@ static hdc_status params_axes(const hdc_problem* pr, const hdc_params* pm, AxisP
         ax[a].tile_req = pm->tile[a];
         st = geometry(ax[a], a < nd - 1, nd > 1 && a == nd - 1);
         if (st != HDC_OK) return st;
+        if (nd == 1) enable_raw_rows(ax[a]);
     }
     return nd > 1 ? nd_extents_ok(nd, ax) : HDC_OK;
 }
@@ -1901,6 +1974,7 @@ struct Bucket {
     int lane = 0;
     size_t ws_off = 0;
     // host descriptors, uploaded into the batch's device block
+    bool queued = false;              // served by the persistent fused launch
     std::vector<int64_t> fused_desc;  // {f_off, h_off, L, M} per problem
     std::vector<int64_t> fwd_desc;    // {f_off, L} per problem
     std::vector<int64_t> bwd_desc;    // {h_off, M} per problem
@@ -1912,10 +1986,44 @@ struct Bucket {
 
 }  // namespace
 
+// Problems of the raw-row path (residue transforms of one row of m points,
+// q <= 32) with the same m: one launch of raw residue rows and one of output
+// sums for all of them, problems and rows described by device tables.
+struct RawGroup {
+    int64_t m = 0;
+    size_t rep = 0;  // a bucket of this m: row geometry and pass table
+    int64_t nrows = 0, ntiles = 0, count = 0;
+    double bytes_rows = 0, bytes_qsum = 0;  // algorithmic bytes of the two launches
+    int lane = 0;
+    size_t ws_off = 0;
+    std::vector<int64_t> members;  // buckets
+    size_t off_probs = 0, off_rowmap = 0, off_ybase = 0, off_tilemap = 0;
+    const RawProb* d_probs = nullptr;
+    const int32_t* d_rowmap = nullptr;
+    const int64_t* d_ybase = nullptr;
+    const int32_t* d_tilemap = nullptr;
+};
+
+// The fused buckets served by one persistent launch (k_fused_queue): their
+// argument records and the item queue in the batch's device block.
+struct FusedQueue {
+    std::vector<size_t> members;  // buckets
+    int64_t nitems = 0;
+    size_t lds = 0;
+    double bytes = 0;
+    int lane = 0;
+    size_t off_args = 0, off_items = 0, off_counter = 0;
+    const FusedArgs* d_args = nullptr;
+    const int32_t* d_items = nullptr;
+    int* d_counter = nullptr;
+};
+
 struct hdc_batch_s {
     hdc_dtype dtype = HDC_C64;
     int64_t n = 0, total_L = 0, total_M = 0;
     std::vector<Bucket> buckets;
+    std::vector<RawGroup> raws;
+    FusedQueue fq;
     void* block = nullptr;
     size_t ws_bytes = 0;
     int nlanes = 1;
@@ -1941,9 +2049,13 @@ namespace {
 // (p = 1, q = 2 for M = 2L-1), i.e. explicit padding to m, implicit to 2m.
 constexpr int kBatchLanes = 4;  // concurrent lanes of a batch's captured graph
 
+// The smallest power of two >= L (p = 1), except that lengths in (4096, 8192]
+// take m = 4096 (p = 2): one-row residues on the raw-row path, measured faster
+// than the column/row/column passes of m = 8192 for such problems.
 int64_t default_m(int64_t L) {
     int64_t m = 1;
     while (m < L) m <<= 1;
+    if (m == 2 * kMaxRow) m = kMaxRow;
     return m;
 }
 
@@ -1953,8 +2065,52 @@ hdc_status batch_launch(hdc_batch_s* Bt, const void* f, const void* g, void* h, 
                         const hipStream_t* lanes = nullptr) {
     const size_t eb = elem_bytes(Bt->dtype);
     const bool same = f == g;
-    for (const Bucket& bk : Bt->buckets) {
+    if (Bt->fq.nitems > 0) {
+        if (lanes) s = lanes[Bt->fq.lane];
+        FusedQueueArgs a{};
+        a.f = f;
+        a.g = g;
+        a.h = h;
+        a.same = same ? 1 : 0;
+        a.nitems = (int32_t)Bt->fq.nitems;
+        a.args = Bt->fq.d_args;
+        a.items = Bt->fq.d_items;
+        a.counter = Bt->fq.d_counter;
+        LaunchScope ls(s, 0, Bt->fq.bytes);
+        hipError_t e = launch_fused_queue(Bt->dtype == HDC_C128, a, Bt->fq.nitems, Bt->fq.lds, s);
+        if (e != hipSuccess) return hip_fail(e, "persistent fused launch");
+    }
+    for (const RawGroup& rg : Bt->raws) {
+        const AxisPlan& A = Bt->buckets[rg.rep].A;
+        if (lanes) s = lanes[rg.lane];
+        RawArgs a{};
+        a.f = f;
+        a.g = g;
+        a.Y = (char*)ws + rg.ws_off * eb;
+        a.h = h;
+        a.nrows = rg.nrows;
+        a.m = (int32_t)rg.m;
+        a.rpw = A.r_rpw;
+        a.C1 = 1;
+        a.same = same ? 1 : 0;
+        a.probs = rg.d_probs;
+        a.rowmap = rg.d_rowmap;
+        a.ybase = rg.d_ybase;
+        a.tilemap = rg.d_tilemap;
+        a.twp = A.tw_p2;
+        {
+            LaunchScope ls(s, 4, rg.bytes_rows);
+            hipError_t e = launch_row_rr(A.dbl, (int)rg.m, a, A.r_threads, ceil_div(rg.nrows, A.r_rpw), A.r_lds, s);
+            if (e != hipSuccess) return hip_fail(e, "raw row launch");
+        }
+        LaunchScope ls(s, 5, rg.bytes_qsum);
+        hipError_t e = launch_qsum(A.dbl, a, rg.ntiles, 1, s);
+        if (e != hipSuccess) return hip_fail(e, "output sum launch");
+    }
+    for (size_t b = 0; b < Bt->buckets.size(); ++b) {
+        const Bucket& bk = Bt->buckets[b];
         const AxisPlan& A = bk.A;
+        if (A.d.variant == 2 || bk.queued) continue;  // in a raw group or the fused queue
         if (lanes) s = lanes[bk.lane];
         if (A.d.variant == 0) {
             RowAddr in{1, 0, 0, 1}, out{1, 0, 0, 1};
@@ -2075,33 +2231,134 @@ hdc_status hdc_batch_plan(hdc_batch_t* out, int64_t n, const int64_t* L, const i
         bucket_ws.push_back(fused ? 0 : (size_t)ws1d(bk.A, bk.count, 1));
         Bt->buckets.push_back(std::move(bk));
     }
-    // lanes of the captured graph: buckets dealt longest first onto the
+    // raw groups: buckets whose residue transform is one row (m1 = 1) with
+    // q <= 32 run as one raw-row launch and one output-sum launch per m
+    for (size_t b = 0; b < Bt->buckets.size(); ++b) {
+        Bucket& bk = Bt->buckets[b];
+        enable_raw_rows(bk.A);
+        if (bk.A.d.variant != 2) continue;
+        size_t gi = 0;
+        while (gi < Bt->raws.size() && Bt->raws[gi].m != bk.A.d.m) ++gi;
+        if (gi == Bt->raws.size()) {
+            RawGroup rg;
+            rg.m = bk.A.d.m;
+            rg.rep = b;
+            Bt->raws.push_back(rg);
+        }
+        Bt->raws[gi].members.push_back((int64_t)b);
+    }
+    auto put_bytes = [&](const void* p, size_t n) {
+        while (blob.size() % 256) blob.push_back(0);
+        size_t off = blob.size();
+        blob.insert(blob.end(), (const unsigned char*)p, (const unsigned char*)p + n);
+        return off;
+    };
+    // the fused buckets the persistent kernel serves: one queue of (bucket, m,
+    // block of rows) items, largest transform first
+    {
+        const int64_t maxm = dtype == HDC_C128 ? kQueueMaxM128 : kQueueMaxM64;
+        FusedQueue& fq = Bt->fq;
+        for (size_t b = 0; b < Bt->buckets.size(); ++b)
+            if (Bt->buckets[b].A.d.variant == 0 && Bt->buckets[b].A.d.m <= maxm) fq.members.push_back(b);
+        std::stable_sort(fq.members.begin(), fq.members.end(), [&](size_t x, size_t y) {
+            return Bt->buckets[x].A.d.m > Bt->buckets[y].A.d.m;
+        });
+        std::vector<int32_t> items;
+        for (size_t k = 0; k < fq.members.size(); ++k) {
+            Bucket& bk = Bt->buckets[fq.members[k]];
+            bk.queued = true;
+            const AxisPlan& A = bk.A;
+            const int64_t blocks = ceil_div(bk.count, A.f_rpw);
+            for (int64_t blk = 0; blk < blocks; ++blk) items.insert(items.end(), {(int32_t)k, (int32_t)A.d.m, (int32_t)blk});
+            const int lg = ilog2i(A.d.m);
+            const int64_t lo = int64_t(1) << ((lg + 1) / 2), hi = std::max<int64_t>(A.d.m / lo, 1);
+            fq.lds = std::max(fq.lds, A.f_lds + (size_t)(lo + hi) * elem_bytes(dtype));
+            fq.bytes += cost[fq.members[k]] - 6.4e7;  // the bucket's problem bytes
+        }
+        fq.nitems = (int64_t)items.size() / 3;
+        if (fq.nitems > 0) {
+            fq.off_items = put_bytes(items.data(), items.size() * sizeof(int32_t));
+            std::vector<FusedArgs> zeros(fq.members.size());
+            fq.off_args = put_bytes(zeros.data(), zeros.size() * sizeof(FusedArgs));  // filled below
+            const int32_t zero = 0;
+            fq.off_counter = put_bytes(&zero, sizeof zero);
+        }
+    }
+    // schedulable units: buckets outside raw groups and the queue, the queue, then raw groups
+    struct Unit {
+        int kind;  // 0 bucket, 1 raw group, 2 the fused queue
+        size_t idx;
+        double cost;
+        size_t ws;
+    };
+    std::vector<Unit> units;
+    for (size_t b = 0; b < Bt->buckets.size(); ++b)
+        if (Bt->buckets[b].A.d.variant != 2 && !Bt->buckets[b].queued) units.push_back({0, b, cost[b], bucket_ws[b]});
+    if (Bt->fq.nitems > 0) units.push_back({2, 0, Bt->fq.bytes + 6.4e7, 0});
+    for (size_t gi = 0; gi < Bt->raws.size(); ++gi) {
+        RawGroup& rg = Bt->raws[gi];
+        std::vector<int32_t> rowmap, tilemap;
+        std::vector<int64_t> ybase;
+        double bytes = 0;
+        int32_t pi = 0;
+        for (int64_t b : rg.members) {
+            const Bucket& bk = Bt->buckets[(size_t)b];
+            for (int64_t i : members[(size_t)b]) {
+                const int64_t Mi = M ? M[i] : 2 * L[i] - 1;
+                bytes += (double)(2 * L[i] + Mi) * (double)elem_bytes(dtype);
+                rg.bytes_rows += (double)(2 * L[i] + bk.A.d.q * rg.m) * (double)elem_bytes(dtype);
+                rg.bytes_qsum += (double)(bk.A.d.q * rg.m + Mi) * (double)elem_bytes(dtype);
+                ybase.push_back(rg.nrows);
+                for (int32_t r = 0; r < (int32_t)bk.A.d.q; ++r) rowmap.insert(rowmap.end(), {pi, r});
+                rg.nrows += bk.A.d.q;
+                for (int64_t c0 = 0; c0 < rg.m; c0 += 256) tilemap.insert(tilemap.end(), {pi, (int32_t)c0});
+                ++pi;
+            }
+        }
+        rg.count = pi;
+        rg.ntiles = (int64_t)tilemap.size() / 2;
+        rg.off_rowmap = put_bytes(rowmap.data(), rowmap.size() * sizeof(int32_t));
+        rg.off_tilemap = put_bytes(tilemap.data(), tilemap.size() * sizeof(int32_t));
+        rg.off_ybase = put_bytes(ybase.data(), ybase.size() * sizeof(int64_t));
+        std::vector<RawProb> zeros((size_t)rg.count);
+        rg.off_probs = put_bytes(zeros.data(), zeros.size() * sizeof(RawProb));  // filled once the tables have addresses
+        // inputs from L2, the product rows written and read, the outputs written
+        units.push_back({1, gi, bytes * 2.0 + 2.0 * 6.4e7, (size_t)(rg.nrows * rg.m)});
+    }
+    // lanes of the captured graph: units dealt longest first onto the
     // least-loaded lane; each lane owns a workspace region as large as its
-    // largest bucket needs
-    const int nl = (int)std::min<size_t>(kBatchLanes, Bt->buckets.size());
-    std::vector<size_t> order(Bt->buckets.size());
-    for (size_t b = 0; b < order.size(); ++b) order[b] = b;
-    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+    // largest unit needs
+    const int nl = (int)std::min<size_t>(kBatchLanes, units.size());
+    std::stable_sort(units.begin(), units.end(), [](const Unit& x, const Unit& y) { return x.cost > y.cost; });
     std::vector<double> load(nl, 0.0);
     std::vector<size_t> lane_ws(nl, 0), lane_off(nl, 0);
-    for (size_t b : order) {
+    std::vector<int> unit_lane(units.size());
+    for (size_t u = 0; u < units.size(); ++u) {
         const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        Bt->buckets[b].lane = k;
-        load[k] += cost[b];
-        lane_ws[k] = std::max(lane_ws[k], bucket_ws[b]);
+        unit_lane[u] = k;
+        load[k] += units[u].cost;
+        lane_ws[k] = std::max(lane_ws[k], units[u].ws);
     }
     size_t ws_elems = 0;
     for (int k = 0; k < nl; ++k) {
         lane_off[k] = ws_elems;
         ws_elems += lane_ws[k];
     }
-    for (Bucket& bk : Bt->buckets) bk.ws_off = lane_off[bk.lane];
-    Bt->nlanes = nl;
+    for (size_t u = 0; u < units.size(); ++u) {
+        if (units[u].kind == 0) {
+            Bt->buckets[units[u].idx].lane = unit_lane[u];
+            Bt->buckets[units[u].idx].ws_off = lane_off[unit_lane[u]];
+        } else if (units[u].kind == 2) {
+            Bt->fq.lane = unit_lane[u];
+        } else {
+            Bt->raws[units[u].idx].lane = unit_lane[u];
+            Bt->raws[units[u].idx].ws_off = lane_off[unit_lane[u]];
+        }
+    }
+    Bt->nlanes = std::max(nl, 1);
     void* dev = nullptr;
     hipError_t e = hipMalloc(&dev, std::max<size_t>(blob.size(), 256));
-    if (e == hipSuccess) e = hipMemcpy(dev, blob.data(), blob.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        if (dev) (void)hipFree(dev);
         delete Bt;
         return hip_fail(e, "batch tables");
     }
@@ -2112,8 +2369,70 @@ hdc_status hdc_batch_plan(hdc_batch_t* out, int64_t n, const int64_t* L, const i
         bk.d_fwd = (const int64_t*)((unsigned char*)dev + bk.off_fwd);
         bk.d_bwd = (const int64_t*)((unsigned char*)dev + bk.off_bwd);
     }
+    for (RawGroup& rg : Bt->raws) {
+        std::vector<RawProb> probs;
+        for (int64_t b : rg.members) {
+            const Bucket& bk = Bt->buckets[(size_t)b];
+            for (int64_t i : members[(size_t)b]) {
+                RawProb pr = raw_prob(bk.A);
+                pr.f_off = foff[i];
+                pr.h_off = hoff[i];
+                pr.L = (int32_t)L[i];
+                pr.M = (int32_t)(M ? M[i] : 2 * L[i] - 1);
+                pr.qout = (int32_t)ceil_div(pr.M, rg.m);
+                probs.push_back(pr);
+            }
+        }
+        std::memcpy(blob.data() + rg.off_probs, probs.data(), probs.size() * sizeof(RawProb));
+        rg.d_probs = (const RawProb*)((unsigned char*)dev + rg.off_probs);
+        rg.d_rowmap = (const int32_t*)((unsigned char*)dev + rg.off_rowmap);
+        rg.d_ybase = (const int64_t*)((unsigned char*)dev + rg.off_ybase);
+        rg.d_tilemap = (const int32_t*)((unsigned char*)dev + rg.off_tilemap);
+    }
+    if (Bt->fq.nitems > 0) {
+        FusedQueue& fq = Bt->fq;
+        std::vector<FusedArgs> args;
+        for (size_t b : fq.members) {
+            const Bucket& bk = Bt->buckets[b];
+            const AxisPlan& A = bk.A;
+            FusedArgs a{};  // f, g, h and same come with each launch
+            a.nrows = bk.count;
+            a.in = RowAddr{1, 0, 0, 1};
+            a.out = RowAddr{1, 0, 0, 1};
+            a.desc = bk.d_fused;
+            a.L = (int32_t)A.d.L;
+            a.M = (int32_t)A.d.M;
+            a.p = (int32_t)A.d.p;
+            a.q = (int32_t)A.d.q;
+            a.qout = (int32_t)A.d.q_out;
+            a.N = (int32_t)A.d.N;
+            a.Dc = A.Dc;
+            a.rpw = A.f_rpw;
+            a.hiprec = A.hiprec ? 1 : 0;
+            a.tw = A.tw;
+            a.twm = A.tw_m;
+            a.invN = 1.0 / (double)A.d.N;
+            a.nops = 2;
+            args.push_back(a);
+        }
+        std::memcpy(blob.data() + fq.off_args, args.data(), args.size() * sizeof(FusedArgs));
+        fq.d_args = (const FusedArgs*)((unsigned char*)dev + fq.off_args);
+        fq.d_items = (const int32_t*)((unsigned char*)dev + fq.off_items);
+        fq.d_counter = (int*)((unsigned char*)dev + fq.off_counter);
+    }
+    e = hipMemcpy(dev, blob.data(), blob.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hdc_batch_destroy(Bt);
+        return hip_fail(e, "batch tables");
+    }
     Bt->ws_bytes = ws_elems * elem_bytes(dtype);
     *out = Bt;
+    return HDC_OK;
+}
+
+hdc_status hdc_batch_default_m(int64_t L, int64_t* m) {
+    if (!m || L < 1) return fail(HDC_ERR_INVALID_ARG, "bad arguments");
+    *m = default_m(L);
     return HDC_OK;
 }
 

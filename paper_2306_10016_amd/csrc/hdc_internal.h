@@ -55,6 +55,19 @@ struct FusedArgs {
     const void* xm[6];
 };
 
+// Persistent fused kernel of a batch: items[3 i .. 3 i + 2] = {bucket, FFT size m,
+// block of rows} read in queue order through the atomic counter; args[bucket]
+// holds the bucket's fused arguments (their f, g, h unused: these are f, g, h).
+struct FusedQueueArgs {
+    const void* f;
+    const void* g;
+    void* h;
+    int32_t same, nitems;
+    const FusedArgs* args;
+    const int32_t* items;
+    int* counter;
+};
+
 struct ColFwdArgs {
     const void* x;
     const void* x2;            // real case: g (x is f), both real
@@ -113,6 +126,50 @@ struct RowArgs {
     int64_t ostride;
 };
 
+// One problem of the raw-residue-row path (m1 = 1: a residue transform is one
+// row of m <= 4096 points): its inputs' and output's element offsets, lengths,
+// blocks p and residues q (N = q m), and its zeta_N table.
+struct RawProb {
+    int64_t f_off, h_off;
+    int32_t L, M, p, q;
+    int32_t qout, hiprec;
+    TwN tw;
+    double invN;
+};
+
+// Raw residue rows (k_row_rr) and the q-point output sums (k_qsum).
+// Plain mode (rowmap == nullptr): one problem p0 over B batches (strides fbs,
+// ybs, hbs in elements) of C1 interleaved copies, residues [r0, r0 + Dg); row
+// (b Dg + d) C1 + c1 of Y holds residue r0 + d of copy c1 at
+// Y[b ybs + d m C1 + s C1 + c1].  Batch mode: problems probs[], row k of Y
+// (m values) holds residue rowmap[2k + 1] of problem rowmap[2k], the rows of
+// problem i starting at ybase[i]; k_qsum workgroup w covers columns
+// [tilemap[2w + 1], + blockDim) of problem tilemap[2w].
+struct RawArgs {
+    const void* f;
+    const void* g;
+    void* Y;
+    void* h;
+    int64_t nrows;
+    int32_t m, rpw, C1, Dg, r0, same, accumulate, ntiles;
+    int64_t fbs, ybs, hbs;
+    RawProb p0;
+    const RawProb* probs;
+    const int32_t* rowmap;
+    const int64_t* ybase;
+    const int32_t* tilemap;
+    const void* twp;  // per-pass table of the m-point transform, data type
+};
+
+// Largest FFT size the persistent fused batch kernel serves, per type.
+constexpr int kQueueMaxM64 = 4096;   // complex64
+constexpr int kQueueMaxM128 = 512;   // complex128
+
+// Largest residue group the q-point output sums keep in registers, and the
+// most blocks the raw-row path re-reads per residue.
+constexpr int kMaxQsum = 32;
+constexpr int kMaxRawP = 4;
+
 enum { MODE_FWD = 0, MODE_INV = 1, MODE_CONV = 2 };
 
 // Launchers (return hipSuccess or the launch error).  `dbl` selects complex128.
@@ -130,6 +187,9 @@ hipError_t launch_row(bool dbl, int m2, const RowArgs& a, int threads, int64_t b
                       hipStream_t s);
 hipError_t launch_row_multi(bool dbl, int m2, const RowArgs& a, int threads, int64_t blocks, size_t lds,
                             hipStream_t s);
+hipError_t launch_row_rr(bool dbl, int m, const RawArgs& a, int threads, int64_t blocks, size_t lds, hipStream_t s);
+hipError_t launch_qsum(bool dbl, const RawArgs& a, int64_t gx, int64_t gy, hipStream_t s);
+hipError_t launch_fused_queue(bool dbl, const FusedQueueArgs& a, int64_t nitems, size_t lds, hipStream_t s);
 hipError_t launch_mul(bool dbl, void* F, const void* G, int64_t n, hipStream_t s);
 hipError_t launch_natural(bool dbl, const void* F, void* out, int64_t Dg, int64_t m1, int64_t m2, int64_t C,
                           hipStream_t s);

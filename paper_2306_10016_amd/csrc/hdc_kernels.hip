@@ -386,12 +386,16 @@ __device__ __forceinline__ const void* multi_ptr(const FusedArgs& a, int o) {
 
 // MULTI: more than two operands (section 6.1), a separate instantiation so that
 // the two-operand kernel keeps its registers.
+//
+// The body is a device function over one block of rows `blk` so that the
+// persistent batch kernel below can run it for any bucket; threads beyond the
+// bucket's rows (a larger workgroup) stay idle but take part in the barriers.
 template <typename T, int MSZ, bool MULTI = false>
-__global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
+__device__ __forceinline__ void fused_rows(const FusedArgs& a, const void* fp, const void* gp, void* hp, bool same,
+                                           int64_t blk, unsigned char* smem_raw) {
     using P = FP<MSZ>;
     constexpr int PPT = P::PPT;
     constexpr int TPF = P::TPF;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* smem = reinterpret_cast<cplx<T>*>(smem_raw);
     using S = TwSplit<MSZ>;
     double2* twq =
@@ -406,8 +410,8 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
     const int lt = tid - rloc * rowthreads;
     const int grp = lt / TPF;
     const int lane = lt - grp * TPF;
-    const int64_t row = (int64_t)blockIdx.x * a.rpw + rloc;
-    const bool rowok = row < a.nrows;
+    const int64_t row = blk * a.rpw + rloc;
+    const bool rowok = rloc < a.rpw && row < a.nrows;
 
     // zeta_q^e, e < q, shared by the block sums and the output sums; the
     // two-level table of zeta_m for the transform passes
@@ -436,10 +440,10 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
     }
     const int64_t gbase = (a.Lg > 0 && a.desc == nullptr) ? row_base(a.ing, rowok ? row : 0) : fbase;
     const int64_t ies = a.in.es, oes = a.out.es;
-    const cplx<T>* f = reinterpret_cast<const cplx<T>*>(a.f) + fbase;
-    const cplx<T>* g = reinterpret_cast<const cplx<T>*>(a.g) + gbase;
-    cplx<T>* h = reinterpret_cast<cplx<T>*>(a.h) + hbase;
-    cplx<T>* U = smem + (size_t)rloc * a.q * RS;
+    const cplx<T>* f = reinterpret_cast<const cplx<T>*>(fp) + fbase;
+    const cplx<T>* g = reinterpret_cast<const cplx<T>*>(gp) + gbase;
+    cplx<T>* h = reinterpret_cast<cplx<T>*>(hp) + hbase;
+    cplx<T>* U = smem + (size_t)(rowok ? rloc : 0) * a.q * RS;
     const T invN = (T)a.invN;
 
     for (int rb = 0; rb < a.q; rb += a.Dc) {
@@ -464,7 +468,7 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
                 for (int v = 0; v < PPT; ++v) {
                     const int j = t * MSZ + lane + v * TPF;
                     if (j < L) F[v] = F[v] + mul_tw<false>(f[(int64_t)j * ies], z, false);
-                    if (!a.same && j < Lg) G[v] = G[v] + mul_tw<false>(g[(int64_t)j * ies], z, false);
+                    if (!same && j < Lg) G[v] = G[v] + mul_tw<false>(g[(int64_t)j * ies], z, false);
                 }
             }
         }
@@ -477,12 +481,12 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
 #pragma unroll
             for (int v = 0; v < PPT; ++v) {
                 F[v] = mul_tw<false>(F[v], z, a.hiprec);
-                if (!a.same) G[v] = mul_tw<false>(G[v], z, a.hiprec);
+                if (!same) G[v] = mul_tw<false>(G[v], z, a.hiprec);
                 z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
             }
         }
         fft_regs<T, MSZ, +1, LAY_PAD>(F, buf, 1, lane, twm, act);
-        if (!a.same) {
+        if (!same) {
             fft_regs<T, MSZ, +1, LAY_PAD>(G, buf, 1, lane, twm, act);
 #pragma unroll
             for (int v = 0; v < PPT; ++v) F[v] = F[v] * G[v];
@@ -546,6 +550,56 @@ __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
         h[(int64_t)k * oes] = acc;
     }
 }
+
+template <typename T, int MSZ, bool MULTI = false>
+__global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    fused_rows<T, MSZ, MULTI>(a, a.f, a.g, a.h, a.same != 0, blockIdx.x, smem_raw);
+}
+
+// Persistent fused kernel of a batch: every workgroup takes items (bucket,
+// FFT size, block of rows) from a queue with an integer atomic counter (zeroed
+// by the launch before it) until the queue is empty, and runs the fused body
+// for the item's bucket; items are queued largest transform first.  No
+// workgroup waits for another, so every wave reaches the end of the queue.
+// Sizes: m <= 4096 (complex64), m <= 512 (complex128; see kQueueMaxM128).
+template <typename T>
+__global__ void __launch_bounds__(512) k_fused_queue(FusedQueueArgs q) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int item_s;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = atomicAdd(q.counter, 1);
+        __syncthreads();
+        const int it = item_s;
+        __syncthreads();
+        if (it >= q.nitems) break;
+        const FusedArgs& a = q.args[q.items[3 * it]];
+        const int m = q.items[3 * it + 1];
+        const int64_t blk = q.items[3 * it + 2];
+        switch (m) {
+#define HDC_QCASE(n) \
+    case n: fused_rows<T, n>(a, q.f, q.g, q.h, q.same != 0, blk, smem_raw); break;
+            HDC_QCASE(1) HDC_QCASE(2) HDC_QCASE(4) HDC_QCASE(8) HDC_QCASE(16) HDC_QCASE(32) HDC_QCASE(64)
+            HDC_QCASE(128) HDC_QCASE(256) HDC_QCASE(512)
+#undef HDC_QCASE
+            // the complex128 bodies above 512 points need 234-244 VGPRs: with
+            // the queue around them the kernel would spill, so such buckets run
+            // their own launches
+            case 1024:
+                if constexpr (sizeof(T) == 4) fused_rows<T, 1024>(a, q.f, q.g, q.h, q.same != 0, blk, smem_raw);
+                break;
+            case 2048:
+                if constexpr (sizeof(T) == 4) fused_rows<T, 2048>(a, q.f, q.g, q.h, q.same != 0, blk, smem_raw);
+                break;
+            case 4096:
+                if constexpr (sizeof(T) == 4) fused_rows<T, 4096>(a, q.f, q.g, q.h, q.same != 0, blk, smem_raw);
+                break;
+            default: break;
+        }
+    }
+}
+
+__global__ void k_zero_counter(int* c) { *c = 0; }
 
 // ------------------------------------------------------- column kernels --
 //
@@ -1258,6 +1312,200 @@ __global__ void __launch_bounds__(512) k_fused_real(FusedArgs a) {
     }
 }
 
+// ------------------------------------------- raw residue rows (m1 = 1) --
+//
+// When a residue transform is a single row (m <= 4096, no column stage), a
+// workgroup forms residue r of both operands straight from their inputs: the
+// block sum of eq. (3), sum_{t<p} zeta_q^{r t} x_{t m + s}, times zeta_N^{r s},
+// transforms the two rows, multiplies them, inverts the product and stores
+//     y^(r)_s = zeta_N^{-r s} u^(r)_s / N,
+// residue r's term of eq. (4) before the sum over r.  Each residue reads the
+// inputs again; the problems this path serves (q <= 32, so L <= 16 m) keep
+// them in L2, and the residues never pass through HBM before the product.
+// k_qsum then forms h_{t m + s} = sum_r zeta_q^{-t r} y^(r)_s.
+
+// Block sum of residue r of x (length L, p blocks, copy stride C1) into the
+// points s = lane + w TPF of a row, times zeta_N^{r s}.
+template <typename T, int MSZ>
+__device__ __forceinline__ void rr_blocksum(const cplx<T>* x, int32_t L, int32_t p, int32_t q, int32_t C1,
+                                            uint32_t r, const TwN& tw, bool hp, int lane, cplx<T>* v) {
+    constexpr int PPT = FP<MSZ>::PPT;
+    constexpr int TPF = FP<MSZ>::TPF;
+#pragma unroll
+    for (int w = 0; w < PPT; ++w) {
+        const int j = lane + w * TPF;
+        v[w] = j < L ? x[(int64_t)j * C1] : mk<T>(0, 0);
+    }
+    uint32_t e = r;  // (r t) mod q for t = 1
+    if (e >= (uint32_t)q) e -= (uint32_t)q;
+    for (int t = 1; t < p; ++t) {
+        const double2 z = tw_n(tw, e * (uint32_t)MSZ);
+        e += r;
+        if (e >= (uint32_t)q) e -= (uint32_t)q;
+#pragma unroll
+        for (int w = 0; w < PPT; ++w) {
+            const int j = t * MSZ + lane + w * TPF;
+            if (j < L) v[w] = v[w] + mul_tw<false>(x[(int64_t)j * C1], z, false);
+        }
+    }
+    if (r != 0) {
+        // r < q and s < m, so r s < q m = N needs no reduction
+        double2 z = tw_n(tw, r * (uint32_t)lane);
+        const double2 zs = tw_n(tw, r * (uint32_t)TPF);
+#pragma unroll
+        for (int w = 0; w < PPT; ++w) {
+            v[w] = mul_tw<false>(v[w], z, hp);
+            z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
+        }
+    }
+}
+
+template <typename T, int MSZ>
+__global__ void __launch_bounds__(512) k_row_rr(RawArgs a) {
+    using P = FP<MSZ>;
+    constexpr int PPT = P::PPT;
+    constexpr int TPF = P::TPF;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T>* smem = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* tpt = smem + (size_t)a.rpw * 2 * MSZ;
+    const int tid = threadIdx.x;
+    fill_pass_tab<T, MSZ>(tpt, a.twp, tid, blockDim.x);
+    __syncthreads();
+    const TwPass<T> tw{tpt, PassTab<MSZ>::R0};
+
+    const int rloc = tid / TPF;
+    const int lane = tid - rloc * TPF;
+    cplx<T>* buf0 = smem + (size_t)rloc * 2 * MSZ;
+    cplx<T>* buf1 = buf0 + MSZ;
+    int ph = 0;
+    const int64_t stride = (int64_t)gridDim.x * a.rpw;
+    const cplx<T>* F = reinterpret_cast<const cplx<T>*>(a.f);
+    const cplx<T>* G = reinterpret_cast<const cplx<T>*>(a.g);
+    cplx<T>* Y = reinterpret_cast<cplx<T>*>(a.Y);
+    // neighbouring row blocks (the residues of one problem) on one XCD, which
+    // then reads the problem's inputs into its L2 once: block b runs on XCD b % 8
+    const int64_t lb = (gridDim.x % 8 == 0) ? (int64_t)(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8
+                                            : (int64_t)blockIdx.x;
+    for (int64_t base = lb * a.rpw; base < a.nrows; base += stride) {
+        const int64_t row = base + rloc;
+        const bool ok = row < a.nrows;
+        const int64_t rw = ok ? row : 0;
+        RawProb pr;
+        uint32_t r;
+        int64_t xoff, yoff;
+        int C1 = 1;
+        if (a.rowmap != nullptr) {
+            const int i = a.rowmap[2 * rw];
+            r = (uint32_t)a.rowmap[2 * rw + 1];
+            pr = a.probs[i];
+            xoff = pr.f_off;
+            yoff = rw * MSZ;
+        } else {
+            pr = a.p0;
+            C1 = a.C1;
+            const int64_t t1 = rw / C1;
+            const int c1 = (int)(rw - t1 * C1);
+            const int64_t b = t1 / a.Dg;
+            const int d = (int)(t1 - b * a.Dg);
+            r = (uint32_t)(a.r0 + d);
+            xoff = b * a.fbs + c1;
+            yoff = b * a.ybs + (int64_t)d * MSZ * C1 + c1;
+        }
+        const bool hp = pr.hiprec != 0;
+        cplx<T> v[PPT], u[PPT];
+        if (ok) {
+            rr_blocksum<T, MSZ>(F + xoff, pr.L, pr.p, pr.q, C1, r, pr.tw, hp, lane, v);
+            if (!a.same) rr_blocksum<T, MSZ>(G + xoff, pr.L, pr.p, pr.q, C1, r, pr.tw, hp, lane, u);
+        } else {
+#pragma unroll
+            for (int w = 0; w < PPT; ++w) v[w] = u[w] = mk<T>(0, 0);
+        }
+        fft_rows_pp<T, MSZ, +1>(v, buf0, buf1, ph, lane, tw, ok);
+        if (!a.same) {
+            fft_rows_pp<T, MSZ, +1>(u, buf0, buf1, ph, lane, tw, ok);
+#pragma unroll
+            for (int w = 0; w < PPT; ++w) v[w] = v[w] * u[w];
+        } else {
+#pragma unroll
+            for (int w = 0; w < PPT; ++w) v[w] = v[w] * v[w];
+        }
+        fft_rows_pp<T, MSZ, -1>(v, buf0, buf1, ph, lane, tw, ok);
+        if (ok) {
+            const T invN = (T)pr.invN;
+            double2 z = tw_n(pr.tw, r * (uint32_t)lane);
+            const double2 zs = tw_n(pr.tw, r * (uint32_t)TPF);
+#pragma unroll
+            for (int w = 0; w < PPT; ++w) {
+                Y[yoff + (int64_t)(lane + w * TPF) * C1] = scale(mul_tw<true>(v[w], z, hp), invN);
+                z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
+            }
+        }
+    }
+}
+
+// The output sums of eq. (4) over a residue group [r0, r0 + Dg) of the raw
+// rows: h_{t m + s} = sum_d zeta_q^{-t (r0 + d)} y^(r0 + d)_s for t m + s < M,
+// one column (s, copy) per thread, the group's values held in registers;
+// accumulate adds to h (later groups).  Plain mode: grid (column tiles, B);
+// batch mode: one workgroup per tilemap entry, every residue of its problem.
+template <typename T>
+__global__ void __launch_bounds__(256) k_qsum(RawArgs a) {
+    __shared__ double2 twq[kMaxQsum];
+    const int tid = threadIdx.x;
+    RawProb pr;
+    int64_t col, ncols, yb, ystride, hb;
+    int C1 = 1, Dg, r0;
+    if (a.tilemap != nullptr) {
+        const int i = a.tilemap[2 * blockIdx.x];
+        pr = a.probs[i];
+        col = (int64_t)a.tilemap[2 * blockIdx.x + 1] + tid;
+        ncols = a.m;
+        yb = a.ybase[i] * a.m;
+        ystride = a.m;
+        hb = pr.h_off;
+        Dg = pr.q;
+        r0 = 0;
+    } else {
+        pr = a.p0;
+        C1 = a.C1;
+        col = (int64_t)blockIdx.x * blockDim.x + tid;
+        ncols = (int64_t)a.m * C1;
+        yb = (int64_t)blockIdx.y * a.ybs;
+        ystride = (int64_t)a.m * C1;
+        hb = (int64_t)blockIdx.y * a.hbs;
+        Dg = a.Dg;
+        r0 = a.r0;
+    }
+    // zeta_q^e, e < q (exact: zeta_N^{e m})
+    if (tid < pr.q) twq[tid] = tw_n(pr.tw, (uint32_t)tid * (uint32_t)a.m);
+    __syncthreads();
+    if (col >= ncols) return;
+    const cplx<T>* Y = reinterpret_cast<const cplx<T>*>(a.Y) + yb + col;
+    cplx<T>* h = reinterpret_cast<cplx<T>*>(a.h) + hb + col;
+    cplx<T> V[kMaxQsum];
+#pragma unroll
+    for (int d = 0; d < kMaxQsum; ++d) V[d] = d < Dg ? Y[(int64_t)d * ystride] : mk<T>(0, 0);
+    const int64_t s = col / C1;
+    const int64_t ostep = (int64_t)a.m * C1;
+    for (int t = 0; t < pr.qout; ++t) {
+        if ((int64_t)t * a.m + s >= pr.M) break;
+        // exponent t (r0 + d) mod q, advanced by t per residue (t < q)
+        int e = (int)(((int64_t)t * r0) % pr.q);
+        cplx<T> acc = mk<T>(0, 0);
+#pragma unroll
+        for (int d = 0; d < kMaxQsum; ++d) {
+            if (d < Dg) {
+                acc = acc + mul_tw<true>(V[d], twq[e], false);
+                e += t;
+                if (e >= pr.q) e -= pr.q;
+            }
+        }
+        cplx<T>* o = h + (int64_t)t * ostep;
+        if (a.accumulate) acc = acc + *o;
+        *o = acc;
+    }
+}
+
 // ------------------------------------------------------------ elementwise --
 
 template <typename T>
@@ -1534,6 +1782,65 @@ hipError_t launch_fused_real(bool dbl, int m, const FusedArgs& a, int threads, i
                              hipStream_t s) {
     return dbl ? fused_real_disp<double>(m, a, threads, blocks, lds, s)
                : fused_real_disp<float>(m, a, threads, blocks, lds, s);
+}
+
+template <typename T, int MSZ>
+hipError_t row_rr_t(const RawArgs& a, int threads, int64_t blocks, size_t lds, hipStream_t s) {
+    lds += (size_t)PassTab<MSZ>::LEN * sizeof(cplx<T>);
+    auto kern = k_row_rr<T, MSZ>;
+    hipError_t e = allow_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, threads, lds) != hipSuccess || occ < 1) occ = 1;
+    const int64_t resident = (int64_t)occ * cu_count();
+    int64_t grid = blocks < resident ? blocks : resident;
+    if (grid >= 8) grid = (grid + 7) / 8 * 8;  // whole XCD rounds (spare blocks find no rows)
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t row_rr_disp(int m, const RawArgs& a, int th, int64_t bl, size_t lds, hipStream_t s) {
+    switch (m) {
+        HDC_POW2_CASES(row_rr_t, a, th, bl, lds, s)
+        case 2048: return row_rr_t<T, 2048>(a, th, bl, lds, s);
+        case 4096: return row_rr_t<T, 4096>(a, th, bl, lds, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_row_rr(bool dbl, int m, const RawArgs& a, int threads, int64_t blocks, size_t lds, hipStream_t s) {
+    return dbl ? row_rr_disp<double>(m, a, threads, blocks, lds, s) : row_rr_disp<float>(m, a, threads, blocks, lds, s);
+}
+
+hipError_t launch_qsum(bool dbl, const RawArgs& a, int64_t gx, int64_t gy, hipStream_t s) {
+    if (gx <= 0 || gy <= 0) return hipSuccess;
+    if (dbl)
+        hipLaunchKernelGGL(k_qsum<double>, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_qsum<float>, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t fused_queue_t(const FusedQueueArgs& a, int64_t nitems, size_t lds, hipStream_t s) {
+    auto kern = k_fused_queue<T>;
+    hipError_t e = allow_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 512, lds) != hipSuccess || occ < 1) occ = 1;
+    const int64_t resident = (int64_t)occ * cu_count();
+    const int64_t grid = nitems < resident ? nitems : resident;
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(512), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused_queue(bool dbl, const FusedQueueArgs& a, int64_t nitems, size_t lds, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    return dbl ? fused_queue_t<double>(a, nitems, lds, s) : fused_queue_t<float>(a, nitems, lds, s);
 }
 
 hipError_t launch_mul(bool dbl, void* F, const void* G, int64_t n, hipStream_t s) {

@@ -546,28 +546,37 @@ def _batch_gpu_time(Ls: Sequence[int], ms: Sequence[int], dtype: str, reps: int 
     return sorted(ts)[reps // 2]
 
 
+def batch_default_m(L: int) -> int:
+    """The FFT size hdc_batch_plan gives a problem of length L by default (hdc_batch_default_m)."""
+    from ._lib import check, lib
+    m = ctypes.c_int64()
+    check(lib().hdc_batch_default_m(int(L), ctypes.byref(m)))
+    return m.value
+
+
 def tune_batch(Ls: Sequence[int], dtype: str = "c64", timer: Optional[Callable] = None, max_shift: int = 3,
                reps: int = 3) -> Tuple[List[int], Dict[int, List[Tuple[int, float]]]]:
     """Per-bucket exhaustive search (A0 of section 4.2 applied bucket by bucket) for an
-    uneven batch with M = 2L - 1.  Problems are grouped by their default FFT size (the
-    next power of two of L, p = 1); for each group every m = size / 2^j, j = 0 .. max_shift
-    (p = 1, 2, 4, 8), is timed on the group's problems alone and the fastest kept (ties:
-    the larger m).  ``timer(Ls, ms, dtype) -> ms`` defaults to the captured batch on the
+    uneven batch with M = 2L - 1.  Problems are grouped by the next power of two of L
+    (p = 1); for each group every m = size / 2^j, j = 0 .. max_shift (p = 1, 2, 4, 8),
+    and the library's default m (hdc_batch_default_m) are timed on the group's
+    problems alone and the fastest kept (ties: the larger m).  ``timer(Ls, ms, dtype) -> ms`` defaults to the captured batch on the
     GPU.  Returns the FFT size of every problem and each group's table [(m, ms)]."""
     from . import HdcError
     timer = timer or (lambda ls, ms, dt: _batch_gpu_time(ls, ms, dt, reps=reps))
     groups: Dict[int, List[int]] = {}
     for i, L in enumerate(Ls):
         groups.setdefault(pow2_ceil(int(L)), []).append(i)
-    choice = [pow2_ceil(int(L)) for L in Ls]
+    choice = [batch_default_m(int(L)) for L in Ls]
     tables: Dict[int, List[Tuple[int, float]]] = {}
     for size, idx in sorted(groups.items()):
         gl = [int(Ls[i]) for i in idx]
         rows = []
-        for j in range(max_shift + 1):
-            m = size >> j
-            if m < 1:
-                break
+        cands = [size >> j for j in range(max_shift + 1) if size >> j >= 1]
+        dflt = batch_default_m(max(gl))
+        if dflt not in cands:
+            cands.append(dflt)
+        for m in cands:
             try:
                 rows.append((m, float(timer(gl, [m] * len(gl), dtype))))
             except HdcError:

@@ -233,3 +233,11 @@ def test_scratch_size_matches_header():
     src = open(os.path.join(ROOT, "include", "hdc.h")).read()
     a, b = re.search(r"#define HDC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", src).groups()
     assert hdc.SCRATCH_BYTES == int(a) << int(b)
+
+
+def test_batch_default_m():
+    """The batch's default FFT size (host only): the next power of two (p = 1), except
+    4096 (p = 2) for lengths in (4096, 8192]."""
+    from paper_2306_10016_amd import tune
+    assert [tune.batch_default_m(L) for L in (1, 64, 65, 4096, 4097, 8192, 8193, 65536, 65537)] == \
+        [1, 64, 128, 4096, 4096, 4096, 16384, 65536, 131072]

@@ -88,7 +88,7 @@ def test_column_row_passes(L, m, D, dtype):
     d = hdc.derive(L, M, m, D=D, dtype=dtype)
     plan, _ = _check(L, M, m, 0, 0, 1, D, dtype, cfg=203, idx=L)
     if d["N"] * (16 if dtype == "c128" else 8) > 65536:
-        assert plan.axes[0]["variant"] == 1
+        assert plan.axes[0]["variant"] != 0
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])

@@ -233,10 +233,13 @@ def test_batch_tuner_picks_each_buckets_argmin():
         p = -(-L // m)
         assert p == (1 if L <= 4096 else 2), (L, m)
         assert m == tune.pow2_ceil(L) >> (p - 1)
-    # every group timed its 4 candidates once, on its own problems only
+    # every group timed its 4 candidates (plus the library default when it is not
+    # among them) once, on its own problems only
     groups = {tune.pow2_ceil(L) for L in Ls}
-    assert set(tables) == groups and all(len(t) == 4 for t in tables.values())
-    assert len(calls) == 4 * len(groups)
+    want = {g: 4 + (tune.batch_default_m(g) not in [g >> j for j in range(4)]) for g in groups}
+    assert set(tables) == groups and all(len(t) == want[g] for g, t in tables.items())
+    assert len(calls) == sum(want.values())
+    assert all(tune.batch_default_m(g) == (g if g != 8192 else 4096) for g in groups)
     # a flat cost: the larger m wins the tie
     choice, _ = tune.tune_batch([300, 5000], "c64", timer=lambda ls, ms, dt: 1.0)
     assert choice == [512, 8192]
