@@ -497,19 +497,24 @@ def secondary(args, dev, hdc, synth, log):
         shapes = [((256, 256), "c64"), ((512, 512), "c64"), ((1024, 1024), "c64"), ((2048, 512), "c64"),
                   ((1024, 4096), "c64"), ((1024, 1024), "c128"), ((1024, 4096), "c128"), ((4096, 4096), "c64"),
                   ((8192, 8192), "c64"), ((256, 256, 256), "c64")]
-        from paper_2306_10016_amd import predict
-        timer = predict.NDTimer(reps=3, warmup=1)
+        if args.nd_shapes:
+            keep = set(args.nd_shapes.split(","))
+            shapes = [(Ls, dt) for Ls, dt in shapes if "x".join(map(str, Ls)) + "_" + dt in keep]
+        from paper_2306_10016_amd import tune
         nd = {}
         for Ls, dt in shapes:
             Ms = tuple(2 * x - 1 for x in Ls)
-            best, _, _ = predict.tune_separable(list(Ls), list(Ms), dt, timer)  # A0 per axis
-            ms = tuple(b[0] for b in best)
-            Ds = tuple(b[1] for b in best)
+            if args.no_tune:  # p = 1 and all residues per pass on every axis
+                params = {"m": [tune.pow2_ceil(x) for x in Ls], "D": [0] * len(Ls)}
+            else:  # the library's A0, one axis at a time (section 4.2)
+                params = tune.run_search(tune.TuneDB(None), list(Ls), list(Ms), dt, tune.A0)[0].params
             np_dt = np.complex128 if dt == "c128" else np.complex64
             td = torch.complex128 if dt == "c128" else torch.complex64
             f, g = synth.pair(Ls, 4, sum(Ls), np_dt)
             ft, gt = torch.from_numpy(f).to(dev), torch.from_numpy(g).to(dev)
-            plan = hdc.Plan.nd(Ls, Ms, ms, D=Ds, dtype=dt)
+            plan = hdc.Plan.from_params(list(Ls), list(Ms), dt, params)
+            ms = tuple(ax["m"] for ax in plan.axes)
+            Ds = tuple(ax["D"] for ax in plan.axes)
             h = torch.empty(Ms, dtype=td, device=dev)
             ws = plan.workspace(dev)
             reps = 10 if np.prod(Ls) <= (1 << 22) else 3
@@ -523,7 +528,8 @@ def secondary(args, dev, hdc, synth, log):
             te = timed(explicit, reps, warm=1)
             comp = (2 * int(np.prod(Ls)) + int(np.prod(Ms))) * (16 if dt == "c128" else 8)
             key = "x".join(str(x) for x in Ls) + "_" + dt
-            nd[key] = {"params": {"m": list(ms), "D": list(Ds)}, "ms": round(t * 1e3, 4), "compulsory_GBps": round(comp / t / 1e9, 1),
+            nd[key] = {"params": {"m": list(ms), "D": list(Ds), "tile": params.get("tile", [0] * len(Ls))},
+                       "ms": round(t * 1e3, 4), "compulsory_GBps": round(comp / t / 1e9, 1),
                        "explicit_ms": round(te * 1e3, 4), "speedup_vs_explicit": round(te / t, 3),
                        "rel_err_vs_explicit": err}
             log(f"[bench] {key}: {t * 1e3:.3f} ms (explicit {te * 1e3:.3f} ms), rel {err:.1e}")
@@ -765,6 +771,7 @@ def main():
     ap.add_argument("--batch-eager", action="store_true",
                     help="launch the uneven batch eagerly, buckets in turn (per-kernel profiling)")
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--nd-shapes", default="", help="comma list of the N-D shapes to run (e.g. 8192x8192_c64)")
     ap.add_argument("--extras", default="", help="comma list of secondary workloads to run (default: all of "
                     "small,first_L,real,multi,batch,nd,uneq,uneq_nd)")
     ap.add_argument("--streams", type=int, default=16,

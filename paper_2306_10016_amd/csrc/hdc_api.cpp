@@ -341,6 +341,12 @@ hdc_status geometry(AxisPlan& A, bool outer, bool many_rows = false, bool keep_s
     // the LDS a workgroup can have instead of the 80 KiB that leaves room for two
     if (many_rows && !outer && d.m <= kMaxFused && A.f_lds + 4096 <= device_lds_max()) d.variant = 0;
     if (d.variant == 0 && A.f_lds > device_lds_max()) d.variant = 1;
+    // long one-row residues of an innermost N-D axis: a workgroup per (row,
+    // residue) on the raw-row path rather than every residue of a row in turn
+    // in one fused workgroup
+    if (many_rows && !outer && d.m >= 2048 && d.m <= kMaxRow && d.q <= kMaxQsum && d.p <= kMaxRawP &&
+        d.C * d.m <= (int64_t(1) << 30))
+        d.variant = 2;
     A.hiprec = !A.dbl && d.N > (int64_t(1) << 20);
     return HDC_OK;
 }

@@ -177,10 +177,13 @@ def test_outer_axis_four_step(L, m, D, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_inner_axis_fused_with_many_rows(dtype):
-    """Innermost axis with N beyond 80 KiB of LDS uses the fused kernel when rows are many."""
-    L = (64, 3000)
-    plan, _ = _nd(L, (127, 5999), (64, 4096), dtype, idx=11)
+def test_inner_axis_many_rows(dtype):
+    """Innermost axis with many rows: with N beyond 80 KiB of LDS and m below 2048 the
+    fused kernel takes the whole LDS of a workgroup; one-row residues of 2048 points
+    and more run a workgroup per (row, residue) on the raw-row path."""
+    plan, _ = _nd((64, 3000), (127, 5999), (64, 4096), dtype, idx=11)
+    assert plan.axes[1]["variant"] == 2
+    plan, _ = _nd((64, 1500), (127, 2999), (64, 1024), dtype, idx=12)
     assert plan.axes[1]["variant"] == 0
 
 
