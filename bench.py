@@ -222,19 +222,37 @@ def tuner_regret(sizes, params, dtype, log, n=6, timer=None):
 
 
 def predictor_summary():
-    """The learned predictor's regret on the 2D/3D evaluation problems, from the committed
-    evaluation run (training takes minutes, so it is not repeated here)."""
+    """Training record of the committed predictor checkpoint (profiles/predictor_eval.json,
+    written by python -m paper_2306_10016_amd.predict)."""
     path = os.path.join(HERE, "profiles", "predictor_eval.json")
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
-    ev = [{"L": e["L"], "dtype": e["dtype"], "predicted": round(e["predicted"]["regret"], 4),
-           "predicted_top2_verified": round(e["predicted_top2_verified"]["regret"], 4),
-           "separable_A0": round(e["separable_A0"]["regret"], 4), "default": round(e["default"]["regret"], 4)}
-          for e in d.get("eval", [])]
-    return {"source": "profiles/predictor_eval.json (stored run of python -m paper_2306_10016_amd.predict)",
-            "regret_vs": "joint exhaustive search", "eval": ev}
+    t = d.get("train", {})
+    return {"source": "profiles/predictor_eval.json", "checkpoint": d.get("checkpoint"),
+            "train_problems": t.get("problems"), "train_rows": t.get("rows"), "train_accuracy": t.get("accuracy"),
+            "heldout": [{"L": e["L"], "dtype": e["dtype"], "network": round(e["network"]["regret"], 4),
+                         "default": round(e["default"]["regret"], 4)} for e in d.get("heldout", [])]}
+
+
+def predictor_live(log):
+    """The committed checkpoint measured in this run: hdc_predict per axis (an axis outside
+    the training range abstains and the flow falls back to the library's A0), the
+    library's A0 (section 4.2) as the judge, the default beside them, all re-timed here."""
+    from paper_2306_10016_amd import predict
+    if not os.path.exists(predict.DEFAULT_CKPT):
+        return None
+    cp = predict.CheckpointPredictor(predict.DEFAULT_CKPT)
+    rows = predict.evaluate(cp, predict.EVAL_PROBLEMS, log=log)
+    cp.close()
+    ev = [{"L": e["L"], "dtype": e["dtype"], "abstained": e["abstained"],
+           "network_top1": round(e["network"]["regret"], 4), "flow": round(e["flow"]["regret"], 4),
+           "flow_source": e["flow"]["source"], "default": round(e["default"]["regret"], 4),
+           "A0_timings": e["A0"]["timings"]} for e in rows]
+    return {"checkpoint": os.path.relpath(predict.DEFAULT_CKPT, HERE), "regret_vs": "the library's A0 (exhaustive, per axis)",
+            "eval": ev, "worst_flow_regret": max(x["flow"] for x in ev),
+            "worst_network_top1_regret": max(x["network_top1"] for x in ev)}
 
 
 def secondary(args, dev, hdc, synth, log):
@@ -257,8 +275,16 @@ def secondary(args, dev, hdc, synth, log):
     out = {}
     sel = [x for x in args.extras.split(",") if x]
 
+    clock = {"t": time.time(), "name": None}
+
     def want(name):
-        return not sel or name in sel
+        ok = not sel or name in sel
+        if ok:
+            now = time.time()
+            if clock["name"]:
+                log(f"[bench] ({clock['name']} took {now - clock['t']:.1f} s)")
+            clock["t"], clock["name"] = now, name
+        return ok
 
     if want("small"):
         # small workload: L = 1024, M = 2047, m = 256, p = 4, q = 8, C = 1, D = 1, complex128
@@ -493,7 +519,7 @@ def secondary(args, dev, hdc, synth, log):
         del fb, gb, hb, B
 
     if want("nd"):
-        # 2D squares and rectangles, and the 2D/3D evaluation sizes (parameters from the per-axis tuner)
+        # 2D squares and rectangles, and the 2D/3D evaluation sizes (parameters from the library's A1)
         shapes = [((256, 256), "c64"), ((512, 512), "c64"), ((1024, 1024), "c64"), ((2048, 512), "c64"),
                   ((1024, 4096), "c64"), ((1024, 1024), "c128"), ((1024, 4096), "c128"), ((4096, 4096), "c64"),
                   ((8192, 8192), "c64"), ((256, 256, 256), "c64")]
@@ -502,12 +528,13 @@ def secondary(args, dev, hdc, synth, log):
             shapes = [(Ls, dt) for Ls, dt in shapes if "x".join(map(str, Ls)) + "_" + dt in keep]
         from paper_2306_10016_amd import tune
         nd = {}
+        nd_db = tune.TuneDB(None)  # experience accumulates over the shapes, smallest first
         for Ls, dt in shapes:
             Ms = tuple(2 * x - 1 for x in Ls)
             if args.no_tune:  # p = 1 and all residues per pass on every axis
                 params = {"m": [tune.pow2_ceil(x) for x in Ls], "D": [0] * len(Ls)}
-            else:  # the library's A0, one axis at a time (section 4.2)
-                params = tune.run_search(tune.TuneDB(None), list(Ls), list(Ms), dt, tune.A0)[0].params
+            else:  # the library's experience search (A1, section 4.3), axis by axis
+                params = tune.run_search(nd_db, list(Ls), list(Ms), dt, tune.A1)[0].params
             np_dt = np.complex128 if dt == "c128" else np.complex64
             td = torch.complex128 if dt == "c128" else torch.complex64
             f, g = synth.pair(Ls, 4, sum(Ls), np_dt)
@@ -628,6 +655,8 @@ def secondary(args, dev, hdc, synth, log):
             torch.cuda.empty_cache()
         out["uneq_nd"] = und
 
+    if clock["name"]:
+        log(f"[bench] ({clock['name']} took {time.time() - clock['t']:.1f} s)")
     return out
 
 
@@ -936,7 +965,8 @@ def main():
         torch.cuda.empty_cache()
         if not args.no_tune:
             out["tuner"] = tuner_regret(sizes, params, dt, log)
-        out["predictor"] = predictor_summary()
+        out["predictor"] = {"live": predictor_live(log) if not args.no_extras else None,
+                            "stored": predictor_summary()}
         out["secondary"] = secondary(args, dev, hdc, synth, log)
 
     if not args.no_cpu_baseline:

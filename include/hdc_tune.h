@@ -104,10 +104,11 @@ const char* hdc_build_id(void);
  * file holds a multilayer perceptron (ReLU hidden layers, softmax output over
  * scale-free classes (p, D-mode): p in {1, 2, 3, 4, 6, 8, 12, 16}, D-mode 0 = all
  * residues in one pass, 1 = one residue per pass; class index 2 (p index) +
- * D-mode).  Format (little endian): the 8 bytes "HDCMLP01", int32 feature
- * version (1), int32 layer count n, int32 sizes[n + 1] (sizes[0] = 12 inputs,
- * sizes[n] = 16 classes), then per layer W (out x in, row-major) and b (out),
- * float32.
+ * D-mode).  Format (little endian): the 8 bytes "HDCMLP01", int32 format
+ * version (1 or 2), int32 layer count n, int32 sizes[n + 1] (sizes[0] = 12
+ * inputs, sizes[n] = 16 classes), then per layer W (out x in, row-major) and b
+ * (out), float32; version 2 then holds the minimum and the maximum of every
+ * feature over the training rows (12 + 12 float32).
  *
  * hdc_predictor_load reads the file and copies the network to the current
  * device.  hdc_predict evaluates one feature row per axis of `prob` with the
@@ -115,7 +116,10 @@ const char* hdc_build_id(void);
  * probable class per axis (ties: the lowest index) and maps it to parameters:
  * m = the smallest power of two with ceil(L/m) <= p (outer N-D axes at most
  * 2^20; doubled while q < p), D = q or 1.  confidence (may be NULL) receives
- * the winning class's probability per axis (prob->ndim values).
+ * the winning class's probability per axis (prob->ndim values), or 0 for an
+ * axis whose features leave the training range (version 2) by more than 1/16
+ * (a sixteenth of an octave in the length features): the network abstains
+ * there and the caller falls back to hdc_tune.
  * Features per axis (version 1): log2 of this axis's L / 16, log2 of the other
  * two axes' L / 16 (0 if absent, in axis order), one-hot axis (3), one-hot
  * ndim (3), 1 for complex128, log2 batch / 16, log2 of the element count

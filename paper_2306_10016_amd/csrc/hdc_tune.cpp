@@ -759,6 +759,9 @@ std::string device_name() {
 
 constexpr int kFeatures = 12;
 constexpr int kClasses = 16;
+// features outside the training range by more than this (1/16 of an octave in
+// the scaled length features) make an axis abstain
+constexpr float kRangeMargin = 1.0f / 16.0f;
 
 void features(const hdc_problem& pr, int axis, float* v) {
     const int nd = pr.ndim;
@@ -783,6 +786,8 @@ void features(const hdc_problem& pr, int axis, float* v) {
 
 struct hdc_predictor_s {
     std::vector<int> sizes;
+    bool ranged = false;           // format 2: the training range is known
+    float lo[kFeatures], hi[kFeatures];
     std::vector<float*> W, b;  // device
     float *x = nullptr, *y0 = nullptr, *y1 = nullptr, *P = nullptr;
     hipStream_t s = nullptr;
@@ -843,7 +848,7 @@ hdc_status hdc_predictor_load(hdc_predictor_t* out, const char* path) {
     char magic[8];
     int32_t ver = 0, n = 0;
     bool ok = fread(magic, 1, 8, fh) == 8 && !memcmp(magic, "HDCMLP01", 8) && fread(&ver, 4, 1, fh) == 1 &&
-              fread(&n, 4, 1, fh) == 1 && ver == 1 && n >= 1 && n <= 16;
+              fread(&n, 4, 1, fh) == 1 && (ver == 1 || ver == 2) && n >= 1 && n <= 16;
     std::vector<int32_t> sz(ok ? n + 1 : 0);
     if (ok) ok = fread(sz.data(), 4, n + 1, fh) == (size_t)(n + 1);
     if (ok) ok = sz[0] == kFeatures && sz[n] == kClasses;
@@ -855,10 +860,18 @@ hdc_status hdc_predictor_load(hdc_predictor_t* out, const char* path) {
         ok = fread(hw.back().data(), 4, hw.back().size(), fh) == hw.back().size() &&
              fread(hb.back().data(), 4, hb.back().size(), fh) == hb.back().size();
     }
+    float lo[kFeatures], hi[kFeatures];
+    if (ok && ver == 2)
+        ok = fread(lo, 4, kFeatures, fh) == (size_t)kFeatures && fread(hi, 4, kFeatures, fh) == (size_t)kFeatures;
     fclose(fh);
-    if (!ok) return fail(HDC_ERR_INVALID_ARG, "%s is not a predictor checkpoint of feature version 1", path);
+    if (!ok) return fail(HDC_ERR_INVALID_ARG, "%s is not a predictor checkpoint (format 1 or 2)", path);
     hdc_predictor_s* P = new hdc_predictor_s();
     P->sizes.assign(sz.begin(), sz.end());
+    P->ranged = ver == 2;
+    if (P->ranged) {
+        std::memcpy(P->lo, lo, sizeof lo);
+        std::memcpy(P->hi, hi, sizeof hi);
+    }
     int wmax = 0;
     for (int v : sz) wmax = std::max(wmax, v);
     auto up = [&](const std::vector<float>& h, float** d) -> hipError_t {
@@ -918,7 +931,13 @@ hdc_status hdc_predict(hdc_predictor_t P, const hdc_problem* prob, hdc_params* o
         c.m[a] = m_for_class(*prob, a, kPClasses[ci / 2]);
         const int64_t q = cdiv(prob->M[a], c.m[a]);
         c.D[a] = (ci % 2 == 0) ? q : 1;
-        if (confidence) confidence[a] = prob_h[a * kClasses + ci];
+        // an axis whose features leave the training range abstains (confidence 0)
+        bool inside = true;
+        for (int k = 0; P->ranged && k < kFeatures; ++k) {
+            const float x = X[a * kFeatures + k];
+            inside = inside && x >= P->lo[k] - kRangeMargin && x <= P->hi[k] + kRangeMargin;
+        }
+        if (confidence) confidence[a] = inside ? prob_h[a * kClasses + ci] : 0.f;
     }
     hdc_params in_p = to_params(c), full{};
     st = hdc_params_check(prob, &in_p, &full);

@@ -213,16 +213,20 @@ class Predictor:
         self.net = MLP([D_IN, *HIDDEN, len(CLASSES)], seed=seed)
         self.threshold = threshold
         self.history: List[float] = []
+        self.lo = self.hi = None  # training range of the features (set by fit)
 
     def fit(self, X: np.ndarray, y: np.ndarray, epochs: int = 300, lr: float = 2e-3, batch: int = 128):
-        """Train on labels y (n,) or on target distributions y (n x K)."""
+        """Train on labels y (n,) or on target distributions y (n x K); remembers the
+        training range of every feature."""
         soft = y.ndim == 2
+        self.lo, self.hi = X.min(axis=0).astype(np.float32), X.max(axis=0).astype(np.float32)
         self.history = self.net.train(X, y, epochs=epochs, batch=batch, lr=lr, soft=soft)
         return self.history
 
     def save(self, path: str) -> None:
-        """Checkpoint for hdc_predictor_load (see save_checkpoint)."""
-        save_checkpoint(path, self.net.host_params())
+        """Checkpoint for hdc_predictor_load (see save_checkpoint), with the training
+        range when the network has been fitted."""
+        save_checkpoint(path, self.net.host_params(), self.lo, self.hi)
 
     def predict_axes(self, Ls, Ms, dtype, batch=1):
         """Per-axis (m, D), the per-axis confidence, and the class indices."""
@@ -232,7 +236,8 @@ class Predictor:
         for a in range(len(Ls)):
             ci = int(np.argmax(P[a]))  # ties: lowest class index
             out.append(params_of(ci, Ls[a], Ms[a], outer=a < len(Ls) - 1))
-            conf.append(float(P[a, ci]))
+            # an axis outside the training range abstains (confidence 0)
+            conf.append(float(P[a, ci]) if in_range(X[a], self.lo, self.hi) else 0.0)
             cls.append(ci)
         return out, conf, cls
 
@@ -253,31 +258,48 @@ class Predictor:
         return out
 
     def choose(self, Ls, Ms, dtype, timer, batch=1):
-        """Predicted parameters, or exhaustive per-axis tuning when confidence is low."""
+        """Predicted parameters, or exhaustive per-axis tuning when confidence is low
+        (an axis outside the training range has confidence 0)."""
         params, conf, _ = self.predict_axes(Ls, Ms, dtype, batch)
-        if min(conf) < self.threshold:
+        if min(conf) < max(self.threshold, 1e-6):
             best, _, _ = tune_separable(Ls, Ms, dtype, timer, batch)
             return best, "fallback"
         return params, "predicted"
 
 
 FEATURE_VERSION = 1
+# features outside the training range by more than this (in the scaled units of
+# features(): 1/16 of an octave for lengths) make the network abstain on that axis
+RANGE_MARGIN = 1.0 / 16
 
 
-def save_checkpoint(path: str, params) -> None:
+def save_checkpoint(path: str, params, lo=None, hi=None) -> None:
     """Write a network [(W, b), ...] (W out x in) in the checkpoint format that
-    hdc_predictor_load reads (include/hdc_tune.h): "HDCMLP01", int32 feature
-    version, int32 layer count n, int32 sizes[n + 1], then W and b of every
-    layer as float32, little endian."""
+    hdc_predictor_load reads (include/hdc_tune.h): "HDCMLP01", int32 format
+    version (1, or 2 with the training range), int32 layer count n, int32
+    sizes[n + 1], then W and b of every layer as float32, and for version 2 the
+    per-feature minimum and maximum over the training rows (float32), little
+    endian."""
     import struct
     sizes = [int(params[0][0].shape[1])] + [int(W.shape[0]) for W, _ in params]
+    ver = 1 if lo is None else 2
     with open(path, "wb") as fh:
         fh.write(b"HDCMLP01")
-        fh.write(struct.pack("<ii", FEATURE_VERSION, len(params)))
+        fh.write(struct.pack("<ii", ver, len(params)))
         fh.write(struct.pack("<%di" % len(sizes), *sizes))
         for W, b in params:
             fh.write(np.ascontiguousarray(W, dtype="<f4").tobytes())
             fh.write(np.ascontiguousarray(b, dtype="<f4").tobytes())
+        if ver == 2:
+            fh.write(np.ascontiguousarray(lo, dtype="<f4").tobytes())
+            fh.write(np.ascontiguousarray(hi, dtype="<f4").tobytes())
+
+
+def in_range(x: np.ndarray, lo: Optional[np.ndarray], hi: Optional[np.ndarray]) -> bool:
+    """Whether a feature row lies inside the training range (within RANGE_MARGIN)."""
+    if lo is None:
+        return True
+    return bool(np.all(x >= lo - RANGE_MARGIN) and np.all(x <= hi + RANGE_MARGIN))
 
 
 class CheckpointPredictor:
@@ -357,6 +379,14 @@ def training_problems(seed: int = 0, max_elems: int = 1 << 20):
                 dims = [16, 16, 16]
                 dims[pos] = L
                 probs.append((dims, 1, dt))
+        # outer axes of moderate length over many copies (the inner axis long), and
+        # boxes whose every axis runs over a few thousand copies
+        for Lo in (64, 128, 256, 512):
+            for Li in (2048, 4096, 8192, 16384):
+                if Lo * Li <= max_elems:
+                    probs.append(([Lo, Li], 1, dt))
+        for dims in ([32, 32, 1024], [64, 64, 256], [32, 128, 256], [128, 64, 128], [64, 128, 128]):
+            probs.append((list(dims), 1, dt))
         s3 = smooth_sides(8, 101)
         for _ in range(12):
             dims = [int(r.choice(s3)) for _ in range(3)]
@@ -366,12 +396,74 @@ def training_problems(seed: int = 0, max_elems: int = 1 << 20):
 
 
 EVAL_PROBLEMS = [([4096, 4096], "c64"), ([8192, 8192], "c64"), ([256, 256, 256], "c64")]
+# problems inside the training range that training never saw (1D lengths just above a
+# power of two, where p = 1 pads to almost four times L, and 2D rectangles)
+HELDOUT_PROBLEMS = [([4100], "c128"), ([8300], "c128"), ([17000], "c128"), ([33000], "c64"), ([66000], "c64"),
+                    ([131100], "c128"), ([600, 130], "c64"), ([96, 3000], "c128"), ([1100, 700], "c64")]
+DEFAULT_CKPT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "predictor.bin")
+
+
+def time_params(Ls, Ms, dtype, params, reps: int = 5, warmup: int = 2, _bufs={}) -> float:
+    """Median time of one parameter set {"m", "D", "tile"} (hdc_plan_params + hdc_time_convolve)."""
+    import torch
+    from . import Plan, torch_dtype, dtype_code
+    key = (tuple(Ls), tuple(Ms), dtype)
+    if key not in _bufs:
+        _bufs.clear()
+        td = torch_dtype(dtype_code(dtype))
+        _bufs[key] = (torch.randn(int(np.prod(Ls)), dtype=td, device="cuda"),
+                      torch.randn(int(np.prod(Ls)), dtype=td, device="cuda"),
+                      torch.empty(int(np.prod(Ms)), dtype=td, device="cuda"))
+    f, g, h = _bufs[key]
+    L_arg = list(Ls) if len(Ls) > 1 else Ls[0]
+    M_arg = list(Ms) if len(Ms) > 1 else Ms[0]
+    plan = Plan.from_params(L_arg, M_arg, dtype, params)
+    t = plan.time_convolve(f, g, h, ws=tune._shared_ws(plan.workspace_bytes), warmup=warmup, reps=reps)
+    plan.close()
+    t.sort()
+    return t[len(t) // 2]
+
+
+def as_params(pairs, nd):
+    """[(m, D), ...] per axis -> {"m", "D"} in the database's form (scalars for 1D)."""
+    if nd == 1:
+        return {"m": int(pairs[0][0]), "D": int(pairs[0][1])}
+    return {"m": [int(p[0]) for p in pairs], "D": [int(p[1]) for p in pairs]}
+
+
+def evaluate(pred, problems, log=print):
+    """Per problem: the library's exhaustive search (A0, section 4.2) as the judge, the
+    network's top-1 parameters (abstaining axes marked), the flow with the A0 fallback,
+    and the default (p = 1, all residues) -- all re-timed under the same conditions."""
+    out = []
+    for Ls, dt in problems:
+        Ms = [2 * L - 1 for L in Ls]
+        a0, _ = tune.run_search(tune.TuneDB(None), Ls if len(Ls) > 1 else Ls[0],
+                                Ms if len(Ms) > 1 else Ms[0], dt, tune.A0)
+        t_a0 = time_params(Ls, Ms, dt, a0.params)
+        params, conf = pred.predict_axes(Ls, Ms, dt)[:2]
+        t_net = time_params(Ls, Ms, dt, as_params(params, len(Ls)))
+        abstain = min(conf) <= 0.0
+        dflt = default_params(Ls, Ms)
+        t_def = time_params(Ls, Ms, dt, as_params(dflt, len(Ls)))
+        ent = {"L": Ls, "dtype": dt, "A0": {"params": a0.params, "ms": t_a0, "timings": len(a0.table)},
+               "network": {"params": params, "confidence": conf, "ms": t_net, "regret": tune.regret(t_net, t_a0)},
+               "abstained": abstain,
+               "flow": {"source": "A0 fallback" if abstain else "network",
+                        "regret": 0.0 if abstain else tune.regret(t_net, t_a0)},
+               "default": {"params": dflt, "ms": t_def, "regret": tune.regret(t_def, t_a0)}}
+        out.append(ent)
+        log(f"[predict] {Ls} {dt}: A0 {t_a0:.4f} ms ({len(a0.table)} timings); network {params} "
+            f"{'abstains' if abstain else 'conf %.2f' % min(conf)}, regret {ent['network']['regret']:+.3f}; "
+            f"default regret {ent['default']['regret']:+.3f}")
+    return out
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--db", default="results/predictor_db.jsonl")
     ap.add_argument("--out", default="results/predictor.json")
+    ap.add_argument("--ckpt", default=DEFAULT_CKPT)
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--max-problems", type=int, default=0)
     args = ap.parse_args(argv)
@@ -399,69 +491,19 @@ def main(argv=None):
     hist = pred.fit(X, T, epochs=args.epochs)  # soft targets from the timing tables
     train_acc = float(np.mean(np.argmax(pred.net.predict_proba(X), 1) == y))
     print(f"[predict] trained: loss {hist[0]:.3f} -> {hist[-1]:.3f}, train accuracy {train_acc:.3f}", flush=True)
+    os.makedirs(os.path.dirname(args.ckpt) or ".", exist_ok=True)
+    pred.save(args.ckpt)
     results = {"train": {"problems": len(probs), "rows": int(len(y)), "loss_first": hist[0], "loss_last": hist[-1],
-                         "accuracy": train_acc, "class_counts": np.bincount(y, minlength=len(CLASSES)).tolist()},
-               "eval": []}
-    for Ls, dt in EVAL_PROBLEMS:
-        Ms = [2 * L - 1 for L in Ls]
-        joint = tune_joint(Ls, Ms, dt, timer)
-        best_p, best_t = joint[0]
-        params, conf, cls = pred.predict_axes(Ls, Ms, dt)
-        t_pred = timer(Ls, Ms, [p[0] for p in params], [p[1] for p in params], dt)
-        dflt = default_params(Ls, Ms)
-        t_def = timer(Ls, Ms, [p[0] for p in dflt], [p[1] for p in dflt], dt)
-        sep, _, t_sep = tune_separable(Ls, Ms, dt, timer)
-        # section 6.4's heuristic: tune the L_x x 32 rectangle and reuse its x-axis choice
-        # (same L_x, so the same m and D apply); the y axis keeps the default
-        rect, t_rect = None, None
-        if len(Ls) == 2:
-            rb, _, _ = tune_separable([Ls[0], 32], [Ms[0], 63], dt, timer)
-            rect = [rb[0], dflt[1]]
-            t_rect = timer(Ls, Ms, [p[0] for p in rect], [p[1] for p in rect], dt)
-        # the network's top-2 classes per axis, verified by timing at the target size
-        short = pred.shortlist(Ls, Ms, dt, k=2)
-        srows = []
-        for combo in itertools.product(*short):
-            srows.append((list(combo), timer(Ls, Ms, [c[0] for c in combo], [c[1] for c in combo], dt)))
-        srows.sort(key=lambda r: r[1])
-        ent_short = {"params": srows[0][0], "timings": len(srows)}
-        t_short = timer(Ls, Ms, [c[0] for c in srows[0][0]], [c[1] for c in srows[0][0]], dt)
-        ent_short.update({"ms": t_short, "regret": tune.regret(t_short, best_t)})
-        ent = {"L": Ls, "dtype": dt, "joint_best": {"params": best_p, "ms": best_t}, "joint_candidates": len(joint),
-               "predicted_top2_verified": ent_short,
-               "predicted": {"params": params, "confidence": conf, "ms": t_pred,
-                             "regret": tune.regret(t_pred, best_t)},
-               "default": {"params": dflt, "ms": t_def, "regret": tune.regret(t_def, best_t)},
-               "separable_A0": {"params": sep, "ms": t_sep, "regret": tune.regret(t_sep, best_t)}}
-        if t_rect is not None:
-            ent["rect32"] = {"params": rect, "ms": t_rect, "regret": tune.regret(t_rect, best_t)}
-        results["eval"].append(ent)
-        print(f"[predict] {Ls} {dt}: best {best_t:.3f} ms ({len(joint)} timings), predicted {t_pred:.3f} ms "
-              f"(regret {ent['predicted']['regret']:.3f}), top-2 verified {t_short:.3f} ms (regret "
-              f"{ent_short['regret']:.3f}, {len(srows)} timings), default regret {ent['default']['regret']:.3f}",
-              flush=True)
-    # the autotuner's own regret: A1 (experience) against A0 (exhaustive) on 1D sizes
-    # it has not seen, re-timed under the same conditions
-    t1 = tune.Tuner1D(tune.TuneDB(None), reps=5, warmup=2)
-    for L in (3000, 20000, 200000):  # experience from smaller problems first
-        t1.a1(L, 2 * L - 1, "c128")
-    a1rows = []
-    for L in (3 ** 9, 5 ** 7, 2 ** 20 + 7, 7 ** 7, 3 ** 13):
-        M = 2 * L - 1
-        a0 = tune.Tuner1D(tune.TuneDB(None), reps=5, warmup=2).a0(L, M, "c128")
-        r1 = t1.a1(L, M, "c128")
-        ta1 = t1.measure(L, M, r1.params["m"], r1.params["D"], "c128")
-        ta0 = t1.measure(L, M, a0.params["m"], a0.params["D"], "c128")
-        a1rows.append({"L": L, "A0": a0.params, "A0_ms": ta0, "A0_timings": len(a0.table), "A1": r1.params,
-                       "A1_ms": ta1, "A1_timings": len(r1.table), "regret": tune.regret(ta1, ta0)})
-        print(f"[predict] tuner L={L}: A1 {r1.params} {ta1:.3f} ms ({len(r1.table)} timings) vs A0 "
-              f"{a0.params} {ta0:.3f} ms ({len(a0.table)} timings), regret {tune.regret(ta1, ta0):.3f}", flush=True)
-    results["tuner_A1_vs_A0"] = a1rows
+                         "accuracy": train_acc, "class_counts": np.bincount(y, minlength=len(CLASSES)).tolist(),
+                         "seconds": round(time.time() - t0, 1)},
+               "checkpoint": os.path.relpath(args.ckpt, os.path.dirname(os.path.dirname(os.path.abspath(__file__)))),
+               "eval": evaluate(pred, EVAL_PROBLEMS), "heldout": evaluate(pred, HELDOUT_PROBLEMS)}
     os.makedirs(os.path.dirname(args.out) or ".", exist_ok=True)
     json.dump(results, open(args.out, "w"), indent=1)
-    print(json.dumps({"eval": [{"L": e["L"], "regret": round(e["predicted"]["regret"], 4),
-                                "top2_verified_regret": round(e["predicted_top2_verified"]["regret"], 4),
-                                "default_regret": round(e["default"]["regret"], 4)} for e in results["eval"]]}))
+    for part in ("eval", "heldout"):
+        e = results[part]
+        print(json.dumps({part: [{"L": x["L"], "network": round(x["network"]["regret"], 4), "abstained": x["abstained"],
+                                  "default": round(x["default"]["regret"], 4)} for x in e]}), flush=True)
 
 
 if __name__ == "__main__":

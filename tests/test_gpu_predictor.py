@@ -1,0 +1,47 @@
+"""The committed predictor checkpoint (trained by the HIP MLP kernels on the tuner's
+timings of problems of at most 2^20 elements), evaluated through hdc_predict on the
+GPU with real timings:
+
+* outside its training range (the 2D/3D evaluation problems of up to 2^26 elements)
+  an axis abstains (confidence 0) and the flow falls back to the library's A0;
+* on held-out problems inside the range, the network's choices beat or match the
+  method without it -- the default p = 1, all residues per pass -- measured against
+  the library's exhaustive search (A0) re-timed in the same process.
+
+The learned accuracy itself is parity-unpinned (machine-dependent timings; the
+paper prints none)."""
+import numpy as np
+import pytest
+
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+hdc = pytest.importorskip("paper_2306_10016_amd")
+from paper_2306_10016_amd import predict  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def cp():
+    c = predict.CheckpointPredictor(predict.DEFAULT_CKPT)
+    yield c
+    c.close()
+
+
+def test_abstains_outside_the_training_range(cp):
+    for Ls, dt in predict.EVAL_PROBLEMS:
+        params, conf = cp.predict_axes(Ls, [2 * L - 1 for L in Ls], dt)
+        say(f"{Ls} {dt}: {params} confidence {conf}")
+        assert min(conf) == 0.0
+    for Ls, dt in predict.HELDOUT_PROBLEMS:
+        _, conf = cp.predict_axes(Ls, [2 * L - 1 for L in Ls], dt)
+        assert min(conf) > 0.0, Ls
+
+
+def test_network_beats_or_matches_the_default_on_heldout_problems(cp):
+    rows = predict.evaluate(cp, predict.HELDOUT_PROBLEMS, log=say)
+    net = np.array([r["network"]["regret"] for r in rows])
+    dflt = np.array([r["default"]["regret"] for r in rows])
+    say(f"mean regret: network {net.mean():+.3f}, default {dflt.mean():+.3f}")
+    assert not any(r["abstained"] for r in rows)
+    assert net.mean() <= dflt.mean() + 0.02

@@ -243,3 +243,42 @@ def test_batch_tuner_picks_each_buckets_argmin():
     # a flat cost: the larger m wins the tie
     choice, _ = tune.tune_batch([300, 5000], "c64", timer=lambda ls, ms, dt: 1.0)
     assert choice == [512, 8192]
+
+
+def test_checkpoint_format_and_training_range(tmp_path):
+    """save_checkpoint writes the layout hdc_predictor_load reads: magic, format 2,
+    layer sizes, float32 weights, then the per-feature training range."""
+    import struct
+    r = np.random.default_rng(0)
+    params = [(r.normal(size=(5, predict.D_IN)), r.normal(size=5)), (r.normal(size=(16, 5)), r.normal(size=16))]
+    lo, hi = np.zeros(predict.D_IN), np.ones(predict.D_IN)
+    path = str(tmp_path / "net.bin")
+    predict.save_checkpoint(path, params, lo, hi)
+    raw = open(path, "rb").read()
+    assert raw[:8] == b"HDCMLP01"
+    ver, n = struct.unpack("<ii", raw[8:16])
+    sizes = struct.unpack("<3i", raw[16:28])
+    assert (ver, n, sizes) == (2, 2, (predict.D_IN, 5, 16))
+    w = np.frombuffer(raw[28:], dtype="<f4")
+    assert w.size == 5 * predict.D_IN + 5 + 16 * 5 + 16 + 2 * predict.D_IN
+    assert np.allclose(w[:5 * predict.D_IN], params[0][0].ravel().astype(np.float32))
+    assert np.array_equal(w[-2 * predict.D_IN:], np.concatenate([lo, hi]).astype(np.float32))
+    x = np.full(predict.D_IN, 0.5)
+    assert predict.in_range(x, lo, hi)
+    x[3] = 1.0 + 2 * predict.RANGE_MARGIN
+    assert not predict.in_range(x, lo, hi)
+    assert predict.in_range(x, None, None)
+
+
+def test_evaluation_problems_lie_outside_the_training_range():
+    """The 2D/3D evaluation problems have more elements than any training problem, so the
+    total-size feature leaves the range; the held-out problems stay inside it."""
+    rows = []
+    for Ls, batch, dt in predict.training_problems():
+        rows += [predict.features(Ls, a, dt, batch) for a in range(len(Ls))]
+    X = np.stack(rows)
+    lo, hi = X.min(0), X.max(0)
+    for Ls, dt in predict.EVAL_PROBLEMS:
+        assert not all(predict.in_range(predict.features(Ls, a, dt), lo, hi) for a in range(len(Ls)))
+    for Ls, dt in predict.HELDOUT_PROBLEMS:
+        assert all(predict.in_range(predict.features(Ls, a, dt), lo, hi) for a in range(len(Ls))), Ls
