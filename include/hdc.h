@@ -81,8 +81,12 @@ typedef struct {
  * alias), q >= p, C >= 1, 1 <= D.  p or q = 0 derives the ceiling (q from
  * max(M, 2L-1)); M below 2L-1 writes the first M outputs only; D = 0
  * means D = q; D > q is clamped to q.  Returns HDC_ERR_INVALID_ARG for
- * inadmissible input and HDC_ERR_UNSUPPORTED when m is not a power of two,
- * m > 2^22, or the transform does not fit the kernels' index range.
+ * inadmissible input and HDC_ERR_UNSUPPORTED when m > 2^22, when the
+ * transform does not fit the kernels' index range, or when m is not a power of
+ * two and either its odd factor R (m = R 2^k) has a prime factor above 7 or
+ * exceeds 63, or the residues do not fit the fused kernel (m <= 4096 and
+ * q m b 9/8 <= 80 KiB): such m (section 3.1's FFT-friendly sizes) run on the
+ * mixed-radix fused kernel only, in 1D complex plans and batches.
  */
 hdc_status hdc_derive(int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, int64_t C, int64_t D,
                       hdc_dtype dtype, hdc_axis_desc* out);
@@ -247,7 +251,10 @@ hdc_status hdc_convolve_noalloc(hdc_plan_t plan, const void* f, const void* g, v
  * Forward residues [r0, r0 + D') of a 1D plan, D' = min(D, q - r0): the m-point
  * DFTs of eq. (3).  F holds D' x m x C values; within a residue the order is
  * implementation-defined (hdc_residues_natural gives the natural order).
- * r0 must be a multiple of D.  ws: hdc_workspace_size bytes.
+ * r0 must be a multiple of D.  ws: hdc_workspace_size bytes.  The separate
+ * stages (hdc_forward, hdc_forward_operand, hdc_multiply, hdc_backward,
+ * hdc_residues_natural) take power-of-two m: HDC_ERR_UNSUPPORTED otherwise
+ * (a plan with m = R 2^k, R > 1, convolves with hdc_convolve only).
  */
 hdc_status hdc_forward(hdc_plan_t plan, const void* f, void* F, int64_t r0, void* ws, hipStream_t stream);
 

@@ -62,8 +62,10 @@ hdc_status hdc_params_check(const hdc_problem* prob, const hdc_params* prm, hdc_
  * smaller m, then the smaller D, then the default tile.
  *
  * mode 0 (A0, section 4.2): exhaustive over the candidate grid: power-of-two
- *   m with p = ceil(L/m) in {1, 2, 3, 4, 6, 8, 12, 16} (or q = 1, the explicit
- *   case) and q >= p, D in {q, 1, 2, 4, ...}, then the column tile (half and
+ *   m (for 1D problems also m = R 2^k <= 4096 with R odd and 7-smooth, the
+ *   mixed-radix fused kernel) with p = ceil(L/m) in {1, 2, 3, 4, 6, 8, 12, 16}
+ *   (or q = 1, the explicit case) and q >= p, D in {q, 1, 2, 4, ...} (the
+ *   candidates the kernels cannot run are skipped), then the column tile (half and
  *   double the default) of the best.  N-D problems are searched one axis at a
  *   time with the other axes at their defaults (p = 1, D = q): the
  *   separability argument of section 4.2.

@@ -45,6 +45,13 @@ hdc_status hip_fail(hipError_t e, const char* what) {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+// no prime factor above 7
+bool smooth7(int64_t x) {
+    if (x < 1) return false;
+    for (int p : {2, 3, 5, 7})
+        while (x % p == 0) x /= p;
+    return x == 1;
+}
 int ilog2i(int64_t x) {
     int l = 0;
     while ((int64_t(1) << l) < x) ++l;
@@ -212,7 +219,12 @@ hdc_status derive_axis(int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, in
                     (long long)(q * m), (long long)K);
     if (q < p) return fail(HDC_ERR_INVALID_ARG, "q = %lld < p = %lld", (long long)q, (long long)p);
     if (D == 0 || D > q) D = q;
-    if (!is_pow2(m)) return fail(HDC_ERR_UNSUPPORTED, "m = %lld: only powers of two are implemented", (long long)m);
+    // m = R 2^k with R odd and 7-smooth (section 3.1's FFT-friendly sizes);
+    // R > 1 runs on the mixed-radix fused kernel only
+    const int64_t Rodd = odd_part(m);
+    if (!is_pow2(m) && !(Rodd <= kMaxOddR && smooth7(Rodd)))
+        return fail(HDC_ERR_UNSUPPORTED, "m = %lld: the kernels take m = R 2^k with R odd, 7-smooth and at most %d",
+                    (long long)m, kMaxOddR);
     const int64_t N = q * m;
     if (N >= (int64_t(1) << 31))
         return fail(HDC_ERR_UNSUPPORTED, "N = %lld exceeds the 32-bit twiddle index range", (long long)N);
@@ -240,6 +252,10 @@ hdc_status derive_axis(int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, in
     const size_t fused_lds = (size_t)(q * padded_len(m)) * b + (size_t)q * 16 + 16;
     o->variant = (m <= kMaxFused && fused_lds <= kFusedRowLds) ? 0 : 1;
     o->reserved = 0;
+    if (!is_pow2(m) && (o->variant != 0 || res_threads(m) > 512))
+        return fail(HDC_ERR_UNSUPPORTED,
+                    "m = %lld is not a power of two: it needs the fused kernel (q m b 9/8 = %zu bytes of LDS within "
+                    "%zu, m <= %d)", (long long)m, fused_lds, kFusedRowLds, kMaxFused);
     return HDC_OK;
 }
 
@@ -254,6 +270,8 @@ int tile_for(int tpf, int tmin, int maxthreads) {
 hdc_status geometry(AxisPlan& A, bool outer, bool many_rows = false, bool keep_split = false) {
     hdc_axis_desc& d = A.d;
     const size_t b = A.dbl ? 16 : 8;
+    if (!is_pow2(d.m) && (outer || many_rows))
+        return fail(HDC_ERR_UNSUPPORTED, "m = %lld: N-D axes take powers of two", (long long)d.m);
     if (outer) {
         // an outer axis is transformed down strided columns: m = m1 * m2 with both
         // factors column passes (the second one a plain strided m2-point DFT)
@@ -276,10 +294,9 @@ hdc_status geometry(AxisPlan& A, bool outer, bool many_rows = false, bool keep_s
         A.mb_lds = (size_t)d.m2 * A.mb_tile * b;
     }
     const int tmin = A.dbl ? 8 : 16;
-    // fused
+    // fused (m = R 2^k: R sub-transforms side by side)
     {
-        const int ppt = ppt_for((int)d.m);
-        const int tpf = (int)d.m / ppt;
+        const int tpf = res_threads(d.m);
         // every residue of a row stays in LDS whatever D is (D bounds the
         // workspace of the multi-pass variant), so D does not limit concurrency
         int Dc = (int)d.q;
@@ -605,6 +622,7 @@ hdc_status run_fused(const AxisPlan& A, const void* f, const void* g, void* h, i
     a.invN = 1.0 / (double)A.d.N;
     a.nops = nops;
     for (int o = 2; o < nops; ++o) a.xm[o - 2] = xs[o];
+    a.R = (int32_t)odd_part(A.d.m);
     const int64_t blocks = ceil_div(nrows, A.f_rpw);
     if (blocks > 0x7fffffff) return fail(HDC_ERR_UNSUPPORTED, "too many rows");
     const double eb = A.dbl ? 16.0 : 8.0;
@@ -1429,6 +1447,8 @@ hdc_status hdc_plan(hdc_plan_t* out, int64_t L, int64_t M, int64_t m, int64_t p,
     P->dtype = complex_of(dtype);
     AxisPlan& A = P->ax[0];
     hdc_status st = derive_axis(L, M, m, p, q, C, D, P->dtype, &A.d);
+    if (st == HDC_OK && P->real && !is_pow2(A.d.m))
+        st = fail(HDC_ERR_UNSUPPORTED, "real-data plans take power-of-two m");
     if (st == HDC_OK) {
         A.dbl = P->dtype == HDC_C128;
         st = geometry(A, false);
@@ -1459,6 +1479,8 @@ hdc_status hdc_plan_multi(hdc_plan_t* out, int A, int64_t L, int64_t M, int64_t 
     AxisPlan& Ax = P->ax[0];
     // the A-fold linear convolution has A (L - 1) + 1 terms: the transform must cover them
     hdc_status st = derive_axis(L, M, m, p, q, C, D, dtype, &Ax.d, (int64_t)A * (L - 1) + 1);
+    if (st == HDC_OK && !is_pow2(Ax.d.m))
+        st = fail(HDC_ERR_UNSUPPORTED, "multi-convolution plans take power-of-two m");
     if (st == HDC_OK) {
         Ax.dbl = dtype == HDC_C128;
         st = geometry(Ax, false);
@@ -1815,6 +1837,9 @@ static hdc_status group_check(hdc_plan_t P, int64_t r0, int64_t* Dg) {
     if (P->real) return fail(HDC_ERR_UNSUPPORTED, "a real-data plan exposes hdc_convolve only");
     if (P->ndim != 1) return fail(HDC_ERR_UNSUPPORTED, "forward/multiply/backward are defined for 1D plans");
     const hdc_axis_desc& d = P->ax[0].d;
+    if (!is_pow2(d.m))
+        return fail(HDC_ERR_UNSUPPORTED, "m = %lld: the separate stages take power-of-two m (use hdc_convolve)",
+                    (long long)d.m);
     const int64_t D = std::min(d.D, d.q);
     if (r0 < 0 || r0 >= d.q || r0 % D != 0)
         return fail(HDC_ERR_INVALID_ARG, "r0 = %lld must be a multiple of D = %lld below q = %lld", (long long)r0,
@@ -2265,7 +2290,8 @@ hdc_status hdc_batch_plan(hdc_batch_t* out, int64_t n, const int64_t* L, const i
         const int64_t maxm = dtype == HDC_C128 ? kQueueMaxM128 : kQueueMaxM64;
         FusedQueue& fq = Bt->fq;
         for (size_t b = 0; b < Bt->buckets.size(); ++b)
-            if (Bt->buckets[b].A.d.variant == 0 && Bt->buckets[b].A.d.m <= maxm) fq.members.push_back(b);
+            if (Bt->buckets[b].A.d.variant == 0 && Bt->buckets[b].A.d.m <= maxm && is_pow2(Bt->buckets[b].A.d.m))
+                fq.members.push_back(b);
         std::stable_sort(fq.members.begin(), fq.members.end(), [&](size_t x, size_t y) {
             return Bt->buckets[x].A.d.m > Bt->buckets[y].A.d.m;
         });

@@ -53,6 +53,8 @@ struct FusedArgs {
     // xm[o - 2] the others (same lengths and layout as f)
     int32_t nops;
     const void* xm[6];
+    // m = R msz with R odd (R = 1: m a power of two): the mixed-radix fused kernel
+    int32_t R;
 };
 
 // Persistent fused kernel of a batch: items[3 i .. 3 i + 2] = {bucket, FFT size m,
@@ -210,6 +212,21 @@ inline int64_t pass_tab_len(int64_t n) {
 
 // Points per thread of the Stockham transforms for size n.
 inline int ppt_for(int n) { return n >= 8 ? 8 : n; }
+
+// m = R 2^k: the odd factor R, and the threads of one m-point residue transform
+// (R sub-transforms of 2^k points side by side).
+inline int64_t odd_part(int64_t m) {
+    while (m > 0 && (m & 1) == 0) m >>= 1;
+    return m;
+}
+inline int res_threads(int64_t m) {
+    const int64_t R = odd_part(m), p2 = m / R;
+    return (int)(R * (p2 / ppt_for((int)p2)));
+}
+
+// Largest odd factor of m the mixed-radix fused kernel takes (its direct
+// R-point stage costs R products per point).
+constexpr int kMaxOddR = 63;
 
 // Largest column-stage transform and row-stage transform the kernels implement.
 constexpr int kMaxM1 = 1024;

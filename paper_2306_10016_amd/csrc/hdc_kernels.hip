@@ -551,6 +551,209 @@ __device__ __forceinline__ void fused_rows(const FusedArgs& a, const void* fp, c
     }
 }
 
+// Mixed-radix fused kernel: m = R MSZ with R odd (3, 5, 7, 9, 15, ... <= 63),
+// section 3.1's FFT-friendly sizes.  The m-point DFT of a residue is split by
+// decimation in time, s = rho + R s': R sub-transforms of MSZ points (one
+// thread group each, the radix-8 engine above) and a direct R-point stage
+//     F_{l' + MSZ k} = sum_rho zeta_R^{rho k} zeta_m^{rho l'} X_rho[l'],
+// exchanged through LDS; the inverse runs the two stages in the opposite order,
+//     u_{rho + R s'} = sum_{l'} zeta_MSZ^{-s' l'} zeta_m^{-rho l'} sum_k zeta_R^{-rho k} H_{l' + MSZ k}.
+// Everything else (block sums, product, output sums) is the fused kernel's.
+template <typename T, int MSZ>
+__device__ __forceinline__ void fused_rows_mixed(const FusedArgs& a, const void* fp, const void* gp, void* hp,
+                                                 bool same, int64_t blk, unsigned char* smem_raw) {
+    using P = FP<MSZ>;
+    constexpr int PPT = P::PPT;
+    constexpr int TPF = P::TPF;
+    constexpr int SUB = padded(MSZ);  // LDS slots of one sub-transform
+    cplx<T>* smem = reinterpret_cast<cplx<T>*>(smem_raw);
+    using S = TwSplit<MSZ>;
+    const int R = a.R;
+    const int m = R * MSZ;
+    const int RSm = m + (m >> 3);  // LDS slots per residue (holds R sub-buffers)
+    double2* twq =
+        reinterpret_cast<double2*>(smem_raw + ((size_t)a.rpw * a.q * RSm * sizeof(cplx<T>) + 15) / 16 * 16);
+    cplx<T>* tlo = reinterpret_cast<cplx<T>*>(twq + a.q);
+    cplx<T>* thi = tlo + S::LO;
+
+    const int rowthreads = TPF * R * a.Dc;  // Dc residues of R units each
+    const int tid = threadIdx.x;
+    const int rloc = tid / rowthreads;
+    const int lt = tid - rloc * rowthreads;
+    const int unit = lt / TPF;  // (residue in the round, rho)
+    const int lane = lt - unit * TPF;
+    const int rr = unit / R;
+    const int rho = unit - rr * R;
+    const int64_t row = blk * a.rpw + rloc;
+    const bool rowok = rloc < a.rpw && row < a.nrows;
+
+    const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.twm);  // zeta_m^e, e < m
+    for (int e = tid; e < a.q; e += blockDim.x) twq[e] = tw_n(a.tw, (uint32_t)e * (uint32_t)m);
+    // zeta_MSZ^e = zeta_m^{R e} for the sub-transforms' passes
+    for (int e = tid; e < S::LO; e += blockDim.x) tlo[e] = twg[R * e];
+    for (int e = tid; e < S::HI; e += blockDim.x) thi[e] = twg[R * e * S::LO];
+    __syncthreads();
+    const TwLds<T> twm{tlo, thi, S::LO - 1, S::LG};
+
+    int L = a.L, M = a.M;
+    int64_t fbase, hbase;
+    if (a.desc != nullptr) {
+        const int64_t* d = a.desc + 4 * (rowok ? row : 0);
+        fbase = d[0];
+        hbase = d[1];
+        L = (int)d[2];
+        M = (int)d[3];
+    } else {
+        fbase = row_base(a.in, rowok ? row : 0);
+        hbase = row_base(a.out, rowok ? row : 0);
+    }
+    const int64_t ies = a.in.es, oes = a.out.es;
+    const cplx<T>* f = reinterpret_cast<const cplx<T>*>(fp) + fbase;
+    const cplx<T>* g = reinterpret_cast<const cplx<T>*>(gp) + fbase;
+    cplx<T>* h = reinterpret_cast<cplx<T>*>(hp) + hbase;
+    cplx<T>* U = smem + (size_t)(rowok ? rloc : 0) * a.q * RSm;
+    const T invN = (T)a.invN;
+
+    for (int rb = 0; rb < a.q; rb += a.Dc) {
+        const int r = rb + rr;
+        const bool act = rowok && r < a.q;
+        cplx<T>* res = U + (size_t)(act ? r : 0) * RSm;  // this residue's region
+        cplx<T>* buf = res + rho * SUB;                  // this unit's sub-buffer
+
+        // block sums of eq. (3) at the points s = rho + R (lane + v TPF)
+        cplx<T> F[PPT], G[PPT];
+#pragma unroll
+        for (int v = 0; v < PPT; ++v) {
+            F[v] = mk<T>(0, 0);
+            G[v] = mk<T>(0, 0);
+        }
+        if (act) {
+            int e = 0;  // (r t) mod q
+            for (int t = 0; t < a.p; ++t) {
+                const double2 z = twq[e];
+                e += r;
+                if (e >= a.q) e -= a.q;
+#pragma unroll
+                for (int v = 0; v < PPT; ++v) {
+                    const int j = t * m + rho + R * (lane + v * TPF);
+                    if (j < L) {
+                        F[v] = F[v] + mul_tw<false>(f[(int64_t)j * ies], z, false);
+                        if (!same) G[v] = G[v] + mul_tw<false>(g[(int64_t)j * ies], z, false);
+                    }
+                }
+            }
+        }
+        const uint32_t ru = (uint32_t)(act ? r : 0);
+        // zeta_N^{r s}, s = rho + R lane + R TPF v, as z0 zs^v (r s < q m = N)
+        const double2 z0 = tw_n(a.tw, ru * (uint32_t)(rho + R * lane));
+        const double2 zs = tw_n(a.tw, ru * (uint32_t)(R * TPF));
+        {
+            double2 z = z0;
+#pragma unroll
+            for (int v = 0; v < PPT; ++v) {
+                F[v] = mul_tw<false>(F[v], z, a.hiprec);
+                if (!same) G[v] = mul_tw<false>(G[v], z, a.hiprec);
+                z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
+            }
+        }
+        // forward: MSZ-point sub-transform, then the R-point stage through LDS;
+        // afterwards unit rho holds F_{l' + MSZ rho} at l' = lane + v TPF
+        auto forward = [&](cplx<T>(&X)[PPT]) {
+            fft_regs<T, MSZ, +1, LAY_PAD>(X, buf, 1, lane, twm, act);
+            if (act) {
+#pragma unroll
+                for (int v = 0; v < PPT; ++v) {
+                    const int l = lane + v * TPF;
+                    buf[lds_at<LAY_PAD, T, MSZ>(l, 1)] = X[v] * twg[rho * l];  // zeta_m^{rho l'}
+                }
+            }
+            __syncthreads();
+            if (act) {
+#pragma unroll
+                for (int v = 0; v < PPT; ++v) {
+                    const int l = lane + v * TPF;
+                    cplx<T> acc = mk<T>(0, 0);
+                    int e = 0;  // (rho2 rho) mod R
+                    for (int rho2 = 0; rho2 < R; ++rho2) {
+                        acc = acc + res[rho2 * SUB + lds_at<LAY_PAD, T, MSZ>(l, 1)] * twg[e * MSZ];
+                        e += rho;
+                        if (e >= R) e -= R;
+                    }
+                    X[v] = acc;
+                }
+            }
+            __syncthreads();
+        };
+        forward(F);
+        if (!same) {
+            forward(G);
+#pragma unroll
+            for (int v = 0; v < PPT; ++v) F[v] = F[v] * G[v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < PPT; ++v) F[v] = F[v] * F[v];
+        }
+        // inverse: the R-point stage (unit rho gathers H_{l' + MSZ k}, k < R), then
+        // the MSZ-point inverse sub-transform
+        if (act) {
+#pragma unroll
+            for (int v = 0; v < PPT; ++v) buf[lds_at<LAY_PAD, T, MSZ>(lane + v * TPF, 1)] = F[v];
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int v = 0; v < PPT; ++v) {
+                const int l = lane + v * TPF;
+                cplx<T> acc = mk<T>(0, 0);
+                int e = 0;  // (rho k) mod R, conjugated below
+                for (int k = 0; k < R; ++k) {
+                    const cplx<T> w = twg[e * MSZ];
+                    acc = acc + res[k * SUB + lds_at<LAY_PAD, T, MSZ>(l, 1)] * mk<T>(w.x, -w.y);
+                    e += rho;
+                    if (e >= R) e -= R;
+                }
+                const cplx<T> w = twg[rho * l];
+                F[v] = acc * mk<T>(w.x, -w.y);  // zeta_m^{-rho l'}
+            }
+        }
+        __syncthreads();
+        fft_regs<T, MSZ, -1, LAY_PAD>(F, buf, 1, lane, twm, act);
+        // every unit of the residue has read its sub-buffer for the last time (the
+        // transform's final barrier, or the one above when it has a single pass):
+        // the residue's region now takes u^(r)_s zeta_N^{-r s} / N in natural order
+        if (act) {
+            double2 z = z0;
+#pragma unroll
+            for (int v = 0; v < PPT; ++v) {
+                const int s = rho + R * (lane + v * TPF);
+                res[lds_at<LAY_PAD, T, MSZ>(s, 1)] = scale(mul_tw<true>(F[v], z, a.hiprec), invN);
+                z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
+            }
+        }
+        __syncthreads();
+    }
+    if (!rowok) return;
+    // h_{t m + s} = sum_r zeta_q^{-t r} U[r][s]
+    for (int k = lt; k < M; k += rowthreads) {
+        const int t = k / m;
+        const int s = k - t * m;
+        cplx<T> acc = mk<T>(0, 0);
+        int e = 0;  // (t r) mod q
+        for (int r = 0; r < a.q; ++r) {
+            acc = acc + mul_tw<true>(U[(size_t)r * RSm + lds_at<LAY_PAD, T, MSZ>(s, 1)], twq[e], false);
+            e += t;
+            if (e >= a.q) e -= a.q;
+        }
+        h[(int64_t)k * oes] = acc;
+    }
+}
+
+template <typename T, int MSZ>
+__global__ void __launch_bounds__(512) k_fused_mixed(FusedArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    fused_rows_mixed<T, MSZ>(a, a.f, a.g, a.h, a.same != 0, blockIdx.x, smem_raw);
+}
+
 template <typename T, int MSZ, bool MULTI = false>
 __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1677,8 +1880,23 @@ hipError_t row_t(const RowArgs& a, int threads, int64_t blocks, size_t lds, hipS
     case 512: return F<T, 512>(__VA_ARGS__);   \
     case 1024: return F<T, 1024>(__VA_ARGS__);
 
+template <typename T, int MSZ>
+hipError_t fused_mixed_t(const FusedArgs& a, int threads, int64_t blocks, size_t lds, hipStream_t s) {
+    lds += (size_t)(TwSplit<MSZ>::LO + TwSplit<MSZ>::HI) * sizeof(cplx<T>);
+    hipError_t e = allow_lds(k_fused_mixed<T, MSZ>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_fused_mixed<T, MSZ>), dim3((unsigned)blocks), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t fused_disp(int m, const FusedArgs& a, int th, int64_t bl, size_t lds, hipStream_t s) {
+    if (a.R > 1) {  // m = R 2^k: dispatch on the power-of-two part
+        switch (m / a.R) {
+            HDC_POW2_CASES(fused_mixed_t, a, th, bl, lds, s)
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (m) {
         HDC_POW2_CASES(fused_t, a, th, bl, lds, s)
         case 2048: return fused_t<T, 2048>(a, th, bl, lds, s);

@@ -389,14 +389,26 @@ Cand default_cand(const hdc_problem& pr) {
 // (m, D) candidates of one axis (section 4.2's grid): power-of-two m with
 // p = ceil(L/m) in the classes (or q = 1) and q >= p; D = q, and with
 // all_d also 1, 2, 4, ... < q.
+// 1D problems also take m = R 2^k with R in these odd 7-smooth factors (the
+// mixed-radix fused kernel; such m only fit the fused kernel, m <= 4096)
+constexpr int kOddR[] = {3, 5, 7, 9, 15, 21, 25, 27, 35, 45, 49, 63};
+
 std::vector<std::pair<int64_t, int64_t>> axis_grid(const hdc_problem& pr, int a, bool all_d) {
     std::vector<std::pair<int64_t, int64_t>> out;
     const int64_t L = pr.L[a], K = std::max(pr.M[a], 2 * pr.L[a] - 1);
-    for (int64_t m = 1; m <= axis_limit(pr, a); m *= 2) {
+    std::vector<int64_t> ms;
+    for (int64_t m = 1; m <= axis_limit(pr, a); m *= 2) ms.push_back(m);
+    if (pr.ndim == 1)
+        for (int R : kOddR)
+            for (int64_t m = R; m <= 4096; m *= 2) ms.push_back(m);
+    std::sort(ms.begin(), ms.end());
+    for (int64_t m : ms) {
         const int64_t p = cdiv(L, m), q = cdiv(K, m);
         if (q < p || !(in_pclasses(p) || q == 1)) continue;
         out.push_back({m, q});
-        if (all_d)
+        // D only sizes the workspace of the column/row passes: the fused kernel
+        // (every m = R 2^k) runs the same for any D
+        if (all_d && (m & (m - 1)) == 0)
             for (int64_t d = 1; d < q; d *= 2) out.push_back({m, d});
     }
     return out;

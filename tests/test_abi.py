@@ -47,7 +47,10 @@ def test_derive_fig2_shape():
     ((10, 19, 4, 2, 0), 1),      # p m < L
     ((10, 19, 4, 0, 4), 1),      # q m < M
     ((10, 19, 4, 5, 4), 1),      # q < p (and qm < M)
-    ((10, 19, 6), 2),            # m not a power of two: unsupported by the kernels
+    ((10, 19, 11), 2),           # m with a prime factor above 7
+    ((200, 399, 66), 2),         # m = 2 * 33: the odd factor has the prime 11
+    ((10, 19, 127), 2),          # odd factor beyond 63
+    ((3000, 5999, 3 * 1024), 2),  # m = 3 2^10: the residues do not fit the fused kernel's LDS
     ((10, 19, 4, 0, 0, 0), 1),   # C < 1
     ((1 << 23, (1 << 24) - 1, 1 << 24), 2),  # m beyond the column x row limit
     ((1 << 62, 1 << 40, 1 << 20), 2),           # L far beyond any supported size (2L - 1 would overflow)
@@ -60,6 +63,27 @@ def test_derive_rejects(args, status):
         hdc.derive(*args)
     assert e.value.status == status
     assert len(str(e.value)) > 10
+
+
+@pytest.mark.parametrize("m", [3, 5, 6, 7, 12, 15, 96, 320, 448, 63 * 16, 45 * 16])
+def test_derive_takes_7_smooth_m(m):
+    """m = R 2^k with R odd, 7-smooth and at most 63 (section 3.1's FFT-friendly
+    sizes) runs on the fused kernel: variant 0."""
+    L = m + 1
+    d = hdc.derive(L, 2 * L - 1, m, dtype="c64")
+    assert d["m"] == m and d["variant"] == 0 and d["p"] == 2 and d["q"] == 3
+    # the largest: 63 sub-transforms of 64 points, q = 2 within the LDS budget
+    d = hdc.derive(3000, 5999, 63 * 64, dtype="c64")
+    assert d["variant"] == 0 and d["q"] == 2
+
+
+def test_non_pow2_m_is_1d_complex_only():
+    with pytest.raises(hdc.HdcError):
+        hdc.Plan(100, 199, 12, dtype="r64")
+    with pytest.raises(hdc.HdcError):
+        hdc.MultiPlan(3, 100, m=12)
+    with pytest.raises(hdc.HdcError):
+        hdc.check_nd([100, 100], [199, 199], [16, 12])
 
 
 def test_derive_clamps_D():

@@ -56,7 +56,8 @@ SWEEP = []
 for L in (1, 2, 3, 6, 37, 100, 513):
     for extra in (0, 7):
         M = 2 * L - 1 + extra
-        for m in (1, 2, 4, 8, 32, 128, 1024):
+        # powers of two, and m = R 2^k with R in 3, 5, 7 (the mixed-radix fused kernel)
+        for m in (1, 2, 4, 8, 32, 128, 1024, 3, 5, 6, 7, 12, 96, 320, 448):
             if m > 2 * M:
                 continue
             SWEEP.append((L, M, m))

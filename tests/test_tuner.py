@@ -29,8 +29,9 @@ def test_candidates_are_admissible(L):
     assert cands
     for c in cands:
         m, D = c["m"], c["D"]
-        d = hdc.derive(L, M, m, D=D)
+        d = hdc.derive(L, M, m, D=D, dtype="c64")
         assert d["p"] * m >= L and d["q"] * m >= M and d["q"] >= d["p"]
+        assert m & (m - 1) == 0 or (d["variant"] == 0 and m <= 4096)  # m = R 2^k: the fused kernel
         assert d["p"] in tune.P_CLASSES or d["q"] == 1
         assert D == d["q"] or (D & (D - 1)) == 0  # all residues, or a power of two per pass
     grid = {(c["m"], c["D"]) for c in cands if "tile" not in c}
