@@ -69,7 +69,9 @@ typedef struct {
     int64_t C;        /* copies                                               */
     int64_t q_out;    /* output blocks ceil(M/m)                              */
     int64_t m1, m2;   /* m = m1*m2: column-stage and row-stage FFT lengths    */
-    int32_t variant;  /* 0 = fused single kernel, 1 = column/row/column passes */
+    int32_t variant;  /* 0 = fused single kernel, 1 = column/row/column passes,
+                         2 = raw residue rows + output sums (one-row residues),
+                         3 = whole-row convolution (innermost N-D axis)       */
     int32_t reserved;
 } hdc_axis_desc;
 
@@ -342,7 +344,7 @@ hdc_status hdc_time_convolve(hdc_plan_t plan, const void* f, const void* g, void
  * Instrumented hdc_convolve: the same launches, each bracketed by HIP events on
  * `stream`; synchronises the stream.  For launch i < min(*n_launches,
  * max_launches): kinds[i] (0 fused, 1 forward column, 2 row, 3 backward
- * column, 4 raw residue rows, 5 output sums), ms[i] (event-measured duration) and bytes[i] (the launch's
+ * column, 4 raw residue rows, 5 output sums, 6 whole-row convolution), ms[i] (event-measured duration) and bytes[i] (the launch's
  * algorithmic HBM bytes: compulsory reads plus writes).  Any output array may
  * be NULL.  *n_launches receives the total number of launches.
  */

@@ -142,6 +142,9 @@ struct AxisPlan {
     // fused geometry
     int Dc = 1, f_rpw = 1, f_threads = 1;
     size_t f_lds = 0;
+    // whole-row convolution (variant 3)
+    int rc_rpw = 1, rc_threads = 1;
+    size_t rc_lds = 0;
     // column/row geometry
     int cf_tile = 1, cf_threads = 1, cb_tile = 1, cb_threads = 1, r_rpw = 1, r_threads = 1;
     size_t cf_lds = 0, cb_lds = 0, r_lds = 0;
@@ -364,6 +367,18 @@ hdc_status geometry(AxisPlan& A, bool outer, bool many_rows = false, bool keep_s
     if (many_rows && !outer && d.m >= 2048 && d.m <= kMaxRow && d.q <= kMaxQsum && d.p <= kMaxRawP &&
         d.C * d.m <= (int64_t(1) << 30))
         d.variant = 2;
+    // ... and when the output blocks fit the registers, the whole row in one
+    // workgroup: residues in turn, output sums accumulated in registers
+    if (many_rows && !outer && is_pow2(d.m) && d.m >= kRowconvMinM && d.m <= kRowconvMaxM &&
+        d.q_out <= (A.dbl ? kRowconvQO128 : kRowconvQO64) && d.p <= kRowconvMaxP &&
+        !(A.dbl && d.m < 2048)) {
+        // two exchange buffers per row, the m-point pass table, q twiddles
+        const int tpf = (int)d.m / 8;
+        A.rc_rpw = std::max(1, 256 / tpf);
+        A.rc_threads = A.rc_rpw * tpf;
+        A.rc_lds = (((size_t)A.rc_rpw * 2 * d.m + (size_t)pass_tab_len(d.m)) * b + 15) / 16 * 16 + (size_t)d.q * 16;
+        if (A.rc_lds <= device_lds_max()) d.variant = 3;
+    }
     A.hiprec = !A.dbl && d.N > (int64_t(1) << 20);
     return HDC_OK;
 }
@@ -587,6 +602,39 @@ void bind_tables(AxisPlan& A, unsigned char* base) {
 }
 
 // ---------------------------------------------------------------- launches --
+
+// Whole-row convolutions (variant 3) of nrows rows addressed by in / out.
+hdc_status run_rowconv(const AxisPlan& A, const void* f, const void* g, void* h, int64_t nrows, RowAddr in,
+                       RowAddr out, hipStream_t s) {
+    if (nrows <= 0) return HDC_OK;
+    FusedArgs a{};
+    a.f = f;
+    a.g = g;
+    a.h = h;
+    a.nrows = nrows;
+    a.in = in;
+    a.out = out;
+    a.L = (int32_t)A.d.L;
+    a.M = (int32_t)A.d.M;
+    a.p = (int32_t)A.d.p;
+    a.q = (int32_t)A.d.q;
+    a.qout = (int32_t)A.d.q_out;
+    a.N = (int32_t)A.d.N;
+    a.rpw = A.rc_rpw;
+    a.same = f == g ? 1 : 0;
+    a.hiprec = A.hiprec ? 1 : 0;
+    a.tw = A.tw;
+    a.twm = A.tw_p2;  // the pass table of the m-point transform (m2 = m)
+    a.invN = 1.0 / (double)A.d.N;
+    a.R = 1;
+    const int64_t blocks = ceil_div(nrows, A.rc_rpw);
+    if (blocks > 0x7fffffff) return fail(HDC_ERR_UNSUPPORTED, "too many rows");
+    const double eb = A.dbl ? 16.0 : 8.0;
+    LaunchScope ls(s, 6, eb * (double)nrows * ((a.same ? 1.0 : 2.0) * (double)A.d.L + (double)A.d.M));
+    hipError_t e = launch_rowconv(A.dbl, (int)A.d.m, a, A.rc_threads, blocks, A.rc_lds, s);
+    if (e != hipSuccess) return hip_fail(e, "row convolution launch");
+    return HDC_OK;
+}
 
 // Lf >= 0: f has length Lf and g the axis length, g's rows addressed by ing
 // (section 3.5 with Lambda = 1).
@@ -887,7 +935,7 @@ size_t elem(const hdc_plan_s* P) { return elem_bytes(P->dtype); }
 
 // Workspace (elements) of a 1D convolution of B rows x C1 copies on axis A.
 int64_t ws1d(const AxisPlan& A, int64_t B, int64_t C1) {
-    if (A.d.variant == 0) return 0;
+    if (A.d.variant == 0 || A.d.variant == 3) return 0;
     const int64_t Dg = std::min(A.d.D, A.d.q);
     if (A.d.variant == 2) return B * Dg * A.d.m * C1;  // the product rows only
     return 2 * B * Dg * A.d.m * C1;
@@ -949,9 +997,10 @@ hdc_status run_raw_group(const AxisPlan& A, const void* xf, const void* xg, void
 // 1D convolution along axis A: B batches (strides in_bs / out_bs) of C1 interleaved copies.
 hdc_status conv1d(const AxisPlan& A, const void* xf, const void* xg, void* out, int64_t B, int64_t in_bs, int64_t out_bs,
                   int64_t C1, char* ws, size_t eb, hipStream_t s) {
-    if (A.d.variant == 0) {
+    if (A.d.variant == 0 || A.d.variant == 3) {
         RowAddr in{C1, in_bs, 1, C1};
         RowAddr ou{C1, out_bs, 1, C1};
+        if (A.d.variant == 3) return run_rowconv(A, xf, xg, out, B * C1, in, ou, s);
         return run_fused(A, xf, xg, out, B * C1, in, ou, nullptr, s);
     }
     const bool same = xf == xg;

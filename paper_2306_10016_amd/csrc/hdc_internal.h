@@ -172,7 +172,19 @@ constexpr int kQueueMaxM128 = 512;   // complex128
 constexpr int kMaxQsum = 32;
 constexpr int kMaxRawP = 4;
 
+// Whole-row convolution of an innermost N-D axis (k_rowconv): FFT sizes, the
+// output blocks its registers hold per type, and the most input blocks each
+// residue re-reads.
+constexpr int kRowconvMinM = 1024;
+constexpr int kRowconvMaxM = 4096;
+constexpr int kRowconvQO64 = 4;   // complex64
+constexpr int kRowconvQO128 = 2;  // complex128
+constexpr int kRowconvMaxP = 4;
+
 enum { MODE_FWD = 0, MODE_INV = 1, MODE_CONV = 2 };
+
+// Compute units of the current device (cached).
+int cu_count();
 
 // Launchers (return hipSuccess or the launch error).  `dbl` selects complex128.
 hipError_t launch_fused(bool dbl, int m, const FusedArgs& a, int threads, int64_t blocks, size_t lds,
@@ -191,6 +203,8 @@ hipError_t launch_row_multi(bool dbl, int m2, const RowArgs& a, int threads, int
                             hipStream_t s);
 hipError_t launch_row_rr(bool dbl, int m, const RawArgs& a, int threads, int64_t blocks, size_t lds, hipStream_t s);
 hipError_t launch_qsum(bool dbl, const RawArgs& a, int64_t gx, int64_t gy, hipStream_t s);
+hipError_t launch_rowconv(bool dbl, int m, const FusedArgs& a, int threads, int64_t blocks, size_t lds,
+                          hipStream_t s);
 hipError_t launch_fused_queue(bool dbl, const FusedQueueArgs& a, int64_t nitems, size_t lds, hipStream_t s);
 hipError_t launch_mul(bool dbl, void* F, const void* G, int64_t n, hipStream_t s);
 hipError_t launch_natural(bool dbl, const void* F, void* out, int64_t Dg, int64_t m1, int64_t m2, int64_t C,

@@ -754,6 +754,137 @@ __global__ void __launch_bounds__(512) k_fused_mixed(FusedArgs a) {
     fused_rows_mixed<T, MSZ>(a, a.f, a.g, a.h, a.same != 0, blockIdx.x, smem_raw);
 }
 
+// Whole-row convolution for the many rows of an innermost N-D axis: one group
+// of TPF = m / 8 threads per row runs the row's q residues in turn (block sums
+// of eq. (3), forward transforms of f and g, product, inverse, the
+// zeta_N^{-rs} / N twiddle) and accumulates eq. (4)'s output sums
+//     h_{t m + s} += zeta_q^{-t r} y^(r)_s,   t < ceil(M/m) <= QO,
+// in registers: thread lane holds the same points s = lane + v TPF of every
+// residue, so no residue is kept in LDS or HBM.  The transforms are the row
+// kernels' (two exchange buffers per row, per-pass twiddle tables in LDS).
+// Persistent: the workgroup walks rows base, base + stride, ...; every residue
+// sums the row's p input blocks again (from L2 after the first).
+template <typename T, int MSZ, int QO>
+__global__ void __launch_bounds__(512) k_rowconv(FusedArgs a) {
+    using P = FP<MSZ>;
+    constexpr int PPT = P::PPT;
+    constexpr int TPF = P::TPF;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T>* smem = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* tpt = smem + (size_t)a.rpw * 2 * MSZ;
+    double2* twq = reinterpret_cast<double2*>(
+        smem_raw + (((size_t)a.rpw * 2 * MSZ + PassTab<MSZ>::LEN) * sizeof(cplx<T>) + 15) / 16 * 16);
+    const int tid = threadIdx.x;
+    fill_pass_tab<T, MSZ>(tpt, a.twm, tid, blockDim.x);
+    for (int e = tid; e < a.q; e += blockDim.x) twq[e] = tw_n(a.tw, (uint32_t)e * (uint32_t)MSZ);
+    __syncthreads();
+    const TwPass<T> tw{tpt, PassTab<MSZ>::R0};
+
+    const int rloc = tid / TPF;
+    const int lane = tid - rloc * TPF;
+    cplx<T>* buf0 = smem + (size_t)rloc * 2 * MSZ;
+    cplx<T>* buf1 = buf0 + MSZ;
+    int ph = 0;
+    const int L = a.L, M = a.M;
+    const int64_t ies = a.in.es, oes = a.out.es;
+    const bool same = a.same != 0;
+    const T invN = (T)a.invN;
+    const cplx<T>* fg = reinterpret_cast<const cplx<T>*>(a.f);
+    const cplx<T>* gg = reinterpret_cast<const cplx<T>*>(a.g);
+    cplx<T>* hg = reinterpret_cast<cplx<T>*>(a.h);
+    const int64_t stride = (int64_t)gridDim.x * a.rpw;
+
+    for (int64_t base = (int64_t)blockIdx.x * a.rpw; base < a.nrows; base += stride) {  // uniform
+        const int64_t row = base + rloc;
+        const bool ok = row < a.nrows;
+        const int64_t fb = row_base(a.in, ok ? row : 0);
+        cplx<T> acc[QO][PPT];
+#pragma unroll
+        for (int t = 0; t < QO; ++t)
+#pragma unroll
+            for (int v = 0; v < PPT; ++v) acc[t][v] = mk<T>(0, 0);
+        for (int r = 0; r < a.q; ++r) {
+            cplx<T> F[PPT], G[PPT];
+#pragma unroll
+            for (int v = 0; v < PPT; ++v) {
+                F[v] = mk<T>(0, 0);
+                G[v] = mk<T>(0, 0);
+            }
+            if (ok) {
+                int e = 0;  // (r t) mod q
+                for (int t = 0; t < a.p; ++t) {
+                    const double2 z = twq[e];
+                    e += r;
+                    if (e >= a.q) e -= a.q;
+#pragma unroll
+                    for (int v = 0; v < PPT; ++v) {
+                        const int j = t * MSZ + lane + v * TPF;
+                        if (j < L) {
+                            F[v] = F[v] + mul_tw<false>(fg[fb + (int64_t)j * ies], z, false);
+                            if (!same) G[v] = G[v] + mul_tw<false>(gg[fb + (int64_t)j * ies], z, false);
+                        }
+                    }
+                }
+            }
+            // zeta_N^{r s} for s = lane + v TPF, as z0 zs^v (1 for r = 0)
+            const double2 z0 = tw_n(a.tw, (uint32_t)r * (uint32_t)lane);
+            const double2 zs = tw_n(a.tw, (uint32_t)r * (uint32_t)TPF);
+            if (r > 0) {
+                double2 z = z0;
+#pragma unroll
+                for (int v = 0; v < PPT; ++v) {
+                    F[v] = mul_tw<false>(F[v], z, a.hiprec);
+                    if (!same) G[v] = mul_tw<false>(G[v], z, a.hiprec);
+                    z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
+                }
+            }
+            fft_rows_pp<T, MSZ, +1>(F, buf0, buf1, ph, lane, tw, ok);
+            if (!same) {
+                fft_rows_pp<T, MSZ, +1>(G, buf0, buf1, ph, lane, tw, ok);
+#pragma unroll
+                for (int v = 0; v < PPT; ++v) F[v] = F[v] * G[v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < PPT; ++v) F[v] = F[v] * F[v];
+            }
+            fft_rows_pp<T, MSZ, -1>(F, buf0, buf1, ph, lane, tw, ok);
+            {
+                double2 z = z0;
+#pragma unroll
+                for (int v = 0; v < PPT; ++v) {
+                    F[v] = scale(r > 0 ? mul_tw<true>(F[v], z, a.hiprec) : F[v], invN);
+                    z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
+                }
+            }
+            int e = 0;  // (t r) mod q
+#pragma unroll
+            for (int t = 0; t < QO; ++t) {
+                if (t < a.qout) {
+                    const double2 w = twq[e];
+#pragma unroll
+                    for (int v = 0; v < PPT; ++v)
+                        acc[t][v] = acc[t][v] + (t == 0 ? F[v] : mul_tw<true>(F[v], w, false));
+                }
+                e += r;
+                if (e >= a.q) e -= a.q;
+            }
+        }
+        if (ok) {
+            cplx<T>* h = hg + row_base(a.out, row);
+#pragma unroll
+            for (int t = 0; t < QO; ++t) {
+                if (t < a.qout) {
+#pragma unroll
+                    for (int v = 0; v < PPT; ++v) {
+                        const int k = t * MSZ + lane + v * TPF;
+                        if (k < M) h[(int64_t)k * oes] = acc[t][v];
+                    }
+                }
+            }
+        }
+    }
+}
+
 template <typename T, int MSZ, bool MULTI = false>
 __global__ void __launch_bounds__(512) k_fused(FusedArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -980,35 +1111,36 @@ __global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
     for (int db = 0; db < a.Dg; db += DMAX) {
         const int nd = min(DMAX, a.Dg - db);
         cplx<T> V[DMAX][PPT];
+        // every residue's reads are issued first, so that those of the later
+        // residues stay in flight behind the first transforms
 #pragma unroll
         for (int dd = 0; dd < DMAX; ++dd) {
-            const int d = db + dd;
-            if (dd < nd) {
-                cplx<T> w[PPT];
+            const int64_t rb = (int64_t)(db + dd) * istep_t + ibase;
 #pragma unroll
-                for (int v = 0; v < PPT; ++v) w[v] = ok ? Y[d * istep_t + ibase + v * istep_v] : mk<T>(0, 0);
+            for (int v = 0; v < PPT; ++v) V[dd][v] = (ok && dd < nd) ? Y[rb + v * istep_v] : mk<T>(0, 0);
+        }
+#pragma unroll
+        for (int dd = 0; dd < DMAX; ++dd) {
+            if (dd < nd) {
                 if (fs) {
                     double2 z = fz0;
 #pragma unroll
                     for (int v = 0; v < PPT; ++v) {
-                        w[v] = mul_tw<true>(w[v], z, a.hiprec);
+                        V[dd][v] = mul_tw<true>(V[dd][v], z, a.hiprec);
                         z = make_double2(z.x * fzs.x - z.y * fzs.y, z.x * fzs.y + z.y * fzs.x);
                     }
                 }
-                fft_regs<T, M1, -1, LAY_COL>(w, lds + cc, tile, lane, tw1, true);
-                const int r = a.r0 + d;
+                fft_regs<T, M1, -1, LAY_COL>(V[dd], lds + cc, tile, lane, tw1, true);
+                const int r = a.r0 + db + dd;
                 // conj(zeta_N^{r s}), s = (lane + v TPF) m2 + s2, as z0 zs^v (r < q and
                 // s < m, so r s < q m = N needs no reduction)
                 double2 z = tw_n(a.tw, (uint32_t)r * (uint32_t)kbase);
                 const double2 zs = tw_n(a.tw, (uint32_t)r * (uint32_t)kstep_v);
 #pragma unroll
                 for (int v = 0; v < PPT; ++v) {
-                    V[dd][v] = scale(mul_tw<true>(w[v], z, a.hiprec), invN);
+                    V[dd][v] = scale(mul_tw<true>(V[dd][v], z, a.hiprec), invN);
                     z = make_double2(z.x * zs.x - z.y * zs.y, z.x * zs.y + z.y * zs.x);
                 }
-            } else {
-#pragma unroll
-                for (int v = 0; v < PPT; ++v) V[dd][v] = mk<T>(0, 0);
             }
         }
         const bool add = a.accumulate || db > 0;
@@ -1734,8 +1866,7 @@ __global__ void k_natural(const cplx<T>* F, cplx<T>* out, int64_t Dg, int64_t m1
 
 // --------------------------------------------------------------- launchers --
 
-namespace {
-
+// Compute units of the current device (256 on gfx950 when the query fails).
 int cu_count() {
     static int n = 0;
     if (n == 0) {
@@ -1748,6 +1879,9 @@ int cu_count() {
     }
     return n;
 }
+
+namespace {
+
 
 template <typename K>
 hipError_t allow_lds(K kernel, size_t lds) {
@@ -1889,6 +2023,40 @@ hipError_t fused_mixed_t(const FusedArgs& a, int threads, int64_t blocks, size_t
     return hipGetLastError();
 }
 
+template <typename T, int MSZ, int QO>
+hipError_t rowconv_t(const FusedArgs& a, int threads, int64_t blocks, size_t lds, hipStream_t s) {
+    auto kern = k_rowconv<T, MSZ, QO>;
+    hipError_t e = allow_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, threads, lds) != hipSuccess || occ < 1) occ = 1;
+    const int64_t resident = (int64_t)occ * cu_count();
+    const int64_t grid = blocks < resident ? blocks : resident;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+// Row-convolution instances: m = 1024 .. 4096, QO = 2 or 4 output blocks
+// (complex128: 2).
+template <typename T, int MSZ>
+static hipError_t rowconv_q(const FusedArgs& a, int th, int64_t bl, size_t lds, hipStream_t s) {
+    if (a.qout <= 2) return rowconv_t<T, MSZ, 2>(a, th, bl, lds, s);
+    if constexpr (sizeof(T) == 4) {
+        if (a.qout <= 4) return rowconv_t<T, MSZ, 4>(a, th, bl, lds, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t rowconv_disp(int m, const FusedArgs& a, int th, int64_t bl, size_t lds, hipStream_t s) {
+    switch (m) {
+        case 1024: return rowconv_q<T, 1024>(a, th, bl, lds, s);
+        case 2048: return rowconv_q<T, 2048>(a, th, bl, lds, s);
+        case 4096: return rowconv_q<T, 4096>(a, th, bl, lds, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 static hipError_t fused_disp(int m, const FusedArgs& a, int th, int64_t bl, size_t lds, hipStream_t s) {
     if (a.R > 1) {  // m = R 2^k: dispatch on the power-of-two part
@@ -1994,6 +2162,12 @@ hipError_t launch_row_multi(bool dbl, int m2, const RowArgs& a, int threads, int
                             hipStream_t s) {
     return dbl ? row_multi_disp<double>(m2, a, threads, blocks, lds, s)
                : row_multi_disp<float>(m2, a, threads, blocks, lds, s);
+}
+
+hipError_t launch_rowconv(bool dbl, int m, const FusedArgs& a, int threads, int64_t blocks, size_t lds,
+                          hipStream_t s) {
+    return dbl ? rowconv_disp<double>(m, a, threads, blocks, lds, s)
+               : rowconv_disp<float>(m, a, threads, blocks, lds, s);
 }
 
 hipError_t launch_fused_real(bool dbl, int m, const FusedArgs& a, int threads, int64_t blocks, size_t lds,
