@@ -369,9 +369,8 @@ hdc_status geometry(AxisPlan& A, bool outer, bool many_rows = false, bool keep_s
         d.variant = 2;
     // ... and when the output blocks fit the registers, the whole row in one
     // workgroup: residues in turn, output sums accumulated in registers
-    if (many_rows && !outer && is_pow2(d.m) && d.m >= kRowconvMinM && d.m <= kRowconvMaxM &&
-        d.q_out <= (A.dbl ? kRowconvQO128 : kRowconvQO64) && d.p <= kRowconvMaxP &&
-        !(A.dbl && d.m < 2048)) {
+    if (many_rows && !outer && !A.dbl && is_pow2(d.m) && d.m >= kRowconvMinM && d.m <= kRowconvMaxM &&
+        d.q_out <= kRowconvQO && d.p <= kRowconvMaxP) {
         // two exchange buffers per row, the m-point pass table, q twiddles
         const int tpf = (int)d.m / 8;
         A.rc_rpw = std::max(1, 256 / tpf);

@@ -172,13 +172,12 @@ constexpr int kQueueMaxM128 = 512;   // complex128
 constexpr int kMaxQsum = 32;
 constexpr int kMaxRawP = 4;
 
-// Whole-row convolution of an innermost N-D axis (k_rowconv): FFT sizes, the
-// output blocks its registers hold per type, and the most input blocks each
+// Whole-row convolution of an innermost N-D axis (k_rowconv, complex64): FFT
+// sizes, the output blocks its registers hold, the most input blocks each
 // residue re-reads.
 constexpr int kRowconvMinM = 1024;
 constexpr int kRowconvMaxM = 4096;
-constexpr int kRowconvQO64 = 4;   // complex64
-constexpr int kRowconvQO128 = 2;  // complex128
+constexpr int kRowconvQO = 4;
 constexpr int kRowconvMaxP = 4;
 
 enum { MODE_FWD = 0, MODE_INV = 1, MODE_CONV = 2 };

@@ -2036,14 +2036,12 @@ hipError_t rowconv_t(const FusedArgs& a, int threads, int64_t blocks, size_t lds
     return hipGetLastError();
 }
 
-// Row-convolution instances: m = 1024 .. 4096, QO = 2 or 4 output blocks
-// (complex128: 2).
+// Row-convolution instances (complex64; complex128 rows would spill
+// registers): m = 1024 .. 4096, QO = 2 or 4 output blocks.
 template <typename T, int MSZ>
 static hipError_t rowconv_q(const FusedArgs& a, int th, int64_t bl, size_t lds, hipStream_t s) {
     if (a.qout <= 2) return rowconv_t<T, MSZ, 2>(a, th, bl, lds, s);
-    if constexpr (sizeof(T) == 4) {
-        if (a.qout <= 4) return rowconv_t<T, MSZ, 4>(a, th, bl, lds, s);
-    }
+    if (a.qout <= 4) return rowconv_t<T, MSZ, 4>(a, th, bl, lds, s);
     return hipErrorInvalidValue;
 }
 
@@ -2166,8 +2164,7 @@ hipError_t launch_row_multi(bool dbl, int m2, const RowArgs& a, int threads, int
 
 hipError_t launch_rowconv(bool dbl, int m, const FusedArgs& a, int threads, int64_t blocks, size_t lds,
                           hipStream_t s) {
-    return dbl ? rowconv_disp<double>(m, a, threads, blocks, lds, s)
-               : rowconv_disp<float>(m, a, threads, blocks, lds, s);
+    return dbl ? hipErrorInvalidValue : rowconv_disp<float>(m, a, threads, blocks, lds, s);
 }
 
 hipError_t launch_fused_real(bool dbl, int m, const FusedArgs& a, int threads, int64_t blocks, size_t lds,
