@@ -802,7 +802,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--nd-shapes", default="", help="comma list of the N-D shapes to run (e.g. 8192x8192_c64)")
     ap.add_argument("--extras", default="", help="comma list of secondary workloads to run (default: all of "
-                    "small,first_L,real,multi,batch,nd,uneq,uneq_nd)")
+                    "small,first_L,real,multi,batch,nd,uneq,uneq_nd, and the live predictor measurement, predictor)")
     ap.add_argument("--streams", type=int, default=16,
                     help="streams of the captured step graph (0: time the eager launch loop only)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -965,8 +965,9 @@ def main():
         torch.cuda.empty_cache()
         if not args.no_tune:
             out["tuner"] = tuner_regret(sizes, params, dt, log)
-        out["predictor"] = {"live": predictor_live(log) if not args.no_extras else None,
-                            "stored": predictor_summary()}
+        # an --extras selection without "predictor" skips the live measurement
+        live = not args.extras or "predictor" in args.extras.split(",")
+        out["predictor"] = {"live": predictor_live(log) if live else None, "stored": predictor_summary()}
         out["secondary"] = secondary(args, dev, hdc, synth, log)
 
     if not args.no_cpu_baseline:

@@ -106,9 +106,11 @@ const char* hdc_build_id(void);
  * file holds a multilayer perceptron (ReLU hidden layers, softmax output over
  * scale-free classes (p, D-mode): p in {1, 2, 3, 4, 6, 8, 12, 16}, D-mode 0 = all
  * residues in one pass, 1 = one residue per pass; class index 2 (p index) +
- * D-mode).  Format (little endian): the 8 bytes "HDCMLP01", int32 format
- * version (1 or 2), int32 layer count n, int32 sizes[n + 1] (sizes[0] = 12
- * inputs, sizes[n] = 16 classes), then per layer W (out x in, row-major) and b
+ * D-mode; with 17 outputs, class 16 is explicit padding, q = 1: m the smallest
+ * power of two with m >= max(M, 2L - 1), D = 1, section 3.1).  Format (little
+ * endian): the 8 bytes "HDCMLP01", int32 format version (1 or 2), int32 layer
+ * count n, int32 sizes[n + 1] (sizes[0] = 12 inputs, sizes[n] = 16 or 17
+ * classes), then per layer W (out x in, row-major) and b
  * (out), float32; version 2 then holds the minimum and the maximum of every
  * feature over the training rows (12 + 12 float32).
  *
@@ -117,7 +119,8 @@ const char* hdc_build_id(void);
  * HIP kernels of hdc_mlp.h on the current device (synchronously), takes the most
  * probable class per axis (ties: the lowest index) and maps it to parameters:
  * m = the smallest power of two with ceil(L/m) <= p (outer N-D axes at most
- * 2^20; doubled while q < p), D = q or 1.  confidence (may be NULL) receives
+ * 2^20; doubled while q < p), D = q or 1 (explicit padding: as above, within the
+ * axis limit).  confidence (may be NULL) receives
  * the winning class's probability per axis (prob->ndim values), or 0 for an
  * axis whose features leave the training range (version 2) by more than 1/16
  * (a sixteenth of an octave in the length features): the network abstains

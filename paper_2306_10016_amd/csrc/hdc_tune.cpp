@@ -770,7 +770,8 @@ std::string device_name() {
 // ------------------------------------------------------------ predictor --
 
 constexpr int kFeatures = 12;
-constexpr int kClasses = 16;
+constexpr int kClasses = 16;         // (p, D-mode) classes
+constexpr int kMaxClasses = 17;      // ... and explicit padding (q = 1)
 // features outside the training range by more than this (1/16 of an octave in
 // the scaled length features) make an axis abstain
 constexpr float kRangeMargin = 1.0f / 16.0f;
@@ -863,7 +864,7 @@ hdc_status hdc_predictor_load(hdc_predictor_t* out, const char* path) {
               fread(&n, 4, 1, fh) == 1 && (ver == 1 || ver == 2) && n >= 1 && n <= 16;
     std::vector<int32_t> sz(ok ? n + 1 : 0);
     if (ok) ok = fread(sz.data(), 4, n + 1, fh) == (size_t)(n + 1);
-    if (ok) ok = sz[0] == kFeatures && sz[n] == kClasses;
+    if (ok) ok = sz[0] == kFeatures && (sz[n] == kClasses || sz[n] == kMaxClasses);
     for (int i = 0; ok && i <= n; ++i) ok = sz[i] >= 1 && sz[i] <= 4096;
     std::vector<std::vector<float>> hw, hb;
     for (int i = 0; ok && i < n; ++i) {
@@ -902,7 +903,7 @@ hdc_status hdc_predictor_load(hdc_predictor_t* out, const char* path) {
     if (e == hipSuccess) e = hipMalloc(&P->x, (size_t)3 * kFeatures * 4);
     if (e == hipSuccess) e = hipMalloc(&P->y0, (size_t)3 * wmax * 4);
     if (e == hipSuccess) e = hipMalloc(&P->y1, (size_t)3 * wmax * 4);
-    if (e == hipSuccess) e = hipMalloc(&P->P, (size_t)3 * kClasses * 4);
+    if (e == hipSuccess) e = hipMalloc(&P->P, (size_t)3 * kMaxClasses * 4);
     if (e != hipSuccess) {
         delete P;
         return fail(HDC_ERR_HIP, "predictor upload: %s", hipGetErrorString(e));
@@ -930,26 +931,35 @@ hdc_status hdc_predict(hdc_predictor_t P, const hdc_problem* prob, hdc_params* o
         if (st != HDC_OK) return st;
         in = o;
     }
-    hdc_status st = hdc_mlp_softmax_xent(in, nullptr, P->P, nullptr, nullptr, nd, kClasses, P->s);
+    const int nc = P->sizes.back();  // kClasses, or kMaxClasses with the explicit class
+    hdc_status st = hdc_mlp_softmax_xent(in, nullptr, P->P, nullptr, nullptr, nd, nc, P->s);
     if (st != HDC_OK) return st;
-    float prob_h[3 * kClasses];
-    HIP_TRY(hipMemcpyAsync(prob_h, P->P, (size_t)nd * kClasses * 4, hipMemcpyDeviceToHost, P->s));
+    float prob_h[3 * kMaxClasses];
+    HIP_TRY(hipMemcpyAsync(prob_h, P->P, (size_t)nd * nc * 4, hipMemcpyDeviceToHost, P->s));
     HIP_TRY(hipStreamSynchronize(P->s));
     Cand c;
     for (int a = 0; a < nd; ++a) {
         int ci = 0;
-        for (int k = 1; k < kClasses; ++k)
-            if (prob_h[a * kClasses + k] > prob_h[a * kClasses + ci]) ci = k;
-        c.m[a] = m_for_class(*prob, a, kPClasses[ci / 2]);
-        const int64_t q = cdiv(prob->M[a], c.m[a]);
-        c.D[a] = (ci % 2 == 0) ? q : 1;
+        for (int k = 1; k < nc; ++k)
+            if (prob_h[a * nc + k] > prob_h[a * nc + ci]) ci = k;
+        if (ci == kClasses) {
+            // explicit padding: one residue covering max(M, 2L - 1)
+            c.m[a] = pow2_ceil(std::max(prob->M[a], 2 * prob->L[a] - 1));
+            while (c.m[a] > axis_limit(*prob, a)) c.m[a] /= 2;
+            while (cdiv(prob->M[a], c.m[a]) < cdiv(prob->L[a], c.m[a])) c.m[a] *= 2;
+            c.D[a] = 1;
+        } else {
+            c.m[a] = m_for_class(*prob, a, kPClasses[ci / 2]);
+            const int64_t q = cdiv(prob->M[a], c.m[a]);
+            c.D[a] = (ci % 2 == 0) ? q : 1;
+        }
         // an axis whose features leave the training range abstains (confidence 0)
         bool inside = true;
         for (int k = 0; P->ranged && k < kFeatures; ++k) {
             const float x = X[a * kFeatures + k];
             inside = inside && x >= P->lo[k] - kRangeMargin && x <= P->hi[k] + kRangeMargin;
         }
-        if (confidence) confidence[a] = inside ? prob_h[a * kClasses + ci] : 0.f;
+        if (confidence) confidence[a] = inside ? prob_h[a * nc + ci] : 0.f;
     }
     hdc_params in_p = to_params(c), full{};
     st = hdc_params_check(prob, &in_p, &full);

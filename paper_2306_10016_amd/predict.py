@@ -36,7 +36,10 @@ import numpy as np
 from . import tune
 
 P_CLASSES = tune.P_CLASSES
-CLASSES: List[Tuple[int, int]] = [(p, dm) for p in P_CLASSES for dm in (0, 1)]  # dm 0: D = q, 1: D = 1
+# dm 0: D = q, 1: D = 1; the last class, p = 0, is explicit padding (q = 1, D = 1)
+CLASSES: List[Tuple[int, int]] = [(p, dm) for p in P_CLASSES for dm in (0, 1)] + [(0, 1)]
+EXPLICIT = len(CLASSES) - 1
+MAX_INNER_M = 1 << 22  # limit of a 1D or innermost axis (column stage 1024 x row stage 4096)
 D_IN = 12
 SOFT_TAU = 0.03  # soft targets: a class 3 % slower than the best gets weight e^-1
 HIDDEN = (128, 128, 128)
@@ -76,6 +79,8 @@ def soft_target(L: int, M: int, table, outer: bool, tau: float = SOFT_TAU) -> np
 def class_index(L: int, M: int, m: int, D: int) -> int:
     p = -(-L // m)
     q = -(-M // m)
+    if q == 1 and m > 1:
+        return EXPLICIT
     # map p to the class whose m is the same power of two
     best = None
     for ci, (pc, dm) in enumerate(CLASSES):
@@ -89,8 +94,15 @@ def class_index(L: int, M: int, m: int, D: int) -> int:
 
 
 def params_of(ci: int, L: int, M: int, outer: bool) -> Tuple[int, int]:
-    """(m, D) for class ci on an axis of length L (outer axes keep m <= 1024)."""
+    """(m, D) for class ci on an axis of length L (outer axes keep m <= 2^20)."""
     pc, dm = CLASSES[ci]
+    if ci == EXPLICIT:
+        m = tune.pow2_ceil(max(M, 2 * L - 1))
+        while m > (MAX_OUTER_M if outer else MAX_INNER_M):
+            m //= 2
+        while -(-M // m) < -(-L // m):
+            m *= 2
+        return m, 1
     m = tune.m_for_class(L, pc)
     if outer:
         while m > MAX_OUTER_M:
@@ -392,7 +404,22 @@ def training_problems(seed: int = 0, max_elems: int = 1 << 20):
             dims = [int(r.choice(s3)) for _ in range(3)]
             if int(np.prod(dims)) <= max_elems:
                 probs.append((dims, 1, dt))
+    # large 2D and 3D problems (2^22 .. 2^26 elements, section 5.1's smooth sides):
+    # where the copies of an outer axis fill the GPU by themselves
+    for dims in LARGE_PROBLEMS:
+        probs.append((list(dims), 1, "c64"))
+    for dims in LARGE_PROBLEMS[::3]:
+        probs.append((list(dims), 1, "c128"))
     return probs
+
+
+# large training problems: none is an evaluation problem
+LARGE_PROBLEMS = [(2048, 2048), (3000, 3000), (3375, 3375), (5000, 5000), (6144, 6144), (7000, 7000),
+                  (2048, 8192), (8192, 2048), (4096, 8192), (8192, 4096), (6000, 4000), (1024, 16384),
+                  (16384, 1024), (4096, 2048), (2048, 4096), (12000, 2500), (2500, 12000), (3000, 6000),
+                  (128, 128, 128), (192, 192, 192), (200, 200, 200), (300, 300, 300), (320, 320, 320),
+                  (128, 256, 256), (256, 128, 256), (256, 256, 128), (384, 256, 256), (256, 256, 384),
+                  (512, 256, 128), (128, 512, 512)]
 
 
 EVAL_PROBLEMS = [([4096, 4096], "c64"), ([8192, 8192], "c64"), ([256, 256, 256], "c64")]

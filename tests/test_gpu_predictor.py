@@ -1,12 +1,17 @@
 """The committed predictor checkpoint (trained by the HIP MLP kernels on the tuner's
-timings of problems of at most 2^20 elements), evaluated through hdc_predict on the
+timings of problems of at most 2^20 elements plus large 2D/3D problems of up to
+2^26, none of them an evaluation problem), evaluated through hdc_predict on the
 GPU with real timings:
 
-* outside its training range (the 2D/3D evaluation problems of up to 2^26 elements)
-  an axis abstains (confidence 0) and the flow falls back to the library's A0;
-* on held-out problems inside the range, the network's choices beat or match the
-  method without it -- the default p = 1, all residues per pass -- measured against
-  the library's exhaustive search (A0) re-timed in the same process.
+* outside its training range (here 16384^2 and 1024^3) an axis abstains
+  (confidence 0) and the flow falls back to the library's A0; the evaluation and
+  held-out problems lie inside it;
+* on the 2D/3D evaluation problems (4096^2, 8192^2, 256^3 complex64) the
+  network's top-1 choices stay within 15 % of the library's exhaustive search
+  (A0) re-timed in the same process (the training run measured +6.6, +9.1 and
+  -0.9 %; the margin above 10 % absorbs timing noise);
+* on held-out problems the network's choices beat or match the method without
+  it -- the default p = 1, all residues per pass.
 
 The learned accuracy itself is parity-unpinned (machine-dependent timings; the
 paper prints none)."""
@@ -29,13 +34,20 @@ def cp():
 
 
 def test_abstains_outside_the_training_range(cp):
-    for Ls, dt in predict.EVAL_PROBLEMS:
+    for Ls, dt in [([16384, 16384], "c64"), ([1024, 1024, 1024], "c64")]:
         params, conf = cp.predict_axes(Ls, [2 * L - 1 for L in Ls], dt)
         say(f"{Ls} {dt}: {params} confidence {conf}")
         assert min(conf) == 0.0
-    for Ls, dt in predict.HELDOUT_PROBLEMS:
+    for Ls, dt in predict.EVAL_PROBLEMS + predict.HELDOUT_PROBLEMS:
         _, conf = cp.predict_axes(Ls, [2 * L - 1 for L in Ls], dt)
         assert min(conf) > 0.0, Ls
+
+
+def test_network_within_bound_on_evaluation_problems(cp):
+    rows = predict.evaluate(cp, predict.EVAL_PROBLEMS, log=say)
+    for r in rows:
+        assert not r["abstained"]
+        assert r["network"]["regret"] <= 0.15, (r["L"], r["network"])
 
 
 def test_network_beats_or_matches_the_default_on_heldout_problems(cp):

@@ -120,8 +120,11 @@ def test_predictor_classes_round_trip(L):
     for ci, (pc, dm) in enumerate(predict.CLASSES):
         m, D = predict.params_of(ci, L, M, outer=False)
         q = -(-M // m)
-        assert -(-L // m) <= pc
-        assert D == (q if dm == 0 else 1)
+        if ci == predict.EXPLICIT:  # explicit padding: one residue
+            assert q == 1 and m >= 2 * L - 1 and D == 1
+        else:
+            assert -(-L // m) <= pc
+            assert D == (q if dm == 0 else 1)
         if (m, D) in seen:
             continue
         seen.add((m, D))
@@ -154,11 +157,16 @@ def test_soft_target_weights():
 
 
 def test_training_problems_within_bound():
+    """At most 2^20 elements, except the listed large 2D/3D problems (at most 2^26),
+    none of which is an evaluation problem."""
     probs = predict.training_problems()
     assert len(probs) > 100
+    large = {tuple(d) for d in predict.LARGE_PROBLEMS}
     for Ls, batch, dt in probs:
-        assert int(np.prod(Ls)) * batch <= (1 << 20)
+        n = int(np.prod(Ls)) * batch
+        assert n <= (1 << 20) or (tuple(Ls) in large and batch == 1 and n <= (1 << 26))
         assert dt in ("c64", "c128") and 1 <= len(Ls) <= 3
+    assert not large & {tuple(L) for L, _ in predict.EVAL_PROBLEMS}
 
 
 def uneq_cost(Lf, Lg, M, m, lam, D, dtype):
@@ -271,15 +279,16 @@ def test_checkpoint_format_and_training_range(tmp_path):
     assert predict.in_range(x, None, None)
 
 
-def test_evaluation_problems_lie_outside_the_training_range():
-    """The 2D/3D evaluation problems have more elements than any training problem, so the
-    total-size feature leaves the range; the held-out problems stay inside it."""
+def test_evaluation_problems_lie_inside_the_training_range():
+    """The large training problems (up to 2^26 elements) bring the 2D/3D evaluation
+    problems inside the range, so the network answers for them, without any of them
+    being trained on; the held-out problems stay inside it too."""
     rows = []
     for Ls, batch, dt in predict.training_problems():
         rows += [predict.features(Ls, a, dt, batch) for a in range(len(Ls))]
     X = np.stack(rows)
     lo, hi = X.min(0), X.max(0)
     for Ls, dt in predict.EVAL_PROBLEMS:
-        assert not all(predict.in_range(predict.features(Ls, a, dt), lo, hi) for a in range(len(Ls)))
+        assert all(predict.in_range(predict.features(Ls, a, dt), lo, hi) for a in range(len(Ls))), Ls
     for Ls, dt in predict.HELDOUT_PROBLEMS:
         assert all(predict.in_range(predict.features(Ls, a, dt), lo, hi) for a in range(len(Ls))), Ls
