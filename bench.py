@@ -531,7 +531,9 @@ def secondary(args, dev, hdc, synth, log):
         nd_db = tune.TuneDB(None)  # experience accumulates over the shapes, smallest first
         for Ls, dt in shapes:
             Ms = tuple(2 * x - 1 for x in Ls)
-            if args.no_tune:  # p = 1 and all residues per pass on every axis
+            if args.nd_m:  # given per-axis m, all residues per pass (profiling runs)
+                params = {"m": [int(x) for x in args.nd_m.split("x")], "D": [0] * len(Ls)}
+            elif args.no_tune:  # p = 1 and all residues per pass on every axis
                 params = {"m": [tune.pow2_ceil(x) for x in Ls], "D": [0] * len(Ls)}
             else:  # the library's experience search (A1, section 4.3), axis by axis
                 params = tune.run_search(nd_db, list(Ls), list(Ms), dt, tune.A1)[0].params
@@ -801,6 +803,7 @@ def main():
                     help="launch the uneven batch eagerly, buckets in turn (per-kernel profiling)")
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--nd-shapes", default="", help="comma list of the N-D shapes to run (e.g. 8192x8192_c64)")
+    ap.add_argument("--nd-m", default="", help="per-axis m for the N-D shapes, e.g. 8192x4096 (profiling runs)")
     ap.add_argument("--extras", default="", help="comma list of secondary workloads to run (default: all of "
                     "small,first_L,real,multi,batch,nd,uneq,uneq_nd, and the live predictor measurement, predictor)")
     ap.add_argument("--streams", type=int, default=16,
