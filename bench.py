@@ -255,6 +255,14 @@ def predictor_live(log):
             "worst_network_top1_regret": max(x["network_top1"] for x in ev)}
 
 
+def tune_pow2(x: int) -> int:
+    """The smallest power of two >= x."""
+    v = 1
+    while v < x:
+        v *= 2
+    return v
+
+
 def secondary(args, dev, hdc, synth, log):
     """Measured secondary workloads: the single small convolution, the uneven batch,
     the 2D squares/rectangles and the 2D/3D evaluation sizes, each against
@@ -480,6 +488,48 @@ def secondary(args, dev, hdc, synth, log):
                        "rel_err_vs_explicit": err}
             log(f"[bench] multi {key}: {t * 1e3:.3f} ms (explicit {te * 1e3:.3f}, pairwise {tp * 1e3:.3f}), rel {err:.1e}")
             del xs, best, h, ref, chain, bufs, pads
+            torch.cuda.empty_cache()
+        # 2D multi-convolution (hdc_plan_multi_nd): the best of a few per-axis m against
+        # explicit padding with torch.fft.fftn
+        for A, Ls, dt in ((3, (1024, 1024), "c64"), (3, (2048, 2048), "c64"), (4, (512, 512), "c128")):
+            Ks = tuple(A * (x - 1) + 1 for x in Ls)
+            np_dt = np.complex128 if dt == "c128" else np.complex64
+            td = torch.complex128 if dt == "c128" else torch.complex64
+            xs = [torch.from_numpy(synth.uniform_complex(Ls, 9, sum(Ls), w, np_dt)).to(dev) for w in range(A)]
+            best = None
+            for f0 in (1, 2):
+                for f1 in (1, 2, 4):
+                    ms_ = [max(1, tune_pow2(x) // f) for x, f in zip(Ls, (f0, f1))]
+                    try:
+                        plan = hdc.MultiPlan.nd(A, Ls, Ks, ms_, dtype=dt)
+                    except hdc.HdcError:
+                        continue
+                    h = torch.empty(Ks, dtype=td, device=dev)
+                    ws = plan.workspace(dev)
+                    t = timed(lambda: plan.convolve(xs, h, ws=ws), 5)
+                    if best is None or t < best[0]:
+                        best = (t, {"m": ms_, "q": [ax["q"] for ax in plan.axes]}, h)
+                    del plan, ws
+            ns = [tune_pow2(k) for k in Ks]
+
+            def explicit_nd():
+                H = torch.fft.fftn(xs[0], s=ns)
+                for x in xs[1:]:
+                    H = H * torch.fft.fftn(x, s=ns)
+                return torch.fft.ifftn(H)[tuple(slice(0, k) for k in Ks)]
+            ref = explicit_nd()
+            t, params, h = best
+            err = float(torch.linalg.vector_norm(h - ref) / torch.linalg.vector_norm(ref))
+            te = timed(explicit_nd, 5)
+            key = f"A{A}_{'x'.join(map(str, Ls))}_{dt}"
+            eb = 16 if dt == "c128" else 8
+            n_in = int(np.prod(Ls))
+            mu[key] = {"params": params, "ms": round(t * 1e3, 4),
+                       "compulsory_GBps": round((A * n_in + int(np.prod(Ks))) * eb / t / 1e9, 1),
+                       "explicit_ms": round(te * 1e3, 4), "speedup_vs_explicit": round(te / t, 3),
+                       "rel_err_vs_explicit": err}
+            log(f"[bench] multi {key}: {t * 1e3:.3f} ms (explicit {te * 1e3:.3f}), rel {err:.1e}")
+            del xs, best, h, ref
             torch.cuda.empty_cache()
         out["multi"] = mu
 

@@ -200,7 +200,8 @@ hdc_status hdc_plan_uneq_nd(hdc_plan_t* out, int ndim, const int64_t* Lf, const 
  * one backward, eq. (4), accumulates h.  Other arguments and errors as
  * hdc_plan; complex types only (HDC_ERR_UNSUPPORTED for real ones).
  * hdc_convolve_multi(plan, x, h, ws, stream): x is a HOST array of plan's A
- * DEVICE pointers (A = 2 for a plan of hdc_plan), each of L x C values; h must
+ * DEVICE pointers (A = 2 for a plan of hdc_plan or hdc_plan_nd), each of L x C
+ * values (the operand box for N-D plans); h must
  * not alias any operand; ws as hdc_workspace_size.  hdc_convolve refuses a
  * plan of more than two operands.  The residue-level calls work on such a plan
  * operand by operand: hdc_forward of each, hdc_multiply of the first buffer by
@@ -209,6 +210,22 @@ hdc_status hdc_plan_uneq_nd(hdc_plan_t* out, int ndim, const int64_t* Lf, const 
 hdc_status hdc_plan_multi(hdc_plan_t* out, int A, int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, int64_t C,
                           int64_t D, hdc_dtype dtype);
 hdc_status hdc_convolve_multi(hdc_plan_t plan, const void* const* x, void* h, void* ws, hipStream_t stream);
+
+/*
+ * Multi-convolution of A = 2 .. 8 arrays in 2 or 3 dimensions (section 6.1's
+ * 1D/2D multi-convolution, applied axis by axis as section 3.6 does for two
+ * operands): every operand an L[0] x .. x L[ndim-1] row-major box, h the
+ * M[0] x .. box of the first M[a] terms per axis of the A-fold linear result
+ * (M == NULL: all A(L[a]-1)+1 terms).  Per axis m[a] (a power of two, at
+ * most 2^20 on outer axes, 2^22 on the innermost) and D[a] (NULL or 0: all
+ * residues per pass) as hdc_plan_nd; q[a] is derived from max(M[a],
+ * A(L[a]-1)+1).  Outer axes run the column passes on each operand; the
+ * innermost axis the multi-operand rows.  Convolve with hdc_convolve_multi;
+ * the residue-level calls are 1D only.  Errors as hdc_plan_nd and
+ * hdc_plan_multi.
+ */
+hdc_status hdc_plan_multi_nd(hdc_plan_t* out, int A, int ndim, const int64_t* L, const int64_t* M, const int64_t* m,
+                             const int64_t* D, hdc_dtype dtype);
 
 /* Frees the plan and its device twiddle tables (hipFree: synchronises with the
  * device).  No call that uses the plan may still be in flight.  NULL is a no-op. */

@@ -405,6 +405,31 @@ class MultiPlan(Plan):
         super().__init__(0, 0, 0, dtype=dtype, _handle=h)
         self.A = int(A)
 
+    @classmethod
+    def nd(cls, A: int, L: Sequence[int], M: Optional[Sequence[int]] = None, m: Optional[Sequence[int]] = None,
+           D: Optional[Sequence[int]] = None, dtype="c64"):
+        """2D/3D multi-convolution (hdc_plan_multi_nd): A operands of the box L, output box
+        M (default the A(L-1)+1 terms per axis); m defaults to the power of two >= L per
+        axis (at most 2^20 on outer axes)."""
+        n = len(L)
+        M = [int(A) * (int(x) - 1) + 1 for x in L] if M is None else [int(x) for x in M]
+        if m is None:
+            m = []
+            for a, x in enumerate(L):
+                v = 1
+                while v < int(x):
+                    v <<= 1
+                m.append(min(v, 1 << 20) if a < n - 1 else v)
+        arr = ctypes.c_int64 * n
+        h = ctypes.c_void_p()
+        check(lib().hdc_plan_multi_nd(ctypes.byref(h), int(A), n, arr(*[int(x) for x in L]), arr(*M),
+                                      arr(*[int(x) for x in m]), arr(*[int(x) for x in D]) if D else None,
+                                      dtype_code(dtype)))
+        obj = cls.__new__(cls)
+        Plan.__init__(obj, 0, 0, 0, dtype=dtype, _handle=h)
+        obj.A = int(A)
+        return obj
+
     def convolve(self, xs, out=None, ws=None, stream=None):
         """h = x_0 * ... * x_{A-1} (hdc_convolve_multi); ``xs`` holds the A device tensors."""
         import torch

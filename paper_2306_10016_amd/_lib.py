@@ -62,6 +62,7 @@ SIGNATURES = {
     "hdc_plan_uneq_nd": [_PP, ctypes.c_int, _PI64, _PI64, _PI64, _PI64, _PI64, _PI64, ctypes.c_int],
     "hdc_plan_multi": [_PP, ctypes.c_int, _I64, _I64, _I64, _I64, _I64, _I64, _I64, ctypes.c_int],
     "hdc_convolve_multi": [_P, ctypes.POINTER(ctypes.c_void_p), _P, _P, _P],
+    "hdc_plan_multi_nd": [_PP, ctypes.c_int, ctypes.c_int, _PI64, _PI64, _PI64, _PI64, ctypes.c_int],
     "hdc_plan_destroy": [_P],
     "hdc_plan_axis": [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(AxisDesc)],
     "hdc_workspace_size": [_P, ctypes.POINTER(ctypes.c_size_t)],

@@ -1293,6 +1293,51 @@ hdc_status convnd(const hdc_plan_s* P, int level, const void* xf, const void* xg
     return HDC_OK;
 }
 
+// Multi-convolution in N-D (section 6.1 with section 3.6's recursion): the
+// outer axis's residue group of every operand, the inner (N-1)-D
+// multi-convolution per residue row, the outer backward.
+int64_t wsnd_multi(const hdc_plan_s* P, int level, int64_t B) {
+    const AxisPlan& A = P->ax[level];
+    if (level == P->ndim - 1) return P->nops == 2 ? ws1d(A, B, 1) : ws_multi(A, P->nops, B, 1);
+    const int64_t Dg = std::min(A.d.D, A.d.q);
+    const int64_t inner_in = prod_L(P, level + 1), inner_out = prod_M(P, level + 1);
+    const int64_t nb = B * Dg * A.d.m;
+    return (int64_t)P->nops * nb * inner_in + nb * inner_out + wsnd_multi(P, level + 1, nb);
+}
+
+hdc_status convnd_multi(const hdc_plan_s* P, int level, const void* const* xs, void* out, int64_t B, char* ws,
+                        hipStream_t s) {
+    const AxisPlan& A = P->ax[level];
+    const size_t eb = elem(P);
+    const int nops = P->nops;
+    if (level == P->ndim - 1) {
+        if (nops == 2) return conv1d(A, xs[0], xs[1], out, B, A.d.L, A.d.M, 1, ws, eb, s);
+        return conv1d_multi(A, xs, nops, out, B, A.d.L, A.d.M, 1, ws, eb, s);
+    }
+    const int64_t D = std::min(A.d.D, A.d.q);
+    const int64_t inner_in = prod_L(P, level + 1), inner_out = prod_M(P, level + 1);
+    const int64_t nbmax = B * D * A.d.m;
+    const void* X[kMaxOps];
+    for (int o = 0; o < nops; ++o) X[o] = ws + (size_t)(o * nbmax * inner_in) * eb;
+    char* Y = ws + (size_t)(nops * nbmax * inner_in) * eb;
+    char* rest = Y + (size_t)(nbmax * inner_out) * eb;
+    for (int64_t r0 = 0; r0 < A.d.q; r0 += D) {
+        const int64_t Dg = std::min(D, A.d.q - r0);
+        const int64_t nb = B * Dg * A.d.m;
+        hdc_status st = HDC_OK;
+        for (int o = 0; o < nops && st == HDC_OK; ++o) {
+            st = run_col_fwd(A, xs[o], (void*)X[o], B, A.d.L * inner_in, Dg * A.d.m * inner_in, inner_in, r0, Dg, s);
+            if (st == HDC_OK && A.d.m2 > 1) st = run_col_plain(A, (void*)X[o], B * Dg * A.d.m1, inner_in, +1, s);
+        }
+        if (st == HDC_OK) st = convnd_multi(P, level + 1, X, Y, nb, rest, s);
+        if (st == HDC_OK && A.d.m2 > 1) st = run_col_plain(A, Y, B * Dg * A.d.m1, inner_out, -1, s);
+        if (st == HDC_OK)
+            st = run_col_bwd(A, Y, out, B, Dg * A.d.m * inner_out, A.d.M * inner_out, inner_out, r0, Dg, r0 > 0, s);
+        if (st != HDC_OK) return st;
+    }
+    return HDC_OK;
+}
+
 // Section 3.5: for every residue group of the longer operand, the shorter
 // operand's matching residues r_f = q_g lambda + r_g (lambda < Lambda) are
 // formed by its own column stage, stored row-interleaved so that the row pass
@@ -1454,6 +1499,8 @@ hdc_status finish_plan(hdc_plan_s* P) {
                       elem(P);
     } else if (P->real) {
         P->ws_bytes = (size_t)ws_real(P->ax[0], 1, P->ax[0].d.C) * elem(P);
+    } else if (P->nops > 2 && P->ndim > 1) {
+        P->ws_bytes = (size_t)wsnd_multi(P, 0, 1) * elem(P);
     } else if (P->nops > 2) {
         P->ws_bytes = (size_t)ws_multi(P->ax[0], P->nops, 1, P->ax[0].d.C) * elem(P);
     } else if (P->ndim == 1) {
@@ -1544,8 +1591,9 @@ hdc_status hdc_plan_multi(hdc_plan_t* out, int A, int64_t L, int64_t M, int64_t 
 
 hdc_status hdc_convolve_multi(hdc_plan_t P, const void* const* x, void* h, void* ws, hipStream_t s) {
     if (!P || !x || !h) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
-    if (P->uneq || P->real || P->ndim != 1)
-        return fail(HDC_ERR_INVALID_ARG, "hdc_convolve_multi takes a plan of hdc_plan_multi or hdc_plan");
+    if (P->uneq || P->real)
+        return fail(HDC_ERR_INVALID_ARG,
+                    "hdc_convolve_multi takes a plan of hdc_plan_multi, hdc_plan_multi_nd, hdc_plan or hdc_plan_nd");
     for (int o = 0; o < P->nops; ++o) {
         if (!x[o]) return fail(HDC_ERR_INVALID_ARG, "operand %d is NULL", o);
         if (x[o] == h) return fail(HDC_ERR_INVALID_ARG, "h must not alias an operand");
@@ -1559,9 +1607,51 @@ hdc_status hdc_convolve_multi(hdc_plan_t P, const void* const* x, void* h, void*
         explicit CurPlan(const void* p) { g_cur_plan = p; }
         ~CurPlan() { g_cur_plan = nullptr; }
     } cur(P);
+    if (P->ndim > 1) return convnd_multi(P, 0, x, h, 1, (char*)ws, s);
     const AxisPlan& Ax = P->ax[0];
     if (P->nops == 2) return conv1d(Ax, x[0], x[1], h, 1, 0, 0, Ax.d.C, (char*)ws, elem(P), s);
     return conv1d_multi(Ax, x, P->nops, h, 1, 0, 0, Ax.d.C, (char*)ws, elem(P), s);
+}
+
+static hdc_status nd_extents_ok(int ndim, const AxisPlan* ax);
+
+hdc_status hdc_plan_multi_nd(hdc_plan_t* out, int A, int ndim, const int64_t* L, const int64_t* M, const int64_t* m,
+                             const int64_t* D, hdc_dtype dtype) {
+    if (!out || !L || !m) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    if (A < 2 || A > kMaxOps) return fail(HDC_ERR_INVALID_ARG, "A = %d operands: must be 2 .. %d", A, kMaxOps);
+    if (ndim < 2 || ndim > 3) return fail(HDC_ERR_INVALID_ARG, "ndim = %d must be 2 or 3 (1D: hdc_plan_multi)", ndim);
+    if (dtype != HDC_C64 && dtype != HDC_C128)
+        return fail(HDC_ERR_UNSUPPORTED, "multi-convolution plans are complex (HDC_C64 / HDC_C128)");
+    hdc_plan_s* P = new hdc_plan_s();
+    P->ndim = ndim;
+    P->dtype = dtype;
+    P->nops = A;
+    hdc_status st = HDC_OK;
+    for (int a = 0; a < ndim && st == HDC_OK; ++a) {
+        if (L[a] < 1 || L[a] >= (int64_t(1) << 40)) {
+            st = fail(HDC_ERR_INVALID_ARG, "axis %d: L = %lld out of range", a, (long long)L[a]);
+            break;
+        }
+        const int64_t K = (int64_t)A * (L[a] - 1) + 1;  // terms of the A-fold result
+        AxisPlan& Ax = P->ax[a];
+        st = derive_axis(L[a], M ? M[a] : K, m[a], 0, 0, 1, D ? D[a] : 0, dtype, &Ax.d, K);
+        if (st == HDC_OK && !is_pow2(Ax.d.m))
+            st = fail(HDC_ERR_UNSUPPORTED, "axis %d: multi-convolution plans take power-of-two m", a);
+        if (st == HDC_OK) {
+            Ax.dbl = dtype == HDC_C128;
+            // the innermost axis keeps the two variants the multi-operand kernels implement
+            st = geometry(Ax, a < ndim - 1, false);
+        }
+    }
+    if (st == HDC_OK) st = nd_extents_ok(ndim, P->ax);
+    if (st == HDC_OK) st = finish_plan(P);
+    if (st != HDC_OK) {
+        delete P;
+        return st;
+    }
+    *out = P;
+    return HDC_OK;
 }
 
 hdc_status hdc_uneq_derive(int64_t Lf, int64_t Lg, int64_t M, int64_t m, int64_t Lambda, int64_t C, int64_t D,
