@@ -421,6 +421,48 @@ def secondary(args, dev, hdc, synth, log):
             log(f"[bench] real {key}: {t * 1e3:.3f} ms (complex plan {tc * 1e3:.3f}, rfft {te * 1e3:.3f}), rel {err:.1e}")
             del ft, gt, fc, gc, best, h, ref
             torch.cuda.empty_cache()
+        # real 2D boxes (the packed autoconvolution, h = Im(z * z) / 2s): the plan at the
+        # tuner's complex parameters against the complex plan on the same data and
+        # against explicit padding with torch.fft.rfft2
+        from paper_2306_10016_amd import tune as tune_mod
+        for Ls, dt in (((4096, 4096), "r32"), ((2048, 2048), "r64")):
+            Ms = tuple(2 * x - 1 for x in Ls)
+            np_dt = np.float64 if dt == "r64" else np.float32
+            cdt = "c128" if dt == "r64" else "c64"
+            ctd = torch.complex128 if dt == "r64" else torch.complex64
+            ft = torch.from_numpy(synth.uniform_real(int(np.prod(Ls)), 8, sum(Ls), 0, np_dt).reshape(Ls)).to(dev)
+            gt = torch.from_numpy(synth.uniform_real(int(np.prod(Ls)), 8, sum(Ls), 1, np_dt).reshape(Ls)).to(dev)
+            params = tune_mod.run_search(tune_mod.TuneDB(None), list(Ls), list(Ms), cdt, tune_mod.A1)[0].params
+            ms_ = params["m"]
+            plan = hdc.Plan.nd(list(Ls), list(Ms), ms_, dtype=dt)
+            h = torch.empty(Ms, dtype=ft.dtype, device=dev)
+            ws = plan.workspace(dev)
+            t = timed(lambda: plan.convolve(ft, gt, h, ws=ws), 5)
+            cplan = hdc.Plan.from_params(list(Ls), list(Ms), cdt, params)
+            fc, gc = ft.to(ctd), gt.to(ctd)
+            hc = torch.empty(Ms, dtype=ctd, device=dev)
+            wsc = cplan.workspace(dev)
+            tc = timed(lambda: cplan.convolve(fc, gc, hc, ws=wsc), 5)
+            ns = [tune_pow2(x) for x in Ms]
+
+            def explicit2():
+                H = torch.fft.rfft2(ft, s=ns) * torch.fft.rfft2(gt, s=ns)
+                return torch.fft.irfft2(H, s=ns)[:Ms[0], :Ms[1]]
+            ref = explicit2()
+            err = float(torch.linalg.vector_norm(h - ref) / torch.linalg.vector_norm(ref))
+            te = timed(explicit2, 5)
+            key = f"{Ls[0]}x{Ls[1]}_{dt}"
+            rb = 8 if dt == "r64" else 4
+            n_in, n_out = int(np.prod(Ls)), int(np.prod(Ms))
+            rl[key] = {"params": {"m": ms_}, "ms": round(t * 1e3, 4),
+                       "compulsory_GBps": round((2 * n_in + n_out) * rb / t / 1e9, 1),
+                       "complex_plan_ms": round(tc * 1e3, 4), "speedup_vs_complex_plan": round(tc / t, 3),
+                       "explicit_rfft2_ms": round(te * 1e3, 4), "speedup_vs_explicit_rfft2": round(te / t, 3),
+                       "rel_err_vs_explicit": err}
+            log(f"[bench] real {key}: {t * 1e3:.3f} ms (complex plan {tc * 1e3:.3f}, rfft2 {te * 1e3:.3f}), "
+                f"rel {err:.1e}")
+            del ft, gt, fc, gc, h, hc, ref, plan, cplan, ws, wsc
+            torch.cuda.empty_cache()
         out["real"] = rl
 
     if want("multi"):

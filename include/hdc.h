@@ -46,7 +46,8 @@ extern "C" {
 #endif
 
 /* Data types: complex64 / complex128 (interleaved re, im), and real float32 /
- * float64 (the real case of section 7, 1D plans only; see hdc_plan). */
+ * float64 (the real case of section 7: 1D plans, see hdc_plan, and N-D plans,
+ * see hdc_plan_nd). */
 typedef enum { HDC_C64 = 0, HDC_C128 = 1, HDC_R32 = 2, HDC_R64 = 3 } hdc_dtype;
 
 typedef enum {
@@ -108,9 +109,9 @@ hdc_status hdc_derive(int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, int
  * r = 0 and r = q/2).  Such a plan supports hdc_convolve, hdc_time_convolve
  * and hdc_convolve_profiled; the residue-level calls (hdc_forward,
  * hdc_multiply, hdc_backward, hdc_residues_natural, hdc_residue_buffer_size)
- * return HDC_ERR_UNSUPPORTED for it, as do hdc_plan_nd, hdc_plan_uneq* and
- * hdc_batch_plan given a real dtype.  Pointers need 4-byte (HDC_R32) or
- * 8-byte (HDC_R64) alignment. */
+ * return HDC_ERR_UNSUPPORTED for it, as do hdc_plan_uneq* and hdc_batch_plan
+ * given a real dtype.  Pointers need 4-byte (HDC_R32) or 8-byte (HDC_R64)
+ * alignment. */
 hdc_status hdc_plan(hdc_plan_t* out, int64_t L, int64_t M, int64_t m, int64_t p, int64_t q, int64_t C,
                     int64_t D, hdc_dtype dtype);
 
@@ -118,7 +119,18 @@ hdc_status hdc_plan(hdc_plan_t* out, int64_t L, int64_t M, int64_t m, int64_t p,
  * be 0 to derive).  The outer axes are transformed as strided column passes
  * whose copies are the inner extents (section 2.5's C copies; outer m up to
  * 2^20, split into two column stages when above 1024); the innermost axis is a
- * 1D hybrid convolution per outer-residue row. */
+ * 1D hybrid convolution per outer-residue row.
+ *
+ * Real data (HDC_R32 / HDC_R64, ndim 2 or 3; the real case of section 7): f, g
+ * and h are real boxes.  Because the convolution is bilinear,
+ *     z * z = f * f - s^2 g * g + 2 i s f * g   for z = f + i s g,
+ * so h = Im(z * z) / (2 s): one complex autoconvolution (one forward transform
+ * per axis instead of two) of the packed box z.  s = max|f| / max|g| (1 if
+ * either is 0) keeps the two terms at one scale, so the rounding error relative
+ * to |f| |g| stays that of a complex plan (with g = 0, h is rounding noise at
+ * the scale of f * f rather than exact zeros).  The workspace holds z and the
+ * complex output besides the complex plan's.  ndim = 1 returns
+ * HDC_ERR_UNSUPPORTED (hdc_plan's Hermitian pairing serves 1D real data). */
 hdc_status hdc_plan_nd(hdc_plan_t* out, int ndim, const int64_t* L, const int64_t* M, const int64_t* m,
                        const int64_t* p, const int64_t* q, const int64_t* D, hdc_dtype dtype);
 
@@ -361,7 +373,8 @@ hdc_status hdc_time_convolve(hdc_plan_t plan, const void* f, const void* g, void
  * Instrumented hdc_convolve: the same launches, each bracketed by HIP events on
  * `stream`; synchronises the stream.  For launch i < min(*n_launches,
  * max_launches): kinds[i] (0 fused, 1 forward column, 2 row, 3 backward
- * column, 4 raw residue rows, 5 output sums, 6 whole-row convolution), ms[i] (event-measured duration) and bytes[i] (the launch's
+ * column, 4 raw residue rows, 5 output sums, 6 whole-row convolution, 7 real
+ * N-D packing (scales and z) or extraction of h), ms[i] (event-measured duration) and bytes[i] (the launch's
  * algorithmic HBM bytes: compulsory reads plus writes).  Any output array may
  * be NULL.  *n_launches receives the total number of launches.
  */

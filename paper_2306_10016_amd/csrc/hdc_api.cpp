@@ -178,6 +178,8 @@ struct hdc_plan_s {
     bool uneq = false;
     // real f, g and h (HDC_R32 / HDC_R64, 1D); dtype is then the complex type computed in
     bool real = false;
+    // real f, g and h of an N-D plan: one complex autoconvolution of z = f + i s g
+    bool real_nd = false;
     // operands of a multi-convolution (section 6.1), 2 for every other plan
     int nops = 2;
     bool swap[3] = {false, false, false};
@@ -1505,6 +1507,9 @@ hdc_status finish_plan(hdc_plan_s* P) {
         P->ws_bytes = (size_t)ws_multi(P->ax[0], P->nops, 1, P->ax[0].d.C) * elem(P);
     } else if (P->ndim == 1) {
         P->ws_bytes = (size_t)ws1d(P->ax[0], 1, P->ax[0].d.C) * elem(P);
+    } else if (P->real_nd) {
+        // two scale words, z (the inputs' box), the complex output box, the N-D workspace
+        P->ws_bytes = 256 + (size_t)(prod_L(P, 0) + prod_M(P, 0) + wsnd(P, 0, 1)) * elem(P);
     } else {
         P->ws_bytes = (size_t)wsnd(P, 0, 1) * elem(P);
     }
@@ -1591,9 +1596,10 @@ hdc_status hdc_plan_multi(hdc_plan_t* out, int A, int64_t L, int64_t M, int64_t 
 
 hdc_status hdc_convolve_multi(hdc_plan_t P, const void* const* x, void* h, void* ws, hipStream_t s) {
     if (!P || !x || !h) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
-    if (P->uneq || P->real)
+    if (P->uneq || P->real || P->real_nd)
         return fail(HDC_ERR_INVALID_ARG,
-                    "hdc_convolve_multi takes a plan of hdc_plan_multi, hdc_plan_multi_nd, hdc_plan or hdc_plan_nd");
+                    "hdc_convolve_multi takes a complex plan of hdc_plan_multi, hdc_plan_multi_nd, hdc_plan or "
+                    "hdc_plan_nd");
     for (int o = 0; o < P->nops; ++o) {
         if (!x[o]) return fail(HDC_ERR_INVALID_ARG, "operand %d is NULL", o);
         if (x[o] == h) return fail(HDC_ERR_INVALID_ARG, "h must not alias an operand");
@@ -1757,9 +1763,14 @@ hdc_status hdc_plan_nd(hdc_plan_t* out, int ndim, const int64_t* L, const int64_
     if (!out || !L || !M || !m) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
     *out = nullptr;
     if (ndim < 1 || ndim > 3) return fail(HDC_ERR_INVALID_ARG, "ndim = %d must be 1..3", ndim);
+    if (is_real(dtype) && ndim == 1)
+        return fail(HDC_ERR_UNSUPPORTED, "1D real data take hdc_plan (the Hermitian residue pairing)");
+    const bool real_nd = is_real(dtype);
+    dtype = complex_of(dtype);
     hdc_plan_s* P = new hdc_plan_s();
     P->ndim = ndim;
     P->dtype = dtype;
+    P->real_nd = real_nd;
     hdc_status st = HDC_OK;
     for (int a = 0; a < ndim && st == HDC_OK; ++a) {
         AxisPlan& A = P->ax[a];
@@ -1785,7 +1796,8 @@ hdc_status hdc_plan_nd_check(int ndim, const int64_t* L, const int64_t* M, const
     if (ndim < 1 || ndim > 3) return fail(HDC_ERR_INVALID_ARG, "ndim = %d must be 1..3", ndim);
     AxisPlan ax[3];
     for (int a = 0; a < ndim; ++a) {
-        hdc_status st = derive_axis(L[a], M[a], m[a], p ? p[a] : 0, q ? q[a] : 0, 1, D ? D[a] : 0, dtype, &ax[a].d);
+        hdc_status st = derive_axis(L[a], M[a], m[a], p ? p[a] : 0, q ? q[a] : 0, 1, D ? D[a] : 0,
+                                    complex_of(dtype), &ax[a].d);
         if (st != HDC_OK) return st;
         ax[a].dbl = dtype == HDC_C128;
         st = geometry(ax[a], a < ndim - 1, ndim > 1 && a == ndim - 1);
@@ -1893,7 +1905,7 @@ hdc_status hdc_residue_buffer_size(hdc_plan_t P, size_t* bytes) {
 }
 
 static hdc_status check_ptrs(hdc_plan_t P, const void* a, const void* b, const void* c) {
-    const size_t al = (elem(P) == 16 ? 16 : 8) / (P->real ? 2 : 1);
+    const size_t al = (elem(P) == 16 ? 16 : 8) / ((P->real || P->real_nd) ? 2 : 1);
     if ((a && !aligned(a, al)) || (b && !aligned(b, al)) || (c && !aligned(c, al)))
         return fail(HDC_ERR_INVALID_ARG, "data pointers must be %zu-byte aligned", al);
     return HDC_OK;
@@ -1925,6 +1937,28 @@ hdc_status hdc_convolve(hdc_plan_t P, const void* f, const void* g, void* h, voi
     if (P->ndim == 1) {
         const AxisPlan& A = P->ax[0];
         return conv1d(A, f, g, h, 1, 0, 0, A.d.C, (char*)ws, elem(P), s);
+    }
+    if (P->real_nd) {
+        // h = Im(z * z) / (2 s), z = f + i s g: the workspace holds the two scale
+        // words, z and the complex output ahead of the N-D workspace
+        const size_t eb = elem(P);
+        const int64_t nin = prod_L(P, 0), nout = prod_M(P, 0);
+        char* mx = (char*)ws;
+        char* z = mx + 256;
+        char* hz = z + (size_t)nin * eb;
+        char* rest = hz + (size_t)nout * eb;
+        const bool dbl = P->dtype == HDC_C128;
+        {
+            LaunchScope ls(s, 7, (double)nin * (double)eb * 2.0);
+            hipError_t e = launch_real_pack(dbl, f, g, z, nin, mx, s);
+            if (e != hipSuccess) return hip_fail(e, "real pack launch");
+        }
+        hdc_status st = convnd(P, 0, z, z, hz, 1, rest, s);
+        if (st != HDC_OK) return st;
+        LaunchScope ls(s, 7, (double)nout * (double)eb * 1.5);
+        hipError_t e = launch_real_extract(dbl, hz, h, nout, mx, s);
+        if (e != hipSuccess) return hip_fail(e, "real extract launch");
+        return HDC_OK;
     }
     return convnd(P, 0, f, g, h, 1, (char*)ws, s);
 }

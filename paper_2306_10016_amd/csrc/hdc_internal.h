@@ -206,6 +206,10 @@ hipError_t launch_rowconv(bool dbl, int m, const FusedArgs& a, int threads, int6
                           hipStream_t s);
 hipError_t launch_fused_queue(bool dbl, const FusedQueueArgs& a, int64_t nitems, size_t lds, hipStream_t s);
 hipError_t launch_mul(bool dbl, void* F, const void* G, int64_t n, hipStream_t s);
+// Real N-D data: z = f + i s g with s = max|f| / max|g| (mx: two words the
+// launches clear and fill), and h = Im(hz) / (2 s).
+hipError_t launch_real_pack(bool dbl, const void* f, const void* g, void* z, int64_t n, void* mx, hipStream_t s);
+hipError_t launch_real_extract(bool dbl, const void* hz, void* h, int64_t n, const void* mx, hipStream_t s);
 hipError_t launch_natural(bool dbl, const void* F, void* out, int64_t Dg, int64_t m1, int64_t m2, int64_t C,
                           hipStream_t s);
 

@@ -1849,6 +1849,70 @@ __global__ void k_mul(cplx<T>* F, const cplx<T>* G, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) F[i] = F[i] * G[i];
 }
 
+// Real N-D data: f * g = Im(z * z) / (2 s) for z = f + i s g (the convolution is
+// bilinear: z * z = f * f - s^2 g * g + 2 i s f * g), one complex
+// autoconvolution instead of two forward transforms.  s = max|f| / max|g|
+// balances the two terms' scales; the maxima are exact and order-independent
+// (integer maxima of the non-negative values' bit patterns).
+template <typename T>
+struct AbsBits;
+template <>
+struct AbsBits<float> {
+    using U = unsigned int;
+    static __device__ U bits(float x) { return __float_as_uint(fabsf(x)); }
+    static __device__ float value(U u) { return __uint_as_float(u); }
+};
+template <>
+struct AbsBits<double> {
+    using U = unsigned long long;
+    static __device__ U bits(double x) { return (U)__double_as_longlong(fabs(x)); }
+    static __device__ double value(U u) { return __longlong_as_double((long long)u); }
+};
+
+template <typename T>
+__global__ void k_real_clear(typename AbsBits<T>::U* mx) {
+    if (threadIdx.x < 2) mx[threadIdx.x] = 0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_real_absmax(const T* x, int64_t n, typename AbsBits<T>::U* mx) {
+    using U = typename AbsBits<T>::U;
+    __shared__ U red[256];
+    U v = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const U b = AbsBits<T>::bits(x[i]);
+        v = b > v ? b : v;
+    }
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w && red[threadIdx.x + w] > red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(mx, red[0]);
+}
+
+template <typename T>
+__device__ __forceinline__ T real_scale(const typename AbsBits<T>::U* mx) {
+    const T a = AbsBits<T>::value(mx[0]), b = AbsBits<T>::value(mx[1]);
+    return (a > 0 && b > 0) ? a / b : (T)1;
+}
+
+template <typename T>
+__global__ void k_real_pack(const T* f, const T* g, cplx<T>* z, int64_t n, const typename AbsBits<T>::U* mx) {
+    const T sc = real_scale<T>(mx);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) z[i] = mk<T>(f[i], sc * g[i]);
+}
+
+template <typename T>
+__global__ void k_real_extract(const cplx<T>* hz, T* h, int64_t n, const typename AbsBits<T>::U* mx) {
+    const T w = (T)0.5 / real_scale<T>(mx);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) h[i] = w * hz[i].y;
+}
+
 // out[((d m) + l) C + c] = F[((d m1 + l1) m2 + l2) C + c] with l = l1 + m1 l2.
 template <typename T>
 __global__ void k_natural(const cplx<T>* F, cplx<T>* out, int64_t Dg, int64_t m1, int64_t m2, int64_t C) {
@@ -2242,6 +2306,38 @@ hipError_t launch_mul(bool dbl, void* F, const void* G, int64_t n, hipStream_t s
         hipLaunchKernelGGL(k_mul<float>, dim3((unsigned)blocks), dim3(256), 0, s,
                            reinterpret_cast<cplx<float>*>(F), reinterpret_cast<const cplx<float>*>(G), n);
     return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t real_pack_t(const void* f, const void* g, void* z, int64_t n, void* mx, hipStream_t s) {
+    using U = typename AbsBits<T>::U;
+    U* m = reinterpret_cast<U*>(mx);
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_real_clear<T>, dim3(1), dim3(64), 0, s, m);
+    hipLaunchKernelGGL(k_real_absmax<T>, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<const T*>(f), n, m);
+    hipLaunchKernelGGL(k_real_absmax<T>, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<const T*>(g), n,
+                       m + 1);
+    hipLaunchKernelGGL(k_real_pack<T>, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<const T*>(f),
+                       reinterpret_cast<const T*>(g), reinterpret_cast<cplx<T>*>(z), n, m);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t real_extract_t(const void* hz, void* h, int64_t n, const void* mx, hipStream_t s) {
+    using U = typename AbsBits<T>::U;
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536));
+    hipLaunchKernelGGL(k_real_extract<T>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       reinterpret_cast<const cplx<T>*>(hz), reinterpret_cast<T*>(h), n,
+                       reinterpret_cast<const U*>(mx));
+    return hipGetLastError();
+}
+
+hipError_t launch_real_pack(bool dbl, const void* f, const void* g, void* z, int64_t n, void* mx, hipStream_t s) {
+    return dbl ? real_pack_t<double>(f, g, z, n, mx, s) : real_pack_t<float>(f, g, z, n, mx, s);
+}
+
+hipError_t launch_real_extract(bool dbl, const void* hz, void* h, int64_t n, const void* mx, hipStream_t s) {
+    return dbl ? real_extract_t<double>(hz, h, n, mx, s) : real_extract_t<float>(hz, h, n, mx, s);
 }
 
 hipError_t launch_natural(bool dbl, const void* F, void* out, int64_t Dg, int64_t m1, int64_t m2, int64_t C,
