@@ -128,8 +128,9 @@ hdc_status hdc_plan(hdc_plan_t* out, int64_t L, int64_t M, int64_t m, int64_t p,
  * per axis instead of two) of the packed box z.  s = max|f| / max|g| (1 if
  * either is 0) keeps the two terms at one scale, so the rounding error relative
  * to |f| |g| stays that of a complex plan (with g = 0, h is rounding noise at
- * the scale of f * f rather than exact zeros).  The workspace holds z and the
- * complex output besides the complex plan's.  ndim = 1 returns
+ * the scale of f * f rather than exact zeros).  z is never stored: the outer
+ * axis's forward column pass reads f and s g as z, and its backward pass
+ * writes h; the workspace is the complex plan's plus 256 bytes.  ndim = 1 returns
  * HDC_ERR_UNSUPPORTED (hdc_plan's Hermitian pairing serves 1D real data). */
 hdc_status hdc_plan_nd(hdc_plan_t* out, int ndim, const int64_t* L, const int64_t* M, const int64_t* m,
                        const int64_t* p, const int64_t* q, const int64_t* D, hdc_dtype dtype);
@@ -373,8 +374,8 @@ hdc_status hdc_time_convolve(hdc_plan_t plan, const void* f, const void* g, void
  * Instrumented hdc_convolve: the same launches, each bracketed by HIP events on
  * `stream`; synchronises the stream.  For launch i < min(*n_launches,
  * max_launches): kinds[i] (0 fused, 1 forward column, 2 row, 3 backward
- * column, 4 raw residue rows, 5 output sums, 6 whole-row convolution, 7 real
- * N-D packing (scales and z) or extraction of h), ms[i] (event-measured duration) and bytes[i] (the launch's
+ * column, 4 raw residue rows, 5 output sums, 6 whole-row convolution, 7 the
+ * maxima of real N-D inputs), ms[i] (event-measured duration) and bytes[i] (the launch's
  * algorithmic HBM bytes: compulsory reads plus writes).  Any output array may
  * be NULL.  *n_launches receives the total number of launches.
  */

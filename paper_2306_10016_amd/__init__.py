@@ -254,7 +254,7 @@ class Plan:
                                           int(warmup), int(reps), ms))
         return list(ms)
 
-    KIND_NAMES = ("fused", "col_fwd", "row", "col_bwd", "row_raw", "qsum", "rowconv", "real_pack")
+    KIND_NAMES = ("fused", "col_fwd", "row", "col_bwd", "row_raw", "qsum", "rowconv", "real_scale")
 
     def convolve_profiled(self, f, g, out, ws=None, stream=None, max_launches: int = 4096):
         """hdc_convolve with per-launch HIP-event timing: list of (kind, ms, algorithmic bytes)."""

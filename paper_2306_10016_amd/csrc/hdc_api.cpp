@@ -689,9 +689,10 @@ hdc_status run_fused(const AxisPlan& A, const void* f, const void* g, void* h, i
 hdc_status run_col_fwd(const AxisPlan& A, const void* x, void* X, int64_t B, int64_t in_bs, int64_t out_bs,
                        int64_t C1, int64_t r0, int64_t Dg, hipStream_t s, const int64_t* desc = nullptr,
                        int64_t lam = 1, int64_t rstride = 0, const void* x2 = nullptr, int64_t nsec = 0,
-                       int64_t r2 = 0) {
+                       int64_t r2 = 0, const void* gs = nullptr) {
     ColFwdArgs a{};
     a.desc = desc;
+    a.gs = gs;
     a.x = x;
     a.x2 = x2;
     a.nsec = (int32_t)nsec;
@@ -744,9 +745,10 @@ hdc_status run_col_fwd(const AxisPlan& A, const void* x, void* X, int64_t B, int
 
 hdc_status run_col_bwd(const AxisPlan& A, const void* Y, void* h, int64_t B, int64_t in_bs, int64_t out_bs,
                        int64_t C1, int64_t r0, int64_t Dg, bool accumulate, hipStream_t s,
-                       const int64_t* desc = nullptr, bool real = false) {
+                       const int64_t* desc = nullptr, bool real = false, const void* gs = nullptr) {
     ColBwdArgs a{};
     a.desc = desc;
+    a.gs = gs;
     a.Y = Y;
     a.h = h;
     a.B = B;
@@ -1295,6 +1297,37 @@ hdc_status convnd(const hdc_plan_s* P, int level, const void* xf, const void* xg
     return HDC_OK;
 }
 
+// Real f, g of an N-D plan (section 3.6 with z = f + i s g): the outer axis's
+// forward column passes read f and s g as z, the inner axes run the complex
+// autoconvolution of its residue rows, and the outer backward writes
+// h = Im(z * z) / (2 s) (the convolution is bilinear: z * z = f * f - s^2 g * g
+// + 2 i s f * g).
+hdc_status convnd_real(const hdc_plan_s* P, const void* f, const void* g, void* out, const void* mx, char* ws,
+                       hipStream_t s) {
+    const AxisPlan& A = P->ax[0];
+    const size_t eb = elem(P);
+    const int64_t D = std::min(A.d.D, A.d.q);
+    const int64_t inner_in = prod_L(P, 1), inner_out = prod_M(P, 1);
+    const int64_t nbmax = D * A.d.m;
+    char* X = ws;
+    char* Y = ws + (size_t)(2 * nbmax * inner_in) * eb;  // the complex plan's layout (its Xg unused)
+    char* rest = Y + (size_t)(nbmax * inner_out) * eb;
+    for (int64_t r0 = 0; r0 < A.d.q; r0 += D) {
+        const int64_t Dg = std::min(D, A.d.q - r0);
+        const int64_t nb = Dg * A.d.m;
+        hdc_status st = run_col_fwd(A, f, X, 1, A.d.L * inner_in, Dg * A.d.m * inner_in, inner_in, r0, Dg, s, nullptr,
+                                    1, 0, g, 0, 0, mx);
+        if (st == HDC_OK && A.d.m2 > 1) st = run_col_plain(A, X, Dg * A.d.m1, inner_in, +1, s);
+        if (st == HDC_OK) st = convnd(P, 1, X, X, Y, nb, rest, s);
+        if (st == HDC_OK && A.d.m2 > 1) st = run_col_plain(A, Y, Dg * A.d.m1, inner_out, -1, s);
+        if (st == HDC_OK)
+            st = run_col_bwd(A, Y, out, 1, Dg * A.d.m * inner_out, A.d.M * inner_out, inner_out, r0, Dg, r0 > 0, s,
+                             nullptr, true, mx);
+        if (st != HDC_OK) return st;
+    }
+    return HDC_OK;
+}
+
 // Multi-convolution in N-D (section 6.1 with section 3.6's recursion): the
 // outer axis's residue group of every operand, the inner (N-1)-D
 // multi-convolution per residue row, the outer backward.
@@ -1508,8 +1541,8 @@ hdc_status finish_plan(hdc_plan_s* P) {
     } else if (P->ndim == 1) {
         P->ws_bytes = (size_t)ws1d(P->ax[0], 1, P->ax[0].d.C) * elem(P);
     } else if (P->real_nd) {
-        // two scale words, z (the inputs' box), the complex output box, the N-D workspace
-        P->ws_bytes = 256 + (size_t)(prod_L(P, 0) + prod_M(P, 0) + wsnd(P, 0, 1)) * elem(P);
+        // the two scale words, then the N-D workspace
+        P->ws_bytes = 256 + (size_t)wsnd(P, 0, 1) * elem(P);
     } else {
         P->ws_bytes = (size_t)wsnd(P, 0, 1) * elem(P);
     }
@@ -1939,26 +1972,15 @@ hdc_status hdc_convolve(hdc_plan_t P, const void* f, const void* g, void* h, voi
         return conv1d(A, f, g, h, 1, 0, 0, A.d.C, (char*)ws, elem(P), s);
     }
     if (P->real_nd) {
-        // h = Im(z * z) / (2 s), z = f + i s g: the workspace holds the two scale
-        // words, z and the complex output ahead of the N-D workspace
-        const size_t eb = elem(P);
-        const int64_t nin = prod_L(P, 0), nout = prod_M(P, 0);
+        // h = Im(z * z) / (2 s), z = f + i s g: the scale words, then the outer
+        // axis's real column passes around the inner autoconvolution
         char* mx = (char*)ws;
-        char* z = mx + 256;
-        char* hz = z + (size_t)nin * eb;
-        char* rest = hz + (size_t)nout * eb;
-        const bool dbl = P->dtype == HDC_C128;
         {
-            LaunchScope ls(s, 7, (double)nin * (double)eb * 2.0);
-            hipError_t e = launch_real_pack(dbl, f, g, z, nin, mx, s);
-            if (e != hipSuccess) return hip_fail(e, "real pack launch");
+            LaunchScope ls(s, 7, (double)prod_L(P, 0) * (double)elem(P));
+            hipError_t e = launch_real_scale(P->dtype == HDC_C128, f, g, prod_L(P, 0), mx, s);
+            if (e != hipSuccess) return hip_fail(e, "real scale launch");
         }
-        hdc_status st = convnd(P, 0, z, z, hz, 1, rest, s);
-        if (st != HDC_OK) return st;
-        LaunchScope ls(s, 7, (double)nout * (double)eb * 1.5);
-        hipError_t e = launch_real_extract(dbl, hz, h, nout, mx, s);
-        if (e != hipSuccess) return hip_fail(e, "real extract launch");
-        return HDC_OK;
+        return convnd_real(P, f, g, h, mx, mx + 256, s);
     }
     return convnd(P, 0, f, g, h, 1, (char*)ws, s);
 }

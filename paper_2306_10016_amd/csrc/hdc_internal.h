@@ -84,6 +84,7 @@ struct ColFwdArgs {
     TwN tw;
     const void* tw1;           // per-pass twiddle table of the m1-point transform, data type
     const int64_t* desc;       // optional per-batch {input offset, L}; replaces b*in_bs and L
+    const void* gs;            // real N-D: scale words (z = f + i s g); nullptr: s = 1
 };
 
 struct ColBwdArgs {
@@ -98,6 +99,7 @@ struct ColBwdArgs {
     const void* tw1;
     double invN;
     const int64_t* desc;  // optional per-batch {output offset, M}; replaces b*out_bs and M
+    const void* gs;       // real N-D (REAL): scale words, h = Im(...) / (2 s); nullptr: Hermitian weights
 };
 
 struct RowArgs {
@@ -206,10 +208,9 @@ hipError_t launch_rowconv(bool dbl, int m, const FusedArgs& a, int threads, int6
                           hipStream_t s);
 hipError_t launch_fused_queue(bool dbl, const FusedQueueArgs& a, int64_t nitems, size_t lds, hipStream_t s);
 hipError_t launch_mul(bool dbl, void* F, const void* G, int64_t n, hipStream_t s);
-// Real N-D data: z = f + i s g with s = max|f| / max|g| (mx: two words the
-// launches clear and fill), and h = Im(hz) / (2 s).
-hipError_t launch_real_pack(bool dbl, const void* f, const void* g, void* z, int64_t n, void* mx, hipStream_t s);
-hipError_t launch_real_extract(bool dbl, const void* hz, void* h, int64_t n, const void* mx, hipStream_t s);
+// Real N-D data: the scale words max|f|, max|g| (cleared and filled) that the
+// column passes turn into s = max|f| / max|g| for z = f + i s g, h = Im(z * z) / (2 s).
+hipError_t launch_real_scale(bool dbl, const void* f, const void* g, int64_t n, void* mx, hipStream_t s);
 hipError_t launch_natural(bool dbl, const void* F, void* out, int64_t Dg, int64_t m1, int64_t m2, int64_t C,
                           hipStream_t s);
 

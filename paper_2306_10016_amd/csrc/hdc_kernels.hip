@@ -935,6 +935,56 @@ __global__ void __launch_bounds__(512) k_fused_queue(FusedQueueArgs q) {
 
 __global__ void k_zero_counter(int* c) { *c = 0; }
 
+// Real N-D data: f * g = Im(z * z) / (2 s) for z = f + i s g (the convolution is
+// bilinear: z * z = f * f - s^2 g * g + 2 i s f * g), one complex
+// autoconvolution instead of two forward transforms.  s = max|f| / max|g|
+// balances the two terms' scales; the maxima are exact and order-independent
+// (integer maxima of the non-negative values' bit patterns).
+template <typename T>
+struct AbsBits;
+template <>
+struct AbsBits<float> {
+    using U = unsigned int;
+    static __device__ U bits(float x) { return __float_as_uint(fabsf(x)); }
+    static __device__ float value(U u) { return __uint_as_float(u); }
+};
+template <>
+struct AbsBits<double> {
+    using U = unsigned long long;
+    static __device__ U bits(double x) { return (U)__double_as_longlong(fabs(x)); }
+    static __device__ double value(U u) { return __longlong_as_double((long long)u); }
+};
+
+template <typename T>
+__global__ void k_real_clear(typename AbsBits<T>::U* mx) {
+    if (threadIdx.x < 2) mx[threadIdx.x] = 0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_real_absmax(const T* x, int64_t n, typename AbsBits<T>::U* mx) {
+    using U = typename AbsBits<T>::U;
+    __shared__ U red[256];
+    U v = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const U b = AbsBits<T>::bits(x[i]);
+        v = b > v ? b : v;
+    }
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w && red[threadIdx.x + w] > red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(mx, red[0]);
+}
+
+template <typename T>
+__device__ __forceinline__ T real_scale(const typename AbsBits<T>::U* mx) {
+    const T a = AbsBits<T>::value(mx[0]), b = AbsBits<T>::value(mx[1]);
+    return (a > 0 && b > 0) ? a / b : (T)1;
+}
+
 // ------------------------------------------------------- column kernels --
 //
 // A workgroup owns `tile` adjacent columns c' (coalesced) and all m1 rows of
@@ -954,7 +1004,8 @@ constexpr int colf_ppt() {
     return (REAL && M1 >= 16) ? 16 : (M1 >= 8 ? 8 : M1);
 }
 
-template <typename T, int M1, bool REAL = false>
+// SC (with REAL): real N-D data, g read as s g (the scale words in a.gs).
+template <typename T, int M1, bool REAL = false, bool SC = false>
 __global__ void __launch_bounds__(REAL ? 512 : 1024) k_col_fwd(ColFwdArgs a) {
     using P = FP<M1, colf_ppt<M1, REAL>()>;
     constexpr int PPT = P::PPT;
@@ -996,6 +1047,9 @@ __global__ void __launch_bounds__(REAL ? 512 : 1024) k_col_fwd(ColFwdArgs a) {
     const cplx<T>* x = reinterpret_cast<const cplx<T>*>(a.x) + xoff;
     const T* xr = reinterpret_cast<const T*>(a.x) + xoff;
     const T* xi = reinterpret_cast<const T*>(a.x2) + xoff;
+    // real N-D data: g enters as s g
+    T gsc = (T)1;
+    if constexpr (SC) gsc = real_scale<T>(reinterpret_cast<const typename AbsBits<T>::U*>(a.gs));
     cplx<T>* X = reinterpret_cast<cplx<T>*>(a.X) + b * a.out_bs;
 
     // block t, point v of this thread: x[(t*m1 + s1)*Ccols + cp] with s1 = lane + v TPF,
@@ -1008,7 +1062,8 @@ __global__ void __launch_bounds__(REAL ? 512 : 1024) k_col_fwd(ColFwdArgs a) {
 #define HDC_IDX(t, v) ((t) * istep_t + ibase + (v) * istep_v)
 #define HDC_LOAD(t, v)                                                                        \
     ((ok && (t) * jstep_t + jbase + (v) * jstep_v < L)                                        \
-         ? (REAL ? mk<T>(xr[HDC_IDX(t, v)], xi[HDC_IDX(t, v)]) : x[HDC_IDX(t, v)])            \
+         ? (REAL ? mk<T>(xr[HDC_IDX(t, v)], SC ? gsc * xi[HDC_IDX(t, v)] : xi[HDC_IDX(t, v)])  \
+                 : x[HDC_IDX(t, v)])                                                          \
          : mk<T>(0, 0))
 
     {
@@ -1064,7 +1119,9 @@ __global__ void __launch_bounds__(REAL ? 512 : 1024) k_col_fwd(ColFwdArgs a) {
 // REAL: the residues are those of a Hermitian product (real output, the real
 // case of section 7): only r <= q/2 are given, each counted twice except r = 0
 // and r = q/2, and the real part is written to a real h.
-template <typename T, int M1, int DMAX, bool REAL = false>
+// IM (with REAL): real N-D data, h = Im(...) / (2 s) (the scale words in a.gs)
+// instead of the Hermitian residues' weighted real part.
+template <typename T, int M1, int DMAX, bool REAL = false, bool IM = false>
 __global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
     using P = FP<M1>;
     constexpr int PPT = P::PPT;
@@ -1095,6 +1152,8 @@ __global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
     const cplx<T>* Y = reinterpret_cast<const cplx<T>*>(a.Y) + b * a.in_bs;
     cplx<T>* h = reinterpret_cast<cplx<T>*>(a.h) + hoff;
     T* hr = reinterpret_cast<T*>(a.h) + hoff;
+    T wim = (T)0;
+    if constexpr (IM) wim = (T)0.5 / real_scale<T>(reinterpret_cast<const typename AbsBits<T>::U*>(a.gs));
     const T invN = (T)a.invN;
     // four-step twiddle conj(zeta_m^{l1 s2}), l1 = lane + v TPF, as z0 zs^v
     const bool fs = a.m2 > 1 && s2 != 0;
@@ -1170,9 +1229,13 @@ __global__ void __launch_bounds__(512) k_col_bwd(ColBwdArgs a) {
 #pragma unroll
                     for (int dd = 0; dd < DMAX; ++dd) {
                         if (dd < nd) {
-                            const int r = a.r0 + db + dd;
-                            const T wgt = (r == 0 || 2 * r == a.q) ? (T)1 : (T)2;
-                            acc += wgt * mul_tw<true>(V[dd][v], z[dd], false).x;
+                            const cplx<T> u = mul_tw<true>(V[dd][v], z[dd], false);
+                            if constexpr (IM) {  // real N-D: Im(z * z) / (2 s)
+                                acc += wim * u.y;
+                            } else {  // Hermitian residues: weight 2 but for r = 0 and r = q/2
+                                const int r = a.r0 + db + dd;
+                                acc += ((r == 0 || 2 * r == a.q) ? (T)1 : (T)2) * u.x;
+                            }
                         }
                     }
                     if (add) acc += hr[idx];
@@ -1849,70 +1912,6 @@ __global__ void k_mul(cplx<T>* F, const cplx<T>* G, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) F[i] = F[i] * G[i];
 }
 
-// Real N-D data: f * g = Im(z * z) / (2 s) for z = f + i s g (the convolution is
-// bilinear: z * z = f * f - s^2 g * g + 2 i s f * g), one complex
-// autoconvolution instead of two forward transforms.  s = max|f| / max|g|
-// balances the two terms' scales; the maxima are exact and order-independent
-// (integer maxima of the non-negative values' bit patterns).
-template <typename T>
-struct AbsBits;
-template <>
-struct AbsBits<float> {
-    using U = unsigned int;
-    static __device__ U bits(float x) { return __float_as_uint(fabsf(x)); }
-    static __device__ float value(U u) { return __uint_as_float(u); }
-};
-template <>
-struct AbsBits<double> {
-    using U = unsigned long long;
-    static __device__ U bits(double x) { return (U)__double_as_longlong(fabs(x)); }
-    static __device__ double value(U u) { return __longlong_as_double((long long)u); }
-};
-
-template <typename T>
-__global__ void k_real_clear(typename AbsBits<T>::U* mx) {
-    if (threadIdx.x < 2) mx[threadIdx.x] = 0;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_real_absmax(const T* x, int64_t n, typename AbsBits<T>::U* mx) {
-    using U = typename AbsBits<T>::U;
-    __shared__ U red[256];
-    U v = 0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const U b = AbsBits<T>::bits(x[i]);
-        v = b > v ? b : v;
-    }
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w && red[threadIdx.x + w] > red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicMax(mx, red[0]);
-}
-
-template <typename T>
-__device__ __forceinline__ T real_scale(const typename AbsBits<T>::U* mx) {
-    const T a = AbsBits<T>::value(mx[0]), b = AbsBits<T>::value(mx[1]);
-    return (a > 0 && b > 0) ? a / b : (T)1;
-}
-
-template <typename T>
-__global__ void k_real_pack(const T* f, const T* g, cplx<T>* z, int64_t n, const typename AbsBits<T>::U* mx) {
-    const T sc = real_scale<T>(mx);
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) z[i] = mk<T>(f[i], sc * g[i]);
-}
-
-template <typename T>
-__global__ void k_real_extract(const cplx<T>* hz, T* h, int64_t n, const typename AbsBits<T>::U* mx) {
-    const T w = (T)0.5 / real_scale<T>(mx);
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) h[i] = w * hz[i].y;
-}
-
 // out[((d m) + l) C + c] = F[((d m1 + l1) m2 + l2) C + c] with l = l1 + m1 l2.
 template <typename T>
 __global__ void k_natural(const cplx<T>* F, cplx<T>* out, int64_t Dg, int64_t m1, int64_t m2, int64_t C) {
@@ -1972,9 +1971,10 @@ hipError_t fused_t(const FusedArgs& a, int threads, int64_t blocks, size_t lds, 
 template <typename T, int M1, bool REAL>
 hipError_t colf_r(const ColFwdArgs& a, int threads, int64_t gx, int64_t gy, size_t lds, hipStream_t s) {
     lds += (size_t)PassTab<M1>::LEN * sizeof(cplx<T>);
-    hipError_t e = allow_lds(k_col_fwd<T, M1, REAL>, lds);
+    auto kern = (REAL && a.gs != nullptr) ? k_col_fwd<T, M1, REAL, true> : k_col_fwd<T, M1, REAL, false>;
+    hipError_t e = allow_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_col_fwd<T, M1, REAL>), dim3((unsigned)gx, (unsigned)gy), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)gx, (unsigned)gy), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
@@ -1988,9 +1988,10 @@ hipError_t colb_r(const ColBwdArgs& a, int threads, int64_t gx, int64_t gy, size
     // residues held in registers per pass over h (more passes read-modify-write h)
     constexpr int DMAX = sizeof(T) == 8 ? (M1 >= 1024 ? 2 : 3) : 4;
     lds += (size_t)PassTab<M1>::LEN * sizeof(cplx<T>);
-    hipError_t e = allow_lds(k_col_bwd<T, M1, DMAX, REAL>, lds);
+    auto kern = (REAL && a.gs != nullptr) ? k_col_bwd<T, M1, DMAX, REAL, true> : k_col_bwd<T, M1, DMAX, REAL, false>;
+    hipError_t e = allow_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_col_bwd<T, M1, DMAX, REAL>), dim3((unsigned)gx, (unsigned)gy), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)gx, (unsigned)gy), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
@@ -2309,7 +2310,7 @@ hipError_t launch_mul(bool dbl, void* F, const void* G, int64_t n, hipStream_t s
 }
 
 template <typename T>
-static hipError_t real_pack_t(const void* f, const void* g, void* z, int64_t n, void* mx, hipStream_t s) {
+static hipError_t real_scale_t(const void* f, const void* g, int64_t n, void* mx, hipStream_t s) {
     using U = typename AbsBits<T>::U;
     U* m = reinterpret_cast<U*>(mx);
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
@@ -2317,27 +2318,11 @@ static hipError_t real_pack_t(const void* f, const void* g, void* z, int64_t n, 
     hipLaunchKernelGGL(k_real_absmax<T>, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<const T*>(f), n, m);
     hipLaunchKernelGGL(k_real_absmax<T>, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<const T*>(g), n,
                        m + 1);
-    hipLaunchKernelGGL(k_real_pack<T>, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<const T*>(f),
-                       reinterpret_cast<const T*>(g), reinterpret_cast<cplx<T>*>(z), n, m);
     return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t real_extract_t(const void* hz, void* h, int64_t n, const void* mx, hipStream_t s) {
-    using U = typename AbsBits<T>::U;
-    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536));
-    hipLaunchKernelGGL(k_real_extract<T>, dim3((unsigned)blocks), dim3(256), 0, s,
-                       reinterpret_cast<const cplx<T>*>(hz), reinterpret_cast<T*>(h), n,
-                       reinterpret_cast<const U*>(mx));
-    return hipGetLastError();
-}
-
-hipError_t launch_real_pack(bool dbl, const void* f, const void* g, void* z, int64_t n, void* mx, hipStream_t s) {
-    return dbl ? real_pack_t<double>(f, g, z, n, mx, s) : real_pack_t<float>(f, g, z, n, mx, s);
-}
-
-hipError_t launch_real_extract(bool dbl, const void* hz, void* h, int64_t n, const void* mx, hipStream_t s) {
-    return dbl ? real_extract_t<double>(hz, h, n, mx, s) : real_extract_t<float>(hz, h, n, mx, s);
+hipError_t launch_real_scale(bool dbl, const void* f, const void* g, int64_t n, void* mx, hipStream_t s) {
+    return dbl ? real_scale_t<double>(f, g, n, mx, s) : real_scale_t<float>(f, g, n, mx, s);
 }
 
 hipError_t launch_natural(bool dbl, const void* F, void* out, int64_t Dg, int64_t m1, int64_t m2, int64_t C,
