@@ -125,7 +125,7 @@ hdc_status hdc_plan(hdc_plan_t* out, int64_t L, int64_t M, int64_t m, int64_t p,
  * and h are real boxes.  Because the convolution is bilinear,
  *     z * z = f * f - s^2 g * g + 2 i s f * g   for z = f + i s g,
  * so h = Im(z * z) / (2 s): one complex autoconvolution (one forward transform
- * per axis instead of two) of the packed box z.  s = max|f| / max|g| (1 if
+ * per axis instead of two) of z.  s = max|f| / max|g| (1 if
  * either is 0) keeps the two terms at one scale, so the rounding error relative
  * to |f| |g| stays that of a complex plan (with g = 0, h is rounding noise at
  * the scale of f * f rather than exact zeros).  z is never stored: the outer

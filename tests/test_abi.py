@@ -216,8 +216,8 @@ def test_uneq_first_outputs_mode():
 
 def test_real_dtype_rules():
     """Real data (HDC_R32 / HDC_R64) derive exactly as the complex plan of the same
-    shape, in 1D and N-D (whose real plans run the complex autoconvolution of the
-    packed box), and are refused, with HDC_ERR_UNSUPPORTED, by the unequal-length
+    shape, in 1D and N-D (whose real plans run the complex autoconvolution of
+    z = f + i s g), and are refused, with HDC_ERR_UNSUPPORTED, by the unequal-length
     entry points."""
     for L, M, m in [(6, 11, 4), (1024, 2047, 256), (1 << 22, (1 << 23) - 1, 1 << 22)]:
         assert hdc.derive(L, M, m, dtype="r64") == hdc.derive(L, M, m, dtype="c128")

@@ -1,6 +1,6 @@
 """Real data in 2D and 3D (the real case of section 7): h = Im(z * z) / (2 s) for
-z = f + i s g, one complex autoconvolution of the packed box with s = max|f| /
-max|g|.  Against the oracle's padded N-D convolution of the same (real-valued)
+z = f + i s g, one complex autoconvolution with s = max|f| / max|g| (z formed
+and h extracted inside the outer axis's column passes).  Against the oracle's padded N-D convolution of the same (real-valued)
 data in float64 and float32: the innermost axis on the fused kernel, the
 row-convolution kernel (float32) and the column/row/column passes; an outer
 axis split in two column stages; 3D; first outputs; operands whose scales
