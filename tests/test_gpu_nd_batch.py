@@ -168,9 +168,12 @@ def test_batch_full_workload_sampled():
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("L,m,D", [((3000, 40), (4096, 64), None), ((1500, 100), (2048, 128), (1, 0)),
-                                   ((1100, 6, 5), (2048, 8, 8), None), ((700, 33), (8192, 64), (3, 0))])
+                                   ((1100, 6, 5), (2048, 8, 8), None), ((700, 33), (8192, 64), (3, 0)),
+                                   ((3000, 20), (2048, 32), None), ((3000, 20), (2048, 32), (2, 0))])
 def test_outer_axis_four_step(L, m, D, dtype):
-    """Outer axes with m > 1024 run as two column stages (m1 = 1024, then a strided m2-point pass)."""
+    """Outer axes with m > 1024 run as two column stages (m1 = 1024, then a strided m2-point pass);
+    with q = 3 the backward columns take one group of three residues or groups of two and one
+    (the second accumulating into h)."""
     M = tuple(2 * a - 1 for a in L)
     plan, _ = _nd(L, M, m, dtype, D=D, idx=L[0] + 7)
     assert plan.axes[0]["m1"] * plan.axes[0]["m2"] == m[0]

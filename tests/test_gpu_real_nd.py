@@ -48,6 +48,7 @@ CASES = [
     ((33, 700), None, (64, 1024)),
     ((300, 1500), None, (512, 2048)),
     ((1500, 40), None, (2048, 64)),               # outer m = 1024 x 2
+    ((3000, 20), None, (2048, 32)),               # outer m = 1024 x 2, q = 3 residues in one group
     ((6, 9, 300), None, (8, 16, 512)),
     ((40, 50), (60, 70), None),                    # first outputs
     ((16, 3000), None, (16, 4096)),                # inner axis: row convolution in float32
