@@ -102,6 +102,36 @@ hdc_status hdc_tune_host(const hdc_problem* prob, int mode, const char* db, cons
 const char* hdc_build_id(void);
 
 /*
+ * Uneven batches (hdc_batch_plan) planned from a tuning database: the
+ * per-bucket form of the exhaustive search of section 4.2.  The problems of a
+ * batch are grouped into buckets by the next power of two of L; a database row
+ *     {"key": "{\"bucket\": S, \"dtype\": \"c64\"}", "params": {"m": m}, "ms": t,
+ *      "device": ..., "build": ..., "t": ...}
+ * records that the problems of bucket S ran in t milliseconds with FFT size m.
+ * For each bucket the fastest row of the device and build (equal times: the
+ * larger m) gives the m of its problems whose output length is 2L - 1; other
+ * problems, and buckets without a row, take hdc_batch_default_m.  Rows of other
+ * kinds in the same file are ignored, and hdc_tune ignores these rows.
+ *
+ * hdc_batch_db_choose: host only (no device is touched); fills m[i] (n values,
+ *   caller-owned) for the n problems of lengths L[i] and output lengths M[i]
+ *   (M NULL: 2 L[i] - 1).  db NULL or a missing file: every problem takes the
+ *   default.  device / build NULL: the current device's name and hdc_build_id().
+ *   HDC_ERR_INVALID_ARG for n < 1, NULL L or m, L[i] < 1 or a non-complex dtype.
+ * hdc_batch_db_record: appends one row (bucket a power of two, m >= 1,
+ *   ms >= 0; device / build NULL as above).  HDC_ERR_INVALID_ARG for bad
+ *   values or a file that cannot be opened for appending.
+ * hdc_batch_plan_db: hdc_batch_plan with the m of hdc_batch_db_choose (current
+ *   device and build); its errors are those two calls'.
+ */
+hdc_status hdc_batch_db_choose(int64_t n, const int64_t* L, const int64_t* M, hdc_dtype dtype, const char* db,
+                               const char* device, const char* build, int64_t* m);
+hdc_status hdc_batch_db_record(const char* db, int64_t bucket, hdc_dtype dtype, int64_t m, double ms,
+                               const char* device, const char* build);
+hdc_status hdc_batch_plan_db(hdc_batch_t* out, int64_t n, const int64_t* L, const int64_t* M, hdc_dtype dtype,
+                             const char* db);
+
+/*
  * Learned predictor (section 4.4; classification, section 6.3).  A checkpoint
  * file holds a multilayer perceptron (ReLU hidden layers, softmax output over
  * scale-free classes (p, D-mode): p in {1, 2, 3, 4, 6, 8, 12, 16}, D-mode 0 = all

@@ -486,19 +486,27 @@ class Profile:
 
 
 class Batch:
-    """Uneven-length batch of 1D convolutions packed back to back (hdc_batch_plan)."""
+    """Uneven-length batch of 1D convolutions packed back to back (hdc_batch_plan; with
+    ``tune_db``, hdc_batch_plan_db: each bucket's FFT size from the fastest row that
+    ``tune.tune_batch(..., db=tune_db)`` recorded on this device and build)."""
 
     def __init__(self, L: Sequence[int], M: Optional[Sequence[int]] = None, bucket_m: Optional[Sequence[int]] = None,
-                 dtype="c64"):
+                 dtype="c64", tune_db: Optional[str] = None):
         self._lib = lib()
         n = len(L)
         arr = ctypes.c_int64 * n
         self.L = [int(x) for x in L]
         self.M = [int(x) for x in M] if M is not None else [2 * x - 1 for x in self.L]
         h = ctypes.c_void_p()
-        check(self._lib.hdc_batch_plan(ctypes.byref(h), n, arr(*self.L), arr(*self.M),
-                                       arr(*[int(x) for x in bucket_m]) if bucket_m is not None else None,
-                                       dtype_code(dtype)))
+        if tune_db is not None:
+            if bucket_m is not None:
+                raise ValueError("give bucket_m or tune_db, not both")
+            check(self._lib.hdc_batch_plan_db(ctypes.byref(h), n, arr(*self.L), arr(*self.M), dtype_code(dtype),
+                                              tune_db.encode()))
+        else:
+            check(self._lib.hdc_batch_plan(ctypes.byref(h), n, arr(*self.L), arr(*self.M),
+                                           arr(*[int(x) for x in bucket_m]) if bucket_m is not None else None,
+                                           dtype_code(dtype)))
         self._h = h
         self.dtype = dtype_code(dtype)
         sz = ctypes.c_size_t()

@@ -94,6 +94,11 @@ SIGNATURES = {
     "hdc_tune_host": [ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p,
                       COST_FN, ctypes.c_void_p, ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_double)],
     "hdc_build_id": [],
+    "hdc_batch_db_choose": [_I64, _PI64, _PI64, ctypes.c_int, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p,
+                            _PI64],
+    "hdc_batch_db_record": [ctypes.c_char_p, _I64, ctypes.c_int, _I64, ctypes.c_double, ctypes.c_char_p,
+                            ctypes.c_char_p],
+    "hdc_batch_plan_db": [_PP, _I64, _PI64, _PI64, ctypes.c_int, ctypes.c_char_p],
     "hdc_predictor_load": [_PP, ctypes.c_char_p],
     "hdc_predict": [_P, ctypes.POINTER(Problem), ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_float)],
     "hdc_predictor_destroy": [_P],

@@ -795,6 +795,55 @@ void features(const hdc_problem& pr, int axis, float* v) {
     v[11] = (float)(std::log2(std::max(1.0, n)) / 32.0);
 }
 
+// --------------------------------------------------------- batch buckets --
+
+// Key of an uneven batch's bucket: the problems whose next power of two of L is
+// `size` (the grouping of the per-bucket search).
+std::string bucket_key(int64_t size, hdc_dtype dt) {
+    return "{\"bucket\": " + std::to_string((long long)size) + ", \"dtype\": \"" + dtype_name(dt) + "\"}";
+}
+
+// Fastest recorded m per bucket size (rows of `device` and `build` only; equal
+// times go to the larger m): size -> (ms, m).
+std::map<int64_t, std::pair<double, int64_t>> bucket_best(const char* path, hdc_dtype dt, const std::string& device,
+                                                          const std::string& build) {
+    std::map<int64_t, std::pair<double, int64_t>> best;
+    FILE* fh = fopen(path, "r");
+    if (!fh) return best;
+    auto take = [&](const std::string& line) {
+        JParser P{line.data(), line.data() + line.size()};
+        JVal v = P.value();
+        if (!P.ok || v.kind != JVal::OBJ) return;
+        const JVal *k = v.get("key"), *p = v.get("params"), *ms = v.get("ms"), *dv = v.get("device"),
+                   *bd = v.get("build");
+        if (!k || !p || !ms || !dv || !bd || k->kind != JVal::STR || ms->kind != JVal::NUM ||
+            dv->kind != JVal::STR || bd->kind != JVal::STR || p->kind != JVal::OBJ)
+            return;
+        if (dv->str != device || bd->str != build) return;
+        JParser KP{k->str.data(), k->str.data() + k->str.size()};
+        JVal kv = KP.value();
+        if (!KP.ok || kv.kind != JVal::OBJ) return;
+        const JVal *sz = kv.get("bucket"), *dt_s = kv.get("dtype"), *m = p->get("m");
+        if (!sz || !dt_s || !m || sz->kind != JVal::NUM || dt_s->kind != JVal::STR || m->kind != JVal::NUM) return;
+        if (dt_s->str != dtype_name(dt) || sz->num < 1 || m->num < 1 || !(ms->num >= 0)) return;
+        const int64_t size = (int64_t)sz->num, mm = (int64_t)m->num;
+        auto it = best.find(size);
+        if (it == best.end() || ms->num < it->second.first || (ms->num == it->second.first && mm > it->second.second))
+            best[size] = {ms->num, mm};
+    };
+    std::string line;
+    char buf[4096];
+    while (fgets(buf, sizeof buf, fh)) {
+        line += buf;
+        if (line.empty() || line.back() != '\n') continue;
+        take(line);
+        line.clear();
+    }
+    if (!line.empty()) take(line);
+    fclose(fh);
+    return best;
+}
+
 }  // namespace
 
 struct hdc_predictor_s {
@@ -972,6 +1021,62 @@ hdc_status hdc_predict(hdc_predictor_t P, const hdc_problem* prob, hdc_params* o
 hdc_status hdc_predictor_destroy(hdc_predictor_t P) {
     delete P;
     return HDC_OK;
+}
+
+hdc_status hdc_batch_db_choose(int64_t n, const int64_t* L, const int64_t* M, hdc_dtype dtype, const char* db,
+                               const char* device, const char* build, int64_t* m) {
+    if (n < 1 || !L || !m) return fail(HDC_ERR_INVALID_ARG, "bad batch arguments");
+    if (dtype != HDC_C64 && dtype != HDC_C128) return fail(HDC_ERR_INVALID_ARG, "bad dtype");
+    std::map<int64_t, std::pair<double, int64_t>> best;
+    if (db) best = bucket_best(db, dtype, device ? std::string(device) : device_name(),
+                               build ? std::string(build) : std::string(hdc_build_id()));
+    for (int64_t i = 0; i < n; ++i) {
+        if (L[i] < 1) return fail(HDC_ERR_INVALID_ARG, "problem %lld: L = %lld", (long long)i, (long long)L[i]);
+        const bool full = !M || M[i] == 2 * L[i] - 1;
+        auto it = best.find(pow2_ceil(L[i]));
+        if (full && it != best.end()) {
+            m[i] = it->second.second;
+        } else {
+            hdc_status st = hdc_batch_default_m(L[i], &m[i]);
+            if (st != HDC_OK) return st;
+        }
+    }
+    return HDC_OK;
+}
+
+hdc_status hdc_batch_db_record(const char* db, int64_t bucket, hdc_dtype dtype, int64_t m, double ms,
+                               const char* device, const char* build) {
+    if (!db) return fail(HDC_ERR_INVALID_ARG, "NULL database path");
+    if (bucket < 1 || (bucket & (bucket - 1)) != 0)
+        return fail(HDC_ERR_INVALID_ARG, "bucket = %lld must be a power of two", (long long)bucket);
+    if (m < 1 || !(ms >= 0)) return fail(HDC_ERR_INVALID_ARG, "m = %lld, ms = %g", (long long)m, ms);
+    if (dtype != HDC_C64 && dtype != HDC_C128) return fail(HDC_ERR_INVALID_ARG, "bad dtype");
+    const std::string dev = device ? std::string(device) : device_name();
+    const std::string bld = build ? std::string(build) : std::string(hdc_build_id());
+    FILE* fh = fopen(db, "a+");
+    if (!fh) return fail(HDC_ERR_INVALID_ARG, "cannot open %s", db);
+    // a record cut short by a kill leaves no newline: start a fresh line
+    if (fseek(fh, -1, SEEK_END) == 0) {
+        const int last = fgetc(fh);
+        if (last != '\n' && last != EOF) fputc('\n', fh);
+    }
+    fseek(fh, 0, SEEK_END);
+    fprintf(fh, "{\"key\": %s, \"params\": {\"m\": %lld}, \"ms\": %.9g, \"device\": %s, \"build\": %s, \"t\": %lld}\n",
+            jstr(bucket_key(bucket, dtype)).c_str(), (long long)m, ms, jstr(dev).c_str(), jstr(bld).c_str(),
+            (long long)time(nullptr));
+    fclose(fh);
+    return HDC_OK;
+}
+
+hdc_status hdc_batch_plan_db(hdc_batch_t* out, int64_t n, const int64_t* L, const int64_t* M, hdc_dtype dtype,
+                             const char* db) {
+    if (!out) return fail(HDC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !L) return fail(HDC_ERR_INVALID_ARG, "bad batch arguments");
+    std::vector<int64_t> m((size_t)n);
+    hdc_status st = hdc_batch_db_choose(n, L, M, dtype, db, nullptr, nullptr, m.data());
+    if (st != HDC_OK) return st;
+    return hdc_batch_plan(out, n, L, M, m.data(), dtype);
 }
 
 }  // extern "C"

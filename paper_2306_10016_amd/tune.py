@@ -555,15 +555,25 @@ def batch_default_m(L: int) -> int:
 
 
 def tune_batch(Ls: Sequence[int], dtype: str = "c64", timer: Optional[Callable] = None, max_shift: int = 3,
-               reps: int = 3) -> Tuple[List[int], Dict[int, List[Tuple[int, float]]]]:
+               reps: int = 3, db: Optional[str] = None, device: Optional[str] = None,
+               build: Optional[str] = None) -> Tuple[List[int], Dict[int, List[Tuple[int, float]]]]:
     """Per-bucket exhaustive search (A0 of section 4.2 applied bucket by bucket) for an
     uneven batch with M = 2L - 1.  Problems are grouped by the next power of two of L
     (p = 1); for each group every m = size / 2^j, j = 0 .. max_shift (p = 1, 2, 4, 8),
     and the library's default m (hdc_batch_default_m) are timed on the group's
     problems alone and the fastest kept (ties: the larger m).  ``timer(Ls, ms, dtype) -> ms`` defaults to the captured batch on the
-    GPU.  Returns the FFT size of every problem and each group's table [(m, ms)]."""
-    from . import HdcError
+    GPU.  With ``db`` every timing is appended to that JSON-lines database as a bucket
+    row (hdc_batch_db_record; ``device`` / ``build`` None: this GPU and library), from
+    which ``Batch(..., tune_db=db)`` plans the same choice.  Returns the FFT size of every
+    problem and each group's table [(m, ms)]."""
+    from . import HdcError, dtype_code
+    from ._lib import check, lib
     timer = timer or (lambda ls, ms, dt: _batch_gpu_time(ls, ms, dt, reps=reps))
+
+    def record(size, m, ms):
+        if db is not None:
+            check(lib().hdc_batch_db_record(db.encode(), size, dtype_code(dtype), m, ms,
+                                            device.encode() if device else None, build.encode() if build else None))
     groups: Dict[int, List[int]] = {}
     for i, L in enumerate(Ls):
         groups.setdefault(pow2_ceil(int(L)), []).append(i)
@@ -581,9 +591,25 @@ def tune_batch(Ls: Sequence[int], dtype: str = "c64", timer: Optional[Callable] 
                 rows.append((m, float(timer(gl, [m] * len(gl), dtype))))
             except HdcError:
                 continue
+            record(size, m, rows[-1][1])
         tables[size] = rows
         if rows:
             best = min(rows, key=lambda r: (r[1], -r[0]))[0]
             for i in idx:
                 choice[i] = best
     return choice, tables
+
+
+def batch_db_choose(Ls: Sequence[int], dtype: str = "c64", db: Optional[str] = None, Ms: Optional[Sequence[int]] = None,
+                    device: Optional[str] = None, build: Optional[str] = None) -> List[int]:
+    """The FFT size of every problem that hdc_batch_plan_db takes from ``db``
+    (hdc_batch_db_choose, host only; ``device`` / ``build`` None: this GPU and library)."""
+    from . import dtype_code
+    from ._lib import check, lib
+    n = len(Ls)
+    arr = ctypes.c_int64 * n
+    out = arr()
+    check(lib().hdc_batch_db_choose(n, arr(*[int(x) for x in Ls]), arr(*[int(x) for x in Ms]) if Ms is not None else None,
+                                    dtype_code(dtype), db.encode() if db else None,
+                                    device.encode() if device else None, build.encode() if build else None, out))
+    return [int(x) for x in out]

@@ -83,13 +83,13 @@ def test_2d_autoconvolution():
     assert rel(h, oracle.padded_nd(f64, f64, (119, 89))) <= 1e-12
 
 
-def _batch(Ls, dtype, bucket_m=None, graph=True, cfg=310, check_idx=None, replays=1):
+def _batch(Ls, dtype, bucket_m=None, graph=True, cfg=310, check_idx=None, replays=1, tune_db=None):
     Ls = [int(x) for x in Ls]
     Ms = [2 * x - 1 for x in Ls]
     fs = [synth.uniform_complex(L, cfg, i, 0, NP_DT[dtype]) for i, L in enumerate(Ls)]
     gs = [synth.uniform_complex(L, cfg, i, 1, NP_DT[dtype]) for i, L in enumerate(Ls)]
     fp, gp = to_dev(np.concatenate(fs)), to_dev(np.concatenate(gs))
-    B = hdc.Batch(Ls, bucket_m=bucket_m, dtype=dtype)
+    B = hdc.Batch(Ls, bucket_m=bucket_m, dtype=dtype, tune_db=tune_db)
     say(f"batch n={len(Ls)} buckets={B.n_buckets} {dtype} graph={graph}")
     import torch
     out = torch.empty(B.total_M, dtype=fp.dtype, device="cuda")
@@ -121,6 +121,28 @@ def test_batch_bucket_override(dtype):
     Ls = synth.batch_lengths(40, 4, 12, cfg=312)
     bm = [max(1, int(2 ** np.floor(np.log2(L))) // 2) for L in Ls]  # p = 2 or 3 classes
     _batch(Ls, dtype, bucket_m=bm, graph=True, replays=2)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_planned_from_tuning_database(dtype, tmp_path):
+    """The per-bucket search timed on the GPU into a JSON-lines database; a batch planned
+    from it (hdc_batch_plan_db) takes exactly the search's FFT sizes: the same buckets and
+    bitwise the same output as the batch planned with those sizes, within the oracle's bar."""
+    import torch
+    from paper_2306_10016_amd import tune
+    Ls = [int(x) for x in synth.batch_lengths(48, 5, 13, cfg=314)]
+    db = str(tmp_path / "batch_db.jsonl")
+    choice, tables = tune.tune_batch(Ls, dtype, db=db, reps=1)
+    say(f"tuned {len(tables)} buckets: {[(s, min(t, key=lambda r: r[1])[0]) for s, t in sorted(tables.items())]}")
+    assert tune.batch_db_choose(Ls, dtype, db) == choice
+    Bd = _batch(Ls, dtype, tune_db=db, cfg=314, replays=2)
+    Bc = hdc.Batch(Ls, bucket_m=choice, dtype=dtype)
+    assert Bd.n_buckets == Bc.n_buckets
+    fp = torch.randn(Bd.total_L, dtype=torch.complex128 if dtype == "c128" else torch.complex64, device="cuda")
+    gp = torch.randn_like(fp)
+    hd, hc = Bd.convolve(fp, gp), Bc.convolve(fp, gp)
+    torch.cuda.synchronize()
+    assert torch.equal(hd, hc)
 
 
 def test_batch_edge_lengths():

@@ -254,6 +254,61 @@ def test_batch_tuner_picks_each_buckets_argmin():
     assert choice == [512, 8192]
 
 
+def test_batch_tuning_database(tmp_path):
+    """The per-bucket search recorded in a JSON-lines database (hdc_batch_db_record)
+    gives back, through the library's host-only reader (hdc_batch_db_choose, the
+    choice of hdc_batch_plan_db), exactly the FFT sizes the search returned; rows of
+    another device or build, of the other dtype and of unrelated kinds are ignored;
+    problems whose output is not 2L - 1, and buckets without a row, take the default;
+    equal times go to the larger m; a line cut short by a kill is skipped."""
+    db = str(tmp_path / "batch.jsonl")
+    with open(db, "w") as fh:  # an unrelated row and a torn record
+        fh.write(json.dumps({"key": json.dumps({"L": [64], "M": [127], "batch": 1, "dtype": "c64"}),
+                             "params": {"D": 1, "m": 64}, "ms": 0.1, "device": "dev", "build": "b1"}) + "\n")
+        fh.write('{"key": "{\\"bucket\\": 512')
+    Ls = [70, 100, 300, 1000, 3000, 5000, 7000, 9000, 20000, 40000, 64, 65536]
+
+    def cost(ls, ms, dtype):
+        tot = 0.0
+        for L, m in zip(ls, ms):
+            p = -(-L // m)
+            tot += 1.0 + abs(p - (1 if L <= 4096 else 2))
+        return tot
+    choice, tables = tune.tune_batch(Ls, "c64", timer=cost, db=db, device="dev", build="b1")
+    assert tune.batch_db_choose(Ls, "c64", db, device="dev", build="b1") == choice
+    rows = []
+    for x in open(db):
+        try:
+            r = json.loads(x)
+        except json.JSONDecodeError:
+            continue  # the torn record
+        if "bucket" in json.loads(r["key"]):
+            rows.append(r)
+    assert len(rows) == sum(len(t) for t in tables.values())
+    # the other device/build/dtype sees only defaults
+    dflt = [tune.batch_default_m(L) for L in Ls]
+    assert tune.batch_db_choose(Ls, "c64", db, device="other", build="b1") == dflt
+    assert tune.batch_db_choose(Ls, "c64", db, device="dev", build="b2") == dflt
+    assert tune.batch_db_choose(Ls, "c128", db, device="dev", build="b1") == dflt
+    assert tune.batch_db_choose(Ls, "c64", None) == dflt
+    # first-outputs problems keep the default; a bucket without rows too
+    Ms = [2 * L - 1 for L in Ls]
+    Ms[8] = Ls[8]
+    got = tune.batch_db_choose(Ls + [200000], "c64", db, Ms=Ms + [399999], device="dev", build="b1")
+    assert got[:8] == choice[:8] and got[8] == dflt[8] and got[9:12] == choice[9:] \
+        and got[12] == tune.batch_default_m(200000)
+    # a later, faster row wins; an equal time goes to the larger m
+    lib = hdc._lib.lib()
+    assert lib.hdc_batch_db_record(db.encode(), 1024, 0, 256, 0.0, b"dev", b"b1") == 0
+    assert tune.batch_db_choose([1000], "c64", db, device="dev", build="b1") == [256]
+    assert lib.hdc_batch_db_record(db.encode(), 1024, 0, 512, 0.0, b"dev", b"b1") == 0
+    assert tune.batch_db_choose([1000], "c64", db, device="dev", build="b1") == [512]
+    # bad records are refused
+    assert lib.hdc_batch_db_record(db.encode(), 1000, 0, 256, 1.0, b"dev", b"b1") == 1  # not a power of two
+    assert lib.hdc_batch_db_record(db.encode(), 1024, 0, 0, 1.0, b"dev", b"b1") == 1
+    assert lib.hdc_batch_db_record(db.encode(), 1024, 0, 256, -1.0, b"dev", b"b1") == 1
+
+
 def test_checkpoint_format_and_training_range(tmp_path):
     """save_checkpoint writes the layout hdc_predictor_load reads: magic, format 2,
     layer sizes, float32 weights, then the per-feature training range."""
