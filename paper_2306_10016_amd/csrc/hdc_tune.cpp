@@ -282,7 +282,9 @@ bool cand_from_json(const JVal& p, int nd, Cand* c) {
             return -1;
         };
         const double mv = at(m), dv = at(D), tv = t ? at(t) : 0;
-        if (mv < 1 || dv < 1 || tv < 0) return false;
+        // integral values within range before any conversion
+        auto whole = [](double x, double lo, double hi) { return x >= lo && x <= hi && x == std::floor(x); };
+        if (!whole(mv, 1, 1099511627776.0) || !whole(dv, 1, 1099511627776.0) || !whole(tv, 0, 65536)) return false;
         c->m[a] = (int64_t)mv;
         c->D[a] = (int64_t)dv;
         c->tile[a] = (int32_t)tv;
@@ -825,7 +827,11 @@ std::map<int64_t, std::pair<double, int64_t>> bucket_best(const char* path, hdc_
         if (!KP.ok || kv.kind != JVal::OBJ) return;
         const JVal *sz = kv.get("bucket"), *dt_s = kv.get("dtype"), *m = p->get("m");
         if (!sz || !dt_s || !m || sz->kind != JVal::NUM || dt_s->kind != JVal::STR || m->kind != JVal::NUM) return;
-        if (dt_s->str != dtype_name(dt) || sz->num < 1 || m->num < 1 || !(ms->num >= 0)) return;
+        // integral sizes within range before any conversion (an FFT size above the
+        // library's largest m, or a bucket beyond 2^40, is not a row of this kind)
+        if (dt_s->str != dtype_name(dt) || !(ms->num >= 0)) return;
+        if (!(sz->num >= 1 && sz->num <= 1099511627776.0 && sz->num == std::floor(sz->num))) return;
+        if (!(m->num >= 1 && m->num <= (double)kMaxM && m->num == std::floor(m->num))) return;
         const int64_t size = (int64_t)sz->num, mm = (int64_t)m->num;
         auto it = best.find(size);
         if (it == best.end() || ms->num < it->second.first || (ms->num == it->second.first && mm > it->second.second))

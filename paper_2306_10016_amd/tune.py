@@ -111,9 +111,13 @@ class TuneDB:
                     if not line:
                         continue
                     try:
-                        self.rows.append(json.loads(line))
+                        r = json.loads(line)
                     except json.JSONDecodeError:
                         continue  # a line cut short by a kill
+                    # rows of this form only (a hand-edited or foreign line is skipped)
+                    if isinstance(r, dict) and isinstance(r.get("key"), str) and isinstance(r.get("params"), dict) \
+                            and isinstance(r.get("ms"), (int, float)) and not isinstance(r.get("ms"), bool):
+                        self.rows.append(r)
 
     def add(self, key: str, params: dict, ms: float, extra: Optional[dict] = None):
         row = {"key": key, "params": params, "ms": float(ms), "device": self.device, "build": self.build,

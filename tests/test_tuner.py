@@ -309,6 +309,32 @@ def test_batch_tuning_database(tmp_path):
     assert lib.hdc_batch_db_record(db.encode(), 1024, 0, 256, -1.0, b"dev", b"b1") == 1
 
 
+def test_malformed_database_rows_are_skipped(tmp_path):
+    """Rows a hand edit or a foreign writer could leave -- sizes beyond range (1e30 would
+    overflow a 64-bit conversion), fractional sizes, missing fields, non-objects -- are
+    skipped by the library's readers (bucket rows and tuner rows) and by TuneDB."""
+    db = str(tmp_path / "bad.jsonl")
+    bkey = json.dumps({"bucket": 1024, "dtype": "c64"})
+    pkey = json.dumps({"L": [1000], "M": [1999], "batch": 1, "dtype": "c64"}, sort_keys=True)
+    bad = [{"key": bkey, "params": {"m": 1e30}, "ms": 0.1}, {"key": bkey, "params": {"m": 256.5}, "ms": 0.1},
+           {"key": json.dumps({"bucket": 1e30, "dtype": "c64"}), "params": {"m": 256}, "ms": 0.1},
+           {"key": bkey, "params": {"m": 256}},
+           {"key": pkey, "params": {"D": 1e30, "m": 1024}, "ms": 0.1},
+           {"key": pkey, "params": {"D": 2, "m": [1e30]}, "ms": 0.1},
+           {"key": pkey, "params": {"D": 2, "m": 1024, "tile": 1e12}, "ms": 0.1},
+           {"params": {"D": 2, "m": 1024}, "ms": 0.1}, [1, 2], "text", 7]
+    with open(db, "w") as fh:
+        for r in bad:
+            if isinstance(r, dict):
+                r = dict(r, device="dev", build="b1")
+            fh.write(json.dumps(r) + "\n")
+    assert tune.batch_db_choose([1000], "c64", db, device="dev", build="b1") == [tune.batch_default_m(1000)]
+    tdb = tune.TuneDB(db, device="dev", build="b1")
+    assert all(isinstance(r, dict) and "key" in r for r in tdb.rows)
+    res = tune.Tuner1D(tdb, timer=cost_model).a1(1000, 1999, "c64")
+    assert res.source == "A1" and 128 <= res.params["m"] <= 512  # a search ran: no malformed row was taken
+
+
 def test_checkpoint_format_and_training_range(tmp_path):
     """save_checkpoint writes the layout hdc_predictor_load reads: magic, format 2,
     layer sizes, float32 weights, then the per-feature training range."""
