@@ -74,9 +74,11 @@ struct JVal {
 };
 
 struct JParser {
+    static constexpr int kMaxDepth = 64;  // nesting limit: a malformed line cannot exhaust the stack
     const char* s;
     const char* e;
     bool ok = true;
+    int depth = 0;
     void ws() {
         while (s < e && std::isspace((unsigned char)*s)) ++s;
     }
@@ -130,6 +132,15 @@ struct JParser {
     }
     JVal value() {
         JVal v;
+        if (depth >= kMaxDepth) {
+            ok = false;
+            return v;
+        }
+        struct Nest {
+            int& d;
+            explicit Nest(int& x) : d(x) { ++d; }
+            ~Nest() { --d; }
+        } nest(depth);
         ws();
         if (s >= e) {
             ok = false;

@@ -112,8 +112,8 @@ class TuneDB:
                         continue
                     try:
                         r = json.loads(line)
-                    except json.JSONDecodeError:
-                        continue  # a line cut short by a kill
+                    except (ValueError, RecursionError):  # JSONDecodeError is a ValueError
+                        continue  # a line cut short by a kill, or not a row
                     # rows of this form only (a hand-edited or foreign line is skipped)
                     if isinstance(r, dict) and isinstance(r.get("key"), str) and isinstance(r.get("params"), dict) \
                             and isinstance(r.get("ms"), (int, float)) and not isinstance(r.get("ms"), bool):
@@ -444,15 +444,22 @@ class TunerUneq:
     def experience_classes(self, Lf: int, Lg: int, dtype: str, k: int = 2):
         scored = []
         for key in self.db.keys():
-            d = json.loads(key)
-            if "uneq" not in d or d["dtype"] != dtype:
+            try:
+                d = json.loads(key)
+            except (ValueError, RecursionError):
+                continue
+            if not isinstance(d, dict) or "uneq" not in d or d.get("dtype") != dtype:
                 continue
             b = self.db.best(key)
             if b is None:
                 continue
-            (lf, lg), M = d["uneq"], d["M"]
-            dist = abs(math.log2(max(lf, lg)) - math.log2(max(Lf, Lg))) + abs(math.log2(min(lf, lg)) - math.log2(min(Lf, Lg)))
-            scored.append((dist, _uneq_class(lf, lg, M, b[0]["m"], b[0]["lam"])))
+            try:
+                (lf, lg), M = d["uneq"], d["M"]
+                dist = abs(math.log2(max(lf, lg)) - math.log2(max(Lf, Lg))) + \
+                    abs(math.log2(min(lf, lg)) - math.log2(min(Lf, Lg)))
+                scored.append((dist, _uneq_class(lf, lg, M, b[0]["m"], b[0]["lam"])))
+            except (KeyError, TypeError, ValueError, ZeroDivisionError):
+                continue  # a malformed row
         scored.sort()
         out = []
         for _, c in scored:

@@ -311,8 +311,8 @@ def test_batch_tuning_database(tmp_path):
 
 def test_malformed_database_rows_are_skipped(tmp_path):
     """Rows a hand edit or a foreign writer could leave -- sizes beyond range (1e30 would
-    overflow a 64-bit conversion), fractional sizes, missing fields, non-objects -- are
-    skipped by the library's readers (bucket rows and tuner rows) and by TuneDB."""
+    overflow a 64-bit conversion), fractional sizes, missing fields, non-objects, nesting
+    deep enough to exhaust a recursive parser's stack -- are skipped by the library's readers (bucket rows and tuner rows) and by TuneDB."""
     db = str(tmp_path / "bad.jsonl")
     bkey = json.dumps({"bucket": 1024, "dtype": "c64"})
     pkey = json.dumps({"L": [1000], "M": [1999], "batch": 1, "dtype": "c64"}, sort_keys=True)
@@ -328,6 +328,7 @@ def test_malformed_database_rows_are_skipped(tmp_path):
             if isinstance(r, dict):
                 r = dict(r, device="dev", build="b1")
             fh.write(json.dumps(r) + "\n")
+        fh.write("[" * 100000 + "\n" + '{"a": ' * 100000 + "\n")  # nesting deeper than any row
     assert tune.batch_db_choose([1000], "c64", db, device="dev", build="b1") == [tune.batch_default_m(1000)]
     tdb = tune.TuneDB(db, device="dev", build="b1")
     assert all(isinstance(r, dict) and "key" in r for r in tdb.rows)
