@@ -114,6 +114,15 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"libhdc.so not found at {LIB_PATH}: build it with "
                               f"`python -m paper_2306_10016_amd.build` (there is no CPU fallback)")
+        # PyTorch ships its own HIP runtime under the same soname as the system's
+        # (libamdhip64.so.7); the first one loaded serves the whole process.  Loading
+        # torch first keeps one runtime, torch's, for the library and for the
+        # tensors it is handed; loaded first, the library would pull in the system
+        # runtime and torch would then find no device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, args in SIGNATURES.items():
             fn = getattr(L, name)

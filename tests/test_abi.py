@@ -265,3 +265,22 @@ def test_batch_default_m():
     from paper_2306_10016_amd import tune
     assert [tune.batch_default_m(L) for L in (1, 64, 65, 4096, 4097, 8192, 8193, 65536, 65537)] == \
         [1, 64, 128, 4096, 4096, 4096, 16384, 65536, 131072]
+
+
+def test_library_binds_torchs_hip_runtime():
+    """PyTorch ships its own HIP runtime under the system's soname; loading the library
+    first would pull in the system one and leave torch without a device.  The loader
+    imports torch first, so a fresh process that touches only the library maps torch's
+    runtime (and a single one)."""
+    import subprocess
+    import sys
+    torch = pytest.importorskip("torch")
+    import os
+    code = ("import sys; sys.path.insert(0, %r); import paper_2306_10016_amd._lib as l; l.lib(); "
+            "print('\\n'.join(sorted({x for x in open('/proc/self/maps').read().split() "
+            "if x.endswith('libamdhip64.so') or 'libamdhip64.so.' in x})))") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    maps = [x for x in out.stdout.split() if x]
+    assert len(maps) == 1, maps
+    assert os.path.realpath(maps[0]).startswith(os.path.realpath(os.path.dirname(torch.__file__))), maps
