@@ -8,8 +8,9 @@ GPU with real timings:
   held-out problems lie inside it;
 * on the 2D/3D evaluation problems (4096^2, 8192^2, 256^3 complex64) the
   network's top-1 choices stay within 15 % of the library's exhaustive search
-  (A0) re-timed in the same process (the training run measured +6.6, +9.1 and
-  -0.9 %; the margin above 10 % absorbs timing noise);
+  (A0) re-timed in the same process (the training run measured +10.4, -0.1 and
+  -0.7 %, the bench's live run +8.5, +0.1 and -3.0 %; the margin above 10 % absorbs
+  timing noise);
 * on held-out problems the network's choices beat or match the method without
   it -- the default p = 1, all residues per pass.
 
