@@ -109,8 +109,9 @@ const char* hdc_build_id(void);
  *      "device": ..., "build": ..., "t": ...}
  * records that the problems of bucket S ran in t milliseconds with FFT size m.
  * For each bucket the fastest row of the device and build (equal times: the
- * larger m) gives the m of its problems whose output length is 2L - 1; other
- * problems, and buckets without a row, take hdc_batch_default_m.  Rows of other
+ * larger m) gives the m of its problems whose output length is 2L - 1 and that
+ * admit it (hdc_derive); other problems, and buckets without a row, take
+ * hdc_batch_default_m.  Rows of other
  * kinds in the same file are ignored, and hdc_tune ignores these rows.
  *
  * hdc_batch_db_choose: host only (no device is touched); fills m[i] (n values,

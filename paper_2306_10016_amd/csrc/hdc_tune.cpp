@@ -1051,7 +1051,11 @@ hdc_status hdc_batch_db_choose(int64_t n, const int64_t* L, const int64_t* M, hd
         if (L[i] < 1) return fail(HDC_ERR_INVALID_ARG, "problem %lld: L = %lld", (long long)i, (long long)L[i]);
         const bool full = !M || M[i] == 2 * L[i] - 1;
         auto it = best.find(pow2_ceil(L[i]));
-        if (full && it != best.end()) {
+        hdc_axis_desc d{};
+        // a recorded m that this problem cannot take (a row written for other
+        // lengths or by hand) leaves the problem at the default
+        if (full && it != best.end() &&
+            hdc_derive(L[i], 2 * L[i] - 1, it->second.second, 0, 0, 1, 0, dtype, &d) == HDC_OK) {
             m[i] = it->second.second;
         } else {
             hdc_status st = hdc_batch_default_m(L[i], &m[i]);

@@ -303,6 +303,9 @@ def test_batch_tuning_database(tmp_path):
     assert tune.batch_db_choose([1000], "c64", db, device="dev", build="b1") == [256]
     assert lib.hdc_batch_db_record(db.encode(), 1024, 0, 512, 0.0, b"dev", b"b1") == 0
     assert tune.batch_db_choose([1000], "c64", db, device="dev", build="b1") == [512]
+    # a recorded m that a problem cannot take (here not 7-smooth) leaves it at the default
+    assert lib.hdc_batch_db_record(db.encode(), 2048, 0, 11, 0.0, b"dev", b"b1") == 0
+    assert tune.batch_db_choose([1500], "c64", db, device="dev", build="b1") == [tune.batch_default_m(1500)]
     # bad records are refused
     assert lib.hdc_batch_db_record(db.encode(), 1000, 0, 256, 1.0, b"dev", b"b1") == 1  # not a power of two
     assert lib.hdc_batch_db_record(db.encode(), 1024, 0, 0, 1.0, b"dev", b"b1") == 1
